@@ -1,0 +1,184 @@
+/* csot.h -- C ABI of the cyclic-symmetric entropic optimal transport library (libcsot.so).
+ *
+ * The library implements, on one AMD MI355X (gfx950), the data-parallel path of the cyclic
+ * Sinkhorn method of "Optimal Transport with Cyclic Symmetry" (Takeda, Akagi, Marumo, Niwa;
+ * AAAI 2024) and plain full-size Sinkhorn beside it.  Notation: the paper's vector length d,
+ * cyclic order n and regulariser lambda are called n, K and eps here; m = n / K.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Array arguments are DEVICE pointers unless marked [host].  Arrays are row-major and
+ *   contiguous; points are block-major: point I = r*m + i is the i-th point of block r.
+ *   Floating-point arrays are float32; scalars and statistics are float64.
+ * - `stream` is a hipStream_t (NULL = the default stream).  Every call only enqueues work on
+ *   it and returns, except where a [host] output is requested (the call then synchronises
+ *   the stream) or `opts->validate` is set (it copies inputs to the host first).
+ * - The library never allocates device memory.  Scratch space is the caller's `ws` buffer of
+ *   `ws_bytes` bytes (256-byte aligned, at least ot_workspace_bytes()); its contents need no
+ *   initialisation and are clobbered.  Two calls that share one `ws` must be ordered (same
+ *   stream), and no state is kept between calls.
+ * - Return value: OT_OK (0) or one of the OT_ERR_* codes below; ot_last_error() gives a
+ *   message for the calling thread.  Arguments are validated on the host before any device
+ *   work is enqueued, so an error return has enqueued nothing.  No C++ exception crosses the
+ *   ABI and nothing aborts the process.
+ */
+#ifndef CSOT_H
+#define CSOT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  OT_OK = 0,
+  OT_ERR_ARG = 1,           /* null pointer, n % K != 0, bad dim, eps <= 0, ld too small ...  */
+  OT_ERR_MASS = 2,          /* validate=1: negative/zero/non-finite marginal or |sum a - sum b| > 1e-6 */
+  OT_ERR_NOT_SYMMETRIC = 3, /* validate=1: sampled cost entries are not block-circulant         */
+  OT_ERR_NOCONV = 4,        /* max_iter reached before tol (only reported with host stats);
+                               outputs and statistics are still valid                          */
+  OT_ERR_NONFINITE = 5,     /* a potential became NaN/inf (only reported with host stats)       */
+  OT_ERR_WORKSPACE = 6,     /* ws NULL or smaller than ot_workspace_bytes(), or misaligned      */
+  OT_ERR_HIP = 7,           /* a HIP runtime call failed, or a device-side wait timed out       */
+  OT_ERR_UNSUPPORTED = 8    /* size outside what the kernels are built for                      */
+};
+
+/* One transport problem (eq. problem_ROT of the paper under Assumption 1).
+ *   dim in {2, 3}: costs are squared Euclidean distances C_IJ = |x_I - y_J|^2 recomputed
+ *                  on the fly from the coordinates x, y ([n, dim] each); C must be NULL.
+ *   dim == 0     : dense cost C [rows, ldc] with ldc >= n.  Calls on the reduced problem read
+ *                  only block-row 0 (rows 0..m-1), whose column block k is the cost block
+ *                  C_k of eq. blkstr_cost; full-size calls read all n rows.
+ *   a, b         : marginals [n], positive; sum a == sum b (== 1 for probability vectors).
+ *   eps          : the entropic regulariser lambda of eq. reg_for_entropy_ROT (> 0, absolute;
+ *                  a caller wanting eps = factor * median(C) computes it itself).           */
+typedef struct ot_problem {
+  int32_t n, K, dim;
+  const float* x;
+  const float* y;
+  const float* C;
+  int64_t ldc;
+  const float* a;
+  const float* b;
+  double eps;
+} ot_problem;
+
+/* Solver options; a NULL pointer means the defaults in brackets.
+ *   tol        [1e-6]  stop when the full-space L2 row-marginal residual ||T 1 - a||_2 of the
+ *                      current plan is <= tol (the column marginal is exact after each column
+ *                      update).  tol = 0 runs exactly max_iter iterations.
+ *   max_iter   [10000] >= 1.
+ *   fold_fp64  [-1]    fold's log-sum over the K shifts in float64: 1 yes, 0 no, -1 auto
+ *                      (float64 when K >= 32; callers that know eps is small relative to the
+ *                      cost scale pass 1).
+ *   warm_start [0]     1: on entry g holds the initial column potential (natural units).
+ *   validate   [0]     1: host-side checks of the marginals and of block-circulance (syncs).
+ *   workgroups [0]     persistent solvers: number of cooperating workgroups (0 = automatic).
+ */
+typedef struct ot_opts {
+  double tol;
+  int32_t max_iter;
+  int32_t fold_fp64;
+  int32_t warm_start;
+  int32_t validate;
+  int32_t workgroups;
+  int32_t reserved[3];
+} ot_opts;
+
+/* [host] statistics of a solve.  err_row / err_col are recomputed in float64 on the GPU from
+ * the returned potentials (full-space L2 norms, the marginal-error metric of Sec. 7.1). */
+typedef struct ot_stats {
+  int32_t iters;     /* completed (row, column) update pairs in the returned state            */
+  int32_t converged; /* 1 when the float32 residual test met tol                               */
+  double err_row;    /* ||T 1 - a||_2                                                          */
+  double err_col;    /* ||T^T 1 - b||_2                                                        */
+  double err_row32;  /* the float32 residual the stopping test used                            */
+  int32_t flags;     /* bit 0: non-finite potential; bit 1: device wait timed out              */
+  int32_t reserved;
+} ot_stats;
+
+/* Device-side statistics: solvers write OT_DSTATS_LEN doubles to `dstats` (device) in the
+ * layout {iters, converged, err_row, err_col, err_row32, flags, 0, 0}. */
+#define OT_DSTATS_LEN 8
+
+/* Bytes of scratch space any call below needs for this problem and these options. */
+size_t ot_workspace_bytes(const ot_problem* prob, const ot_opts* opts);
+
+/* Fold (Alg. 2, first step; eq. def_Kij) and marginal fold (Alg. 3, stage 1).
+ *   logK  [m, m] out: logK_ij = log sum_k exp(-C_ijk / eps), C_ijk = cost of block-row 0
+ *         between point i and point k*m + j (C_k[i, j] of eq. blkstr_cost).
+ *   alpha, beta [m] out: alpha_i = (1/K) sum_r a_{r m + i}; equal to the repeated block for
+ *         periodic marginals (eq. assumption_for_input_vectors).
+ * Errors: OT_ERR_ARG, OT_ERR_MASS / OT_ERR_NOT_SYMMETRIC (validate), OT_ERR_HIP. */
+int ot_fold_kernel(const ot_problem* prob, const ot_opts* opts, float* logK, float* alpha,
+                   float* beta, void* ws, size_t ws_bytes, void* stream);
+
+/* Block-circulant projection of the cost of approximately symmetric data (the averaging of
+ * Alg. 3, stage 1, applied to the cost as Lemma 1's proof averages a plan):
+ *   Csym[i, k*m + j] = (1/K) sum_r C[r*m + i, ((r + k) mod K)*m + j],  Csym [m, ldcs], ldcs >= n.
+ * The result is block-row 0 of a block-circulant cost; use it as a dense problem (dim = 0,
+ * C = Csym, ldc = ldcs) for the reduced calls.  Errors: OT_ERR_ARG, OT_ERR_HIP. */
+int ot_symmetrize_cost(const ot_problem* prob, float* Csym, int64_t ldcs, void* stream);
+
+/* Cyclic Sinkhorn iterations on the folded m x m problem (Alg. 2; eq.
+ * optimal_f_sinkhorn_logdomain and the log of eq. optimal_sinkhorn), in the log domain:
+ *   f_i = eps log alpha_i - eps LSE_j(logK_ij + g_j / eps),
+ *   g_j = eps log beta_j  - eps LSE_i(logK_ij + f_i / eps),
+ * from g = 0 (q = 1) or the warm start, until the full-space row residual
+ * sqrt(K) ||T_red 1 - alpha||_2 <= tol.  Only prob->n, K and eps are read.
+ *   f, g [m] out (g is also the warm-start input); dstats [OT_DSTATS_LEN] device out or NULL;
+ *   hstats [host] out or NULL (non-NULL synchronises and enables OT_ERR_NOCONV/NONFINITE).
+ * One persistent cooperative launch: workgroups own row/column slabs of logK in LDS and meet
+ * at device-wide barriers; no host round trip per iteration. */
+int ot_sinkhorn_reduced(const ot_problem* prob, const ot_opts* opts, const float* logK,
+                        const float* alpha, const float* beta, float* f, float* g,
+                        double* dstats, ot_stats* hstats, void* ws, size_t ws_bytes,
+                        void* stream);
+
+/* Plain full-size log-domain Sinkhorn on the n x n problem (Alg. 3, stage 2; the paper's
+ * baseline), costs recomputed per tile from the coordinates (dim 2/3) or streamed from the
+ * dense C (dim 0).  Same stopping rule, statistics and launch structure as the reduced call.
+ *   f, g [n] out (g is also the warm-start input). */
+int ot_sinkhorn_full(const ot_problem* prob, const ot_opts* opts, float* f, float* g,
+                     double* dstats, ot_stats* hstats, void* ws, size_t ws_bytes,
+                     void* stream);
+
+/* Expansion of the reduced solution to the full block-circulant plan (Lemma 1, eq.
+ * blkstr_optimal_solution; eq. optimality_condition; Alg. 2, last steps):
+ *   T[r*m + i, c*m + j] = exp((f_i + g_j - C_{ij,(c - r) mod K}) / eps),  T [n, ldt], ldt >= n.
+ * f, g [m] are reduced potentials.  Errors: OT_ERR_ARG, OT_ERR_HIP. */
+int ot_expand_plan(const ot_problem* prob, const float* f, const float* g, float* T,
+                   int64_t ldt, void* stream);
+
+/* Objective values and gradients from converged potentials.
+ *   reduced = 1: f, g [m] (plan T_ijk = exp((f_i + g_j - C_ijk)/eps) expanded by Lemma 1);
+ *   reduced = 0: f, g [n] (plan T_IJ = exp((f_I + g_J - C_IJ)/eps)).
+ *   out [8] device doubles: {P, D, <C,T>, err_row, err_col, mass, 0, 0} of the FULL problem:
+ *     P = <C,T> + eps sum T (log T - 1)  (eq. problem_ROT with eq. reg_for_entropy_ROT),
+ *         evaluated as sum T (C + eps (Z - 1)), Z = log T;  for reduced = 1 it is K times the
+ *         reduced objective (eq. problem_CROT);
+ *     D = <f,a> + <g,b> - eps sum T (eq. dual_problem_cyclic_ROT);
+ *   dC   [K, m, m] (reduced, dC[k,i,j] = dP/dC[r*m+i, ((r+k) mod K)*m+j] = T_ijk) or
+ *        [n, lddc] (full, = T);  NULL to skip.
+ *   dx, dy [n, dim]: dP/dx_I = 2 sum_J T_IJ (x_I - y_J), dP/dy_J = 2 sum_I T_IJ (y_J - x_I);
+ *        NULL to skip; must be NULL for dim = 0.
+ *   da, db [n]: dP/da = f - mean(f), dP/db = g - mean(g) (tiled for reduced); NULL to skip.
+ * The gradients are the envelope theorem applied to the dual (exact at the optimum).
+ * Errors: OT_ERR_ARG, OT_ERR_WORKSPACE, OT_ERR_HIP. */
+int ot_cost_and_grad(const ot_problem* prob, const float* f, const float* g, int32_t reduced,
+                     double* out, float* dC, int64_t lddc, float* dx, float* dy, float* da,
+                     float* db, void* ws, size_t ws_bytes, void* stream);
+
+/* Message describing the last non-OK return on the calling thread ("" if none). */
+const char* ot_last_error(void);
+
+/* Library version string. */
+const char* ot_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CSOT_H */

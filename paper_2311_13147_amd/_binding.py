@@ -1,0 +1,287 @@
+"""ctypes binding of libcsot.so -- argument marshalling only.
+
+Every function here has the name of the C entry point it calls (include/csot.h) and does
+nothing but check tensor shapes/devices, allocate outputs and workspace with PyTorch, and pass
+raw device pointers plus the current HIP stream.  All arithmetic runs in the library's HIP
+kernels.  There is no CPU fallback: if the library is missing or cannot be loaded, importing
+the package raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libcsot.so")
+
+OT_OK, OT_ERR_ARG, OT_ERR_MASS, OT_ERR_NOT_SYMMETRIC, OT_ERR_NOCONV = 0, 1, 2, 3, 4
+OT_ERR_NONFINITE, OT_ERR_WORKSPACE, OT_ERR_HIP, OT_ERR_UNSUPPORTED = 5, 6, 7, 8
+OT_DSTATS_LEN = 8
+_CODE_NAMES = {0: "OT_OK", 1: "OT_ERR_ARG", 2: "OT_ERR_MASS", 3: "OT_ERR_NOT_SYMMETRIC",
+               4: "OT_ERR_NOCONV", 5: "OT_ERR_NONFINITE", 6: "OT_ERR_WORKSPACE",
+               7: "OT_ERR_HIP", 8: "OT_ERR_UNSUPPORTED"}
+
+
+class CsotError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_CODE_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class OtProblem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("K", ctypes.c_int32), ("dim", ctypes.c_int32),
+                ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("C", ctypes.c_void_p),
+                ("ldc", ctypes.c_int64), ("a", ctypes.c_void_p), ("b", ctypes.c_void_p),
+                ("eps", ctypes.c_double)]
+
+
+class OtOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("fold_fp64", ctypes.c_int32), ("warm_start", ctypes.c_int32),
+                ("validate", ctypes.c_int32), ("workgroups", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
+
+
+class OtStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("err_row", ctypes.c_double), ("err_col", ctypes.c_double),
+                ("err_row32", ctypes.c_double), ("flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing; build it with "
+                          "`python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(_LIB_PATH)
+    P, VP, SZ, I32, I64, D = (ctypes.POINTER(OtProblem), ctypes.c_void_p, ctypes.c_size_t,
+                              ctypes.c_int32, ctypes.c_int64, ctypes.c_double)
+    PO, PS = ctypes.POINTER(OtOpts), ctypes.POINTER(OtStats)
+    sig = {
+        "ot_workspace_bytes": (SZ, [P, PO]),
+        "ot_fold_kernel": (ctypes.c_int, [P, PO, VP, VP, VP, VP, SZ, VP]),
+        "ot_symmetrize_cost": (ctypes.c_int, [P, VP, I64, VP]),
+        "ot_sinkhorn_reduced": (ctypes.c_int, [P, PO, VP, VP, VP, VP, VP, VP, PS, VP, SZ, VP]),
+        "ot_sinkhorn_full": (ctypes.c_int, [P, PO, VP, VP, VP, PS, VP, SZ, VP]),
+        "ot_expand_plan": (ctypes.c_int, [P, VP, VP, VP, I64, VP]),
+        "ot_cost_and_grad": (ctypes.c_int, [P, VP, VP, I32, VP, VP, I64, VP, VP, VP, VP, VP, SZ, VP]),
+        "ot_last_error": (ctypes.c_char_p, []),
+        "ot_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+LIB_PATH = _LIB_PATH
+EXPORTED = ("ot_workspace_bytes", "ot_fold_kernel", "ot_symmetrize_cost", "ot_sinkhorn_reduced",
+            "ot_sinkhorn_full", "ot_expand_plan", "ot_cost_and_grad", "ot_last_error",
+            "ot_version")
+
+
+def raw_lib():
+    """The ctypes handle (for tests of the host-side validation)."""
+    return _lib
+
+
+def _check(rc: int, allow=()):
+    if rc != OT_OK and rc not in allow:
+        raise CsotError(rc, _lib.ot_last_error().decode())
+    return rc
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_f32(t: torch.Tensor, name: str, shape=None) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t
+
+
+class Problem:
+    """Device tensors of one problem.  Coordinates (x, y: [n, dim], dim in {2, 3}) or a dense
+    cost C ([rows, ldc], dim = 0); marginals a, b [n]; eps > 0; cyclic order K."""
+
+    def __init__(self, a, b, eps, K, x=None, y=None, C=None):
+        self.a = _dev_f32(a, "a")
+        self.b = _dev_f32(b, "b")
+        self.n = int(a.shape[0])
+        self.K = int(K)
+        self.eps = float(eps)
+        self.x = self.y = self.C = None
+        if C is not None:
+            self.C = _dev_f32(C, "C")
+            self.dim = 0
+            self.ldc = int(C.stride(0))
+        else:
+            self.x = _dev_f32(x, "x")
+            self.y = _dev_f32(y, "y")
+            self.dim = int(x.shape[1])
+            self.ldc = 0
+        self.device = a.device
+        self._c = OtProblem(self.n, self.K, self.dim, _ptr(self.x), _ptr(self.y), _ptr(self.C),
+                            self.ldc, _ptr(self.a), _ptr(self.b), self.eps)
+
+    @property
+    def m(self):
+        return self.n // self.K
+
+    def c(self):
+        return ctypes.byref(self._c)
+
+
+def make_opts(tol=1e-6, max_iter=10000, fold_fp64=-1, warm_start=0, validate=0, workgroups=0):
+    return OtOpts(float(tol), int(max_iter), int(fold_fp64), int(warm_start), int(validate),
+                  int(workgroups))
+
+
+_ws_cache = {}
+
+
+def workspace(prob: Problem, opts: Optional[OtOpts] = None) -> torch.Tensor:
+    nbytes = int(_lib.ot_workspace_bytes(prob.c(), ctypes.byref(opts) if opts else None))
+    key = (prob.device, torch.cuda.current_stream().cuda_stream)
+    ws = _ws_cache.get(key)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=prob.device)
+        _ws_cache[key] = ws
+    return ws
+
+
+def ot_workspace_bytes(prob: Problem, opts: Optional[OtOpts] = None) -> int:
+    return int(_lib.ot_workspace_bytes(prob.c(), ctypes.byref(opts) if opts else None))
+
+
+def ot_fold_kernel(prob: Problem, opts: Optional[OtOpts] = None, out=None):
+    """-> (logK [m, m], alpha [m], beta [m])"""
+    m = prob.m
+    if out is None:
+        out = (torch.empty((m, m), dtype=torch.float32, device=prob.device),
+               torch.empty(m, dtype=torch.float32, device=prob.device),
+               torch.empty(m, dtype=torch.float32, device=prob.device))
+    logK, alpha, beta = out
+    ws = workspace(prob, opts)
+    _check(_lib.ot_fold_kernel(prob.c(), ctypes.byref(opts) if opts else None, _ptr(logK),
+                               _ptr(alpha), _ptr(beta), _ptr(ws), ws.numel(), _stream()))
+    return logK, alpha, beta
+
+
+def ot_symmetrize_cost(prob: Problem, out=None):
+    """-> Csym [m, n]: block-row 0 of the block-circulant projection of the cost."""
+    if out is None:
+        out = torch.empty((prob.m, prob.n), dtype=torch.float32, device=prob.device)
+    _check(_lib.ot_symmetrize_cost(prob.c(), _ptr(out), int(out.stride(0)), _stream()))
+    return out
+
+
+def _stats_dict(st: OtStats):
+    return {"iters": st.iters, "converged": bool(st.converged), "err_row": st.err_row,
+            "err_col": st.err_col, "err_row32": st.err_row32, "flags": st.flags}
+
+
+def ot_sinkhorn_reduced(prob: Problem, logK, alpha, beta, opts: Optional[OtOpts] = None,
+                        g0=None, host_stats=True, out=None, dstats=None):
+    """-> (f [m], g [m], stats).  stats is a dict (host_stats=True, synchronises) or the
+    device tensor of OT_DSTATS_LEN doubles."""
+    m = prob.m
+    _dev_f32(logK, "logK", (m, m))
+    _dev_f32(alpha, "alpha", (m,))
+    _dev_f32(beta, "beta", (m,))
+    opts = opts or make_opts()
+    if out is None:
+        out = (torch.empty(m, dtype=torch.float32, device=prob.device),
+               torch.empty(m, dtype=torch.float32, device=prob.device))
+    f, g = out
+    if g0 is not None:
+        g.copy_(g0)
+        opts.warm_start = 1
+    if dstats is None:
+        dstats = torch.zeros(OT_DSTATS_LEN, dtype=torch.float64, device=prob.device)
+    ws = workspace(prob, opts)
+    hs = OtStats() if host_stats else None
+    _check(_lib.ot_sinkhorn_reduced(prob.c(), ctypes.byref(opts), _ptr(logK), _ptr(alpha),
+                                    _ptr(beta), _ptr(f), _ptr(g), _ptr(dstats),
+                                    ctypes.byref(hs) if hs is not None else None, _ptr(ws),
+                                    ws.numel(), _stream()), allow=(OT_ERR_NOCONV,))
+    return f, g, (_stats_dict(hs) if hs is not None else dstats)
+
+
+def ot_sinkhorn_full(prob: Problem, opts: Optional[OtOpts] = None, g0=None, host_stats=True,
+                     out=None, dstats=None):
+    """-> (f [n], g [n], stats)"""
+    n = prob.n
+    opts = opts or make_opts()
+    if out is None:
+        out = (torch.empty(n, dtype=torch.float32, device=prob.device),
+               torch.empty(n, dtype=torch.float32, device=prob.device))
+    f, g = out
+    if g0 is not None:
+        g.copy_(g0)
+        opts.warm_start = 1
+    if dstats is None:
+        dstats = torch.zeros(OT_DSTATS_LEN, dtype=torch.float64, device=prob.device)
+    ws = workspace(prob, opts)
+    hs = OtStats() if host_stats else None
+    _check(_lib.ot_sinkhorn_full(prob.c(), ctypes.byref(opts), _ptr(f), _ptr(g), _ptr(dstats),
+                                 ctypes.byref(hs) if hs is not None else None, _ptr(ws),
+                                 ws.numel(), _stream()), allow=(OT_ERR_NOCONV,))
+    return f, g, (_stats_dict(hs) if hs is not None else dstats)
+
+
+def ot_expand_plan(prob: Problem, f, g, out=None):
+    """-> T [n, n], the block-circulant plan from reduced potentials."""
+    if out is None:
+        out = torch.empty((prob.n, prob.n), dtype=torch.float32, device=prob.device)
+    _check(_lib.ot_expand_plan(prob.c(), _ptr(f), _ptr(g), _ptr(out), int(out.stride(0)),
+                               _stream()))
+    return out
+
+
+def ot_cost_and_grad(prob: Problem, f, g, reduced: bool, want_dC=False, want_dxy=False,
+                     want_dab=False, out=None):
+    """-> dict with 'values' (device double[8]: P, D, <C,T>, err_row, err_col, mass) and the
+    requested gradients dC ([K, m, m] reduced or [n, n] full), dx, dy ([n, dim]), da, db
+    ([n])."""
+    dev = prob.device
+    n, m, K = prob.n, prob.m, prob.K
+    vals = out if out is not None else torch.empty(8, dtype=torch.float64, device=dev)
+    dC = None
+    if want_dC:
+        dC = torch.empty((K, m, m) if reduced else (n, n), dtype=torch.float32, device=dev)
+    dx = dy = None
+    if want_dxy:
+        dx = torch.empty((n, prob.dim), dtype=torch.float32, device=dev)
+        dy = torch.empty((n, prob.dim), dtype=torch.float32, device=dev)
+    da = db = None
+    if want_dab:
+        da = torch.empty(n, dtype=torch.float32, device=dev)
+        db = torch.empty(n, dtype=torch.float32, device=dev)
+    ws = workspace(prob)
+    lddc = n if (dC is not None and not reduced) else 0
+    _check(_lib.ot_cost_and_grad(prob.c(), _ptr(f), _ptr(g), 1 if reduced else 0, _ptr(vals),
+                                 _ptr(dC), lddc, _ptr(dx), _ptr(dy), _ptr(da), _ptr(db),
+                                 _ptr(ws), ws.numel(), _stream()))
+    return {"values": vals, "dC": dC, "dx": dx, "dy": dy, "da": da, "db": db}
+
+
+def values_dict(vals: torch.Tensor):
+    v = vals.detach().cpu().tolist()
+    return {"P": v[0], "D": v[1], "CT": v[2], "err_row": v[3], "err_col": v[4], "mass": v[5]}

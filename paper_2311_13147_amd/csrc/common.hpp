@@ -1,0 +1,112 @@
+// Device helpers shared by the csot kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace csot {
+
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+constexpr double kLog2eD = 1.4426950408889634074;
+constexpr double kLn2D = 0.69314718055994530942;
+constexpr float kNegBig = -1.0e30f;  // finite "minus infinity" for running maxima
+constexpr int kWave = 64;
+
+// 2^x and log2(x) on the transcendental unit (v_exp_f32 / v_log_f32, 1 ulp).
+__device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float log2_fast(float x) { return __builtin_amdgcn_logf(x); }
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+// max / sum over groups of `width` consecutive lanes (width a power of two <= 64)
+__device__ __forceinline__ float group_max(float v, int width) {
+  for (int o = width >> 1; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+__device__ __forceinline__ float group_sum(float v, int width) {
+  for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+// Merge of two (max, sum) log-sum-exp partials in base 2: value = M + log2(S).
+__device__ __forceinline__ void lse_merge(float& M, float& S, float M2, float S2) {
+  const float Mn = fmaxf(M, M2);
+  S = S * exp2_fast(M - Mn) + S2 * exp2_fast(M2 - Mn);
+  M = Mn;
+}
+
+// Block-wide sum of a double; every thread gets the result.  `scratch` holds >= nwaves
+// doubles of shared memory.  Must be called by all threads of the block.
+__device__ __forceinline__ double block_sum_d(double v, double* scratch) {
+  v = wave_sum_d(v);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int nw = (blockDim.x + kWave - 1) / kWave;
+  __syncthreads();
+  if (lane == 0) scratch[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int w = 0; w < nw; ++w) t += scratch[w];
+  __syncthreads();
+  return t;
+}
+
+// ----------------------------------------------------------------------------------------
+// Device-wide barrier for cooperative (co-resident) grids.
+//
+// `ctl[0]` is a monotonically increasing arrival counter, zeroed by the host-ordered init
+// kernel before the launch; barrier number b (1, 2, ...) completes when the counter reaches
+// nblocks * b.  Every thread publishes its own global writes with an agent-scope release
+// fence, one thread per block arrives and polls, then an agent-scope acquire fence makes the
+// other blocks' writes visible to the whole block.  The wait is bounded: after `kSpinLimit`
+// polls the block raises the abort flag `ctl[1]`; every other waiter sees it and gives up, so
+// the grid always drains.  Returns false when the barrier was abandoned.
+// ----------------------------------------------------------------------------------------
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+__device__ __forceinline__ bool grid_barrier(uint32_t* ctl, uint32_t target, int* s_flag) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    __hip_atomic_fetch_add(&ctl[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t spins = 0;
+    while (__hip_atomic_load(&ctl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins >= kSpinLimit) {
+        __hip_atomic_store(&ctl[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      if ((spins & 63u) == 0 &&
+          __hip_atomic_load(&ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+        ok = 0;
+        break;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    *s_flag = ok;
+  }
+  __syncthreads();
+  return *s_flag != 0;
+}
+
+// Zero `count` 32-bit words (control blocks) -- a kernel rather than a memset so that a
+// captured graph holds no memset node.
+__global__ void zero_words_kernel(uint32_t* p, int count);
+
+}  // namespace csot

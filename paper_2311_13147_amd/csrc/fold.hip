@@ -1,0 +1,177 @@
+// Fold of the Gibbs kernel over the K cyclic shifts, fold of the marginals, and the
+// block-circulant projection of a cost.
+//
+//   logK_ij = log sum_k exp(-C_ijk / eps)           (eq. def_Kij; Alg. 2, first step)
+//   alpha_i = (1/K) sum_r a_{r m + i}                (Alg. 3, stage 1)
+//   Csym[i, k m + j] = (1/K) sum_r C[r m + i, ((r + k) mod K) m + j]
+//
+// C_ijk is block-row 0 of the block-circulant cost (eq. blkstr_cost): the cost between point
+// i and point k*m + j, recomputed from the float32 coordinates or read from a dense C.  The
+// k-sum is a max-shifted log-sum-exp: two passes over k (minimum cost, then the shifted sum),
+// so no term overflows and the dominant term is exact.  In float64 mode the costs, the shift,
+// the exponentials and the logarithm are all float64 and only the result is rounded; in
+// float32 mode they use the transcendental unit in base 2.
+//
+// Work per output entry: K cost evaluations twice and K exponentials; the output is m*m
+// floats, so the kernel is bound by exp throughput (float32) or float64 FMA throughput.
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace csot {
+
+__global__ void zero_words_kernel(uint32_t* p, int count) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+hipError_t launch_zero_words(uint32_t* p, int count, hipStream_t s) {
+  const int blocks = (count + 255) / 256 < 64 ? (count + 255) / 256 : 64;
+  hipLaunchKernelGGL(zero_words_kernel, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, p,
+                     count);
+  return hipGetLastError();
+}
+
+constexpr int kFoldTJ = 64;  // j per block (one wave wide -> coalesced reads of y / C)
+constexpr int kFoldTI = 4;   // i per block
+
+template <int DIM, typename Real>
+__device__ __forceinline__ Real pt_cost(const float* __restrict__ x, int I,
+                                        const float* __restrict__ y, int J) {
+  Real c = 0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const Real df = (Real)x[(int64_t)I * DIM + d] - (Real)y[(int64_t)J * DIM + d];
+    c += df * df;
+  }
+  return c;
+}
+
+template <int DIM>
+__device__ __forceinline__ void fold_entry_fp64(const Geom& g, int i, int j, float* out) {
+  double cmin = 1.0e300;
+  for (int k = 0; k < g.K; ++k) {
+    double c;
+    if constexpr (DIM == 0) c = (double)g.C[(int64_t)i * g.ldc + (int64_t)k * g.m + j];
+    else c = pt_cost<DIM, double>(g.x, i, g.y, k * g.m + j);
+    cmin = c < cmin ? c : cmin;
+  }
+  const double inv_eps = 1.0 / g.eps;
+  double s = 0.0;
+  for (int k = 0; k < g.K; ++k) {
+    double c;
+    if constexpr (DIM == 0) c = (double)g.C[(int64_t)i * g.ldc + (int64_t)k * g.m + j];
+    else c = pt_cost<DIM, double>(g.x, i, g.y, k * g.m + j);
+    s += exp((cmin - c) * inv_eps);
+  }
+  *out = (float)(-cmin * inv_eps + log(s));
+}
+
+template <int DIM>
+__device__ __forceinline__ void fold_entry_fp32(const Geom& g, int i, int j, float s2,
+                                                float* out) {
+  float cmin = 3.0e38f;
+  for (int k = 0; k < g.K; ++k) {
+    float c;
+    if constexpr (DIM == 0) c = g.C[(int64_t)i * g.ldc + (int64_t)k * g.m + j];
+    else c = pt_cost<DIM, float>(g.x, i, g.y, k * g.m + j);
+    cmin = fminf(c, cmin);
+  }
+  float s = 0.0f;
+  for (int k = 0; k < g.K; ++k) {
+    float c;
+    if constexpr (DIM == 0) c = g.C[(int64_t)i * g.ldc + (int64_t)k * g.m + j];
+    else c = pt_cost<DIM, float>(g.x, i, g.y, k * g.m + j);
+    s += exp2_fast((cmin - c) * s2);
+  }
+  *out = (-cmin * s2 + log2_fast(s)) * kLn2;
+}
+
+// Blocks with blockIdx.y < ceil(m / TI) fold logK; the last row of blocks folds a and b.
+template <int DIM, bool FP64>
+__global__ void __launch_bounds__(kFoldTJ* kFoldTI)
+    fold_kernel(Geom g, float* __restrict__ logK, float* __restrict__ alpha,
+                float* __restrict__ beta, int iblocks) {
+  const int tj = threadIdx.x % kFoldTJ;
+  const int ti = threadIdx.x / kFoldTJ;
+  if ((int)blockIdx.y == iblocks) {
+    // marginal fold: 2*m outputs over the x-dimension of this block row
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < 2 * g.m) {
+      const float* v = t < g.m ? g.a : g.b;
+      const int i = t < g.m ? t : t - g.m;
+      double acc = 0.0;
+      for (int r = 0; r < g.K; ++r) acc += (double)v[(int64_t)r * g.m + i];
+      (t < g.m ? alpha : beta)[i] = (float)(acc / (double)g.K);
+    }
+    return;
+  }
+  const int j = blockIdx.x * kFoldTJ + tj;
+  const int i = blockIdx.y * kFoldTI + ti;
+  if (i >= g.m || j >= g.m) return;
+  float* out = logK + (int64_t)i * g.m + j;
+  if constexpr (FP64) {
+    fold_entry_fp64<DIM>(g, i, j, out);
+  } else {
+    const float s2 = (float)(kLog2eD / g.eps);
+    fold_entry_fp32<DIM>(g, i, j, s2, out);
+  }
+}
+
+template <int DIM, bool FP64>
+static hipError_t launch_fold_t(const Geom& g, float* logK, float* alpha, float* beta,
+                                hipStream_t s) {
+  const int jblocks = (g.m + kFoldTJ - 1) / kFoldTJ;
+  const int iblocks = (g.m + kFoldTI - 1) / kFoldTI;
+  const int mblocks = (2 * g.m + kFoldTJ * kFoldTI - 1) / (kFoldTJ * kFoldTI);
+  const int gx = jblocks > mblocks ? jblocks : mblocks;
+  hipLaunchKernelGGL((fold_kernel<DIM, FP64>), dim3(gx, iblocks + 1), dim3(kFoldTJ * kFoldTI),
+                     0, s, g, logK, alpha, beta, iblocks);
+  return hipGetLastError();
+}
+
+hipError_t launch_fold(const Geom& g, bool fp64, float* logK, float* alpha, float* beta,
+                       hipStream_t s) {
+  switch (g.dim) {
+    case 0: return fp64 ? launch_fold_t<0, true>(g, logK, alpha, beta, s)
+                        : launch_fold_t<0, false>(g, logK, alpha, beta, s);
+    case 2: return fp64 ? launch_fold_t<2, true>(g, logK, alpha, beta, s)
+                        : launch_fold_t<2, false>(g, logK, alpha, beta, s);
+    case 3: return fp64 ? launch_fold_t<3, true>(g, logK, alpha, beta, s)
+                        : launch_fold_t<3, false>(g, logK, alpha, beta, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ---- block-circulant projection ----------------------------------------------------------
+// One thread per output entry (i, j) of block k = blockIdx.z; float64 accumulation of the K
+// float32 costs along the block diagonal.
+template <int DIM>
+__global__ void __launch_bounds__(kFoldTJ* kFoldTI)
+    symmetrize_kernel(Geom g, float* __restrict__ Csym, int64_t ldcs) {
+  const int j = blockIdx.x * kFoldTJ + threadIdx.x % kFoldTJ;
+  const int i = blockIdx.y * kFoldTI + threadIdx.x / kFoldTJ;
+  const int k = blockIdx.z;
+  if (i >= g.m || j >= g.m) return;
+  double acc = 0.0;
+  for (int r = 0; r < g.K; ++r) {
+    const int I = r * g.m + i;
+    const int J = ((r + k) % g.K) * g.m + j;
+    if constexpr (DIM == 0) acc += (double)g.C[(int64_t)I * g.ldc + J];
+    else acc += (double)pt_cost<DIM, float>(g.x, I, g.y, J);
+  }
+  Csym[(int64_t)i * ldcs + (int64_t)k * g.m + j] = (float)(acc / (double)g.K);
+}
+
+hipError_t launch_symmetrize(const Geom& g, float* Csym, int64_t ldcs, hipStream_t s) {
+  const dim3 grid((g.m + kFoldTJ - 1) / kFoldTJ, (g.m + kFoldTI - 1) / kFoldTI, g.K);
+  const dim3 block(kFoldTJ * kFoldTI);
+  switch (g.dim) {
+    case 0: hipLaunchKernelGGL(symmetrize_kernel<0>, grid, block, 0, s, g, Csym, ldcs); break;
+    case 2: hipLaunchKernelGGL(symmetrize_kernel<2>, grid, block, 0, s, g, Csym, ldcs); break;
+    case 3: hipLaunchKernelGGL(symmetrize_kernel<3>, grid, block, 0, s, g, Csym, ldcs); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace csot

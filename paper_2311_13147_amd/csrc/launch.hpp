@@ -1,0 +1,66 @@
+// Host-side launchers of the csot kernels (internal; the public surface is include/csot.h).
+// Every launcher enqueues on `stream` and returns the HIP status of the launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace csot {
+
+// Geometry of one problem as the kernels see it.
+struct Geom {
+  int n, K, m, dim;
+  const float* x;
+  const float* y;
+  const float* C;
+  int64_t ldc;
+  const float* a;
+  const float* b;
+  double eps;
+};
+
+// ---- fold.hip ----------------------------------------------------------------------------
+hipError_t launch_fold(const Geom& g, bool fp64, float* logK, float* alpha, float* beta,
+                       hipStream_t s);
+hipError_t launch_symmetrize(const Geom& g, float* Csym, int64_t ldcs, hipStream_t s);
+hipError_t launch_zero_words(uint32_t* p, int count, hipStream_t s);
+
+// ---- reduced.hip -------------------------------------------------------------------------
+struct ReducedPlan {
+  int W;        // cooperating workgroups
+  int R;        // rows (and columns) per workgroup
+  int threads;  // threads per workgroup
+  size_t lds;   // dynamic LDS bytes
+};
+bool plan_reduced(int m, int workgroups_hint, ReducedPlan* plan);
+size_t reduced_ws_bytes(int m, const ReducedPlan& p);
+hipError_t launch_sinkhorn_reduced(int m, int K, double eps, const float* logK,
+                                   const float* alpha, const float* beta, float* f, float* g,
+                                   double tol, int max_iter, int warm, double* dstats,
+                                   void* ws, const ReducedPlan& p, hipStream_t s);
+
+// ---- full.hip ----------------------------------------------------------------------------
+struct FullPlan {
+  int W;
+  int R;
+  int threads;
+  size_t lds;
+};
+bool plan_full(const Geom& g, int workgroups_hint, FullPlan* plan);
+size_t full_ws_bytes(const Geom& g, const FullPlan& p);
+hipError_t launch_sinkhorn_full(const Geom& g, float* f, float* gpot, double tol, int max_iter,
+                                int warm, double* dstats, void* ws, const FullPlan& p,
+                                hipStream_t s);
+
+// ---- expand.hip --------------------------------------------------------------------------
+hipError_t launch_expand(const Geom& g, const float* f, const float* gp, float* T, int64_t ldt,
+                         hipStream_t s);
+
+// ---- costgrad.hip ------------------------------------------------------------------------
+size_t costgrad_ws_bytes(const Geom& g);
+hipError_t launch_cost_and_grad(const Geom& g, const float* f, const float* gp, int reduced,
+                                double* out, float* dC, int64_t lddc, float* dx, float* dy,
+                                float* da, float* db, void* ws, hipStream_t s);
+
+}  // namespace csot

@@ -1,0 +1,126 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol the header declares,
+and rejects invalid arguments before any device work (these calls never reach HIP, so they
+run on a machine without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    src = open(os.path.join(ROOT, "include", "csot.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ot_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2311_13147_amd import _binding
+    return _binding
+
+
+def test_library_exports_every_declared_symbol(B):
+    lib = ctypes.CDLL(B.LIB_PATH)
+    names = _header_functions()
+    assert len(names) >= 8
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(B.EXPORTED) == set(names)
+
+
+def test_struct_layouts_match_header(B):
+    assert ctypes.sizeof(B.OtProblem) == 72
+    assert ctypes.sizeof(B.OtOpts) == 40
+    assert ctypes.sizeof(B.OtStats) == 40
+    assert B.OtProblem.eps.offset == 64
+
+
+def _prob(B, n=64, K=4, dim=2, eps=0.1, x=1, y=1, C=None, ldc=0, a=1, b=1):
+    return B.OtProblem(n, K, dim, x, y, C, ldc, a, b, eps)
+
+
+def _call_fold(B, p):
+    lib = B.raw_lib()
+    return lib.ot_fold_kernel(ctypes.byref(p) if p is not None else None, None, 8, 8, 8, None,
+                              0, None)
+
+
+@pytest.mark.parametrize("kw,code,msg", [
+    (dict(n=100, K=7), 1, "multiple of K"),
+    (dict(n=0), 1, "n must be positive"),
+    (dict(K=0), 1, "K must be positive"),
+    (dict(eps=0.0), 1, "eps"),
+    (dict(eps=float("nan")), 1, "eps"),
+    (dict(dim=4), 1, "dim must be"),
+    (dict(x=None), 1, "coordinates"),
+    (dict(a=None), 1, "marginals"),
+    (dict(dim=0, C=None), 1, "dense cost"),
+    (dict(dim=0, C=8, ldc=10), 1, "ldc"),
+])
+def test_invalid_problem_is_rejected(B, kw, code, msg):
+    rc = _call_fold(B, _prob(B, **kw))
+    assert rc == code
+    assert msg in B.raw_lib().ot_last_error().decode()
+
+
+def test_null_problem(B):
+    assert _call_fold(B, None) == B.OT_ERR_ARG
+
+
+def test_invalid_options_are_rejected(B):
+    lib = B.raw_lib()
+    p = _prob(B)
+    for opts in (B.make_opts(max_iter=0), B.make_opts(tol=-1.0), B.make_opts(fold_fp64=3),
+                 B.make_opts(workgroups=-2)):
+        rc = lib.ot_fold_kernel(ctypes.byref(p), ctypes.byref(opts), 8, 8, 8, None, 0, None)
+        assert rc == B.OT_ERR_ARG
+
+
+def test_null_outputs_are_rejected(B):
+    lib = B.raw_lib()
+    p = _prob(B)
+    assert lib.ot_fold_kernel(ctypes.byref(p), None, None, 8, 8, None, 0, None) == B.OT_ERR_ARG
+    assert lib.ot_expand_plan(ctypes.byref(p), 8, 8, None, 64, None) == B.OT_ERR_ARG
+    assert lib.ot_expand_plan(ctypes.byref(p), 8, 8, 8, 10, None) == B.OT_ERR_ARG
+    assert lib.ot_symmetrize_cost(ctypes.byref(p), 8, 3, None) == B.OT_ERR_ARG
+    assert lib.ot_sinkhorn_reduced(ctypes.byref(p), None, None, 8, 8, 8, 8, 8, None, None, 0,
+                                   None) == B.OT_ERR_ARG
+    assert lib.ot_sinkhorn_full(ctypes.byref(p), None, None, 8, 8, None, None, 0,
+                                None) == B.OT_ERR_ARG
+    # dx/dy make no sense for a dense cost
+    pd = _prob(B, dim=0, C=8, ldc=64)
+    assert lib.ot_cost_and_grad(ctypes.byref(pd), 8, 8, 1, 8, None, 0, 8, None, None, None,
+                                None, 0, None) == B.OT_ERR_ARG
+    assert lib.ot_cost_and_grad(ctypes.byref(p), 8, 8, 2, 8, None, 0, None, None, None, None,
+                                None, 0, None) == B.OT_ERR_ARG
+
+
+def test_workspace_is_checked_before_launch(B):
+    lib = B.raw_lib()
+    p = _prob(B)
+    need = lib.ot_workspace_bytes(ctypes.byref(p), None)
+    assert need > 0
+    rc = lib.ot_cost_and_grad(ctypes.byref(p), 8, 8, 1, 8, None, 0, None, None, None, None,
+                              None, 0, None)
+    assert rc == B.OT_ERR_WORKSPACE
+    rc = lib.ot_cost_and_grad(ctypes.byref(p), 8, 8, 1, 8, None, 0, None, None, None, None,
+                              256, 16, None)
+    assert rc == B.OT_ERR_WORKSPACE
+    assert "too small" in lib.ot_last_error().decode()
+
+
+def test_workspace_bytes_grows_with_n(B):
+    lib = B.raw_lib()
+    small = lib.ot_workspace_bytes(ctypes.byref(_prob(B, n=512, K=8)), None)
+    big = lib.ot_workspace_bytes(ctypes.byref(_prob(B, n=8192, K=16)), None)
+    assert big > small > 0
+    assert lib.ot_workspace_bytes(None, None) == 0
+
+
+def test_binding_requires_device_tensors(B):
+    import torch
+    with pytest.raises(TypeError):
+        B.Problem(torch.ones(8), torch.ones(8), 0.1, 2, x=torch.ones(8, 2), y=torch.ones(8, 2))

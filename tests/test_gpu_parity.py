@@ -1,0 +1,253 @@
+"""GPU parity: every call of the C ABI against the float64 CPU oracle on the same seeded
+inputs (float32 arrays on the GPU, float64 copies of the same values in the oracle).
+
+Tolerance (the stated target for float32 results): relative error 1e-5 on the objective and
+on the plan (L1), which for an entry T = exp(Z) means |dZ| = |d(f + g - C)| / eps <= 1e-5;
+potentials are therefore compared as max |df| / eps and the fold as max |d logK|.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import cost, grad, objective, projection, sinkhorn
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+REL = 1e-5
+
+
+def T_(v):
+    return torch.from_numpy(np.ascontiguousarray(v)).to(DEV)
+
+
+def _problem(lib, p):
+    if p.dim == 0:
+        return lib.Problem(T_(p.a), T_(p.b), p.eps, p.K, C=T_(p.C_row0))
+    return lib.Problem(T_(p.a), T_(p.b), p.eps, p.K, x=T_(p.x), y=T_(p.y))
+
+
+def _blocks(p):
+    if p.dim == 0:
+        return cost.blocks_from_row0(p.C_row0, p.K)
+    return cost.blocks_from_row0(cost.row0_from_points(p.x, p.y, p.K), p.K)
+
+
+def _f64(v):
+    return np.asarray(v, dtype=np.float64)
+
+
+CASES = [
+    ("sym_n512_K8_d2", lambda: workloads.symmetric_problem(512, 8, 2, 0.05, seed=0)),
+    ("sym_n600_K8_d3_ragged", lambda: workloads.symmetric_problem(600, 8, 3, 0.05, seed=7)),
+    ("sym_n390_K6_d2_ragged", lambda: workloads.symmetric_problem(390, 6, 2, 0.01, seed=9)),
+    ("appd_n700_K7_dense", lambda: workloads.dense_appd_problem(700, 7, seed=0)),
+]
+
+
+@pytest.mark.parametrize("name,mk", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("fp64", [0, 1])
+def test_fold_parity(lib, name, mk, fp64):
+    p = mk()
+    print(f"[fold] {name} fp64={fp64}", flush=True)
+    prob = _problem(lib, p)
+    logK, alpha, beta = lib.ot_fold_kernel(prob, lib.make_opts(fold_fp64=fp64))
+    torch.cuda.synchronize()
+    ref = sinkhorn.fold_kernel(_blocks(p), p.eps)
+    err = np.abs(logK.cpu().numpy() - ref)
+    # float32 rounding of |logK| (<= ~400) plus float32 cost rounding in float32 mode
+    scale = np.abs(ref) + 1.0
+    assert (err / scale).max() < (2e-7 if fp64 else 2e-6)
+    assert np.abs(alpha.cpu().numpy() - sinkhorn.fold_marginals(_f64(p.a), p.K)).max() < 1e-9
+    assert np.abs(beta.cpu().numpy() - sinkhorn.fold_marginals(_f64(p.b), p.K)).max() < 1e-9
+
+
+def _reduced_ref(p, tol, max_iter, record=None):
+    Ck = _blocks(p)
+    alpha = sinkhorn.fold_marginals(_f64(p.a), p.K)
+    beta = sinkhorn.fold_marginals(_f64(p.b), p.K)
+    logK = sinkhorn.fold_kernel(Ck, p.eps)
+    out = sinkhorn.reduced_sinkhorn(alpha, beta, logK, p.eps, p.K, tol=tol, max_iter=max_iter,
+                                    record=record)
+    out.update(Ck=Ck, alpha=alpha, beta=beta, logK=logK)
+    return out
+
+
+@pytest.mark.parametrize("name,mk", CASES, ids=[c[0] for c in CASES])
+def test_reduced_fixed_iterations(lib, name, mk):
+    """Potentials after exactly 1, 3 and 25 iterations (tol = 0) match the oracle's."""
+    p = mk()
+    prob = _problem(lib, p)
+    for its in (1, 3, 25):
+        print(f"[reduced fixed] {name} iters={its}", flush=True)
+        opts = lib.make_opts(tol=0.0, max_iter=its, fold_fp64=1)
+        logK, alpha, beta = lib.ot_fold_kernel(prob, opts)
+        f, g, st = lib.ot_sinkhorn_reduced(prob, logK, alpha, beta, opts)
+        ref = _reduced_ref(p, 0.0, its)
+        assert st["iters"] == its
+        df = np.abs(f.cpu().numpy() - ref["f"]).max() / p.eps
+        dg = np.abs(g.cpu().numpy() - ref["g"]).max() / p.eps
+        assert df < 2e-5 and dg < 2e-5, (df, dg)
+
+
+@pytest.mark.parametrize("name,mk", CASES, ids=[c[0] for c in CASES])
+def test_reduced_to_tolerance(lib, name, mk):
+    p = mk()
+    print(f"[reduced tol] {name}", flush=True)
+    prob = _problem(lib, p)
+    opts = lib.make_opts(tol=1e-6, max_iter=20000, fold_fp64=1)
+    logK, alpha, beta = lib.ot_fold_kernel(prob, opts)
+    f, g, st = lib.ot_sinkhorn_reduced(prob, logK, alpha, beta, opts)
+    ref = _reduced_ref(p, 1e-6, 20000)
+    assert st["converged"] and ref["converged"]
+    assert abs(st["iters"] - ref["iters"]) <= 1, (st["iters"], ref["iters"])
+    # float64 check of the returned state agrees with the oracle's residual of that state
+    er, ec = sinkhorn.reduced_marginal_errors(_f64(f.cpu()), _f64(g.cpu()), ref["logK"], p.eps,
+                                              ref["alpha"], ref["beta"], p.K)
+    assert st["err_row"] <= 1e-6 * 1.05 and abs(st["err_row"] - er) <= 1e-3 * er + 1e-12
+    assert abs(st["err_col"] - ec) <= 1e-3 * ec + 1e-11
+    # objective and plan
+    vg = objective.reduced_values(_f64(f.cpu()), _f64(g.cpu()), ref["Ck"], p.eps,
+                                  ref["alpha"], ref["beta"])
+    vr = objective.reduced_values(ref["f"], ref["g"], ref["Ck"], p.eps, ref["alpha"], ref["beta"])
+    assert abs(vg["P"] - vr["P"]) / max(abs(vr["P"]), vr["CT"]) < REL
+
+
+@pytest.mark.parametrize("name,mk", CASES, ids=[c[0] for c in CASES])
+def test_expand_parity(lib, name, mk):
+    p = mk()
+    print(f"[expand] {name}", flush=True)
+    prob = _problem(lib, p)
+    ref = _reduced_ref(p, 1e-6, 20000)
+    f, g = T_(ref["f"].astype(np.float32)), T_(ref["g"].astype(np.float32))
+    T = lib.ot_expand_plan(prob, f, g).cpu().numpy().astype(np.float64)
+    Tref = sinkhorn.expand_plan(ref["f"].astype(np.float32), ref["g"].astype(np.float32),
+                                ref["Ck"], p.eps)
+    assert np.abs(T - Tref).sum() / Tref.sum() < REL
+    big = Tref > 1e-3 * Tref.max()
+    assert (np.abs(T - Tref)[big] / Tref[big]).max() < 2e-5
+    # Lemma 1: block-circulant (shift invariance), exactly, as every copy is the same value
+    m = p.m
+    assert np.array_equal(T[m:, m:], T[:-m, :-m])
+
+
+@pytest.mark.parametrize("name,mk", CASES, ids=[c[0] for c in CASES])
+def test_cost_and_grad_reduced(lib, name, mk):
+    p = mk()
+    print(f"[costgrad reduced] {name}", flush=True)
+    prob = _problem(lib, p)
+    ref = _reduced_ref(p, 1e-9, 50000)
+    f32, g32 = ref["f"].astype(np.float32), ref["g"].astype(np.float32)
+    res = lib.ot_cost_and_grad(prob, T_(f32), T_(g32), reduced=True, want_dC=True,
+                               want_dxy=p.dim > 0, want_dab=True)
+    v = lib.values_dict(res["values"])
+    vr = objective.reduced_values(_f64(f32), _f64(g32), ref["Ck"], p.eps, ref["alpha"],
+                                  ref["beta"])
+    scale = max(abs(vr["P"]), vr["CT"]) * p.K
+    assert abs(v["P"] - p.K * vr["P"]) / scale < REL
+    assert abs(v["D"] - p.K * vr["D"]) / scale < REL
+    assert abs(v["CT"] - p.K * vr["CT"]) / (p.K * vr["CT"]) < REL
+    assert abs(v["mass"] - p.K * vr["mass"]) < 1e-5
+    Tk = sinkhorn.reduced_plan_blocks(_f64(f32), _f64(g32), ref["Ck"], p.eps)
+    dC = res["dC"].cpu().numpy()
+    assert np.abs(dC - Tk).sum() / Tk.sum() < REL
+    n = p.n
+    fa = np.tile(_f64(f32), p.K)
+    assert np.abs(res["da"].cpu().numpy() - (fa - fa.mean())).max() < 1e-5 * (1 + np.abs(fa).max())
+    if p.dim > 0:
+        Tfull = sinkhorn.expand_plan(_f64(f32), _f64(g32), ref["Ck"], p.eps)
+        x, y = _f64(p.x), _f64(p.y)
+        dx = 2 * (Tfull.sum(1)[:, None] * x - Tfull @ y)
+        dy = 2 * (Tfull.sum(0)[:, None] * y - Tfull.T @ x)
+        for got, want in ((res["dx"], dx), (res["dy"], dy)):
+            got = got.cpu().numpy()
+            assert np.abs(got - want).max() / np.abs(want).max() < 1e-4, np.abs(got - want).max()
+
+
+FULL_CASES = [
+    ("sym_n512_K8_d2", lambda: workloads.symmetric_problem(512, 8, 2, 0.05, seed=0)),
+    ("sym_n1100_K4_d3_ragged", lambda: workloads.symmetric_problem(1100, 4, 3, 0.05, seed=3)),
+    ("jit_n768_K8", lambda: workloads.jittered_problem(768, 8, seed=200)),
+]
+
+
+def _full_ref(p, tol, max_iter):
+    C = cost.sq_euclidean(p.x, p.y)
+    out = sinkhorn.full_sinkhorn(_f64(p.a), _f64(p.b), C, p.eps, tol=tol, max_iter=max_iter)
+    out["C"] = C
+    return out
+
+
+@pytest.mark.parametrize("name,mk", FULL_CASES, ids=[c[0] for c in FULL_CASES])
+def test_full_fixed_and_tolerance(lib, name, mk):
+    p = mk()
+    prob = _problem(lib, p)
+    for its in (1, 4, 30):
+        print(f"[full fixed] {name} iters={its}", flush=True)
+        f, g, st = lib.ot_sinkhorn_full(prob, lib.make_opts(tol=0.0, max_iter=its))
+        ref = _full_ref(p, 0.0, its)
+        assert st["iters"] == its
+        assert np.abs(f.cpu().numpy() - ref["f"]).max() / p.eps < 2e-5
+        assert np.abs(g.cpu().numpy() - ref["g"]).max() / p.eps < 2e-5
+    print(f"[full tol] {name}", flush=True)
+    f, g, st = lib.ot_sinkhorn_full(prob, lib.make_opts(tol=1e-6, max_iter=20000))
+    ref = _full_ref(p, 1e-6, 20000)
+    assert st["converged"] and abs(st["iters"] - ref["iters"]) <= 1
+    v = objective.full_values(_f64(f.cpu()), _f64(g.cpu()), ref["C"], p.eps, _f64(p.a), _f64(p.b))
+    assert abs(st["err_row"] - v["err_row"]) <= 1e-3 * v["err_row"] + 1e-12
+    assert abs(st["err_col"] - v["err_col"]) <= 1e-3 * v["err_col"] + 1e-11
+    vr = objective.full_values(ref["f"], ref["g"], ref["C"], p.eps, _f64(p.a), _f64(p.b))
+    assert abs(v["P"] - vr["P"]) / max(abs(vr["P"]), vr["CT"]) < REL
+    # values and gradients of the full path
+    res = lib.ot_cost_and_grad(prob, f, g, reduced=False, want_dC=True, want_dxy=True,
+                               want_dab=True)
+    gv = lib.values_dict(res["values"])
+    assert abs(gv["P"] - v["P"]) / max(abs(v["P"]), v["CT"]) < REL
+    assert abs(gv["D"] - v["D"]) / max(abs(v["P"]), v["CT"]) < REL
+    G = grad.envelope_grads(_f64(f.cpu()), _f64(g.cpu()), p.x, p.y, p.eps)
+    dC = res["dC"].cpu().numpy()
+    assert np.abs(dC - G["dC"]).sum() / G["dC"].sum() < REL
+    for key in ("dx", "dy"):
+        got = res[key].cpu().numpy()
+        assert np.abs(got - G[key]).max() / np.abs(G[key]).max() < 1e-4
+
+
+def test_full_dense(lib):
+    p = workloads.dense_appd_problem(600, 6, seed=1)
+    print("[full dense] appd n600", flush=True)
+    Cfull = cost.block_circulant_from_row0(p.C_row0, p.K).astype(np.float32)
+    prob = lib.Problem(T_(p.a), T_(p.b), p.eps, p.K, C=T_(Cfull))
+    f, g, st = lib.ot_sinkhorn_full(prob, lib.make_opts(tol=0.0, max_iter=20))
+    ref = sinkhorn.full_sinkhorn(_f64(p.a), _f64(p.b), _f64(Cfull), p.eps, tol=0.0, max_iter=20)
+    assert np.abs(f.cpu().numpy() - ref["f"]).max() / p.eps < 2e-5
+    assert np.abs(g.cpu().numpy() - ref["g"]).max() / p.eps < 2e-5
+
+
+def test_symmetrize_parity(lib):
+    p = workloads.jittered_problem(640, 8, seed=201)
+    print("[symmetrize] jit n640", flush=True)
+    prob = _problem(lib, p)
+    Cs = lib.ot_symmetrize_cost(prob).cpu().numpy()
+    ref = projection.project_blocks(cost.sq_euclidean(p.x, p.y), p.K)
+    got = cost.blocks_from_row0(Cs, p.K)
+    assert np.abs(got - ref).max() / ref.max() < 1e-6
+
+
+def test_reduced_matches_full_on_symmetric_data(lib):
+    """Iterate equivalence on the GPU: the reduced solve and the full solve stop at the same
+    iteration with the same objective (cost recomputed from float32 coordinates, so only
+    equal up to the float32 asymmetry of the rotated copies)."""
+    p = workloads.symmetric_problem(1024, 8, 2, 0.05, seed=11)
+    print("[reduced vs full] n1024 K8", flush=True)
+    prob = _problem(lib, p)
+    opts = lib.make_opts(tol=1e-6, fold_fp64=1)
+    logK, alpha, beta = lib.ot_fold_kernel(prob, opts)
+    f, g, st = lib.ot_sinkhorn_reduced(prob, logK, alpha, beta, opts)
+    ff, gf, stf = lib.ot_sinkhorn_full(prob, opts)
+    assert abs(st["iters"] - stf["iters"]) <= 1
+    vr = lib.values_dict(lib.ot_cost_and_grad(prob, f, g, reduced=True)["values"])
+    vf = lib.values_dict(lib.ot_cost_and_grad(prob, ff, gf, reduced=False)["values"])
+    assert abs(vr["P"] - vf["P"]) / max(abs(vf["P"]), vf["CT"]) < 1e-4
