@@ -151,7 +151,8 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
         err2 = s;
         const bool fin = s == s && s < 1.0e300;
         converged = fin && s <= p.tol2;
-        stop = converged || !fin || (t - 1) >= p.max_iter;
+        // tol = 0 asks for exactly max_iter iterations, even if the residual underflows to 0
+        stop = (converged && p.tol2 > 0.0) || !fin || (t - 1) >= p.max_iter;
         if (!fin) flags |= 1;
       }
       s_stop = stop;
