@@ -105,6 +105,49 @@ __device__ __forceinline__ bool grid_barrier(uint32_t* ctl, uint32_t target, int
   return *s_flag != 0;
 }
 
+// ----------------------------------------------------------------------------------------
+// Epoch-tagged exchange slots.
+//
+// A slot is one 64-bit word holding a float value in the low half and the iteration (epoch)
+// that produced it in the high half, written with a single relaxed agent-scope atomic store.
+// A consumer polls the slot with relaxed agent-scope atomic loads until the epoch it needs
+// appears, so the word is its own ready flag: no counter barrier, no cache write-back or
+// invalidate fences.  Per-location coherence of atomics guarantees the poll eventually sees
+// the store; single-copy atomicity of the aligned 64-bit word guarantees value and epoch
+// belong together.  Polls are bounded: a consumer that spins kSpinLimit times raises the
+// abort flag, and every poller checks that flag, so a grid always drains.
+// ----------------------------------------------------------------------------------------
+__device__ __forceinline__ void slot_publish(uint64_t* slot, float v, uint32_t epoch) {
+  const uint64_t w = ((uint64_t)epoch << 32) | (uint64_t)__float_as_uint(v);
+  __hip_atomic_store(slot, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint64_t slot_load(uint64_t* slot) {
+  return __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until `w` (already loaded from `slot`) carries `epoch`; returns false on abort.
+__device__ __forceinline__ bool slot_wait(uint64_t* slot, uint64_t& w, uint32_t epoch,
+                                          uint32_t* abort_flag) {
+  uint32_t spins = 0;
+  while ((uint32_t)(w >> 32) != epoch) {
+    if (++spins >= kSpinLimit) {
+      __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    if ((spins & 63u) == 0 &&
+        __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
+      return false;
+    __builtin_amdgcn_s_sleep(1);
+    w = slot_load(slot);
+  }
+  return true;
+}
+
+__device__ __forceinline__ float slot_value(uint64_t w) {
+  return __uint_as_float((uint32_t)(w & 0xffffffffull));
+}
+
 // Zero `count` 32-bit words (control blocks) -- a kernel rather than a memset so that a
 // captured graph holds no memset node.
 __global__ void zero_words_kernel(uint32_t* p, int count);

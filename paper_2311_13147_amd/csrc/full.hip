@@ -4,28 +4,31 @@
 //   row    : F_I = log2 a_I - LSE2_J(G_J - C_IJ log2(e)/eps)
 //   column : G_J = log2 b_J - LSE2_I(F_I - C_IJ log2(e)/eps)
 //
-// Workgroup w owns rows and columns [w R, w R + R).  In a row phase every workgroup streams
-// the whole other side -- {coordinates, potential} packed as float4 -- through LDS in chunks
-// of kNC points (double-buffered, next chunk prefetched into registers), and every lane
-// evaluates costs on the fly for RT rows at a time (register blocking), keeping a running
-// (max, sum) per row that is rescaled once per 4 columns.  Dense costs (dim = 0) are streamed
-// from HBM instead: C for row phases, a transposed copy for column phases.  Phases are
-// separated by device-wide barriers; the convergence test is the one of the reduced solver.
+// Workgroup w owns rows and columns [w R, w R + R).  It runs 16 waves: RG row groups of RT
+// rows (register blocking: one staged column feeds RT rows) times CQ column parts.  In a
+// row phase the whole other side streams through LDS in chunks of kNC points -- static
+// coordinates (packed once per solve) plus the current potential, read from epoch-tagged
+// 64-bit slots and polled until they carry the current iteration -- double-buffered with the
+// next chunk prefetched into registers.  Every lane evaluates costs on the fly, keeping a
+// running (max, sum) per row that is rescaled once per 4 columns; lanes, then column parts,
+// are merged at the end.  Dense costs (dim = 0) are streamed from HBM instead: C for row
+// phases, a transposed copy for column phases.  Exchange and stop test are those of the
+// reduced solver (slots as their own ready flags, no counter barrier, no cache flushes).
 #include "common.hpp"
 #include "launch.hpp"
 
 namespace csot {
 
-constexpr int kFullThreads = 256;  // 4 waves
-constexpr int kNC = 1024;          // points per LDS chunk (16 KiB of float4)
-constexpr int kPF = kNC / kFullThreads;
+constexpr int kFullThreads = 1024;  // 16 waves
+constexpr int kFullWaves = kFullThreads / kWave;
+constexpr int kNC = 1024;           // points per LDS chunk (one per thread)
 
 struct FullParams {
-  int n, np, W, R, max_iter, warm;
+  int n, np, W, R, max_iter;
   float s2, to_nat;
   double tol2;
-  const float* x;
-  const float* y;
+  const float4* xc;  // [np] packed x coordinates
+  const float4* yc;  // [np] packed y coordinates
   const float* C;
   int64_t ldc;
   const float* CT;   // dense transpose [n, np]
@@ -33,75 +36,80 @@ struct FullParams {
   const float* b;
   float* f_out;
   float* g_out;
-  float4* xf;        // [np] {x_I, F_I}
-  float4* yg;        // [np] {y_J, G_J}
-  double* rs;        // [W]
-  uint32_t* ctl;
+  uint64_t* fx;      // [np] F slots (epoch t = row phase of iteration t)
+  uint64_t* gx;      // [np] G slots (epoch 0 = initial potential)
+  uint64_t* rsx;     // [W] residual partials
+  uint32_t* ctl;     // [0] abort flag
   double* dstats;
 };
 
-template <int DIM>
-__device__ __forceinline__ float4 pack_point(const float* __restrict__ p, int I, float pot) {
-  float4 v;
-  v.x = p[(int64_t)I * DIM + 0];
-  v.y = p[(int64_t)I * DIM + 1];
-  v.z = DIM == 3 ? p[(int64_t)I * DIM + 2] : 0.0f;
-  v.w = pot;
-  return v;
-}
-
-// One phase: for the RT own rows of this wave, LSE2 over all other points.
-// own: coordinates of the own side; other: packed other side (potential in .w).
-template <int DIM, int RT>
-__device__ __forceinline__ void full_phase(const FullParams& p, int r0,
-                                           const float* __restrict__ own,
+// One phase for this workgroup's rows: LSE2 over all other points of (pot_J - C_IJ s2).
+// Returns false on abort.  lse[rl] receives the result for local row rl.
+template <int DIM, int RT, int CQ>
+__device__ __forceinline__ bool full_phase(const FullParams& p, int r0, const float4* __restrict__ ownc,
                                            const float* __restrict__ dense, int64_t ldd,
-                                           const float4* __restrict__ other,
-                                           float4* __restrict__ buf, float* __restrict__ lse) {
+                                           const float4* __restrict__ othc, uint64_t* oslots,
+                                           uint32_t epoch, float4* __restrict__ buf,
+                                           float2* __restrict__ part, float* __restrict__ lse,
+                                           int* s_bad) {
+  constexpr int RG = kFullWaves / CQ;
+  constexpr int U = kNC / kWave / CQ;  // 64-column steps per wave per chunk
+  constexpr int TU = U < 4 ? U : 4;     // columns per lane between running-max rescales
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wv = tid / kWave;
-  const int rbase = r0 + wv * RT;
+  const int rg = wv / CQ, cq = wv % CQ;
   float xr[RT][3];
   float M[RT], S[RT];
   const float* drow[RT];
 #pragma unroll
   for (int q = 0; q < RT; ++q) {
-    const int I = min(rbase + q, p.n - 1);
+    const int I = min(r0 + rg * RT + q, p.n - 1);
     if constexpr (DIM > 0) {
-#pragma unroll
-      for (int d = 0; d < 3; ++d) xr[q][d] = d < DIM ? own[(int64_t)I * DIM + d] : 0.0f;
+      const float4 c = ownc[I];
+      xr[q][0] = c.x; xr[q][1] = c.y; xr[q][2] = c.z;
     }
     drow[q] = DIM == 0 ? dense + (int64_t)I * ldd : nullptr;
     M[q] = kNegBig;
     S[q] = 0.0f;
   }
   const int nchunks = p.np / kNC;
-  float4 pre[kPF];
-#pragma unroll
-  for (int u = 0; u < kPF; ++u) pre[u] = other[tid + u * kFullThreads];
+  bool ok = true;
+  // prefetch chunk 0: coordinates and slot of point tid
+  float4 pc = DIM > 0 ? othc[tid] : make_float4(0.f, 0.f, 0.f, 0.f);
+  uint64_t ps = tid < p.n ? slot_load(oslots + tid) : 0ull;
   for (int c = 0; c < nchunks; ++c) {
     float4* cur = buf + (c & 1) * kNC;
-#pragma unroll
-    for (int u = 0; u < kPF; ++u) cur[tid + u * kFullThreads] = pre[u];
-    __syncthreads();
-    if (c + 1 < nchunks) {
-#pragma unroll
-      for (int u = 0; u < kPF; ++u) pre[u] = other[(c + 1) * kNC + tid + u * kFullThreads];
+    const int J = c * kNC + tid;
+    if (J < p.n) {
+      if (ok) ok = slot_wait(oslots + J, ps, epoch, p.ctl);
+      pc.w = slot_value(ps);
+    } else {
+      pc.w = -INFINITY;
     }
-    for (int u = 0; u < kNC / kWave; u += 4) {
-      float4 o[4];
+    cur[tid] = pc;
+    if (!ok) *s_bad = 1;
+    __syncthreads();
+    if (*s_bad) return false;
+    if (c + 1 < nchunks) {
+      const int Jn = J + kNC;
+      pc = DIM > 0 ? othc[Jn] : make_float4(0.f, 0.f, 0.f, 0.f);
+      ps = Jn < p.n ? slot_load(oslots + Jn) : 0ull;
+    }
+#pragma unroll 1
+    for (int u = cq * U; u < (cq + 1) * U; u += TU) {
+      float4 o[TU];
 #pragma unroll
-      for (int cc = 0; cc < 4; ++cc) o[cc] = cur[lane + kWave * (u + cc)];
+      for (int cc = 0; cc < TU; ++cc) o[cc] = cur[lane + kWave * (u + cc)];
 #pragma unroll
       for (int q = 0; q < RT; ++q) {
-        float t[4];
+        float t[TU];
 #pragma unroll
-        for (int cc = 0; cc < 4; ++cc) {
+        for (int cc = 0; cc < TU; ++cc) {
           float cst;
           if constexpr (DIM == 0) {
-            const int J = c * kNC + lane + kWave * (u + cc);
-            cst = J < p.n ? drow[q][J] : 0.0f;
+            const int Jc = c * kNC + lane + kWave * (u + cc);
+            cst = Jc < p.n ? drow[q][Jc] : 0.0f;
           } else {
             const float dx = xr[q][0] - o[cc].x;
             const float dy = xr[q][1] - o[cc].y;
@@ -114,15 +122,19 @@ __device__ __forceinline__ void full_phase(const FullParams& p, int r0,
           }
           t[cc] = fmaf(-cst, p.s2, o[cc].w);
         }
-        const float tm = fmaxf(fmaxf(t[0], t[1]), fmaxf(t[2], t[3]));
+        float tm = t[0];
+#pragma unroll
+        for (int cc = 1; cc < TU; ++cc) tm = fmaxf(tm, t[cc]);
         const float Mn = fmaxf(M[q], tm);
-        S[q] = S[q] * exp2_fast(M[q] - Mn) + exp2_fast(t[0] - Mn) + exp2_fast(t[1] - Mn) +
-               exp2_fast(t[2] - Mn) + exp2_fast(t[3] - Mn);
+        float acc = S[q] * exp2_fast(M[q] - Mn);
+#pragma unroll
+        for (int cc = 0; cc < TU; ++cc) acc += exp2_fast(t[cc] - Mn);
+        S[q] = acc;
         M[q] = Mn;
       }
     }
   }
-  // merge the 64 lanes' partials of each row
+  // merge the 64 lanes of each row, then the CQ column parts
 #pragma unroll
   for (int q = 0; q < RT; ++q) {
     float m_ = M[q], s_ = S[q];
@@ -132,24 +144,35 @@ __device__ __forceinline__ void full_phase(const FullParams& p, int r0,
       const float s2 = __shfl_xor(s_, o, kWave);
       lse_merge(m_, s_, m2, s2);
     }
-    if (lane == 0) lse[wv * RT + q] = m_ + log2_fast(s_);
+    if (lane == 0) part[(rg * RT + q) * CQ + cq] = make_float2(m_, s_);
   }
   __syncthreads();
+  for (int rl = tid; rl < RG * RT; rl += kFullThreads) {
+    float m_ = kNegBig, s_ = 0.0f;
+    for (int k = 0; k < CQ; ++k) {
+      const float2 v = part[rl * CQ + k];
+      lse_merge(m_, s_, v.x, v.y);
+    }
+    lse[rl] = m_ + log2_fast(s_);
+  }
+  __syncthreads();
+  return true;
 }
 
-template <int DIM, int RT>
+template <int DIM, int RT, int CQ>
 __global__ void __launch_bounds__(kFullThreads) full_solver_kernel(FullParams p) {
+  constexpr int R = (kFullWaves / CQ) * RT;
   __shared__ float4 buf[2 * kNC];
-  __shared__ float lse[4 * RT];
-  __shared__ float Fcur[4 * RT], Fprev[4 * RT], Gcur[4 * RT], la2[4 * RT], lb2[4 * RT];
-  __shared__ double red[8];
-  __shared__ int s_flag, s_stop;
+  __shared__ float2 part[R * CQ];
+  __shared__ float lse[R];
+  __shared__ float Fcur[R], Fprev[R], Gcur[R], la2[R], lb2[R];
+  __shared__ float rsv[256];
+  __shared__ double red[kFullWaves];
+  __shared__ int s_bad, s_stop;
   const int w = blockIdx.x, tid = threadIdx.x;
-  const int R = p.R;  // == 4 * RT
   const int r0 = w * R;
   const int nr = max(0, min(R, p.n - r0));
 
-  // ---- setup: publish own rows / columns, pad the exchange arrays -----------------------
   for (int rl = tid; rl < R; rl += blockDim.x) {
     const bool ok = rl < nr;
     const int I = r0 + rl;
@@ -157,32 +180,17 @@ __global__ void __launch_bounds__(kFullThreads) full_solver_kernel(FullParams p)
     lb2[rl] = ok ? log2f(p.b[I]) : 0.0f;
     Fcur[rl] = 0.0f;
     Fprev[rl] = 0.0f;
-    const float G0 = ok && p.warm ? p.g_out[I] * p.s2 : 0.0f;
-    Gcur[rl] = G0;
-    if (ok) {
-      if constexpr (DIM > 0) {
-        p.xf[I] = pack_point<DIM>(p.x, I, 0.0f);
-        p.yg[I] = pack_point<DIM>(p.y, I, G0);
-      } else {
-        p.xf[I] = make_float4(0.f, 0.f, 0.f, 0.f);
-        p.yg[I] = make_float4(0.f, 0.f, 0.f, G0);
-      }
-    }
+    Gcur[rl] = ok ? slot_value(slot_load(p.gx + I)) : 0.0f;  // initial G (epoch 0)
   }
-  if (w == 0) {
-    for (int I = p.n + tid; I < p.np; I += blockDim.x) {
-      p.xf[I] = make_float4(0.f, 0.f, 0.f, -INFINITY);
-      p.yg[I] = make_float4(0.f, 0.f, 0.f, -INFINITY);
-    }
-  }
-  uint32_t bar = 0;
+  if (tid == 0) s_bad = 0;
+  __syncthreads();
   int iters_done = 0, converged = 0, flags = 0;
   double err2 = 0.0;
-  if (!grid_barrier(p.ctl, (uint32_t)p.W * (++bar), &s_flag)) flags |= 2;
 
-  for (int t = 1; !(flags & 2); ++t) {
-    // ---- row phase ----------------------------------------------------------------------
-    full_phase<DIM, RT>(p, r0, p.x, p.C, p.ldc, p.yg, buf, lse);
+  for (uint32_t t = 1;; ++t) {
+    // ---- row phase: F^t from G^{t-1} ----------------------------------------------------
+    if (!full_phase<DIM, RT, CQ>(p, r0, p.xc, p.C, p.ldc, p.yc, p.gx, t - 1, buf, part, lse,
+                                 &s_bad)) { flags |= 2; break; }
     double rpart = 0.0;
     for (int rl = tid; rl < nr; rl += blockDim.x) {
       const int I = r0 + rl;
@@ -193,40 +201,40 @@ __global__ void __launch_bounds__(kFullThreads) full_solver_kernel(FullParams p)
       }
       Fprev[rl] = Fcur[rl];
       Fcur[rl] = Fn;
-      float4 v = DIM > 0 ? pack_point<(DIM > 0 ? DIM : 2)>(p.x, I, Fn) : make_float4(0.f, 0.f, 0.f, Fn);
-      p.xf[I] = v;
+      slot_publish(p.fx + I, Fn, t);
     }
     const double rtot = block_sum_d(rpart, red);
-    if (tid == 0) p.rs[w] = rtot;
-    if (!grid_barrier(p.ctl, (uint32_t)p.W * (++bar), &s_flag)) { flags |= 2; break; }
-    if (tid == 0) {
-      int stop = 0;
-      if (t >= 2) {
+    if (tid == 0) slot_publish(p.rsx + w, (float)rtot, t);
+    // ---- stop test on the state after iteration t-1 --------------------------------------
+    if (t >= 2) {
+      for (int v = tid; v < p.W; v += blockDim.x) {
+        uint64_t wv = slot_load(p.rsx + v);
+        if (!slot_wait(p.rsx + v, wv, t, p.ctl)) s_bad = 1;
+        rsv[v] = slot_value(wv);
+      }
+      __syncthreads();
+      if (s_bad) { flags |= 2; break; }
+      if (tid == 0) {
         double s = 0.0;
-        for (int v = 0; v < p.W; ++v)
-          s += __hip_atomic_load(&p.rs[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int v = 0; v < p.W; ++v) s += (double)rsv[v];
         err2 = s;
         const bool fin = s == s && s < 1.0e300;
         converged = fin && s <= p.tol2;
         // tol = 0 asks for exactly max_iter iterations, even if the residual underflows to 0
-        stop = (converged && p.tol2 > 0.0) || !fin || (t - 1) >= p.max_iter;
+        s_stop = (converged && p.tol2 > 0.0) || !fin || (int)(t - 1) >= p.max_iter;
         if (!fin) flags |= 1;
       }
-      s_stop = stop;
+      __syncthreads();
+      if (s_stop) { iters_done = (int)t - 1; break; }
     }
-    __syncthreads();
-    if (s_stop) { iters_done = t - 1; break; }
-
-    // ---- column phase -------------------------------------------------------------------
-    full_phase<DIM, RT>(p, r0, p.y, p.CT, p.np, p.xf, buf, lse);
+    // ---- column phase: G^t from F^t -------------------------------------------------------
+    if (!full_phase<DIM, RT, CQ>(p, r0, p.yc, p.CT, p.np, p.xc, p.fx, t, buf, part, lse,
+                                 &s_bad)) { flags |= 2; break; }
     for (int cl = tid; cl < nr; cl += blockDim.x) {
-      const int J = r0 + cl;
       const float Gn = lb2[cl] - lse[cl];
       Gcur[cl] = Gn;
-      float4 v = DIM > 0 ? pack_point<(DIM > 0 ? DIM : 2)>(p.y, J, Gn) : make_float4(0.f, 0.f, 0.f, Gn);
-      p.yg[J] = v;
+      slot_publish(p.gx + r0 + cl, Gn, t);
     }
-    if (!grid_barrier(p.ctl, (uint32_t)p.W * (++bar), &s_flag)) { flags |= 2; break; }
   }
 
   __syncthreads();
@@ -241,6 +249,28 @@ __global__ void __launch_bounds__(kFullThreads) full_solver_kernel(FullParams p)
     p.dstats[5] = (double)flags;
   } else if (tid == 0 && flags) {
     p.dstats[5] = (double)flags;
+  }
+}
+
+// Per-solve setup: pack coordinates, publish the initial column potential as epoch 0.
+template <int DIM>
+__global__ void full_init_kernel(int n, int np, const float* __restrict__ x,
+                                 const float* __restrict__ y, const float* __restrict__ g0,
+                                 int warm, float s2, float4* __restrict__ xc,
+                                 float4* __restrict__ yc, uint64_t* __restrict__ gx) {
+  for (int I = blockIdx.x * blockDim.x + threadIdx.x; I < np; I += gridDim.x * blockDim.x) {
+    float4 vx = make_float4(0.f, 0.f, 0.f, 0.f), vy = vx;
+    if (I < n) {
+      if constexpr (DIM > 0) {
+        vx.x = x[(int64_t)I * DIM]; vx.y = x[(int64_t)I * DIM + 1];
+        vy.x = y[(int64_t)I * DIM]; vy.y = y[(int64_t)I * DIM + 1];
+        if constexpr (DIM == 3) { vx.z = x[(int64_t)I * 3 + 2]; vy.z = y[(int64_t)I * 3 + 2]; }
+      }
+      const float G0 = warm ? g0[I] * s2 : 0.0f;
+      gx[I] = (uint64_t)__float_as_uint(G0);  // epoch 0
+    }
+    xc[I] = vx;
+    yc[I] = vy;
   }
 }
 
@@ -266,7 +296,8 @@ __global__ void transpose_kernel(const float* __restrict__ C, int64_t ldc, float
 // accumulators with atomics; the last block forms the two norms.
 template <int DIM>
 __global__ void __launch_bounds__(256)
-    full_check_kernel(FullParams p, double eps, double* __restrict__ rowsum,
+    full_check_kernel(Geom g, const float* __restrict__ f, const float* __restrict__ gp,
+                      double* __restrict__ dstats, double* __restrict__ rowsum,
                       double* __restrict__ colsum, uint32_t* __restrict__ counter, int ntiles) {
   __shared__ double cpart[4][64];
   __shared__ double red[8];
@@ -274,34 +305,34 @@ __global__ void __launch_bounds__(256)
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int J = blockIdx.x * 64 + lane;
   const int I0 = blockIdx.y * 32;
-  const double ie = 1.0 / eps;
+  const double ie = 1.0 / g.eps;
   double csum = 0.0;
-  const double gJ = J < p.n ? (double)p.g_out[J] : 0.0;
+  const double gJ = J < g.n ? (double)gp[J] : 0.0;
   for (int q = 0; q < 8; ++q) {
     const int I = I0 + wv + 4 * q;
     double v = 0.0;
-    if (I < p.n && J < p.n) {
+    if (I < g.n && J < g.n) {
       double c;
       if constexpr (DIM == 0) {
-        c = (double)p.C[(int64_t)I * p.ldc + J];
+        c = (double)g.C[(int64_t)I * g.ldc + J];
       } else {
         c = 0.0;
         for (int d = 0; d < DIM; ++d) {
-          const double df = (double)p.x[(int64_t)I * DIM + d] - (double)p.y[(int64_t)J * DIM + d];
+          const double df = (double)g.x[(int64_t)I * DIM + d] - (double)g.y[(int64_t)J * DIM + d];
           c += df * df;
         }
       }
-      v = exp(((double)p.f_out[I] + gJ - c) * ie);
+      v = exp(((double)f[I] + gJ - c) * ie);
     }
     csum += v;
     const double rs = wave_sum_d(v);
-    if (lane == 0 && I < p.n) atomicAdd(&rowsum[I], rs);
+    if (lane == 0 && I < g.n) atomicAdd(&rowsum[I], rs);
   }
   cpart[wv][lane] = csum;
   __syncthreads();
-  if (wv == 0 && J < p.n)
+  if (wv == 0 && J < g.n)
     atomicAdd(&colsum[J], cpart[0][lane] + cpart[1][lane] + cpart[2][lane] + cpart[3][lane]);
-  // last block: norms
+  // the last block to finish forms the two norms
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -312,17 +343,17 @@ __global__ void __launch_bounds__(256)
   if (!s_last) return;
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   double er = 0.0, ec = 0.0;
-  for (int I = threadIdx.x; I < p.n; I += blockDim.x) {
-    const double dr = __hip_atomic_load(&rowsum[I], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - (double)p.a[I];
-    const double dc = __hip_atomic_load(&colsum[I], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - (double)p.b[I];
+  for (int I = threadIdx.x; I < g.n; I += blockDim.x) {
+    const double dr = __hip_atomic_load(&rowsum[I], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - (double)g.a[I];
+    const double dc = __hip_atomic_load(&colsum[I], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - (double)g.b[I];
     er += dr * dr;
     ec += dc * dc;
   }
   er = block_sum_d(er, red);
   ec = block_sum_d(ec, red);
   if (threadIdx.x == 0) {
-    p.dstats[2] = sqrt(er);
-    p.dstats[3] = sqrt(ec);
+    dstats[2] = sqrt(er);
+    dstats[3] = sqrt(ec);
   }
 }
 
@@ -342,22 +373,27 @@ static int cu_count() {
   return cus;
 }
 
-template <int DIM, int RT>
-static const void* full_kernel_ptr() { return (const void*)full_solver_kernel<DIM, RT>; }
+// (RT, CQ) variants: rows per workgroup R = (16 / CQ) * RT
+struct FullVariant { int RT, CQ; };
+static constexpr FullVariant kVariants[] = {{8, 2}, {8, 4}, {4, 4}, {4, 8}, {2, 8}, {1, 8}, {1, 16}};
 
-static const void* pick_full_kernel(int dim, int RT) {
-#define CSOT_FK(D)                                    \
-  switch (RT) {                                       \
-    case 1: return full_kernel_ptr<D, 1>();           \
-    case 2: return full_kernel_ptr<D, 2>();           \
-    case 4: return full_kernel_ptr<D, 4>();           \
-    case 8: return full_kernel_ptr<D, 8>();           \
-    default: return nullptr;                          \
-  }
+template <int DIM, int RT, int CQ>
+static const void* fk() { return (const void*)full_solver_kernel<DIM, RT, CQ>; }
+
+static const void* pick_full_kernel(int dim, int RT, int CQ) {
+#define CSOT_FK(D)                                                    \
+  if (RT == 8 && CQ == 2) return fk<D, 8, 2>();                       \
+  if (RT == 8 && CQ == 4) return fk<D, 8, 4>();                       \
+  if (RT == 4 && CQ == 4) return fk<D, 4, 4>();                       \
+  if (RT == 4 && CQ == 8) return fk<D, 4, 8>();                       \
+  if (RT == 2 && CQ == 8) return fk<D, 2, 8>();                       \
+  if (RT == 1 && CQ == 8) return fk<D, 1, 8>();                       \
+  if (RT == 1 && CQ == 16) return fk<D, 1, 16>();                     \
+  return nullptr;
   switch (dim) {
-    case 0: CSOT_FK(0)
-    case 2: CSOT_FK(2)
-    case 3: CSOT_FK(3)
+    case 0: { CSOT_FK(0) }
+    case 2: { CSOT_FK(2) }
+    case 3: { CSOT_FK(3) }
     default: return nullptr;
   }
 #undef CSOT_FK
@@ -366,47 +402,40 @@ static const void* pick_full_kernel(int dim, int RT) {
 bool plan_full(const Geom& g, int hint, FullPlan* plan) {
   const int cus = cu_count();
   if (cus <= 0) return false;
-  int RT = 1;
-  if (hint > 0) {
-    // rows per wave from the requested workgroup count
-    const int rows = (g.n + hint - 1) / hint;
-    RT = rows <= 4 ? 1 : rows <= 8 ? 2 : rows <= 16 ? 4 : 8;
-  } else {
-    for (int cand : {8, 4, 2, 1}) {
-      if ((g.n + 4 * cand - 1) / (4 * cand) >= cus) { RT = cand; break; }
-    }
+  const int Wmax = hint > 0 ? hint : cus;  // one 16-wave workgroup per CU
+  // smallest R (most parallelism) such that W = ceil(n / R) <= Wmax
+  int best = -1;
+  for (int v = (int)(sizeof(kVariants) / sizeof(kVariants[0])) - 1; v >= 0; --v) {
+    const int R = (kFullWaves / kVariants[v].CQ) * kVariants[v].RT;
+    if ((g.n + R - 1) / R <= Wmax) { best = v; break; }
   }
-  const int R = 4 * RT;
+  if (best < 0) best = 0;
+  const int RT = kVariants[best].RT, CQ = kVariants[best].CQ;
+  const int R = (kFullWaves / CQ) * RT;
   const int W = (g.n + R - 1) / R;
-  const void* k = pick_full_kernel(g.dim, RT);
+  const void* k = pick_full_kernel(g.dim, RT, CQ);
   if (!k) return false;
+  hipFuncAttributes attr;
+  if (hipFuncGetAttributes(&attr, k) != hipSuccess) return false;
   int per_cu = 0;
-  hipError_t e = hipSuccess;
-  switch (g.dim) {  // occupancy query needs the typed kernel
-#define CSOT_OCC(D)                                                                        \
-  e = RT == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, full_solver_kernel<D, 1>, kFullThreads, 0) \
-    : RT == 2 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, full_solver_kernel<D, 2>, kFullThreads, 0) \
-    : RT == 4 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, full_solver_kernel<D, 4>, kFullThreads, 0) \
-              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, full_solver_kernel<D, 8>, kFullThreads, 0);
-    case 0: CSOT_OCC(0) break;
-    case 2: CSOT_OCC(2) break;
-    case 3: CSOT_OCC(3) break;
-    default: return false;
-#undef CSOT_OCC
-  }
-  if (e != hipSuccess || per_cu * cus < W) return false;
+  // all variants have the same block size; occupancy from the kernel's own resource use
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kFullThreads, 0) != hipSuccess)
+    return false;
+  if (per_cu * cus < W) return false;
   plan->W = W;
   plan->R = R;
-  plan->threads = kFullThreads;
+  plan->threads = RT * 100 + CQ;  // variant code (threads per block is always kFullThreads)
   plan->lds = 0;
   return true;
 }
 
-// workspace: ctl | xf[np] | yg[np] | rs[W] | rowsum[n] | colsum[n] | CT[n*np] (dense)
+static int full_np(int n) { return (n + kNC - 1) / kNC * kNC; }
+
+// workspace: ctl | fx[np] | gx[np] | rsx[W] | xc[np] | yc[np] | rowsum[n] | colsum[n] | CT
 size_t full_ws_bytes(const Geom& g, const FullPlan& pl) {
-  const size_t np = (size_t)((g.n + kNC - 1) / kNC * kNC);
-  size_t b = align256(256) + 2 * align256(sizeof(float4) * np) + align256(sizeof(double) * pl.W) +
-             2 * align256(sizeof(double) * g.n);
+  const size_t np = (size_t)full_np(g.n);
+  size_t b = align256(256) + 2 * align256(sizeof(uint64_t) * np) + align256(sizeof(uint64_t) * pl.W) +
+             2 * align256(sizeof(float4) * np) + 2 * align256(sizeof(double) * g.n);
   if (g.dim == 0) b += align256(sizeof(float) * (size_t)g.n * np);
   return b;
 }
@@ -414,35 +443,47 @@ size_t full_ws_bytes(const Geom& g, const FullPlan& pl) {
 hipError_t launch_sinkhorn_full(const Geom& g, float* f, float* gpot, double tol, int max_iter,
                                 int warm, double* dstats, void* ws, const FullPlan& pl,
                                 hipStream_t s) {
-  const int np = (g.n + kNC - 1) / kNC * kNC;
+  const int np = full_np(g.n);
   char* base = static_cast<char*>(ws);
   uint32_t* ctl = reinterpret_cast<uint32_t*>(base);
   size_t off = align256(256);
-  float4* xf = reinterpret_cast<float4*>(base + off); off += align256(sizeof(float4) * np);
-  float4* yg = reinterpret_cast<float4*>(base + off); off += align256(sizeof(float4) * np);
-  double* rs = reinterpret_cast<double*>(base + off); off += align256(sizeof(double) * pl.W);
+  uint64_t* fx = reinterpret_cast<uint64_t*>(base + off); off += align256(sizeof(uint64_t) * np);
+  uint64_t* gx = reinterpret_cast<uint64_t*>(base + off); off += align256(sizeof(uint64_t) * np);
+  uint64_t* rsx = reinterpret_cast<uint64_t*>(base + off); off += align256(sizeof(uint64_t) * pl.W);
+  const size_t zero_bytes = off;
+  float4* xc = reinterpret_cast<float4*>(base + off); off += align256(sizeof(float4) * np);
+  float4* yc = reinterpret_cast<float4*>(base + off); off += align256(sizeof(float4) * np);
   double* rowsum = reinterpret_cast<double*>(base + off); off += align256(sizeof(double) * g.n);
   double* colsum = reinterpret_cast<double*>(base + off); off += align256(sizeof(double) * g.n);
   float* CT = reinterpret_cast<float*>(base + off);
 
-  hipError_t e = launch_zero_words(ctl, 64, s);
+  hipError_t e = launch_zero_words(ctl, (int)(zero_bytes / 4), s);
   if (e != hipSuccess) return e;
+  const float s2 = (float)(kLog2eD / g.eps);
+  const int ib = (np + 255) / 256 < 1024 ? (np + 255) / 256 : 1024;
+  switch (g.dim) {
+    case 0: hipLaunchKernelGGL(full_init_kernel<0>, dim3(ib), dim3(256), 0, s, g.n, np, g.x, g.y, gpot, warm, s2, xc, yc, gx); break;
+    case 2: hipLaunchKernelGGL(full_init_kernel<2>, dim3(ib), dim3(256), 0, s, g.n, np, g.x, g.y, gpot, warm, s2, xc, yc, gx); break;
+    case 3: hipLaunchKernelGGL(full_init_kernel<3>, dim3(ib), dim3(256), 0, s, g.n, np, g.x, g.y, gpot, warm, s2, xc, yc, gx); break;
+    default: return hipErrorInvalidValue;
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   if (g.dim == 0) {
     hipLaunchKernelGGL(transpose_kernel, dim3((g.n + 31) / 32, (g.n + 31) / 32), dim3(256), 0, s,
                        g.C, g.ldc, CT, (int64_t)np, g.n);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   FullParams p;
-  p.n = g.n; p.np = np; p.W = pl.W; p.R = pl.R; p.max_iter = max_iter; p.warm = warm;
-  p.s2 = (float)(kLog2eD / g.eps);
+  p.n = g.n; p.np = np; p.W = pl.W; p.R = pl.R; p.max_iter = max_iter;
+  p.s2 = s2;
   p.to_nat = (float)(g.eps * kLn2D);
   p.tol2 = tol * tol;
-  p.x = g.x; p.y = g.y; p.C = g.C; p.ldc = g.ldc; p.CT = CT; p.a = g.a; p.b = g.b;
-  p.f_out = f; p.g_out = gpot; p.xf = xf; p.yg = yg; p.rs = rs; p.ctl = ctl; p.dstats = dstats;
+  p.xc = xc; p.yc = yc; p.C = g.C; p.ldc = g.ldc; p.CT = CT; p.a = g.a; p.b = g.b;
+  p.f_out = f; p.g_out = gpot; p.fx = fx; p.gx = gx; p.rsx = rsx; p.ctl = ctl; p.dstats = dstats;
   void* args[] = {&p};
-  const void* k = pick_full_kernel(g.dim, pl.R / 4);
+  const void* k = pick_full_kernel(g.dim, pl.threads / 100, pl.threads % 100);
   if (!k) return hipErrorInvalidValue;
-  e = hipLaunchCooperativeKernel(k, dim3(pl.W), dim3(pl.threads), args, 0, s);
+  e = hipLaunchCooperativeKernel(k, dim3(pl.W), dim3(kFullThreads), args, 0, s);
   if (e != hipSuccess) return e;
 
   // float64 check
@@ -452,9 +493,9 @@ hipError_t launch_sinkhorn_full(const Geom& g, float* f, float* gpot, double tol
   const dim3 grid((g.n + 63) / 64, (g.n + 31) / 32);
   const int ntiles = grid.x * grid.y;
   switch (g.dim) {
-    case 0: hipLaunchKernelGGL(full_check_kernel<0>, grid, dim3(256), 0, s, p, g.eps, rowsum, colsum, ctl + 8, ntiles); break;
-    case 2: hipLaunchKernelGGL(full_check_kernel<2>, grid, dim3(256), 0, s, p, g.eps, rowsum, colsum, ctl + 8, ntiles); break;
-    case 3: hipLaunchKernelGGL(full_check_kernel<3>, grid, dim3(256), 0, s, p, g.eps, rowsum, colsum, ctl + 8, ntiles); break;
+    case 0: hipLaunchKernelGGL(full_check_kernel<0>, grid, dim3(256), 0, s, g, f, gpot, dstats, rowsum, colsum, ctl + 8, ntiles); break;
+    case 2: hipLaunchKernelGGL(full_check_kernel<2>, grid, dim3(256), 0, s, g, f, gpot, dstats, rowsum, colsum, ctl + 8, ntiles); break;
+    case 3: hipLaunchKernelGGL(full_check_kernel<3>, grid, dim3(256), 0, s, g, f, gpot, dstats, rowsum, colsum, ctl + 8, ntiles); break;
   }
   return hipGetLastError();
 }

@@ -7,16 +7,20 @@
 //
 // Work split: workgroup w owns rows [w R, w R + R) and columns [w R, w R + R).  It keeps its
 // row slab of L and its column slab (a transposed copy) in LDS for the whole solve, so an
-// iteration reads no matrix data from memory: only the other potential (m floats) is
-// exchanged through global memory between two device-wide barriers per iteration.
+// iteration reads no matrix data from memory.  The new potentials are published as
+// epoch-tagged 64-bit slots (value | iteration); each workgroup polls the m slots of the other
+// potential until they carry the current iteration and stages them in LDS.  The data is its
+// own ready flag, so there is no counter barrier and no cache flush; the dependency chain
+// (F^t needs every G^{t-1}, G^t needs every F^t) is what keeps workgroups in step.
 //
 // Convergence (a reading of "until convergence"): the row residual of the plan after
 // iteration t-1 falls out of the row update of iteration t for free,
 //   r_i = alpha_i (2^(F_i^{t-1} - F_i^t) - 1),
-// because the row sums of that plan are alpha_i 2^(F^{t-1} - F^t).  Per-workgroup partial
-// sums of r_i^2 are combined after the first barrier in a fixed order by every workgroup,
-// so all take the same stop decision; the returned state is (F^{t-1}, G^{t-1}).  The
-// full-space norm is sqrt(K) ||r||_2 (every block-row of the expanded plan has these sums).
+// because the row sums of that plan are alpha_i 2^(F^{t-1} - F^t).  Each workgroup publishes
+// its partial sum of r_i^2 in a slot next to F^t; every workgroup sums the W partials in the
+// same order before its column update, so all take the same stop decision.  The returned
+// state is (F^{t-1}, G^{t-1}); the full-space norm is sqrt(K) ||r||_2 (every block-row of the
+// expanded plan has these row sums).
 //
 // A separate check kernel recomputes both marginal errors in float64 from the returned f, g.
 #include "common.hpp"
@@ -25,8 +29,6 @@
 namespace csot {
 
 constexpr int kRedThreads = 256;
-constexpr int kRedLPR = 16;            // lanes cooperating on one row / column
-constexpr int kRedChunk = 4 * kRedLPR; // elements covered by one float4 sweep of a group
 constexpr int kMaxLds = 150 * 1024;
 
 struct RedParams {
@@ -39,54 +41,88 @@ struct RedParams {
   const float* beta;
   float* f_out;
   float* g_out;
-  float* fbuf;     // [mp] F exchange
-  float* gbuf;     // [mp] G exchange
-  double* rs;      // [W] residual partials
-  uint32_t* ctl;   // barrier counter, abort flag, ...
+  uint64_t* fx;    // [m] F exchange slots
+  uint64_t* gx;    // [m] G exchange slots
+  uint64_t* rsx;   // [W] residual-partial slots
+  uint32_t* ctl;   // [1] abort flag
   double* dstats;
 };
 
-// LSE2 over a padded LDS row `row` (length mp) plus `vec`, by a group of kRedLPR lanes.
+// LSE2 over a padded LDS row (length mp, a multiple of 4*LPR) plus `vec`, computed by a group
+// of LPR lanes: exact maximum first, then the shifted sum.
+template <int LPR>
 __device__ __forceinline__ float group_lse2(const float* __restrict__ row,
                                             const float* __restrict__ vec, int mp, int gl) {
   float M = kNegBig;
-  for (int q = gl * 4; q < mp; q += kRedChunk) {
+  for (int q = gl * 4; q < mp; q += 4 * LPR) {
     const float4 l = *reinterpret_cast<const float4*>(row + q);
     const float4 v = *reinterpret_cast<const float4*>(vec + q);
     M = fmaxf(M, fmaxf(fmaxf(l.x + v.x, l.y + v.y), fmaxf(l.z + v.z, l.w + v.w)));
   }
-  M = group_max(M, kRedLPR);
+  M = group_max(M, LPR);
   float S = 0.0f;
-  for (int q = gl * 4; q < mp; q += kRedChunk) {
+  for (int q = gl * 4; q < mp; q += 4 * LPR) {
     const float4 l = *reinterpret_cast<const float4*>(row + q);
     const float4 v = *reinterpret_cast<const float4*>(vec + q);
     S += exp2_fast(l.x + v.x - M) + exp2_fast(l.y + v.y - M) + exp2_fast(l.z + v.z - M) +
          exp2_fast(l.w + v.w - M);
   }
-  S = group_sum(S, kRedLPR);
+  S = group_sum(S, LPR);
   return M + log2_fast(S);
 }
 
+// Stage the m slots of `src` carrying `epoch` into Vs (zero padding up to mp).  Every thread
+// issues its loads first, then waits on the ones not yet current.  Returns false on abort.
+__device__ __forceinline__ bool stage_slots(uint64_t* src, int m, int mp, uint32_t epoch,
+                                            float* Vs, uint32_t* abort_flag, int* s_bad) {
+  constexpr int kB = 4;
+  bool ok = true;
+  for (int base = threadIdx.x; base < mp; base += kB * kRedThreads) {
+    uint64_t w[kB];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      const int j = base + u * kRedThreads;
+      w[u] = j < m ? slot_load(src + j) : 0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      const int j = base + u * kRedThreads;
+      if (j < m) {
+        if (ok) ok = slot_wait(src + j, w[u], epoch, abort_flag);
+        Vs[j] = slot_value(w[u]);
+      } else if (j < mp) {
+        Vs[j] = 0.0f;
+      }
+    }
+  }
+  if (!ok) *s_bad = 1;
+  __syncthreads();
+  return *s_bad == 0;
+}
+
+template <int LPR>
 __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p) {
   extern __shared__ float4 lds4[];
   float* lds = reinterpret_cast<float*>(lds4);
   const int R = p.R, mp = p.mp, m = p.m;
   float* Ls = lds;                      // [R][mp] row slab
   float* LTs = Ls + (size_t)R * mp;     // [R][mp] column slab (transposed)
-  float* Vs = LTs + (size_t)R * mp;     // [mp] exchanged potential
+  float* Vs = LTs + (size_t)R * mp;     // [mp] staged potential
   float* la2 = Vs + mp;                 // [R] log2 alpha (my rows)
   float* lb2 = la2 + R;                 // [R] log2 beta (my columns)
   float* Fcur = lb2 + R;                // [R]
   float* Fprev = Fcur + R;              // [R]
   float* Gcur = Fprev + R;              // [R]
-  double* red = reinterpret_cast<double*>(Gcur + R + (R & 1));  // [8] reduction scratch
-  __shared__ int s_flag;
+  float* rsv = Gcur + R;                // [W] residual partials of every workgroup
+  double* red = reinterpret_cast<double*>(rsv + p.W + ((5 * R + p.W) & 1));  // [8]
+  __shared__ int s_bad;
   __shared__ int s_stop;
 
   const int w = blockIdx.x;
   const int r0 = w * R;
   const int nr = max(0, min(R, m - r0));  // rows (= columns) this workgroup owns
   const int tid = threadIdx.x;
+  uint32_t* abort_flag = p.ctl;
 
   // ---- load the slabs (once) ------------------------------------------------------------
   for (int e = tid; e < R * mp; e += blockDim.x) {
@@ -96,10 +132,8 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
   }
   for (int e = tid; e < R * mp; e += blockDim.x) {
     const int i = e / R, cl = e - i * R;  // consecutive threads read consecutive columns
-    if (i < mp) {
-      const bool ok = cl < nr && i < m;
-      LTs[(size_t)cl * mp + i] = ok ? p.logK[(int64_t)i * m + r0 + cl] * kLog2e : -INFINITY;
-    }
+    const bool ok = cl < nr && i < m;
+    LTs[(size_t)cl * mp + i] = ok ? p.logK[(int64_t)i * m + r0 + cl] * kLog2e : -INFINITY;
   }
   for (int rl = tid; rl < R; rl += blockDim.x) {
     const bool ok = rl < nr;
@@ -111,21 +145,21 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
   }
   for (int j = tid; j < mp; j += blockDim.x)
     Vs[j] = (j < m && p.warm) ? p.g_out[j] * p.s2 : 0.0f;
+  if (tid == 0) s_bad = 0;
   __syncthreads();
 
   const int lane = tid & (kWave - 1);
-  const int gl = lane % kRedLPR;                     // lane within its group
-  const int grp = tid / kRedLPR;                     // group index in the block
-  const int ngrp = blockDim.x / kRedLPR;
-  uint32_t bar = 0;
+  const int gl = lane % LPR;             // lane within its group
+  const int grp = tid / LPR;             // group index in the block
+  const int ngrp = kRedThreads / LPR;
   int iters_done = 0, converged = 0, flags = 0;
   double err2 = 0.0;
 
-  for (int t = 1;; ++t) {
+  for (uint32_t t = 1;; ++t) {
     // ---- row update: F^t from G^{t-1} (in Vs) -------------------------------------------
     double rpart = 0.0;
     for (int rl = grp; rl < nr; rl += ngrp) {
-      const float lse = group_lse2(Ls + (size_t)rl * mp, Vs, mp, gl);
+      const float lse = group_lse2<LPR>(Ls + (size_t)rl * mp, Vs, mp, gl);
       const float Fn = la2[rl] - lse;
       if (gl == 0) {
         if (t >= 2) {
@@ -134,50 +168,49 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
         }
         Fprev[rl] = Fcur[rl];
         Fcur[rl] = Fn;
-        p.fbuf[r0 + rl] = Fn;
+        slot_publish(p.fx + r0 + rl, Fn, t);
       }
     }
     const double rtot = block_sum_d(rpart, red);
-    if (tid == 0) p.rs[w] = rtot;
-    if (!grid_barrier(p.ctl, (uint32_t)p.W * (++bar), &s_flag)) { flags |= 2; break; }
+    if (tid == 0) slot_publish(p.rsx + w, (float)rtot, t);
 
-    // ---- stop test on the state after iteration t-1 --------------------------------------
+    // ---- gather F^t and the residual partials; stop test on the state after t-1 ----------
+    if (!stage_slots(p.fx, m, mp, t, Vs, abort_flag, &s_bad)) { flags |= 2; break; }
+    for (int v = tid; v < p.W; v += blockDim.x) {
+      uint64_t wv = slot_load(p.rsx + v);
+      if (!slot_wait(p.rsx + v, wv, t, abort_flag)) s_bad = 1;
+      rsv[v] = slot_value(wv);
+    }
+    __syncthreads();
+    if (s_bad) { flags |= 2; break; }
     if (tid == 0) {
       int stop = 0;
       if (t >= 2) {
         double s = 0.0;
-        for (int v = 0; v < p.W; ++v)
-          s += __hip_atomic_load(&p.rs[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int v = 0; v < p.W; ++v) s += (double)rsv[v];
         err2 = s;
         const bool fin = s == s && s < 1.0e300;
         converged = fin && s <= p.tol2;
         // tol = 0 asks for exactly max_iter iterations, even if the residual underflows to 0
-        stop = (converged && p.tol2 > 0.0) || !fin || (t - 1) >= p.max_iter;
+        stop = (converged && p.tol2 > 0.0) || !fin || (int)(t - 1) >= p.max_iter;
         if (!fin) flags |= 1;
       }
       s_stop = stop;
     }
     __syncthreads();
-    if (s_stop) { iters_done = t - 1; break; }
+    if (s_stop) { iters_done = (int)t - 1; break; }
 
     // ---- column update: G^t from F^t -----------------------------------------------------
-    for (int j = tid; j < mp; j += blockDim.x)
-      Vs[j] = j < m ? __hip_atomic_load(&p.fbuf[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                    : 0.0f;
-    __syncthreads();
     for (int cl = grp; cl < nr; cl += ngrp) {
-      const float lse = group_lse2(LTs + (size_t)cl * mp, Vs, mp, gl);
+      const float lse = group_lse2<LPR>(LTs + (size_t)cl * mp, Vs, mp, gl);
       const float Gn = lb2[cl] - lse;
       if (gl == 0) {
         Gcur[cl] = Gn;
-        p.gbuf[r0 + cl] = Gn;
+        slot_publish(p.gx + r0 + cl, Gn, t);
       }
     }
-    if (!grid_barrier(p.ctl, (uint32_t)p.W * (++bar), &s_flag)) { flags |= 2; break; }
-    for (int j = tid; j < mp; j += blockDim.x)
-      Vs[j] = j < m ? __hip_atomic_load(&p.gbuf[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                    : 0.0f;
-    __syncthreads();
+    __syncthreads();  // everyone is done reading Vs (F^t)
+    if (!stage_slots(p.gx, m, mp, t, Vs, abort_flag, &s_bad)) { flags |= 2; break; }
   }
 
   // ---- outputs: the state after iteration iters_done ------------------------------------
@@ -268,45 +301,59 @@ static int device_cu_count() {
   return cus;
 }
 
-static size_t reduced_lds_bytes(int R, int mp) {
-  return sizeof(float) * ((size_t)2 * R * mp + mp + 5 * (size_t)R + 2) + 8 * sizeof(double) + 16;
+static size_t reduced_lds_bytes(int R, int mp, int W) {
+  return sizeof(float) * ((size_t)2 * R * mp + mp + 5 * (size_t)R + W + 1) + 8 * sizeof(double) + 16;
 }
+
+static int pick_lpr(int R) { return R <= 4 ? 64 : R <= 8 ? 32 : 16; }
+
+static const void* reduced_kernel_ptr(int lpr) {
+  switch (lpr) {
+    case 64: return (const void*)reduced_solver_kernel<64>;
+    case 32: return (const void*)reduced_solver_kernel<32>;
+    default: return (const void*)reduced_solver_kernel<16>;
+  }
+}
+
+static int reduced_mp(int m) { return (m + 63) / 64 * 64; }
 
 bool plan_reduced(int m, int hint, ReducedPlan* plan) {
   const int cus = device_cu_count();
   if (cus <= 0) return false;
-  const int mp = (m + kRedChunk - 1) / kRedChunk * kRedChunk;
+  const int mp = reduced_mp(m);
   int W = hint;
   if (W <= 0) {
-    // about 16 rows per workgroup, at most one workgroup per CU
-    W = (m + 15) / 16;
+    // about 8 rows per workgroup, at most one workgroup per CU
+    W = (m + 7) / 8;
     if (W < 1) W = 1;
     if (W > cus) W = cus;
   }
   if (W > m) W = m;
   int R = (m + W - 1) / W;
   W = (m + R - 1) / R;  // no empty workgroups
-  size_t lds = reduced_lds_bytes(R, mp);
+  size_t lds = reduced_lds_bytes(R, mp, W);
   while (lds > (size_t)kMaxLds && W < cus && W < m) {
     ++W;
     R = (m + W - 1) / W;
     W = (m + R - 1) / R;
-    lds = reduced_lds_bytes(R, mp);
+    lds = reduced_lds_bytes(R, mp, W);
   }
   if (lds > (size_t)kMaxLds) return false;
-  // co-residency: the cooperative launch needs all W workgroups resident at once
-  static bool attr_set = false;
-  if (!attr_set) {
-    if (hipFuncSetAttribute((const void*)reduced_solver_kernel,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds) != hipSuccess)
+  const int lpr = pick_lpr(R);
+  const void* k = reduced_kernel_ptr(lpr);
+  static bool attr_set[3] = {false, false, false};
+  const int ai = lpr == 64 ? 0 : lpr == 32 ? 1 : 2;
+  if (!attr_set[ai]) {
+    if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds) != hipSuccess)
       return false;
-    attr_set = true;
+    attr_set[ai] = true;
   }
+  // co-residency: the cooperative launch needs all W workgroups resident at once
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reduced_solver_kernel, kRedThreads,
-                                                   lds) != hipSuccess)
-    return false;
-  if (per_cu * cus < W) return false;
+  hipError_t e = lpr == 64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reduced_solver_kernel<64>, kRedThreads, lds)
+               : lpr == 32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reduced_solver_kernel<32>, kRedThreads, lds)
+                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reduced_solver_kernel<16>, kRedThreads, lds);
+  if (e != hipSuccess || per_cu * cus < W) return false;
   plan->W = W;
   plan->R = R;
   plan->threads = kRedThreads;
@@ -314,30 +361,34 @@ bool plan_reduced(int m, int hint, ReducedPlan* plan) {
   return true;
 }
 
-// workspace: ctl[64] words | fbuf[mp] | gbuf[mp] | rs[W] doubles | check partials
+// workspace: ctl[64 words] | fx[mp] | gx[mp] | rsx[W] (64-bit slots) | check partials
 static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
+static size_t slots_bytes(int m, int W) {
+  return align256(256) + 2 * align256(sizeof(uint64_t) * reduced_mp(m)) +
+         align256(sizeof(uint64_t) * W);
+}
+
 size_t reduced_ws_bytes(int m, const ReducedPlan& p) {
-  const int mp = (m + kRedChunk - 1) / kRedChunk * kRedChunk;
   const int nchk = (m + 3) / 4 + (m + 63) / 64;
-  return align256(256) + 2 * align256(sizeof(float) * mp) + align256(sizeof(double) * p.W) +
-         align256(sizeof(double) * nchk);
+  return slots_bytes(m, p.W) + align256(sizeof(double) * nchk);
 }
 
 hipError_t launch_sinkhorn_reduced(int m, int K, double eps, const float* logK,
                                    const float* alpha, const float* beta, float* f, float* g,
                                    double tol, int max_iter, int warm, double* dstats,
                                    void* ws, const ReducedPlan& pl, hipStream_t s) {
-  const int mp = (m + kRedChunk - 1) / kRedChunk * kRedChunk;
+  const int mp = reduced_mp(m);
   char* base = static_cast<char*>(ws);
   uint32_t* ctl = reinterpret_cast<uint32_t*>(base);
   size_t off = align256(256);
-  float* fbuf = reinterpret_cast<float*>(base + off); off += align256(sizeof(float) * mp);
-  float* gbuf = reinterpret_cast<float*>(base + off); off += align256(sizeof(float) * mp);
-  double* rs = reinterpret_cast<double*>(base + off); off += align256(sizeof(double) * pl.W);
+  uint64_t* fx = reinterpret_cast<uint64_t*>(base + off); off += align256(sizeof(uint64_t) * mp);
+  uint64_t* gx = reinterpret_cast<uint64_t*>(base + off); off += align256(sizeof(uint64_t) * mp);
+  uint64_t* rsx = reinterpret_cast<uint64_t*>(base + off); off += align256(sizeof(uint64_t) * pl.W);
   double* part = reinterpret_cast<double*>(base + off);
 
-  hipError_t e = launch_zero_words(ctl, 64, s);
+  // epochs start at 1, so zeroed slots are never mistaken for current ones
+  hipError_t e = launch_zero_words(ctl, (int)(slots_bytes(m, pl.W) / 4), s);
   if (e != hipSuccess) return e;
 
   RedParams p;
@@ -346,9 +397,9 @@ hipError_t launch_sinkhorn_reduced(int m, int K, double eps, const float* logK,
   p.to_nat = (float)(eps * kLn2D);
   p.tol2 = tol * tol / (double)K;
   p.logK = logK; p.alpha = alpha; p.beta = beta; p.f_out = f; p.g_out = g;
-  p.fbuf = fbuf; p.gbuf = gbuf; p.rs = rs; p.ctl = ctl; p.dstats = dstats;
+  p.fx = fx; p.gx = gx; p.rsx = rsx; p.ctl = ctl; p.dstats = dstats;
   void* args[] = {&p};
-  e = hipLaunchCooperativeKernel((const void*)reduced_solver_kernel, dim3(pl.W),
+  e = hipLaunchCooperativeKernel(reduced_kernel_ptr(pick_lpr(pl.R)), dim3(pl.W),
                                  dim3(pl.threads), args, (unsigned)pl.lds, s);
   if (e != hipSuccess) return e;
 
