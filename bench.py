@@ -1,0 +1,237 @@
+"""Benchmark: cyclic (reduced) vs plain full-size entropic-OT Sinkhorn on one MI355X.
+
+Workload: n = 8192 points per side, cyclic order K = 16 (m = 512), 2-D K-fold rotationally
+symmetric point clouds (area-uniform annulus r in [0.5, 1]), squared Euclidean cost recomputed
+on the fly from float32 coordinates, a and b = Dirichlet(1) blocks tiled K times,
+eps = 0.01 * median(C), stopping tolerance 1e-6 on the full-space L2 row-marginal residual.
+Synthetic, seeded (seed 100); inputs are resident in HBM before the timed region.
+
+One step = one pass of the whole path on that input:
+  reduced : fold (float64 log-sum) -> Sinkhorn to 1e-6 -> expand to the n x n plan ->
+            objective + gradients (dx, dy, da, db);
+            plus a fixed-count reduced solve (tol = 0, --fixed-reduced iterations);
+  full    : plain full-size Sinkhorn to 1e-6 -> objective + gradients;
+            plus a fixed-count full solve (tol = 0, --fixed-full iterations).
+`value` is the reduced Sinkhorn iteration rate (iterations / second) of the fixed-count legs;
+the time-to-tolerance and the full-size rates are reported beside it.  All timing uses HIP
+events on the stream the kernels run on.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+N, K, DIM, SEED, EPS_FACTOR, TOL = 8192, 16, 2, 100, 0.01, 1e-6
+FLOPS_PER_ENTRY = {2: 11, 3: 14}  # algorithmic fp32 ops per (I, J) entry of a half-step
+PEAK_FP32_TFLOPS = 157.3          # MI355X published fp32 vector peak
+HBM_PEAK_GBS = 8000.0
+
+
+def _args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--fixed-reduced", type=int, default=1000)
+    ap.add_argument("--fixed-full", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def _source_hash(*names):
+    h = hashlib.sha256()
+    for nm in names:
+        with open(os.path.join(ROOT, "paper_2311_13147_amd", "csrc", nm), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(kernel_file, launches_per_call):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 --pmc
+    summary, or None when it is missing or the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "full_solver_n8192_K16_pmc.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != _source_hash(kernel_file, "common.hpp"):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def main():
+    args = _args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2311_13147_amd as csot
+    import workloads
+
+    dev = torch.device("cuda:0")
+    p = workloads.symmetric_problem(N, K, DIM, EPS_FACTOR, seed=SEED)
+    T_ = lambda v: torch.from_numpy(np.ascontiguousarray(v)).to(dev)
+    prob = csot.Problem(T_(p.a), T_(p.b), p.eps, p.K, x=T_(p.x), y=T_(p.y))
+    m = p.m
+    o_tol = csot.make_opts(tol=TOL, max_iter=100000, fold_fp64=1)
+    o_fr = csot.make_opts(tol=0.0, max_iter=args.fixed_reduced, fold_fp64=1)
+    o_ff = csot.make_opts(tol=0.0, max_iter=args.fixed_full)
+    # preallocated outputs (nothing allocated inside the timed region)
+    logK = torch.empty((m, m), device=dev)
+    al, be = torch.empty(m, device=dev), torch.empty(m, device=dev)
+    fr, gr = torch.empty(m, device=dev), torch.empty(m, device=dev)
+    fr2, gr2 = torch.empty(m, device=dev), torch.empty(m, device=dev)
+    ff, gf = torch.empty(N, device=dev), torch.empty(N, device=dev)
+    ff2, gf2 = torch.empty(N, device=dev), torch.empty(N, device=dev)
+    Tplan = torch.empty((N, N), device=dev)
+    ds = [torch.zeros(8, dtype=torch.float64, device=dev) for _ in range(4)]
+    vals_r = torch.empty(8, dtype=torch.float64, device=dev)
+    vals_f = torch.empty(8, dtype=torch.float64, device=dev)
+    csot.workspace(prob, o_tol)
+
+    E = lambda: torch.cuda.Event(enable_timing=True)
+    legs = ["fold", "red_solve", "expand", "red_grad", "red_fixed", "full_solve", "full_grad",
+            "full_fixed"]
+
+    def step(record):
+        ev = {k: (E(), E()) for k in legs}
+        def run(name, fn):
+            ev[name][0].record()
+            out = fn()
+            ev[name][1].record()
+            return out
+        run("fold", lambda: csot.ot_fold_kernel(prob, o_tol, out=(logK, al, be)))
+        run("red_solve", lambda: csot.ot_sinkhorn_reduced(prob, logK, al, be, o_tol,
+                                                          host_stats=False, out=(fr, gr),
+                                                          dstats=ds[0]))
+        run("expand", lambda: csot.ot_expand_plan(prob, fr, gr, out=Tplan))
+        res_r = run("red_grad", lambda: csot.ot_cost_and_grad(prob, fr, gr, True, want_dxy=True,
+                                                              want_dab=True, out=vals_r))
+        run("red_fixed", lambda: csot.ot_sinkhorn_reduced(prob, logK, al, be, o_fr,
+                                                          host_stats=False, out=(fr2, gr2),
+                                                          dstats=ds[1]))
+        run("full_solve", lambda: csot.ot_sinkhorn_full(prob, o_tol, host_stats=False,
+                                                        out=(ff, gf), dstats=ds[2]))
+        run("full_grad", lambda: csot.ot_cost_and_grad(prob, ff, gf, False, want_dxy=True,
+                                                       want_dab=True, out=vals_f))
+        run("full_fixed", lambda: csot.ot_sinkhorn_full(prob, o_ff, host_stats=False,
+                                                        out=(ff2, gf2), dstats=ds[3]))
+        return ev
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs = [step(True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    ms = {k: sum(e[k][0].elapsed_time(e[k][1]) for e in evs) / args.steps for k in legs}
+    st = [d.cpu().tolist() for d in ds]
+    it_red, it_full = int(st[0][0]), int(st[2][0])
+    vr, vf = csot.values_dict(vals_r), csot.values_dict(vals_f)
+    red_ips = args.fixed_reduced / (ms["red_fixed"] * 1e-3)
+    full_ips = args.fixed_full / (ms["full_fixed"] * 1e-3)
+    ttt_red = ms["fold"] + ms["red_solve"]
+    ttt_full = ms["full_solve"]
+    step_ms = wall * 1e3 / args.steps
+
+    # roofline of the dominant kernel: the full-size solver (fixed-count leg)
+    entries = 2.0 * N * N * args.fixed_full
+    achieved = entries * FLOPS_PER_ENTRY[DIM] / (ms["full_fixed"] * 1e-3) / 1e12
+    roof = {"bound": "alu", "kernel": "full_solver_kernel", "achieved": round(achieved, 3),
+            "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+            "traffic": _traffic("full.hip", 1)}
+
+    out = {
+        "metric": "Sinkhorn iters/s & time-to-1e-6 marginal err, reduced vs full, n=8192 K=16",
+        "value": round(red_ips, 1),
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(step_ms, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"cyclic EROT, 2-D {K}-fold rotational point clouds, n={N}, K={K}, "
+                               f"m={m}, eps={EPS_FACTOR}*median(C), tol={TOL}",
+                   "n": N, "K": K, "m": m, "dim": DIM, "eps": p.eps, "seed": SEED},
+        "reduced_iters_per_s": round(red_ips, 1),
+        "full_iters_per_s": round(full_ips, 1),
+        "iter_speedup": round(red_ips / full_ips, 2),
+        "time_to_tol_ms": {"reduced_fold_plus_solve": round(ttt_red, 4),
+                           "reduced_end_to_end_with_expand": round(ttt_red + ms["expand"], 4),
+                           "full_solve": round(ttt_full, 4),
+                           "speedup_solve": round(ttt_full / ttt_red, 2)},
+        "forward_backward_ms": {"reduced": round(ttt_red + ms["red_grad"], 4),
+                                "full": round(ttt_full + ms["full_grad"], 4)},
+        "iterations_to_tol": {"reduced": it_red, "full": it_full},
+        "marginal_err_fp64": {"reduced_row": st[0][2], "reduced_col": st[0][3],
+                              "full_row": st[2][2], "full_col": st[2][3]},
+        "objective": {"reduced_P": vr["P"], "full_P": vf["P"],
+                      "rel_gap": abs(vr["P"] - vf["P"]) / max(abs(vf["P"]), vf["CT"])},
+        "leg_ms": {k: round(v, 4) for k, v in ms.items()},
+        "expand_GBps": round(4.0 * N * N / (ms["expand"] * 1e-3) / 1e9, 1),
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, fr, gr, vr, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(p, f_gpu, g_gpu, vr, budget_s):
+    """The float64 oracle as it stands, timed on the host: reduced cyclic Sinkhorn on the same
+    workload (a bounded number of iterations), plus the error of the GPU result against the
+    oracle's converged reduced solution."""
+    import numpy as np
+
+    from oracle import cost, objective, sinkhorn
+
+    Ck = cost.blocks_from_row0(cost.row0_from_points(p.x, p.y, p.K), p.K)
+    a, b = p.a.astype(np.float64), p.b.astype(np.float64)
+    alpha, beta = sinkhorn.fold_marginals(a, p.K), sinkhorn.fold_marginals(b, p.K)
+    t0 = time.perf_counter()
+    logK = sinkhorn.fold_kernel(Ck, p.eps)
+    t_fold = time.perf_counter() - t0
+    # one timed probe iteration sizes the sample to the time budget
+    t0 = time.perf_counter()
+    sinkhorn.reduced_sinkhorn(alpha, beta, logK, p.eps, p.K, tol=0.0, max_iter=2)
+    per_it = (time.perf_counter() - t0) / 2
+    iters = max(5, min(2000, int(budget_s / per_it)))
+    t0 = time.perf_counter()
+    sinkhorn.reduced_sinkhorn(alpha, beta, logK, p.eps, p.K, tol=0.0, max_iter=iters)
+    dt = time.perf_counter() - t0
+    ref = sinkhorn.reduced_sinkhorn(alpha, beta, logK, p.eps, p.K, tol=TOL)
+    rv = objective.reduced_values(ref["f"], ref["g"], Ck, p.eps, alpha, beta)
+    P_ref = p.K * rv["P"]
+    f = f_gpu.detach().cpu().numpy().astype(np.float64)
+    g = g_gpu.detach().cpu().numpy().astype(np.float64)
+    Tg = sinkhorn.reduced_plan_blocks(f, g, Ck, p.eps)
+    Tr = sinkhorn.reduced_plan_blocks(ref["f"], ref["g"], Ck, p.eps)
+    return {"value": round(iters / dt, 2), "unit": "iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"{iters} float64 reduced Sinkhorn iterations (m={p.m}, NumPy/SciPy "
+                      f"logsumexp, one thread) after a {t_fold:.2f} s fold",
+            "oracle_iters_to_tol": ref["iters"],
+            "gpu_vs_fp64": {"objective_rel": abs(vr["P"] - P_ref) / max(abs(P_ref), p.K * rv["CT"]),
+                            "plan_l1_rel": float(np.abs(Tg - Tr).sum() / Tr.sum())}}
+
+
+if __name__ == "__main__":
+    main()

@@ -207,6 +207,7 @@ size_t ot_workspace_bytes(const ot_problem* prob, const ot_opts* opts) {
     rp.W = g.m < 1024 ? g.m : 1024;
     if (o.workgroups > rp.W) rp.W = o.workgroups;
     rp.R = 1;
+    rp.stride = 1;
     rp.threads = 256;
     rp.lds = 0;
     need = std::max(need, csot::reduced_ws_bytes(g.m, rp));

@@ -29,6 +29,7 @@ hipError_t launch_zero_words(uint32_t* p, int count, hipStream_t s);
 // ---- reduced.hip -------------------------------------------------------------------------
 struct ReducedPlan {
   int W;        // cooperating workgroups
+  int stride;   // launched blocks per workgroup (8 keeps the workgroups on one XCD)
   int R;        // rows (and columns) per workgroup
   int threads;  // threads per workgroup
   size_t lds;   // dynamic LDS bytes

@@ -33,6 +33,7 @@ constexpr int kMaxLds = 150 * 1024;
 
 struct RedParams {
   int m, mp, K, W, R, max_iter, warm;
+  int stride;      // launched blocks per workgroup slot (8: keep all workgroups on one XCD)
   float s2;        // log2(e) / eps
   float to_nat;    // eps ln 2
   double tol2;     // tol^2 / K  (compared with sum r_i^2)
@@ -71,18 +72,23 @@ __device__ __forceinline__ float group_lse2(const float* __restrict__ row,
   return M + log2_fast(S);
 }
 
-// Stage the m slots of `src` carrying `epoch` into Vs (zero padding up to mp).  Every thread
-// issues its loads first, then waits on the ones not yet current.  Returns false on abort.
+// Stage the m slots of `src` carrying `epoch` into Vs (zero padding up to mp) and, when
+// `extra` is non-null, the `nextra` slots of `extra` into xv.  Every thread issues all its
+// loads first and then waits on the ones not yet current, so both sets cost one round trip.
+// Returns false on abort.
 __device__ __forceinline__ bool stage_slots(uint64_t* src, int m, int mp, uint32_t epoch,
-                                            float* Vs, uint32_t* abort_flag, int* s_bad) {
+                                            float* Vs, uint64_t* extra, int nextra, float* xv,
+                                            uint32_t* abort_flag, int* s_bad) {
   constexpr int kB = 4;
   bool ok = true;
-  for (int base = threadIdx.x; base < mp; base += kB * kRedThreads) {
+  const int total = mp + nextra;
+  for (int base = threadIdx.x; base < total; base += kB * kRedThreads) {
     uint64_t w[kB];
 #pragma unroll
     for (int u = 0; u < kB; ++u) {
       const int j = base + u * kRedThreads;
-      w[u] = j < m ? slot_load(src + j) : 0ull;
+      w[u] = j < m ? slot_load(src + j)
+                   : (j >= mp && j < total) ? slot_load(extra + (j - mp)) : 0ull;
     }
 #pragma unroll
     for (int u = 0; u < kB; ++u) {
@@ -92,6 +98,9 @@ __device__ __forceinline__ bool stage_slots(uint64_t* src, int m, int mp, uint32
         Vs[j] = slot_value(w[u]);
       } else if (j < mp) {
         Vs[j] = 0.0f;
+      } else if (j < total) {
+        if (ok) ok = slot_wait(extra + (j - mp), w[u], epoch, abort_flag);
+        xv[j - mp] = slot_value(w[u]);
       }
     }
   }
@@ -118,7 +127,8 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
   __shared__ int s_bad;
   __shared__ int s_stop;
 
-  const int w = blockIdx.x;
+  if (blockIdx.x % p.stride) return;  // placeholder block: frees its CU at once
+  const int w = blockIdx.x / p.stride;
   const int r0 = w * R;
   const int nr = max(0, min(R, m - r0));  // rows (= columns) this workgroup owns
   const int tid = threadIdx.x;
@@ -175,14 +185,10 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
     if (tid == 0) slot_publish(p.rsx + w, (float)rtot, t);
 
     // ---- gather F^t and the residual partials; stop test on the state after t-1 ----------
-    if (!stage_slots(p.fx, m, mp, t, Vs, abort_flag, &s_bad)) { flags |= 2; break; }
-    for (int v = tid; v < p.W; v += blockDim.x) {
-      uint64_t wv = slot_load(p.rsx + v);
-      if (!slot_wait(p.rsx + v, wv, t, abort_flag)) s_bad = 1;
-      rsv[v] = slot_value(wv);
+    if (!stage_slots(p.fx, m, mp, t, Vs, p.rsx, p.W, rsv, abort_flag, &s_bad)) {
+      flags |= 2;
+      break;
     }
-    __syncthreads();
-    if (s_bad) { flags |= 2; break; }
     if (tid == 0) {
       int stop = 0;
       if (t >= 2) {
@@ -210,7 +216,10 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
       }
     }
     __syncthreads();  // everyone is done reading Vs (F^t)
-    if (!stage_slots(p.gx, m, mp, t, Vs, abort_flag, &s_bad)) { flags |= 2; break; }
+    if (!stage_slots(p.gx, m, mp, t, Vs, nullptr, 0, nullptr, abort_flag, &s_bad)) {
+      flags |= 2;
+      break;
+    }
   }
 
   // ---- outputs: the state after iteration iters_done ------------------------------------
@@ -323,8 +332,8 @@ bool plan_reduced(int m, int hint, ReducedPlan* plan) {
   const int mp = reduced_mp(m);
   int W = hint;
   if (W <= 0) {
-    // about 8 rows per workgroup, at most one workgroup per CU
-    W = (m + 7) / 8;
+    // about 16 rows per workgroup, at most one workgroup per CU
+    W = (m + 15) / 16;
     if (W < 1) W = 1;
     if (W > cus) W = cus;
   }
@@ -353,7 +362,11 @@ bool plan_reduced(int m, int hint, ReducedPlan* plan) {
   hipError_t e = lpr == 64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reduced_solver_kernel<64>, kRedThreads, lds)
                : lpr == 32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reduced_solver_kernel<32>, kRedThreads, lds)
                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reduced_solver_kernel<16>, kRedThreads, lds);
-  if (e != hipSuccess || per_cu * cus < W) return false;
+  // keep every workgroup on one XCD (blocks are dealt to the 8 XCDs round-robin) when the
+  // placeholder blocks still fit in one co-resident grid: polls then stay within one L2
+  const int stride = (8 * W <= cus && cus % 8 == 0) ? 8 : 1;
+  if (e != hipSuccess || per_cu * cus < W * stride) return false;
+  plan->stride = stride;
   plan->W = W;
   plan->R = R;
   plan->threads = kRedThreads;
@@ -393,13 +406,14 @@ hipError_t launch_sinkhorn_reduced(int m, int K, double eps, const float* logK,
 
   RedParams p;
   p.m = m; p.mp = mp; p.K = K; p.W = pl.W; p.R = pl.R; p.max_iter = max_iter; p.warm = warm;
+  p.stride = pl.stride;
   p.s2 = (float)(kLog2eD / eps);
   p.to_nat = (float)(eps * kLn2D);
   p.tol2 = tol * tol / (double)K;
   p.logK = logK; p.alpha = alpha; p.beta = beta; p.f_out = f; p.g_out = g;
   p.fx = fx; p.gx = gx; p.rsx = rsx; p.ctl = ctl; p.dstats = dstats;
   void* args[] = {&p};
-  e = hipLaunchCooperativeKernel(reduced_kernel_ptr(pick_lpr(pl.R)), dim3(pl.W),
+  e = hipLaunchCooperativeKernel(reduced_kernel_ptr(pick_lpr(pl.R)), dim3(pl.W * pl.stride),
                                  dim3(pl.threads), args, (unsigned)pl.lds, s);
   if (e != hipSuccess) return e;
 
