@@ -42,11 +42,67 @@ __device__ __forceinline__ float group_sum(float v, int width) {
   return v;
 }
 
+// Cross-lane moves on the VALU (DPP) within a row of 16 lanes: lane i reads lane i^1, i^2,
+// the mirror within its half-row (7 - i) and the mirror within its row (15 - i).  Applied in
+// that order, a reduction leaves every lane of the row with the row's result.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141; // row_half_mirror
+constexpr int kDppMirror = 0x140;     // row_mirror
+
 // Merge of two (max, sum) log-sum-exp partials in base 2: value = M + log2(S).
 __device__ __forceinline__ void lse_merge(float& M, float& S, float M2, float S2) {
   const float Mn = fmaxf(M, M2);
   S = S * exp2_fast(M - Mn) + S2 * exp2_fast(M2 - Mn);
   M = Mn;
+}
+
+// Wave-wide max / sum with every lane receiving the result: DPP inside rows of 16 lanes,
+// a swizzle across rows (xor 16), then the two half-waves combined through lanes 0 and 32.
+__device__ __forceinline__ float wave_max_all(float v) {
+  v = fmaxf(v, dpp_f32<kDppXor1>(v));
+  v = fmaxf(v, dpp_f32<kDppXor2>(v));
+  v = fmaxf(v, dpp_f32<kDppHalfMirror>(v));
+  v = fmaxf(v, dpp_f32<kDppMirror>(v));
+  v = fmaxf(v, __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F)));
+  const float a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+  const float b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+  return fmaxf(a, b);
+}
+__device__ __forceinline__ float wave_sum_all(float v) {
+  v += dpp_f32<kDppXor1>(v);
+  v += dpp_f32<kDppXor2>(v);
+  v += dpp_f32<kDppHalfMirror>(v);
+  v += dpp_f32<kDppMirror>(v);
+  v += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
+  const float a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+  const float b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+  return a + b;
+}
+
+// (max, sum) merge across the 64 lanes of a wave: DPP inside each row of 16 lanes, then a
+// lane swizzle across rows (xor 16) and a read of lane 32 for the last step.  The result is
+// valid in lane 0.
+__device__ __forceinline__ void wave_lse_merge(float& M, float& S) {
+  float m2 = dpp_f32<kDppXor1>(M), s2 = dpp_f32<kDppXor1>(S);
+  lse_merge(M, S, m2, s2);
+  m2 = dpp_f32<kDppXor2>(M); s2 = dpp_f32<kDppXor2>(S);
+  lse_merge(M, S, m2, s2);
+  m2 = dpp_f32<kDppHalfMirror>(M); s2 = dpp_f32<kDppHalfMirror>(S);
+  lse_merge(M, S, m2, s2);
+  m2 = dpp_f32<kDppMirror>(M); s2 = dpp_f32<kDppMirror>(S);
+  lse_merge(M, S, m2, s2);
+  // xor 16 within each half-wave (ds_swizzle bit mode: and 0x1f, xor 0x10)
+  m2 = __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(M), 0x401F));
+  s2 = __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(S), 0x401F));
+  lse_merge(M, S, m2, s2);
+  m2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(M), 32));
+  s2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(S), 32));
+  lse_merge(M, S, m2, s2);
 }
 
 // Block-wide sum of a double; every thread gets the result.  `scratch` holds >= nwaves

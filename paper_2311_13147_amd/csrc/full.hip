@@ -21,7 +21,8 @@ namespace csot {
 
 constexpr int kFullThreads = 1024;  // 16 waves
 constexpr int kFullWaves = kFullThreads / kWave;
-constexpr int kNC = 1024;           // points per LDS chunk (one per thread)
+constexpr int kNC = 2048;           // points per LDS chunk (two per thread)
+constexpr int kPF = kNC / kFullThreads;
 
 struct FullParams {
   int n, np, W, R, max_iter;
@@ -75,26 +76,38 @@ __device__ __forceinline__ bool full_phase(const FullParams& p, int r0, const fl
   }
   const int nchunks = p.np / kNC;
   bool ok = true;
-  // prefetch chunk 0: coordinates and slot of point tid
-  float4 pc = DIM > 0 ? othc[tid] : make_float4(0.f, 0.f, 0.f, 0.f);
-  uint64_t ps = tid < p.n ? slot_load(oslots + tid) : 0ull;
+  // prefetch chunk 0: coordinates and slots of points tid + k * kFullThreads
+  float4 pc[kPF];
+  uint64_t ps[kPF];
+#pragma unroll
+  for (int k = 0; k < kPF; ++k) {
+    const int J = tid + k * kFullThreads;
+    pc[k] = DIM > 0 ? othc[J] : make_float4(0.f, 0.f, 0.f, 0.f);
+    ps[k] = J < p.n ? slot_load(oslots + J) : 0ull;
+  }
   for (int c = 0; c < nchunks; ++c) {
     float4* cur = buf + (c & 1) * kNC;
-    const int J = c * kNC + tid;
-    if (J < p.n) {
-      if (ok) ok = slot_wait(oslots + J, ps, epoch, p.ctl);
-      pc.w = slot_value(ps);
-    } else {
-      pc.w = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < kPF; ++k) {
+      const int J = c * kNC + tid + k * kFullThreads;
+      if (J < p.n) {
+        if (ok) ok = slot_wait(oslots + J, ps[k], epoch, p.ctl);
+        pc[k].w = slot_value(ps[k]);
+      } else {
+        pc[k].w = -INFINITY;
+      }
+      cur[tid + k * kFullThreads] = pc[k];
     }
-    cur[tid] = pc;
     if (!ok) *s_bad = 1;
     __syncthreads();
     if (*s_bad) return false;
     if (c + 1 < nchunks) {
-      const int Jn = J + kNC;
-      pc = DIM > 0 ? othc[Jn] : make_float4(0.f, 0.f, 0.f, 0.f);
-      ps = Jn < p.n ? slot_load(oslots + Jn) : 0ull;
+#pragma unroll
+      for (int k = 0; k < kPF; ++k) {
+        const int Jn = (c + 1) * kNC + tid + k * kFullThreads;
+        pc[k] = DIM > 0 ? othc[Jn] : make_float4(0.f, 0.f, 0.f, 0.f);
+        ps[k] = Jn < p.n ? slot_load(oslots + Jn) : 0ull;
+      }
     }
 #pragma unroll 1
     for (int u = cq * U; u < (cq + 1) * U; u += TU) {
@@ -138,12 +151,7 @@ __device__ __forceinline__ bool full_phase(const FullParams& p, int r0, const fl
 #pragma unroll
   for (int q = 0; q < RT; ++q) {
     float m_ = M[q], s_ = S[q];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const float m2 = __shfl_xor(m_, o, kWave);
-      const float s2 = __shfl_xor(s_, o, kWave);
-      lse_merge(m_, s_, m2, s2);
-    }
+    wave_lse_merge(m_, s_);
     if (lane == 0) part[(rg * RT + q) * CQ + cq] = make_float2(m_, s_);
   }
   __syncthreads();
@@ -375,15 +383,15 @@ static int cu_count() {
 
 // (RT, CQ) variants: rows per workgroup R = (16 / CQ) * RT
 struct FullVariant { int RT, CQ; };
-static constexpr FullVariant kVariants[] = {{8, 2}, {8, 4}, {4, 4}, {4, 8}, {2, 8}, {1, 8}, {1, 16}};
+static constexpr FullVariant kVariants[] = {{4, 1}, {4, 2}, {4, 4}, {4, 8}, {2, 8}, {1, 8}, {1, 16}};
 
 template <int DIM, int RT, int CQ>
 static const void* fk() { return (const void*)full_solver_kernel<DIM, RT, CQ>; }
 
 static const void* pick_full_kernel(int dim, int RT, int CQ) {
 #define CSOT_FK(D)                                                    \
-  if (RT == 8 && CQ == 2) return fk<D, 8, 2>();                       \
-  if (RT == 8 && CQ == 4) return fk<D, 8, 4>();                       \
+  if (RT == 4 && CQ == 1) return fk<D, 4, 1>();                       \
+  if (RT == 4 && CQ == 2) return fk<D, 4, 2>();                       \
   if (RT == 4 && CQ == 4) return fk<D, 4, 4>();                       \
   if (RT == 4 && CQ == 8) return fk<D, 4, 8>();                       \
   if (RT == 2 && CQ == 8) return fk<D, 2, 8>();                       \

@@ -28,8 +28,10 @@
 
 namespace csot {
 
-constexpr int kRedThreads = 256;
+constexpr int kRedThreads = 1024;        // 16 waves; one row (column) per wave at a time
+constexpr int kRedWaves = kRedThreads / kWave;
 constexpr int kMaxLds = 150 * 1024;
+constexpr int kSweep = 4 * kWave * 2;    // elements per register sweep (two float4 per lane)
 
 struct RedParams {
   int m, mp, K, W, R, max_iter, warm;
@@ -44,31 +46,36 @@ struct RedParams {
   float* g_out;
   uint64_t* fx;    // [m] F exchange slots
   uint64_t* gx;    // [m] G exchange slots
-  uint64_t* rsx;   // [W] residual-partial slots
-  uint32_t* ctl;   // [1] abort flag
+  uint64_t* rsx;   // [2][W] residual-partial slots, double-buffered by iteration parity
+  uint32_t* ctl;   // [0] abort flag
   double* dstats;
 };
 
-// LSE2 over a padded LDS row (length mp, a multiple of 4*LPR) plus `vec`, computed by a group
-// of LPR lanes: exact maximum first, then the shifted sum.
-template <int LPR>
-__device__ __forceinline__ float group_lse2(const float* __restrict__ row,
-                                            const float* __restrict__ vec, int mp, int gl) {
-  float M = kNegBig;
-  for (int q = gl * 4; q < mp; q += 4 * LPR) {
-    const float4 l = *reinterpret_cast<const float4*>(row + q);
-    const float4 v = *reinterpret_cast<const float4*>(vec + q);
-    M = fmaxf(M, fmaxf(fmaxf(l.x + v.x, l.y + v.y), fmaxf(l.z + v.z, l.w + v.w)));
+// LSE2 over a padded LDS row (length mp, a multiple of kSweep) plus `vec`, by one wave: each
+// lane keeps its 8 values of a sweep in registers, the exact sweep maximum and the shifted sum
+// are reduced with DPP, and sweeps are merged online.  Every lane returns the result.
+__device__ __forceinline__ float wave_lse2(const float* __restrict__ row,
+                                           const float* __restrict__ vec, int mp, int lane) {
+  float M = kNegBig, S = 0.0f;
+  for (int base = 0; base < mp; base += kSweep) {
+    const int q0 = base + 4 * lane, q1 = q0 + 4 * kWave;
+    const float4 l0 = *reinterpret_cast<const float4*>(row + q0);
+    const float4 v0 = *reinterpret_cast<const float4*>(vec + q0);
+    const float4 l1 = *reinterpret_cast<const float4*>(row + q1);
+    const float4 v1 = *reinterpret_cast<const float4*>(vec + q1);
+    const float t[8] = {l0.x + v0.x, l0.y + v0.y, l0.z + v0.z, l0.w + v0.w,
+                        l1.x + v1.x, l1.y + v1.y, l1.z + v1.z, l1.w + v1.w};
+    float mx = fmaxf(fmaxf(fmaxf(t[0], t[1]), fmaxf(t[2], t[3])),
+                     fmaxf(fmaxf(t[4], t[5]), fmaxf(t[6], t[7])));
+    mx = wave_max_all(mx);
+    const float Mn = fmaxf(M, mx);
+    float s = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s += exp2_fast(t[k] - Mn);
+    s = wave_sum_all(s);
+    S = S * exp2_fast(M - Mn) + s;
+    M = Mn;
   }
-  M = group_max(M, LPR);
-  float S = 0.0f;
-  for (int q = gl * 4; q < mp; q += 4 * LPR) {
-    const float4 l = *reinterpret_cast<const float4*>(row + q);
-    const float4 v = *reinterpret_cast<const float4*>(vec + q);
-    S += exp2_fast(l.x + v.x - M) + exp2_fast(l.y + v.y - M) + exp2_fast(l.z + v.z - M) +
-         exp2_fast(l.w + v.w - M);
-  }
-  S = group_sum(S, LPR);
   return M + log2_fast(S);
 }
 
@@ -77,9 +84,10 @@ __device__ __forceinline__ float group_lse2(const float* __restrict__ row,
 // loads first and then waits on the ones not yet current, so both sets cost one round trip.
 // Returns false on abort.
 __device__ __forceinline__ bool stage_slots(uint64_t* src, int m, int mp, uint32_t epoch,
-                                            float* Vs, uint64_t* extra, int nextra, float* xv,
-                                            uint32_t* abort_flag, int* s_bad) {
-  constexpr int kB = 4;
+                                            float* Vs, uint64_t* extra, int nextra,
+                                            uint32_t xepoch, float* xv, uint32_t* abort_flag,
+                                            int* s_bad) {
+  constexpr int kB = 2;
   bool ok = true;
   const int total = mp + nextra;
   for (int base = threadIdx.x; base < total; base += kB * kRedThreads) {
@@ -99,7 +107,7 @@ __device__ __forceinline__ bool stage_slots(uint64_t* src, int m, int mp, uint32
       } else if (j < mp) {
         Vs[j] = 0.0f;
       } else if (j < total) {
-        if (ok) ok = slot_wait(extra + (j - mp), w[u], epoch, abort_flag);
+        if (ok) ok = slot_wait(extra + (j - mp), w[u], xepoch, abort_flag);
         xv[j - mp] = slot_value(w[u]);
       }
     }
@@ -109,7 +117,6 @@ __device__ __forceinline__ bool stage_slots(uint64_t* src, int m, int mp, uint32
   return *s_bad == 0;
 }
 
-template <int LPR>
 __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p) {
   extern __shared__ float4 lds4[];
   float* lds = reinterpret_cast<float*>(lds4);
@@ -119,11 +126,13 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
   float* Vs = LTs + (size_t)R * mp;     // [mp] staged potential
   float* la2 = Vs + mp;                 // [R] log2 alpha (my rows)
   float* lb2 = la2 + R;                 // [R] log2 beta (my columns)
-  float* Fcur = lb2 + R;                // [R]
-  float* Fprev = Fcur + R;              // [R]
-  float* Gcur = Fprev + R;              // [R]
-  float* rsv = Gcur + R;                // [W] residual partials of every workgroup
-  double* red = reinterpret_cast<double*>(rsv + p.W + ((5 * R + p.W) & 1));  // [8]
+  float* av = lb2 + R;                  // [R] alpha (my rows)
+  float* Fcur = av + R;                 // [R] F^t
+  float* Fprev = Fcur + R;              // [R] F^{t-1}
+  float* Gcur = Fprev + R;              // [R] G^t
+  float* Gprev = Gcur + R;              // [R] G^{t-1}
+  float* rsv = Gprev + R;               // [W] residual partials of every workgroup
+  __shared__ float wsum[kRedWaves];
   __shared__ int s_bad;
   __shared__ int s_stop;
 
@@ -132,6 +141,8 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
   const int r0 = w * R;
   const int nr = max(0, min(R, m - r0));  // rows (= columns) this workgroup owns
   const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wv = tid / kWave;
   uint32_t* abort_flag = p.ctl;
 
   // ---- load the slabs (once) ------------------------------------------------------------
@@ -149,7 +160,9 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
     const bool ok = rl < nr;
     la2[rl] = ok ? log2f(p.alpha[r0 + rl]) : 0.0f;
     lb2[rl] = ok ? log2f(p.beta[r0 + rl]) : 0.0f;
+    av[rl] = ok ? p.alpha[r0 + rl] : 0.0f;
     Gcur[rl] = ok && p.warm ? p.g_out[r0 + rl] * p.s2 : 0.0f;
+    Gprev[rl] = Gcur[rl];
     Fcur[rl] = 0.0f;
     Fprev[rl] = 0.0f;
   }
@@ -158,80 +171,88 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
   if (tid == 0) s_bad = 0;
   __syncthreads();
 
-  const int lane = tid & (kWave - 1);
-  const int gl = lane % LPR;             // lane within its group
-  const int grp = tid / LPR;             // group index in the block
-  const int ngrp = kRedThreads / LPR;
   int iters_done = 0, converged = 0, flags = 0;
-  double err2 = 0.0;
+  float err2 = 0.0f;
 
+  // Iteration t: row update (F^t from G^{t-1}, residual of the state after t-1 as a by-product),
+  // exchange of F^t, column update (G^t), exchange of G^t together with the residual partials
+  // of iteration t, stop test on the state after t-1 (returned as Fprev, Gprev).
   for (uint32_t t = 1;; ++t) {
-    // ---- row update: F^t from G^{t-1} (in Vs) -------------------------------------------
-    double rpart = 0.0;
-    for (int rl = grp; rl < nr; rl += ngrp) {
-      const float lse = group_lse2<LPR>(Ls + (size_t)rl * mp, Vs, mp, gl);
-      const float Fn = la2[rl] - lse;
-      if (gl == 0) {
+    // ---- row update ----------------------------------------------------------------------
+    float racc = 0.0f;
+    for (int rl = wv; rl < nr; rl += kRedWaves) {
+      const float Fn = la2[rl] - wave_lse2(Ls + (size_t)rl * mp, Vs, mp, lane);
+      if (lane == 0) {
         if (t >= 2) {
-          const float rr = p.alpha[r0 + rl] * expm1f((Fcur[rl] - Fn) * kLn2);
-          rpart += (double)rr * (double)rr;
+          const float rr = av[rl] * expm1f((Fcur[rl] - Fn) * kLn2);
+          racc += rr * rr;
         }
         Fprev[rl] = Fcur[rl];
         Fcur[rl] = Fn;
         slot_publish(p.fx + r0 + rl, Fn, t);
       }
     }
-    const double rtot = block_sum_d(rpart, red);
-    if (tid == 0) slot_publish(p.rsx + w, (float)rtot, t);
+    if (lane == 0) wsum[wv] = racc;
+    __syncthreads();  // every wave is done with Vs (G^{t-1}) and wrote its residual part
+    if (tid == 0) {
+      float s = 0.0f;
+      for (int k = 0; k < kRedWaves; ++k) s += wsum[k];
+      slot_publish(p.rsx + (t & 1u) * p.W + w, s, t);
+    }
 
-    // ---- gather F^t and the residual partials; stop test on the state after t-1 ----------
-    if (!stage_slots(p.fx, m, mp, t, Vs, p.rsx, p.W, rsv, abort_flag, &s_bad)) {
+    // ---- exchange F^t, column update -------------------------------------------------------
+    if (!stage_slots(p.fx, m, mp, t, Vs, nullptr, 0, 0, nullptr, abort_flag, &s_bad)) {
       flags |= 2;
       break;
     }
-    if (tid == 0) {
-      int stop = 0;
-      if (t >= 2) {
-        double s = 0.0;
-        for (int v = 0; v < p.W; ++v) s += (double)rsv[v];
-        err2 = s;
-        const bool fin = s == s && s < 1.0e300;
-        converged = fin && s <= p.tol2;
-        // tol = 0 asks for exactly max_iter iterations, even if the residual underflows to 0
-        stop = (converged && p.tol2 > 0.0) || !fin || (int)(t - 1) >= p.max_iter;
-        if (!fin) flags |= 1;
-      }
-      s_stop = stop;
-    }
-    __syncthreads();
-    if (s_stop) { iters_done = (int)t - 1; break; }
-
-    // ---- column update: G^t from F^t -----------------------------------------------------
-    for (int cl = grp; cl < nr; cl += ngrp) {
-      const float lse = group_lse2<LPR>(LTs + (size_t)cl * mp, Vs, mp, gl);
-      const float Gn = lb2[cl] - lse;
-      if (gl == 0) {
+    for (int cl = wv; cl < nr; cl += kRedWaves) {
+      const float Gn = lb2[cl] - wave_lse2(LTs + (size_t)cl * mp, Vs, mp, lane);
+      if (lane == 0) {
+        Gprev[cl] = Gcur[cl];
         Gcur[cl] = Gn;
         slot_publish(p.gx + r0 + cl, Gn, t);
       }
     }
     __syncthreads();  // everyone is done reading Vs (F^t)
-    if (!stage_slots(p.gx, m, mp, t, Vs, nullptr, 0, nullptr, abort_flag, &s_bad)) {
+
+    // ---- exchange G^t and the residual partials of iteration t; stop test --------------------
+    const int nres = t >= 2 ? p.W : 0;
+    // A workgroup that is one iteration ahead may already publish its next residual partial
+    // while this one still polls; the parity buffers keep the two apart.
+    if (!stage_slots(p.gx, m, mp, t, Vs, p.rsx + (t & 1u) * p.W, nres, t, rsv, abort_flag,
+                     &s_bad)) {
       flags |= 2;
       break;
     }
+    if (t >= 2) {
+      if (wv == 0) {  // fixed-order reduction: every workgroup gets the same sum
+        float s = 0.0f;
+        for (int v = lane; v < p.W; v += kWave) s += rsv[v];
+        s = wave_sum_all(s);
+        if (lane == 0) {
+          err2 = s;
+          const bool fin = s == s && s < 3.0e38f;
+          converged = fin && (double)s <= p.tol2;
+          // tol = 0 asks for exactly max_iter iterations, even if the residual underflows
+          s_stop = (converged && p.tol2 > 0.0) || !fin || (int)(t - 1) >= p.max_iter;
+          if (!fin) flags |= 1;
+        }
+      }
+      __syncthreads();
+      if (s_stop) { iters_done = (int)t - 1; break; }
+    }
   }
 
-  // ---- outputs: the state after iteration iters_done ------------------------------------
+  // ---- outputs: the state after iteration iters_done = (F^{t-1}, G^{t-1}) ---------------
   __syncthreads();
   for (int rl = tid; rl < nr; rl += blockDim.x) {
     p.f_out[r0 + rl] = Fprev[rl] * p.to_nat;
-    p.g_out[r0 + rl] = Gcur[rl] * p.to_nat;
+    p.g_out[r0 + rl] = Gprev[rl] * p.to_nat;
   }
   if (w == 0 && tid == 0) {
     p.dstats[0] = (double)iters_done;
     p.dstats[1] = (double)converged;
-    p.dstats[4] = sqrt((double)p.K * err2);
+    p.dstats[4] = sqrt((double)p.K * (double)err2);
     p.dstats[5] = (double)flags;
   } else if (tid == 0 && flags) {
     p.dstats[5] = (double)flags;
@@ -311,20 +332,10 @@ static int device_cu_count() {
 }
 
 static size_t reduced_lds_bytes(int R, int mp, int W) {
-  return sizeof(float) * ((size_t)2 * R * mp + mp + 5 * (size_t)R + W + 1) + 8 * sizeof(double) + 16;
+  return sizeof(float) * ((size_t)2 * R * mp + mp + 8 * (size_t)R + W) + 16;
 }
 
-static int pick_lpr(int R) { return R <= 4 ? 64 : R <= 8 ? 32 : 16; }
-
-static const void* reduced_kernel_ptr(int lpr) {
-  switch (lpr) {
-    case 64: return (const void*)reduced_solver_kernel<64>;
-    case 32: return (const void*)reduced_solver_kernel<32>;
-    default: return (const void*)reduced_solver_kernel<16>;
-  }
-}
-
-static int reduced_mp(int m) { return (m + 63) / 64 * 64; }
+static int reduced_mp(int m) { return (m + kSweep - 1) / kSweep * kSweep; }
 
 bool plan_reduced(int m, int hint, ReducedPlan* plan) {
   const int cus = device_cu_count();
@@ -332,8 +343,9 @@ bool plan_reduced(int m, int hint, ReducedPlan* plan) {
   const int mp = reduced_mp(m);
   int W = hint;
   if (W <= 0) {
-    // about 16 rows per workgroup, at most one workgroup per CU
-    W = (m + 15) / 16;
+    // about 8 rows per workgroup, at most one workgroup per CU (measured best at m = 512:
+    // more, smaller workgroups shorten each phase more than they lengthen the exchange)
+    W = (m + 7) / 8;
     if (W < 1) W = 1;
     if (W > cus) W = cus;
   }
@@ -348,20 +360,17 @@ bool plan_reduced(int m, int hint, ReducedPlan* plan) {
     lds = reduced_lds_bytes(R, mp, W);
   }
   if (lds > (size_t)kMaxLds) return false;
-  const int lpr = pick_lpr(R);
-  const void* k = reduced_kernel_ptr(lpr);
-  static bool attr_set[3] = {false, false, false};
-  const int ai = lpr == 64 ? 0 : lpr == 32 ? 1 : 2;
-  if (!attr_set[ai]) {
-    if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds) != hipSuccess)
+  static bool attr_set = false;
+  if (!attr_set) {
+    if (hipFuncSetAttribute((const void*)reduced_solver_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds) != hipSuccess)
       return false;
-    attr_set[ai] = true;
+    attr_set = true;
   }
   // co-residency: the cooperative launch needs all W workgroups resident at once
   int per_cu = 0;
-  hipError_t e = lpr == 64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reduced_solver_kernel<64>, kRedThreads, lds)
-               : lpr == 32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reduced_solver_kernel<32>, kRedThreads, lds)
-                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reduced_solver_kernel<16>, kRedThreads, lds);
+  const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu, reduced_solver_kernel, kRedThreads, lds);
   // keep every workgroup on one XCD (blocks are dealt to the 8 XCDs round-robin) when the
   // placeholder blocks still fit in one co-resident grid: polls then stay within one L2
   const int stride = (8 * W <= cus && cus % 8 == 0) ? 8 : 1;
@@ -379,7 +388,7 @@ static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
 static size_t slots_bytes(int m, int W) {
   return align256(256) + 2 * align256(sizeof(uint64_t) * reduced_mp(m)) +
-         align256(sizeof(uint64_t) * W);
+         align256(sizeof(uint64_t) * 2 * W);
 }
 
 size_t reduced_ws_bytes(int m, const ReducedPlan& p) {
@@ -397,7 +406,7 @@ hipError_t launch_sinkhorn_reduced(int m, int K, double eps, const float* logK,
   size_t off = align256(256);
   uint64_t* fx = reinterpret_cast<uint64_t*>(base + off); off += align256(sizeof(uint64_t) * mp);
   uint64_t* gx = reinterpret_cast<uint64_t*>(base + off); off += align256(sizeof(uint64_t) * mp);
-  uint64_t* rsx = reinterpret_cast<uint64_t*>(base + off); off += align256(sizeof(uint64_t) * pl.W);
+  uint64_t* rsx = reinterpret_cast<uint64_t*>(base + off); off += align256(sizeof(uint64_t) * 2 * pl.W);
   double* part = reinterpret_cast<double*>(base + off);
 
   // epochs start at 1, so zeroed slots are never mistaken for current ones
@@ -413,7 +422,7 @@ hipError_t launch_sinkhorn_reduced(int m, int K, double eps, const float* logK,
   p.logK = logK; p.alpha = alpha; p.beta = beta; p.f_out = f; p.g_out = g;
   p.fx = fx; p.gx = gx; p.rsx = rsx; p.ctl = ctl; p.dstats = dstats;
   void* args[] = {&p};
-  e = hipLaunchCooperativeKernel(reduced_kernel_ptr(pick_lpr(pl.R)), dim3(pl.W * pl.stride),
+  e = hipLaunchCooperativeKernel((const void*)reduced_solver_kernel, dim3(pl.W * pl.stride),
                                  dim3(pl.threads), args, (unsigned)pl.lds, s);
   if (e != hipSuccess) return e;
 
