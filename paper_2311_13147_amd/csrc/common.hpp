@@ -183,10 +183,19 @@ __device__ __forceinline__ uint64_t slot_load(uint64_t* slot) {
 }
 
 // Wait until `w` (already loaded from `slot`) carries `epoch`; returns false on abort.
+// Polls are pipelined: the next load is issued before the previous one is examined, so a
+// new poll leaves every half round trip instead of every full one.
 __device__ __forceinline__ bool slot_wait(uint64_t* slot, uint64_t& w, uint32_t epoch,
                                           uint32_t* abort_flag) {
+  if ((uint32_t)(w >> 32) == epoch) return true;
   uint32_t spins = 0;
-  while ((uint32_t)(w >> 32) != epoch) {
+  uint64_t next = slot_load(slot);
+  for (;;) {
+    __builtin_amdgcn_s_sleep(2);
+    const uint64_t after = slot_load(slot);
+    w = next;
+    if ((uint32_t)(w >> 32) == epoch) return true;
+    next = after;
     if (++spins >= kSpinLimit) {
       __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return false;
@@ -194,10 +203,15 @@ __device__ __forceinline__ bool slot_wait(uint64_t* slot, uint64_t& w, uint32_t 
     if ((spins & 63u) == 0 &&
         __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u)
       return false;
-    __builtin_amdgcn_s_sleep(1);
-    w = slot_load(slot);
   }
-  return true;
+}
+
+// alpha * (2^d - 1), accurate also for tiny d (series below 2^-5, exp2 otherwise).
+__device__ __forceinline__ float scaled_exp2m1(float alpha, float d) {
+  const float u = d * kLn2;
+  if (fabsf(d) < 0.03125f)
+    return alpha * u * (1.0f + u * (0.5f + u * (0.16666667f + u * (0.041666668f + u * 0.008333334f))));
+  return alpha * (exp2_fast(d) - 1.0f);
 }
 
 __device__ __forceinline__ float slot_value(uint64_t w) {

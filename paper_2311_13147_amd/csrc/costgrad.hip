@@ -1,29 +1,36 @@
-// Objective values and gradients of entropic OT from the (converged) dual potentials.
+// Objective values, gradients and float64 marginal checks from dual potentials.
 //
 // Values (full problem; for reduced potentials the sums over (i, j, k) are multiplied by K,
 // the 1/K identity of eq. problem_CROT):
 //   P = sum T (C + eps (Z - 1)),  Z = (f + g - C) / eps,  T = exp(Z)   -- the primal of eq.
 //       problem_ROT with the entropic regulariser evaluated without forming log T;
 //   D = <f, a> + <g, b> - eps sum T                                    -- eq. dual_problem_cyclic_ROT;
-//   <C, T>, sum T and the L2 marginal errors (row / column sums accumulated in float64).
+//   <C, T>, sum T and the L2 marginal errors.
 // Gradients (envelope theorem on the dual; exact at the optimum):
 //   dC = T;  da = f - mean(f);  db = g - mean(g);
 //   dx_I = 2 sum_J T_IJ (x_I - y_J);  dy_J = 2 sum_I T_IJ (y_J - x_I).
-// With reduced potentials T_IJ is the expanded plan, T[r m + i, c m + j] = T_{ij,(c-r) mod K},
-// whose cost is block-row 0's; the gradient weights use the actual coordinates of I and J.
+// With reduced potentials T_IJ is the expanded plan, T[r m + i, c m + j] = T_{ij,(c-r) mod K}
+// (Lemma 1), whose cost is block-row 0's; the gradient weights use the actual coordinates.
 //
-// Per-term arithmetic is float32 (one exponential per entry); scalar sums are float64.
+// Everything is organised as "passes": a wave owns four points of one side (rows for the row
+// pass, columns for the column pass) and its lanes stride over all points of the other side,
+// so every sum over the other side is a register accumulation plus one wave reduction -- no
+// atomics.  For reduced potentials the other side is walked block by block, so the cyclic
+// block index (c - r) mod K is computed once per block, not per entry.  Per-term arithmetic is
+// float32 with one exponential per entry; sums of squares and scalars are float64.  The
+// float64 marginal checks of the solvers use the same passes with float64 exponentials.
 #include "common.hpp"
 #include "launch.hpp"
 
 namespace csot {
 
-constexpr int kCgTJ = 64;
-constexpr int kCgTI = 4;
+constexpr int kPassThreads = 256;
+constexpr int kPassRT = 4;  // own points per wave
+constexpr int kPassPts = kPassThreads / kWave * kPassRT;
 
 template <int DIM>
-__device__ __forceinline__ float cost_pts(const float* __restrict__ x, int I,
-                                          const float* __restrict__ y, int J) {
+__device__ __forceinline__ float pt_cost_f(const float* __restrict__ x, int I,
+                                           const float* __restrict__ y, int J) {
   float c = 0.0f;
 #pragma unroll
   for (int d = 0; d < DIM; ++d) {
@@ -33,137 +40,216 @@ __device__ __forceinline__ float cost_pts(const float* __restrict__ x, int I,
   return c;
 }
 
-// ---- values, dC, row / column sums ------------------------------------------------------
-// reduced: thread (i, j) of block k = blockIdx.z (cost of block-row 0);
-// full:    thread (I, J), blockIdx.z == 0.
-template <int DIM, bool RED>
-__global__ void __launch_bounds__(kCgTJ* kCgTI)
-    values_kernel(Geom g, const float* __restrict__ f, const float* __restrict__ gp, float s2,
-                  float eps, float* __restrict__ dC, int64_t lddc,
-                  double* __restrict__ part, double* __restrict__ rowsum,
-                  double* __restrict__ colsum) {
-  __shared__ double red[8];
-  __shared__ double cacc[kCgTI][kCgTJ];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int N = RED ? g.m : g.n;
-  const int j = blockIdx.x * kCgTJ + lane;
-  const int i = blockIdx.y * kCgTI + wv;
-  const int k = blockIdx.z;
-  double P = 0.0, CT = 0.0, mass = 0.0, T64 = 0.0;
-  if (i < N && j < N) {
-    float c;
-    if constexpr (RED) {
-      if constexpr (DIM == 0) c = g.C[(int64_t)i * g.ldc + (int64_t)k * g.m + j];
-      else c = cost_pts<DIM>(g.x, i, g.y, k * g.m + j);
-    } else {
-      if constexpr (DIM == 0) c = g.C[(int64_t)i * g.ldc + j];
-      else c = cost_pts<DIM>(g.x, i, g.y, j);
+struct PassOut {
+  double* sums;   // [own points] sum over the other side of T (row or column sums)
+  double* part;   // [blocks][3] P, <C,T>, mass partials (row pass) or nullptr
+  float* grad;    // [own points, DIM] 2 sum T (own - other), or nullptr
+  float* dC;      // full: [n, lddc] (row pass only); reduced: [K, m, m] or nullptr
+  int64_t lddc;
+};
+
+// One pass in float32 (values / gradients).  ROW: own = rows I (x), other = columns J (y).
+// RED: potentials f, g have length m and the cost is block-row 0's.  `own_count` limits the
+// own points (m when only block 0 is needed, n otherwise).
+template <int DIM, bool RED, bool ROW>
+__global__ void __launch_bounds__(kPassThreads)
+    pass_kernel(Geom g, const float* __restrict__ f, const float* __restrict__ gp, float s2,
+                float eps, int own_count, PassOut out) {
+  __shared__ double red[kPassThreads / kWave][3];
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const int a0 = (blockIdx.x * (kPassThreads / kWave) + wv) * kPassRT;
+  const float* ownp = ROW ? g.x : g.y;
+  const float* othp = ROW ? g.y : g.x;
+  float po[kPassRT][DIM > 0 ? DIM : 1];
+  float pot[kPassRT];
+  int ab[kPassRT], ai[kPassRT], ax[kPassRT];  // block, in-block and clamped global index
+  float tsum[kPassRT], gacc[kPassRT][DIM > 0 ? DIM : 1];
+  float vP[kPassRT], vC[kPassRT];
+#pragma unroll
+  for (int q = 0; q < kPassRT; ++q) {
+    const int A = min(a0 + q, own_count - 1);
+    ax[q] = A;
+    ab[q] = A / g.m;
+    ai[q] = A - ab[q] * g.m;
+    if constexpr (DIM > 0) {
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) po[q][d] = ownp[(int64_t)A * DIM + d];
     }
-    const float fg = f[i] + gp[j];
-    const float z = (fg - c) / eps;
-    const float T = exp2_fast((fg - c) * s2);
-    P = (double)(T * (c + eps * (z - 1.0f)));
-    CT = (double)(T * c);
-    mass = (double)T;
-    T64 = (double)T;
-    if (dC) {
-      if constexpr (RED) dC[((int64_t)k * g.m + i) * g.m + j] = T;
-      else dC[(int64_t)i * lddc + j] = T;
+    pot[q] = RED ? (ROW ? f[ai[q]] : gp[ai[q]]) : (ROW ? f[A] : gp[A]);
+    tsum[q] = 0.0f;
+    vP[q] = 0.0f;
+    vC[q] = 0.0f;
+#pragma unroll
+    for (int d = 0; d < (DIM > 0 ? DIM : 1); ++d) gacc[q][d] = 0.0f;
+  }
+  const int nblk = RED ? g.K : 1;
+  const int bl = RED ? g.m : g.n;
+  for (int cb = 0; cb < nblk; ++cb) {
+    int kk[kPassRT];
+#pragma unroll
+    for (int q = 0; q < kPassRT; ++q) {
+      // block of the cost: ROW: (c - r) mod K with c = cb, r = own block; COL: (own c - r)
+      int k = ROW ? cb - ab[q] : ab[q] - cb;
+      kk[q] = k < 0 ? k + g.K : k;
+    }
+    for (int b = lane; b < bl; b += kWave) {
+      const int B = cb * bl + b;  // other point (global index)
+      float pb[DIM > 0 ? DIM : 1];
+      if constexpr (DIM > 0) {
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) pb[d] = othp[(int64_t)B * DIM + d];
+      }
+      const float opot = RED ? (ROW ? gp[b] : f[b]) : (ROW ? gp[B] : f[B]);
+#pragma unroll
+      for (int q = 0; q < kPassRT; ++q) {
+        float c;
+        if constexpr (RED) {
+          // block-row 0 cost between point i (row) and point k m + j (column)
+          const int i = ROW ? ai[q] : b;
+          const int j = ROW ? b : ai[q];
+          if constexpr (DIM == 0) c = g.C[(int64_t)i * g.ldc + (int64_t)kk[q] * g.m + j];
+          else c = pt_cost_f<DIM>(g.x, i, g.y, kk[q] * g.m + j);
+        } else {
+          if constexpr (DIM == 0) {
+            const int I = ROW ? ax[q] : B, J = ROW ? B : ax[q];
+            c = g.C[(int64_t)I * g.ldc + J];
+          } else {
+            c = 0.0f;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+              const float df = po[q][d] - pb[d];
+              c = fmaf(df, df, c);
+            }
+          }
+        }
+        const float fg = pot[q] + opot;
+        const float T = exp2_fast((fg - c) * s2);
+        tsum[q] += T;
+        if constexpr (ROW) {
+          const float z = (fg - c) / eps;
+          vP[q] = fmaf(T, c + eps * (z - 1.0f), vP[q]);
+          vC[q] = fmaf(T, c, vC[q]);
+          if (out.dC && a0 + q < own_count) {
+            if constexpr (RED) {
+              if (ab[q] == 0) out.dC[((int64_t)kk[q] * g.m + ai[q]) * g.m + b] = T;
+            } else {
+              out.dC[(int64_t)(a0 + q) * out.lddc + B] = T;
+            }
+          }
+        }
+        if constexpr (DIM > 0) {
+          if (out.grad) {
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) gacc[q][d] = fmaf(T, po[q][d] - pb[d], gacc[q][d]);
+          }
+        }
+      }
     }
   }
-  // row sums: reduce across the wave; column sums: across the 4 waves
-  const double rs = wave_sum_d(T64);
-  if (lane == 0 && i < N) atomicAdd(&rowsum[i], rs);
-  cacc[wv][lane] = T64;
-  __syncthreads();
-  if (wv == 0 && j < N)
-    atomicAdd(&colsum[j], cacc[0][lane] + cacc[1][lane] + cacc[2][lane] + cacc[3][lane]);
-  P = block_sum_d(P, red);
-  CT = block_sum_d(CT, red);
-  mass = block_sum_d(mass, red);
-  if (threadIdx.x == 0) {
-    const int64_t b = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-    part[3 * b + 0] = P;
-    part[3 * b + 1] = CT;
-    part[3 * b + 2] = mass;
+  double bp = 0.0, bc = 0.0, bm = 0.0;
+#pragma unroll
+  for (int q = 0; q < kPassRT; ++q) {
+    const bool ok = a0 + q < own_count;
+    const double ts = wave_sum_d((double)tsum[q]);
+    if (ROW) {
+      const double P = wave_sum_d((double)vP[q]);
+      const double C = wave_sum_d((double)vC[q]);
+      if (ok) { bp += P; bc += C; bm += ts; }
+    }
+    if (lane == 0 && ok) out.sums[a0 + q] = ts;
+    if constexpr (DIM > 0) {
+      if (out.grad) {
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+          const float v = wave_sum(gacc[q][d]);
+          if (lane == 0 && ok) out.grad[(int64_t)(a0 + q) * DIM + d] = 2.0f * v;
+        }
+      }
+    }
+  }
+  if (ROW && out.part) {
+    if (lane == 0) { red[wv][0] = bp; red[wv][1] = bc; red[wv][2] = bm; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double P = 0, C = 0, M = 0;
+      for (int w = 0; w < kPassThreads / kWave; ++w) { P += red[w][0]; C += red[w][1]; M += red[w][2]; }
+      out.part[3 * blockIdx.x + 0] = P;
+      out.part[3 * blockIdx.x + 1] = C;
+      out.part[3 * blockIdx.x + 2] = M;
+    }
   }
 }
 
-// ---- coordinate gradients -----------------------------------------------------------------
-// Each wave owns 4 points of the "own" side (x for dx, y for dy); lanes stride over the other
-// side.  OWN_X: own = x (rows I), other = y (columns J); else own = y, other = x.
-template <int DIM, bool RED, bool OWN_X>
-__global__ void __launch_bounds__(256)
-    coord_grad_kernel(Geom g, const float* __restrict__ f, const float* __restrict__ gp,
-                      float s2, float* __restrict__ out) {
-  constexpr int RT = 4;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int own0 = (blockIdx.x * 4 + wv) * RT;
-  const float* ownp = OWN_X ? g.x : g.y;
-  const float* othp = OWN_X ? g.y : g.x;
-  float acc[RT][DIM];
-  float po[RT][DIM];
-#pragma unroll
-  for (int q = 0; q < RT; ++q) {
-    const int A = min(own0 + q, g.n - 1);
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      acc[q][d] = 0.0f;
-      po[q][d] = ownp[(int64_t)A * DIM + d];
-    }
-  }
-  for (int B = lane; B < g.n; B += 64) {
-    float pb[DIM];
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) pb[d] = othp[(int64_t)B * DIM + d];
-#pragma unroll
-    for (int q = 0; q < RT; ++q) {
-      const int A = min(own0 + q, g.n - 1);
-      const int I = OWN_X ? A : B;  // row index of the plan entry
-      const int J = OWN_X ? B : A;  // column index
-      float c, fg;
-      if constexpr (RED) {
-        const int r = I / g.m, i = I - r * g.m, cb = J / g.m, j = J - cb * g.m;
-        int kk = cb - r;
-        if (kk < 0) kk += g.K;
-        c = cost_pts<DIM>(g.x, i, g.y, kk * g.m + j);
-        fg = f[i] + gp[j];
+// float64 marginal sums.  MODE 0: reduced, exponent logK_ij + (f_i + g_j)/eps over [0, m);
+// MODE 1: full from coordinates (DIM) or dense C, exponent (f_I + g_J - C_IJ)/eps.
+template <int MODE, int DIM, bool ROW>
+__global__ void __launch_bounds__(kPassThreads)
+    check_pass_kernel(Geom g, const float* __restrict__ logK, const float* __restrict__ f,
+                      const float* __restrict__ gp, int N, double* __restrict__ sums) {
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const int a = blockIdx.x * (kPassThreads / kWave) + wv;
+  if (a >= N) return;
+  const double ie = 1.0 / g.eps;
+  const double pa = ROW ? (double)f[a] : (double)gp[a];
+  double s = 0.0;
+  for (int b = lane; b < N; b += kWave) {
+    const double pb = ROW ? (double)gp[b] : (double)f[b];
+    const int I = ROW ? a : b, J = ROW ? b : a;
+    double z;
+    if constexpr (MODE == 0) {
+      z = (double)logK[(int64_t)I * N + J] + (pa + pb) * ie;
+    } else {
+      double c;
+      if constexpr (DIM == 0) {
+        c = (double)g.C[(int64_t)I * g.ldc + J];
       } else {
-        c = 0.0f;
+        c = 0.0;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
-          const float df = po[q][d] - pb[d];
-          c = fmaf(df, df, c);
+          const double df = (double)g.x[(int64_t)I * DIM + d] - (double)g.y[(int64_t)J * DIM + d];
+          c += df * df;
         }
-        fg = f[I] + gp[J];
       }
-      const float T = exp2_fast((fg - c) * s2);
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) acc[q][d] = fmaf(T, po[q][d] - pb[d], acc[q][d]);
+      z = (pa + pb - c) * ie;
     }
+    s += exp(z);
   }
-#pragma unroll
-  for (int q = 0; q < RT; ++q) {
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-      const float v = wave_sum(acc[q][d]);
-      if (lane == 0 && own0 + q < g.n) out[(int64_t)(own0 + q) * DIM + d] = 2.0f * v;
-    }
+  s = wave_sum_d(s);
+  if (lane == 0) sums[a] = s;
+}
+
+// norms of (rowsum - ra), (colsum - rb) over N entries; `scale` (K for reduced sums) turns
+// them into full-space norms.
+__global__ void __launch_bounds__(256)
+    check_finalize_kernel(int N, double scale, const double* __restrict__ rowsum,
+                          const double* __restrict__ colsum, const float* __restrict__ ra,
+                          const float* __restrict__ rb, double* __restrict__ dstats) {
+  __shared__ double red[8];
+  double er = 0.0, ec = 0.0;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    const double dr = rowsum[i] - (double)ra[i], dc = colsum[i] - (double)rb[i];
+    er += dr * dr;
+    ec += dc * dc;
+  }
+  er = block_sum_d(er, red);
+  ec = block_sum_d(ec, red);
+  if (threadIdx.x == 0) {
+    dstats[2] = sqrt(scale * er);
+    dstats[3] = sqrt(scale * ec);
   }
 }
 
 // ---- finalize: scalars, marginal errors, da / db ----------------------------------------
 __global__ void __launch_bounds__(256)
-    finalize_kernel(Geom g, int red_mode, const float* __restrict__ f,
-                    const float* __restrict__ gp, const double* __restrict__ part,
-                    int64_t nparts, const double* __restrict__ rowsum,
-                    const double* __restrict__ colsum, double* __restrict__ out,
-                    float* __restrict__ da, float* __restrict__ db) {
+    finalize_kernel(Geom g, int red_mode, double scale, const float* __restrict__ f,
+                    const float* __restrict__ gp, const double* __restrict__ part, int nparts,
+                    const double* __restrict__ rowsum, const double* __restrict__ colsum,
+                    double* __restrict__ out, float* __restrict__ da, float* __restrict__ db) {
   __shared__ double red[8];
   const int N = red_mode ? g.m : g.n;
-  const double scale = red_mode ? (double)g.K : 1.0;
+  const double K = red_mode ? (double)g.K : 1.0;
   double P = 0.0, CT = 0.0, mass = 0.0;
-  for (int64_t b = threadIdx.x; b < nparts; b += blockDim.x) {
+  for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
     P += part[3 * b];
     CT += part[3 * b + 1];
     mass += part[3 * b + 2];
@@ -203,10 +289,10 @@ __global__ void __launch_bounds__(256)
   gs = block_sum_d(gs, red);
   if (threadIdx.x == 0) {
     out[0] = scale * P;
-    out[1] = scale * (fa + gb) - g.eps * scale * mass;
+    out[1] = K * (fa + gb) - g.eps * scale * mass;
     out[2] = scale * CT;
-    out[3] = sqrt(scale * er);
-    out[4] = sqrt(scale * ec);
+    out[3] = sqrt(K * er);
+    out[4] = sqrt(K * ec);
     out[5] = scale * mass;
     out[6] = 0.0;
     out[7] = 0.0;
@@ -219,70 +305,97 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-__global__ void zero_d_kernel(double* p, int64_t count) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
-       i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = 0.0;
-}
-
 // ---- host ------------------------------------------------------------------------------
 static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
-static int64_t values_blocks(const Geom& g, int reduced, dim3* grid) {
-  const int N = reduced ? g.m : g.n;
-  *grid = dim3((N + kCgTJ - 1) / kCgTJ, (N + kCgTI - 1) / kCgTI, reduced ? g.K : 1);
-  return (int64_t)grid->x * grid->y * grid->z;
-}
+static int pass_blocks(int count) { return (count + kPassPts - 1) / kPassPts; }
 
 size_t costgrad_ws_bytes(const Geom& g) {
-  dim3 gr;
-  const int64_t nb = values_blocks(g, 0, &gr);
-  const int64_t nbr = values_blocks(g, 1, &gr);
-  const int64_t nmax = nb > nbr ? nb : nbr;
-  return 2 * align256(sizeof(double) * g.n) + align256(sizeof(double) * 3 * nmax);
+  return 2 * align256(sizeof(double) * g.n) + align256(sizeof(double) * 3 * pass_blocks(g.n));
+}
+
+template <int DIM>
+static hipError_t launch_passes(const Geom& g, const float* f, const float* gp, int reduced,
+                                float s2, float eps, int rows, int cols, PassOut ro,
+                                PassOut co, hipStream_t s) {
+  if (reduced) {
+    hipLaunchKernelGGL((pass_kernel<DIM, true, true>), dim3(pass_blocks(rows)),
+                       dim3(kPassThreads), 0, s, g, f, gp, s2, eps, rows, ro);
+    hipLaunchKernelGGL((pass_kernel<DIM, true, false>), dim3(pass_blocks(cols)),
+                       dim3(kPassThreads), 0, s, g, f, gp, s2, eps, cols, co);
+  } else {
+    hipLaunchKernelGGL((pass_kernel<DIM, false, true>), dim3(pass_blocks(rows)),
+                       dim3(kPassThreads), 0, s, g, f, gp, s2, eps, rows, ro);
+    hipLaunchKernelGGL((pass_kernel<DIM, false, false>), dim3(pass_blocks(cols)),
+                       dim3(kPassThreads), 0, s, g, f, gp, s2, eps, cols, co);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_cost_and_grad(const Geom& g, const float* f, const float* gp, int reduced,
                                 double* out, float* dC, int64_t lddc, float* dx, float* dy,
                                 float* da, float* db, void* ws, hipStream_t s) {
   char* base = static_cast<char*>(ws);
-  const int N = reduced ? g.m : g.n;
   double* rowsum = reinterpret_cast<double*>(base);
   double* colsum = reinterpret_cast<double*>(base + align256(sizeof(double) * g.n));
   double* part = reinterpret_cast<double*>(base + 2 * align256(sizeof(double) * g.n));
-  hipLaunchKernelGGL(zero_d_kernel, dim3(32), dim3(256), 0, s, rowsum,
-                     (int64_t)(2 * align256(sizeof(double) * g.n) / sizeof(double)));
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  dim3 grid;
-  const int64_t nparts = values_blocks(g, reduced, &grid);
+  // Reduced potentials: the values need block 0 only (K m^2 terms, scaled by K); the
+  // coordinate gradients need every point (n^2 terms, exact sums, scale 1).
+  const bool all_rows = !reduced || dx != nullptr;
+  const bool all_cols = !reduced || dy != nullptr;
+  const int rows = all_rows ? g.n : g.m;
+  const int cols = all_cols ? g.n : g.m;
+  const double scale = (reduced && !all_rows) ? (double)g.K : 1.0;
+  PassOut ro{rowsum, part, dx, dC, lddc};
+  PassOut co{colsum, nullptr, dy, nullptr, 0};
   const float s2 = (float)(kLog2eD / g.eps);
-  const float epsf = (float)g.eps;
-#define CSOT_VAL(D)                                                                             \
-  if (reduced) hipLaunchKernelGGL((values_kernel<D, true>), grid, dim3(256), 0, s, g, f, gp, s2, epsf, dC, lddc, part, rowsum, colsum); \
-  else hipLaunchKernelGGL((values_kernel<D, false>), grid, dim3(256), 0, s, g, f, gp, s2, epsf, dC, lddc, part, rowsum, colsum);
+  const float eps = (float)g.eps;
+  hipError_t e;
   switch (g.dim) {
-    case 0: CSOT_VAL(0) break;
-    case 2: CSOT_VAL(2) break;
-    case 3: CSOT_VAL(3) break;
+    case 0: e = launch_passes<0>(g, f, gp, reduced, s2, eps, rows, cols, ro, co, s); break;
+    case 2: e = launch_passes<2>(g, f, gp, reduced, s2, eps, rows, cols, ro, co, s); break;
+    case 3: e = launch_passes<3>(g, f, gp, reduced, s2, eps, rows, cols, ro, co, s); break;
     default: return hipErrorInvalidValue;
   }
-#undef CSOT_VAL
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  (void)N;
-  if (g.dim > 0 && (dx || dy)) {
-    const dim3 gg((g.n + 15) / 16);
-#define CSOT_GR(D)                                                                                      \
-  if (dx) { if (reduced) hipLaunchKernelGGL((coord_grad_kernel<D, true, true>), gg, dim3(256), 0, s, g, f, gp, s2, dx); \
-            else hipLaunchKernelGGL((coord_grad_kernel<D, false, true>), gg, dim3(256), 0, s, g, f, gp, s2, dx); } \
-  if (dy) { if (reduced) hipLaunchKernelGGL((coord_grad_kernel<D, true, false>), gg, dim3(256), 0, s, g, f, gp, s2, dy); \
-            else hipLaunchKernelGGL((coord_grad_kernel<D, false, false>), gg, dim3(256), 0, s, g, f, gp, s2, dy); }
-    if (g.dim == 2) { CSOT_GR(2) } else { CSOT_GR(3) }
-#undef CSOT_GR
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, g, reduced, scale, f, gp, part,
+                     pass_blocks(rows), rowsum, colsum, out, da, db);
+  return hipGetLastError();
+}
+
+// float64 marginal check used by the solvers.  reduced: potentials [m], logK, folded
+// marginals ra, rb [m]; full: potentials [n], cost from g, ra = a, rb = b.  `sums` holds
+// 2 N doubles of scratch.
+hipError_t launch_check(const Geom& g, int reduced, const float* logK, const float* f,
+                        const float* gp, const float* ra, const float* rb, double* sums,
+                        double* dstats, hipStream_t s) {
+  const int N = reduced ? g.m : g.n;
+  double* rowsum = sums;
+  double* colsum = sums + N;
+  const dim3 grid((N + kPassThreads / kWave - 1) / (kPassThreads / kWave));
+  const dim3 blk(kPassThreads);
+  if (reduced) {
+    hipLaunchKernelGGL((check_pass_kernel<0, 2, true>), grid, blk, 0, s, g, logK, f, gp, N, rowsum);
+    hipLaunchKernelGGL((check_pass_kernel<0, 2, false>), grid, blk, 0, s, g, logK, f, gp, N, colsum);
+  } else {
+    switch (g.dim) {
+      case 0:
+        hipLaunchKernelGGL((check_pass_kernel<1, 0, true>), grid, blk, 0, s, g, logK, f, gp, N, rowsum);
+        hipLaunchKernelGGL((check_pass_kernel<1, 0, false>), grid, blk, 0, s, g, logK, f, gp, N, colsum);
+        break;
+      case 2:
+        hipLaunchKernelGGL((check_pass_kernel<1, 2, true>), grid, blk, 0, s, g, logK, f, gp, N, rowsum);
+        hipLaunchKernelGGL((check_pass_kernel<1, 2, false>), grid, blk, 0, s, g, logK, f, gp, N, colsum);
+        break;
+      case 3:
+        hipLaunchKernelGGL((check_pass_kernel<1, 3, true>), grid, blk, 0, s, g, logK, f, gp, N, rowsum);
+        hipLaunchKernelGGL((check_pass_kernel<1, 3, false>), grid, blk, 0, s, g, logK, f, gp, N, colsum);
+        break;
+      default: return hipErrorInvalidValue;
+    }
   }
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, g, reduced, f, gp, part, nparts,
-                     rowsum, colsum, out, da, db);
+  hipLaunchKernelGGL(check_finalize_kernel, dim3(1), dim3(256), 0, s, N,
+                     reduced ? (double)g.K : 1.0, rowsum, colsum, ra, rb, dstats);
   return hipGetLastError();
 }
 

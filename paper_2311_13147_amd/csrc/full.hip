@@ -299,78 +299,6 @@ __global__ void transpose_kernel(const float* __restrict__ C, int64_t ldc, float
   }
 }
 
-// ---- float64 marginal check of the full plan ------------------------------------------
-// Tile of 32 rows x 64 columns per block; row and column partial sums go to double
-// accumulators with atomics; the last block forms the two norms.
-template <int DIM>
-__global__ void __launch_bounds__(256)
-    full_check_kernel(Geom g, const float* __restrict__ f, const float* __restrict__ gp,
-                      double* __restrict__ dstats, double* __restrict__ rowsum,
-                      double* __restrict__ colsum, uint32_t* __restrict__ counter, int ntiles) {
-  __shared__ double cpart[4][64];
-  __shared__ double red[8];
-  __shared__ int s_last;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int J = blockIdx.x * 64 + lane;
-  const int I0 = blockIdx.y * 32;
-  const double ie = 1.0 / g.eps;
-  double csum = 0.0;
-  const double gJ = J < g.n ? (double)gp[J] : 0.0;
-  for (int q = 0; q < 8; ++q) {
-    const int I = I0 + wv + 4 * q;
-    double v = 0.0;
-    if (I < g.n && J < g.n) {
-      double c;
-      if constexpr (DIM == 0) {
-        c = (double)g.C[(int64_t)I * g.ldc + J];
-      } else {
-        c = 0.0;
-        for (int d = 0; d < DIM; ++d) {
-          const double df = (double)g.x[(int64_t)I * DIM + d] - (double)g.y[(int64_t)J * DIM + d];
-          c += df * df;
-        }
-      }
-      v = exp(((double)f[I] + gJ - c) * ie);
-    }
-    csum += v;
-    const double rs = wave_sum_d(v);
-    if (lane == 0 && I < g.n) atomicAdd(&rowsum[I], rs);
-  }
-  cpart[wv][lane] = csum;
-  __syncthreads();
-  if (wv == 0 && J < g.n)
-    atomicAdd(&colsum[J], cpart[0][lane] + cpart[1][lane] + cpart[2][lane] + cpart[3][lane]);
-  // the last block to finish forms the two norms
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const uint32_t prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    s_last = prev == (uint32_t)ntiles - 1;
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  double er = 0.0, ec = 0.0;
-  for (int I = threadIdx.x; I < g.n; I += blockDim.x) {
-    const double dr = __hip_atomic_load(&rowsum[I], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - (double)g.a[I];
-    const double dc = __hip_atomic_load(&colsum[I], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - (double)g.b[I];
-    er += dr * dr;
-    ec += dc * dc;
-  }
-  er = block_sum_d(er, red);
-  ec = block_sum_d(ec, red);
-  if (threadIdx.x == 0) {
-    dstats[2] = sqrt(er);
-    dstats[3] = sqrt(ec);
-  }
-}
-
-__global__ void zero_doubles_kernel(double* p, int64_t count) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
-       i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = 0.0;
-}
-
 // ---- host side -------------------------------------------------------------------------
 static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
@@ -439,11 +367,11 @@ bool plan_full(const Geom& g, int hint, FullPlan* plan) {
 
 static int full_np(int n) { return (n + kNC - 1) / kNC * kNC; }
 
-// workspace: ctl | fx[np] | gx[np] | rsx[W] | xc[np] | yc[np] | rowsum[n] | colsum[n] | CT
+// workspace: ctl | fx[np] | gx[np] | rsx[W] | xc[np] | yc[np] | sums[2n] | CT
 size_t full_ws_bytes(const Geom& g, const FullPlan& pl) {
   const size_t np = (size_t)full_np(g.n);
   size_t b = align256(256) + 2 * align256(sizeof(uint64_t) * np) + align256(sizeof(uint64_t) * pl.W) +
-             2 * align256(sizeof(float4) * np) + 2 * align256(sizeof(double) * g.n);
+             2 * align256(sizeof(float4) * np) + align256(sizeof(double) * 2 * g.n);
   if (g.dim == 0) b += align256(sizeof(float) * (size_t)g.n * np);
   return b;
 }
@@ -461,8 +389,7 @@ hipError_t launch_sinkhorn_full(const Geom& g, float* f, float* gpot, double tol
   const size_t zero_bytes = off;
   float4* xc = reinterpret_cast<float4*>(base + off); off += align256(sizeof(float4) * np);
   float4* yc = reinterpret_cast<float4*>(base + off); off += align256(sizeof(float4) * np);
-  double* rowsum = reinterpret_cast<double*>(base + off); off += align256(sizeof(double) * g.n);
-  double* colsum = reinterpret_cast<double*>(base + off); off += align256(sizeof(double) * g.n);
+  double* sums = reinterpret_cast<double*>(base + off); off += align256(sizeof(double) * 2 * g.n);
   float* CT = reinterpret_cast<float*>(base + off);
 
   hipError_t e = launch_zero_words(ctl, (int)(zero_bytes / 4), s);
@@ -494,18 +421,8 @@ hipError_t launch_sinkhorn_full(const Geom& g, float* f, float* gpot, double tol
   e = hipLaunchCooperativeKernel(k, dim3(pl.W), dim3(kFullThreads), args, 0, s);
   if (e != hipSuccess) return e;
 
-  // float64 check
-  hipLaunchKernelGGL(zero_doubles_kernel, dim3(64), dim3(256), 0, s, rowsum,
-                     (int64_t)(align256(sizeof(double) * g.n) / sizeof(double)) * 2);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  const dim3 grid((g.n + 63) / 64, (g.n + 31) / 32);
-  const int ntiles = grid.x * grid.y;
-  switch (g.dim) {
-    case 0: hipLaunchKernelGGL(full_check_kernel<0>, grid, dim3(256), 0, s, g, f, gpot, dstats, rowsum, colsum, ctl + 8, ntiles); break;
-    case 2: hipLaunchKernelGGL(full_check_kernel<2>, grid, dim3(256), 0, s, g, f, gpot, dstats, rowsum, colsum, ctl + 8, ntiles); break;
-    case 3: hipLaunchKernelGGL(full_check_kernel<3>, grid, dim3(256), 0, s, g, f, gpot, dstats, rowsum, colsum, ctl + 8, ntiles); break;
-  }
-  return hipGetLastError();
+  // float64 check of the returned state
+  return launch_check(g, 0, nullptr, f, gpot, g.a, g.b, sums, dstats, s);
 }
 
 }  // namespace csot

@@ -60,6 +60,9 @@ hipError_t launch_expand(const Geom& g, const float* f, const float* gp, float* 
 
 // ---- costgrad.hip ------------------------------------------------------------------------
 size_t costgrad_ws_bytes(const Geom& g);
+hipError_t launch_check(const Geom& g, int reduced, const float* logK, const float* f,
+                        const float* gp, const float* ra, const float* rb, double* sums,
+                        double* dstats, hipStream_t s);
 hipError_t launch_cost_and_grad(const Geom& g, const float* f, const float* gp, int reduced,
                                 double* out, float* dC, int64_t lddc, float* dx, float* dy,
                                 float* da, float* db, void* ws, hipStream_t s);

@@ -131,7 +131,8 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
   float* Fprev = Fcur + R;              // [R] F^{t-1}
   float* Gcur = Fprev + R;              // [R] G^t
   float* Gprev = Gcur + R;              // [R] G^{t-1}
-  float* rsv = Gprev + R;               // [W] residual partials of every workgroup
+  float* Fold = Gprev + R;              // [R] F^{t-2} while the stop test of t-1 runs
+  float* rsv = Fold + R;                // [W] residual partials of every workgroup
   __shared__ float wsum[kRedWaves];
   __shared__ int s_bad;
   __shared__ int s_stop;
@@ -165,6 +166,7 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
     Gprev[rl] = Gcur[rl];
     Fcur[rl] = 0.0f;
     Fprev[rl] = 0.0f;
+    Fold[rl] = 0.0f;
   }
   for (int j = tid; j < mp; j += blockDim.x)
     Vs[j] = (j < m && p.warm) ? p.g_out[j] * p.s2 : 0.0f;
@@ -174,9 +176,10 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
   int iters_done = 0, converged = 0, flags = 0;
   float err2 = 0.0f;
 
-  // Iteration t: row update (F^t from G^{t-1}, residual of the state after t-1 as a by-product),
-  // exchange of F^t, column update (G^t), exchange of G^t together with the residual partials
-  // of iteration t, stop test on the state after t-1 (returned as Fprev, Gprev).
+  // Iteration t: row update (F^t from G^{t-1}; the residual of the state after t-1 falls out
+  // of it), publication of F^t, then the stop test on the state after t-2 whose residual
+  // partials arrived with G^{t-1} (so it never delays a publication), exchange of F^t, column
+  // update (G^t), exchange of G^t together with the residual partials of iteration t.
   for (uint32_t t = 1;; ++t) {
     // ---- row update ----------------------------------------------------------------------
     float racc = 0.0f;
@@ -184,9 +187,10 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
       const float Fn = la2[rl] - wave_lse2(Ls + (size_t)rl * mp, Vs, mp, lane);
       if (lane == 0) {
         if (t >= 2) {
-          const float rr = av[rl] * expm1f((Fcur[rl] - Fn) * kLn2);
+          const float rr = scaled_exp2m1(av[rl], Fcur[rl] - Fn);
           racc += rr * rr;
         }
+        Fold[rl] = Fprev[rl];
         Fprev[rl] = Fcur[rl];
         Fcur[rl] = Fn;
         slot_publish(p.fx + r0 + rl, Fn, t);
@@ -198,6 +202,25 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
       float s = 0.0f;
       for (int k = 0; k < kRedWaves; ++k) s += wsum[k];
       slot_publish(p.rsx + (t & 1u) * p.W + w, s, t);
+    }
+
+    // ---- stop test on the state after iteration t-2 (its residual came with G^{t-1}) -------
+    if (t >= 3) {
+      if (wv == 0) {  // fixed-order reduction: every workgroup gets the same sum
+        float s = 0.0f;
+        for (int v = lane; v < p.W; v += kWave) s += rsv[v];
+        s = wave_sum_all(s);
+        if (lane == 0) {
+          err2 = s;
+          const bool fin = s == s && s < 3.0e38f;
+          converged = fin && (double)s <= p.tol2;
+          // tol = 0 asks for exactly max_iter iterations, even if the residual underflows
+          s_stop = (converged && p.tol2 > 0.0) || !fin || (int)(t - 2) >= p.max_iter;
+          if (!fin) flags |= 1;
+        }
+      }
+      __syncthreads();
+      if (s_stop) { iters_done = (int)t - 2; break; }
     }
 
     // ---- exchange F^t, column update -------------------------------------------------------
@@ -215,38 +238,23 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
     }
     __syncthreads();  // everyone is done reading Vs (F^t)
 
-    // ---- exchange G^t and the residual partials of iteration t; stop test --------------------
-    const int nres = t >= 2 ? p.W : 0;
+    // ---- exchange G^t and the residual partials of iteration t -------------------------------
     // A workgroup that is one iteration ahead may already publish its next residual partial
     // while this one still polls; the parity buffers keep the two apart.
+    const int nres = t >= 2 ? p.W : 0;
     if (!stage_slots(p.gx, m, mp, t, Vs, p.rsx + (t & 1u) * p.W, nres, t, rsv, abort_flag,
                      &s_bad)) {
       flags |= 2;
       break;
     }
-    if (t >= 2) {
-      if (wv == 0) {  // fixed-order reduction: every workgroup gets the same sum
-        float s = 0.0f;
-        for (int v = lane; v < p.W; v += kWave) s += rsv[v];
-        s = wave_sum_all(s);
-        if (lane == 0) {
-          err2 = s;
-          const bool fin = s == s && s < 3.0e38f;
-          converged = fin && (double)s <= p.tol2;
-          // tol = 0 asks for exactly max_iter iterations, even if the residual underflows
-          s_stop = (converged && p.tol2 > 0.0) || !fin || (int)(t - 1) >= p.max_iter;
-          if (!fin) flags |= 1;
-        }
-      }
-      __syncthreads();
-      if (s_stop) { iters_done = (int)t - 1; break; }
-    }
   }
 
-  // ---- outputs: the state after iteration iters_done = (F^{t-1}, G^{t-1}) ---------------
+  // ---- outputs: the state after iteration iters_done = t - 2, i.e. (F^{t-2}, G^{t-2}) -----
+  // At the stop test of iteration t the row update of t has run (Fcur = F^t, Fprev = F^{t-1},
+  // Fold = F^{t-2}) and the column update of t has not (Gcur = G^{t-1}, Gprev = G^{t-2}).
   __syncthreads();
   for (int rl = tid; rl < nr; rl += blockDim.x) {
-    p.f_out[r0 + rl] = Fprev[rl] * p.to_nat;
+    p.f_out[r0 + rl] = Fold[rl] * p.to_nat;
     p.g_out[r0 + rl] = Gprev[rl] * p.to_nat;
   }
   if (w == 0 && tid == 0) {
@@ -256,68 +264,6 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
     p.dstats[5] = (double)flags;
   } else if (tid == 0 && flags) {
     p.dstats[5] = (double)flags;
-  }
-}
-
-// ---- float64 marginal check -------------------------------------------------------------
-// Blocks [0, nrb): four rows each (one wave per row); blocks [nrb, nrb + ncb): 64 columns
-// each (lane = column, four row phases).  The last block to finish sums the partials.
-__global__ void __launch_bounds__(256)
-    reduced_check_kernel(int m, int K, double eps, const float* __restrict__ logK,
-                         const float* __restrict__ f, const float* __restrict__ g,
-                         const float* __restrict__ alpha, const float* __restrict__ beta,
-                         double* __restrict__ part, uint32_t* __restrict__ counter,
-                         double* __restrict__ dstats, int nrb, int ncb) {
-  __shared__ double red[8];
-  __shared__ double colacc[256];
-  __shared__ int s_last;
-  const double ie = 1.0 / eps;
-  double r2 = 0.0;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if ((int)blockIdx.x < nrb) {
-    const int i = blockIdx.x * 4 + wv;
-    if (i < m) {
-      const double fi = f[i];
-      double s = 0.0;
-      for (int j = lane; j < m; j += 64)
-        s += exp((double)logK[(int64_t)i * m + j] + (fi + (double)g[j]) * ie);
-      s = wave_sum_d(s);
-      const double d = s - (double)alpha[i];
-      r2 = lane == 0 ? d * d : 0.0;
-    }
-  } else {
-    const int j = (blockIdx.x - nrb) * 64 + lane;
-    double s = 0.0;
-    if (j < m) {
-      const double gj = g[j];
-      for (int i = wv; i < m; i += 4)
-        s += exp((double)logK[(int64_t)i * m + j] + ((double)f[i] + gj) * ie);
-    }
-    colacc[threadIdx.x] = s;
-    __syncthreads();
-    if (wv == 0 && j < m) {
-      const double c = colacc[lane] + colacc[lane + 64] + colacc[lane + 128] + colacc[lane + 192];
-      const double d = c - (double)beta[j];
-      r2 = d * d;
-    }
-  }
-  const double tot = block_sum_d(r2, red);
-  if (threadIdx.x == 0) {
-    part[blockIdx.x] = tot;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    const uint32_t prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-    s_last = prev == gridDim.x - 1;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  }
-  __syncthreads();
-  if (s_last && threadIdx.x == 0) {
-    double er = 0.0, ec = 0.0;
-    for (int b = 0; b < nrb; ++b) er += __hip_atomic_load(&part[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (int b = nrb; b < nrb + ncb; ++b) ec += __hip_atomic_load(&part[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    dstats[2] = sqrt((double)K * er);
-    dstats[3] = sqrt((double)K * ec);
-    *counter = 0u;
   }
 }
 
@@ -332,7 +278,7 @@ static int device_cu_count() {
 }
 
 static size_t reduced_lds_bytes(int R, int mp, int W) {
-  return sizeof(float) * ((size_t)2 * R * mp + mp + 8 * (size_t)R + W) + 16;
+  return sizeof(float) * ((size_t)2 * R * mp + mp + 9 * (size_t)R + W) + 16;
 }
 
 static int reduced_mp(int m) { return (m + kSweep - 1) / kSweep * kSweep; }
@@ -343,9 +289,9 @@ bool plan_reduced(int m, int hint, ReducedPlan* plan) {
   const int mp = reduced_mp(m);
   int W = hint;
   if (W <= 0) {
-    // about 8 rows per workgroup, at most one workgroup per CU (measured best at m = 512:
-    // more, smaller workgroups shorten each phase more than they lengthen the exchange)
-    W = (m + 7) / 8;
+    // about 16 rows per workgroup (one per wave), at most one workgroup per CU; at m = 512
+    // the 32 workgroups then fit on one XCD
+    W = (m + kRedWaves - 1) / kRedWaves;
     if (W < 1) W = 1;
     if (W > cus) W = cus;
   }
@@ -392,8 +338,7 @@ static size_t slots_bytes(int m, int W) {
 }
 
 size_t reduced_ws_bytes(int m, const ReducedPlan& p) {
-  const int nchk = (m + 3) / 4 + (m + 63) / 64;
-  return slots_bytes(m, p.W) + align256(sizeof(double) * nchk);
+  return slots_bytes(m, p.W) + align256(sizeof(double) * 2 * m);
 }
 
 hipError_t launch_sinkhorn_reduced(int m, int K, double eps, const float* logK,
@@ -426,10 +371,11 @@ hipError_t launch_sinkhorn_reduced(int m, int K, double eps, const float* logK,
                                  dim3(pl.threads), args, (unsigned)pl.lds, s);
   if (e != hipSuccess) return e;
 
-  const int nrb = (m + 3) / 4, ncb = (m + 63) / 64;
-  hipLaunchKernelGGL(reduced_check_kernel, dim3(nrb + ncb), dim3(256), 0, s, m, K, eps, logK,
-                     f, g, alpha, beta, part, ctl + 8, dstats, nrb, ncb);
-  return hipGetLastError();
+  // float64 check of the returned state: full-space row and column errors
+  Geom geo;
+  geo.n = m * K; geo.K = K; geo.m = m; geo.dim = 2; geo.x = geo.y = geo.C = nullptr; geo.ldc = 0;
+  geo.a = alpha; geo.b = beta; geo.eps = eps;
+  return launch_check(geo, 1, logK, f, g, alpha, beta, part, dstats, s);
 }
 
 }  // namespace csot
