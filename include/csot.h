@@ -171,6 +171,59 @@ int ot_cost_and_grad(const ot_problem* prob, const float* f, const float* g, int
                      double* out, float* dC, int64_t lddc, float* dx, float* dy, float* da,
                      float* db, void* ws, size_t ws_bytes, void* stream);
 
+/* One problem of a batch.  The array of descriptors lives in DEVICE memory (all pointers in
+ * it are device pointers); a host copy of the same array is given to ot_batched_plan.
+ *   n, K, dim (2 or 3), eps   as in ot_problem; points and marginals x, y [n, dim], a, b [n];
+ *   tile_cfg   lanes cooperating on one row in the solve (16, 32, 64; 0 = by size) -- the
+ *              value the autotuner picks per size bucket;
+ *   logK       scratch of 2 m^2 + 2 m floats (folded kernel, its transpose, folded marginals);
+ *   f, g [m]   out: reduced potentials (g is also the warm-start input);
+ *   dx, dy [m, dim] out or NULL: gradients of the full objective w.r.t. the first block's
+ *              points, dP/dx_i = 2 sum_{k,j} T_ijk (x_i - y_{km+j}) and
+ *              dP/dy_j = 2 sum_{r,i} T_{ij,(K-r) mod K} (y_j - x_{rm+i}), i, j < m;
+ *   out [8]    out: {P, D, <C,T>, err_row, err_col, iters, converged, flags} of the full
+ *              problem, as ot_cost_and_grad and ot_stats define them. */
+typedef struct ot_batch_desc {
+  int32_t n, K, dim, tile_cfg;
+  double eps;
+  const float* x;
+  const float* y;
+  const float* a;
+  const float* b;
+  float* logK;
+  float* f;
+  float* g;
+  float* dx;
+  float* dy;
+  double* out;
+} ot_batch_desc;
+
+/* Number of int32 entries of a batch plan for `count` problems. */
+size_t ot_batched_plan_len(int32_t count);
+
+/* [host] Plan a batch: the work-queue order (largest problems first) and the tile offsets of
+ * the fold and value kernels.  `host_descs` is a host copy of the descriptor array; `plan`
+ * [host] receives ot_batched_plan_len(count) int32 values that the caller copies to the
+ * device.  Errors: OT_ERR_ARG (bad descriptor), OT_ERR_UNSUPPORTED (too many tiles). */
+int ot_batched_plan(const ot_batch_desc* host_descs, int32_t count, int32_t* plan);
+
+/* Scratch bytes of ot_sinkhorn_reduced_batched for `count` problems. */
+size_t ot_batched_workspace_bytes(int32_t count);
+
+/* Many independent cyclic problems of uneven size (the reduced path of Alg. 2 for each):
+ * fold, cyclic Sinkhorn to tol (each problem stops on its own), objective values, float64
+ * marginal errors and first-block gradients.  Four launches on `stream`: a tiled fold, ONE
+ * persistent solve launch whose workgroups pop problems from a device work queue, a tiled
+ * value/gradient kernel and a per-problem finalize.  No host synchronisation, memset or
+ * allocation, so the call can be captured in a HIP graph.  `plan` is the device copy of
+ * ot_batched_plan's output for the same descriptors; fold_tiles and value_tiles are its first
+ * two entries (plan[0], plan[1]), passed by value so that no device read is needed.  opts:
+ * tol, max_iter, fold_fp64, warm_start are honoured.
+ * Errors: OT_ERR_ARG, OT_ERR_WORKSPACE, OT_ERR_HIP. */
+int ot_sinkhorn_reduced_batched(const ot_batch_desc* descs, int32_t count, const int32_t* plan,
+                                int32_t fold_tiles, int32_t value_tiles, const ot_opts* opts,
+                                void* ws, size_t ws_bytes, void* stream);
+
 /* Message describing the last non-OK return on the calling thread ("" if none). */
 const char* ot_last_error(void);
 

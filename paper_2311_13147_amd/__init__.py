@@ -25,3 +25,4 @@ from ._binding import (  # noqa: F401
     workspace,
 )
 from .autograd import CyclicOT, CyclicOTCost, FullOT  # noqa: F401
+from .batched import Batch, BatchDesc  # noqa: F401

@@ -81,8 +81,9 @@ def _load():
 _lib = _load()
 LIB_PATH = _LIB_PATH
 EXPORTED = ("ot_workspace_bytes", "ot_fold_kernel", "ot_symmetrize_cost", "ot_sinkhorn_reduced",
-            "ot_sinkhorn_full", "ot_expand_plan", "ot_cost_and_grad", "ot_last_error",
-            "ot_version")
+            "ot_sinkhorn_full", "ot_expand_plan", "ot_cost_and_grad", "ot_batched_plan_len",
+            "ot_batched_plan", "ot_batched_workspace_bytes", "ot_sinkhorn_reduced_batched",
+            "ot_last_error", "ot_version")
 
 
 def raw_lib():

@@ -328,4 +328,48 @@ int ot_cost_and_grad(const ot_problem* prob, const float* f, const float* g, int
   return ok();
 }
 
+size_t ot_batched_plan_len(int32_t count) {
+  return count > 0 ? csot::batched_plan_len(count) : 0;
+}
+
+int ot_batched_plan(const ot_batch_desc* h, int32_t count, int32_t* plan) {
+  if (!h || !plan || count <= 0) return fail(OT_ERR_ARG, "descriptors, plan and count > 0 required");
+  for (int p = 0; p < count; ++p) {
+    const ot_batch_desc& d = h[p];
+    if (d.n <= 0 || d.K <= 0 || d.n % d.K != 0)
+      return fail(OT_ERR_ARG, "problem %d: n (%d) must be a positive multiple of K (%d)", p, d.n, d.K);
+    if (d.dim != 2 && d.dim != 3) return fail(OT_ERR_ARG, "problem %d: dim must be 2 or 3", p);
+    if (!(d.eps > 0.0) || !std::isfinite(d.eps)) return fail(OT_ERR_ARG, "problem %d: eps must be > 0", p);
+    if (!d.x || !d.y || !d.a || !d.b || !d.logK || !d.f || !d.g || !d.out)
+      return fail(OT_ERR_ARG, "problem %d: x, y, a, b, logK, f, g and out must be non-NULL", p);
+    if (d.n / d.K > 4096)
+      return fail(OT_ERR_UNSUPPORTED, "problem %d: block size m = %d above 4096", p, d.n / d.K);
+    if (d.tile_cfg != 0 && d.tile_cfg != 16 && d.tile_cfg != 32 && d.tile_cfg != 64)
+      return fail(OT_ERR_ARG, "problem %d: tile_cfg must be 0, 16, 32 or 64", p);
+  }
+  if (csot::batched_plan(h, count, plan) != 0) return fail(OT_ERR_UNSUPPORTED, "too many tiles");
+  return ok();
+}
+
+size_t ot_batched_workspace_bytes(int32_t count) {
+  return count > 0 ? csot::batched_ws_bytes(count) : 0;
+}
+
+int ot_sinkhorn_reduced_batched(const ot_batch_desc* descs, int32_t count, const int32_t* plan,
+                                int32_t fold_tiles, int32_t value_tiles, const ot_opts* opts,
+                                void* ws, size_t ws_bytes, void* stream) {
+  if (!descs || !plan || count <= 0) return fail(OT_ERR_ARG, "descriptors, plan and count > 0 required");
+  ot_opts o = opts ? *opts : defaults();
+  int rc = check_opts(o);
+  if (rc) return rc;
+  if ((rc = check_ws(ws, ws_bytes, csot::batched_ws_bytes(count)))) return rc;
+  const int nfold = fold_tiles, nval = value_tiles;
+  if (nfold < count || nval < 2 * count)
+    return fail(OT_ERR_ARG, "fold_tiles / value_tiles must be plan[0] / plan[1]");
+  hipError_t e = csot::launch_batched(descs, count, plan, nfold, nval, o.tol, o.max_iter,
+                                      o.fold_fp64, o.warm_start, ws, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "batched launch");
+  return ok();
+}
+
 }  // extern "C"

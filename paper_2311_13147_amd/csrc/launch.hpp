@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "csot.h"
+
 namespace csot {
 
 // Geometry of one problem as the kernels see it.
@@ -66,5 +68,13 @@ hipError_t launch_check(const Geom& g, int reduced, const float* logK, const flo
 hipError_t launch_cost_and_grad(const Geom& g, const float* f, const float* gp, int reduced,
                                 double* out, float* dC, int64_t lddc, float* dx, float* dy,
                                 float* da, float* db, void* ws, hipStream_t s);
+
+// ---- batched.hip -------------------------------------------------------------------------
+size_t batched_plan_len(int count);
+int batched_plan(const ot_batch_desc* host_descs, int count, int32_t* plan);
+size_t batched_ws_bytes(int count);
+hipError_t launch_batched(const ot_batch_desc* descs, int count, const int32_t* dplan,
+                          int nfold, int nval, double tol, int max_iter, int fold_fp64,
+                          int warm, void* ws, hipStream_t s);
 
 }  // namespace csot

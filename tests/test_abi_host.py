@@ -120,6 +120,28 @@ def test_workspace_bytes_grows_with_n(B):
     assert lib.ot_workspace_bytes(None, None) == 0
 
 
+def test_batched_plan_validation_and_order(B):
+    from paper_2311_13147_amd.batched import BatchDesc, _lib
+    descs = (BatchDesc * 3)()
+    for d, (n, K) in zip(descs, [(64, 4), (512, 8), (96, 2)]):
+        d.n, d.K, d.dim, d.eps = n, K, 2, 0.1
+        d.x = d.y = d.a = d.b = d.logK = d.f = d.g = d.out = 8
+    plan = (ctypes.c_int32 * _lib.ot_batched_plan_len(3))()
+    assert _lib.ot_batched_plan(descs, 3, plan) == 0
+    order = list(plan[4:7])
+    assert order == [1, 2, 0]              # m = 16, 64, 48: largest first
+    assert list(plan[7:10]) == [0, 1, 5]   # fold tiles: ceil(m/16) = 1, 4, 3
+    assert plan[0] == 8 and plan[1] == 16
+    descs[1].K = 7                          # 512 % 7 != 0
+    assert _lib.ot_batched_plan(descs, 3, plan) == B.OT_ERR_ARG
+    descs[1].K, descs[1].tile_cfg = 8, 24
+    assert _lib.ot_batched_plan(descs, 3, plan) == B.OT_ERR_ARG
+    descs[1].tile_cfg = 0                   # m = 8192 is above the supported 4096
+    descs[1].K = 2
+    descs[1].n = 2 * 8192
+    assert _lib.ot_batched_plan(descs, 3, plan) == B.OT_ERR_UNSUPPORTED
+
+
 def test_binding_requires_device_tensors(B):
     import torch
     with pytest.raises(TypeError):
