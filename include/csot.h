@@ -70,9 +70,9 @@ typedef struct ot_problem {
  *                      current plan is <= tol (the column marginal is exact after each column
  *                      update).  tol = 0 runs exactly max_iter iterations.
  *   max_iter   [10000] >= 1.
- *   fold_fp64  [-1]    fold's log-sum over the K shifts in float64: 1 yes, 0 no, -1 auto
- *                      (float64 when K >= 32; callers that know eps is small relative to the
- *                      cost scale pass 1).
+ *   fold_fp64  [-1]    fold's log-sum over the K shifts in float64: 1 yes, 0 or -1 no.  The
+ *                      float32 fold's error grows with C/eps, not with K, so float64 is for
+ *                      callers that know eps is small relative to the cost scale.
  *   warm_start [0]     1: on entry g holds the initial column potential (natural units).
  *   validate   [0]     1: host-side checks of the marginals and of block-circulance (syncs).
  *   workgroups [0]     persistent solvers: number of cooperating workgroups (0 = automatic).
@@ -176,7 +176,9 @@ int ot_cost_and_grad(const ot_problem* prob, const float* f, const float* g, int
  *   n, K, dim (2 or 3), eps   as in ot_problem; points and marginals x, y [n, dim], a, b [n];
  *   tile_cfg   lanes cooperating on one row in the solve (16, 32, 64; 0 = by size) -- the
  *              value the autotuner picks per size bucket;
- *   logK       scratch of 2 m^2 + 2 m floats (folded kernel, its transpose, folded marginals);
+ *   logK       scratch of 2 m mp + 2 m floats, 16-byte aligned, mp = m rounded up to a
+ *              multiple of 4 (folded kernel and its transpose with padded rows, folded
+ *              marginals);
  *   f, g [m]   out: reduced potentials (g is also the warm-start input);
  *   dx, dy [m, dim] out or NULL: gradients of the full objective w.r.t. the first block's
  *              points, dP/dx_i = 2 sum_{k,j} T_ijk (x_i - y_{km+j}) and

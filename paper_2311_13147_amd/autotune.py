@@ -44,7 +44,8 @@ def _sample_problems(m: int, count: int, rng: np.random.Generator):
     return probs
 
 
-def tune(arch="gfx950", per_bucket=64, buckets=(32, 64, 128, 256, 512, 1024), reps=3, seed=0):
+def tune(arch="gfx950", per_bucket=64, buckets=(32, 64, 128, 256, 512, 1024), reps=3, seed=0,
+         out_dir=None):
     rng = np.random.default_rng(seed)
     table, timings = {}, {}
     opts = B.make_opts(tol=1e-6, max_iter=200)
@@ -67,8 +68,9 @@ def tune(arch="gfx950", per_bucket=64, buckets=(32, 64, 128, 256, 512, 1024), re
             if ms < best_ms:
                 best, best_ms = cfg, ms
         table[size_bucket(mb)] = best
-    os.makedirs(_TUNING_DIR, exist_ok=True)
-    path = os.path.join(_TUNING_DIR, f"{arch}.json")
+    out_dir = out_dir or _TUNING_DIR
+    os.makedirs(out_dir, exist_ok=True)
+    path = os.path.join(out_dir, f"{arch}.json")
     with open(path, "w") as fh:
         json.dump({"arch": arch, "tile_cfg": table, "timings_ms": timings,
                    "per_bucket": per_bucket}, fh, indent=1, sort_keys=True)
@@ -79,5 +81,6 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--arch", default="gfx950")
     ap.add_argument("--per-bucket", type=int, default=64)
+    ap.add_argument("--out-dir", default=None)
     args = ap.parse_args()
-    print(tune(args.arch, args.per_bucket))
+    print(tune(args.arch, args.per_bucket, out_dir=args.out_dir))

@@ -90,7 +90,9 @@ class Batch:
         off = lambda sizes: np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
         oxy = off([n * d for n, d in zip(ns, dims)])
         oab = off(ns)
-        osc = off([2 * m * m + 2 * m for m in ms])
+        # scratch per problem: logK and its transpose with rows padded to mp = m rounded up
+        # to 4 floats, then alpha and beta; each problem's scratch starts 16-byte aligned
+        osc = off([(2 * m * ((m + 3) // 4 * 4) + 2 * m + 3) // 4 * 4 for m in ms])
         ofg = off(ms)
         ogr = off([m * d for m, d in zip(ms, dims)])
         f32 = dict(dtype=torch.float32, device=dev)

@@ -39,8 +39,9 @@ __device__ __forceinline__ int find_problem(const int32_t* __restrict__ start, i
   return lo;
 }
 
-__device__ __forceinline__ float* bscratch_L(const ot_batch_desc& d) { return d.logK; }
 __device__ __forceinline__ int bm(const ot_batch_desc& d) { return d.n / d.K; }
+// scratch rows are padded to a multiple of 4 floats (16-byte aligned float4 loads)
+__device__ __forceinline__ int bmp(int m) { return (m + 3) & ~3; }
 
 template <int DIM, typename Real>
 __device__ __forceinline__ Real bcost(const float* __restrict__ x, int I,
@@ -57,14 +58,18 @@ __device__ __forceinline__ Real bcost(const float* __restrict__ x, int I,
 // ---- 1. fold -------------------------------------------------------------------------------
 template <int DIM>
 __device__ void fold_tile(const ot_batch_desc& d, int i0, int fp64_mode) {
-  const int m = bm(d), K = d.K;
+  const int m = bm(d), K = d.K, mp = bmp(m);
   float* L = d.logK;
-  float* LT = L + (size_t)m * m;
-  const bool fp64 = fp64_mode == 1 || (fp64_mode == -1 && K >= 32);
+  float* LT = L + (size_t)m * mp;
+  const bool fp64 = fp64_mode == 1;
   const double ie = 1.0 / d.eps;
   const int rows = min(kBT, m - i0);
-  for (int e = threadIdx.x; e < rows * m; e += blockDim.x) {
-    const int i = i0 + e / m, j = e - (e / m) * m;
+  for (int e = threadIdx.x; e < rows * mp; e += blockDim.x) {
+    const int i = i0 + e / mp, j = e - (e / mp) * mp;
+    if (j >= m) {  // padding: -inf contributes nothing to a log-sum-exp
+      L[(size_t)i * mp + j] = -INFINITY;
+      continue;
+    }
     float v;
     if (fp64) {
       double cmin = 1.0e300;
@@ -80,11 +85,19 @@ __device__ void fold_tile(const ot_batch_desc& d, int i0, int fp64_mode) {
       for (int k = 0; k < K; ++k) s += exp2_fast((cmin - bcost<DIM, float>(d.x, i, d.y, k * m + j)) * s2);
       v = -cmin * s2 + log2_fast(s);
     }
-    L[(size_t)i * m + j] = v;
-    LT[(size_t)j * m + i] = v;
+    L[(size_t)i * mp + j] = v;
+    LT[(size_t)j * mp + i] = v;
+  }
+  // padding columns of the transpose (rows j < m, columns i in [m, mp)) are written by the
+  // first tile
+  if (i0 == 0) {
+    for (int e = threadIdx.x; e < m * (mp - m); e += blockDim.x) {
+      const int j = e / (mp - m), i = m + e % (mp - m);
+      LT[(size_t)j * mp + i] = -INFINITY;
+    }
   }
   if (i0 == 0) {  // folded marginals
-    float* al = LT + (size_t)m * m;
+    float* al = LT + (size_t)m * mp;
     float* be = al + m;
     for (int i = threadIdx.x; i < 2 * m; i += blockDim.x) {
       const float* v = i < m ? d.a : d.b;
@@ -108,36 +121,59 @@ __global__ void __launch_bounds__(256)
 }
 
 // ---- 2. solve ------------------------------------------------------------------------------
-// LSE2 of (row[j] + vec[j]) over j < m by a group of LPR lanes (every lane gets the result).
+// LSE2 of (row[j] + vec[j]) over j < mp by a group of LPR lanes in ONE pass: each lane keeps
+// a running (max, sum) over its elements (four float4 per step, one rescale per step), then
+// the group merges the pairs.  Rows and vec are 16-byte aligned and padded with -inf / 0 up
+// to mp (a multiple of 4).  Every lane of the group returns the result.
 template <int LPR>
-__device__ __forceinline__ float grp_reduce_max(float v) {
-  v = fmaxf(v, dpp_f32<kDppXor1>(v));
-  v = fmaxf(v, dpp_f32<kDppXor2>(v));
-  v = fmaxf(v, dpp_f32<kDppHalfMirror>(v));
-  v = fmaxf(v, dpp_f32<kDppMirror>(v));
-  if constexpr (LPR >= 32) v = fmaxf(v, __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F)));
-  if constexpr (LPR == 64) v = fmaxf(v, __shfl_xor(v, 32, kWave));
-  return v;
-}
-template <int LPR>
-__device__ __forceinline__ float grp_reduce_sum(float v) {
-  v += dpp_f32<kDppXor1>(v);
-  v += dpp_f32<kDppXor2>(v);
-  v += dpp_f32<kDppHalfMirror>(v);
-  v += dpp_f32<kDppMirror>(v);
-  if constexpr (LPR >= 32) v += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
-  if constexpr (LPR == 64) v += __shfl_xor(v, 32, kWave);
-  return v;
+__device__ __forceinline__ void grp_merge(float& M, float& S) {
+  float m2 = dpp_f32<kDppXor1>(M), s2 = dpp_f32<kDppXor1>(S);
+  lse_merge(M, S, m2, s2);
+  m2 = dpp_f32<kDppXor2>(M); s2 = dpp_f32<kDppXor2>(S);
+  lse_merge(M, S, m2, s2);
+  m2 = dpp_f32<kDppHalfMirror>(M); s2 = dpp_f32<kDppHalfMirror>(S);
+  lse_merge(M, S, m2, s2);
+  m2 = dpp_f32<kDppMirror>(M); s2 = dpp_f32<kDppMirror>(S);
+  lse_merge(M, S, m2, s2);
+  if constexpr (LPR >= 32) {
+    m2 = __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(M), 0x401F));
+    s2 = __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(S), 0x401F));
+    lse_merge(M, S, m2, s2);
+  }
+  if constexpr (LPR == 64) {
+    m2 = __shfl_xor(M, 32, kWave);
+    s2 = __shfl_xor(S, 32, kWave);
+    lse_merge(M, S, m2, s2);
+  }
 }
 
 template <int LPR>
-__device__ __forceinline__ float grp_lse2(const float* row, const float* vec, int m, int gl) {
-  float M = kNegBig;
-  for (int j = gl; j < m; j += LPR) M = fmaxf(M, row[j] + vec[j]);
-  M = grp_reduce_max<LPR>(M);
-  float S = 0.0f;
-  for (int j = gl; j < m; j += LPR) S += exp2_fast(row[j] + vec[j] - M);
-  S = grp_reduce_sum<LPR>(S);
+__device__ __forceinline__ float grp_lse2(const float* row, const float* vec, int mp, int gl) {
+  float M = kNegBig, S = 0.0f;
+  for (int q = 4 * gl; q < mp; q += 16 * LPR) {
+    float t[16];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int qq = q + 4 * LPR * u;
+      if (qq < mp) {
+        const float4 l = *reinterpret_cast<const float4*>(row + qq);
+        const float4 v = *reinterpret_cast<const float4*>(vec + qq);
+        t[4 * u] = l.x + v.x; t[4 * u + 1] = l.y + v.y; t[4 * u + 2] = l.z + v.z; t[4 * u + 3] = l.w + v.w;
+      } else {
+        t[4 * u] = t[4 * u + 1] = t[4 * u + 2] = t[4 * u + 3] = -INFINITY;
+      }
+    }
+    float tm = t[0];
+#pragma unroll
+    for (int k = 1; k < 16; ++k) tm = fmaxf(tm, t[k]);
+    const float Mn = fmaxf(M, tm);
+    float acc = S * exp2_fast(M - Mn);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) acc += exp2_fast(t[k] - Mn);
+    S = acc;
+    M = Mn;
+  }
+  grp_merge<LPR>(M, S);
   return M + log2_fast(S);
 }
 
@@ -154,30 +190,31 @@ struct BSolveArgs {
 template <int LPR>
 __device__ void solve_one(const ot_batch_desc& d, const BSolveArgs& a, float* lds,
                           size_t lds_floats, float* red) {
-  const int m = bm(d), K = d.K;
+  const int m = bm(d), K = d.K, mp = bmp(m);
   const int tid = threadIdx.x, lane = tid & (kWave - 1);
   const int gl = lane % LPR, grp = tid / LPR, ngrp = kBSolveThreads / LPR;
-  // LDS: F, Fprev, G, la2, lb2, al (m each) [+ L, LT when they fit]
+  // LDS: F, Fprev, G (mp each, zero padded), la2, lb2, al (m each) [+ L, LT when they fit]
   float* F = lds;
-  float* Fp = F + m;
-  float* G = Fp + m;
-  float* la2 = G + m;
-  float* lb2 = la2 + m;
-  float* al = lb2 + m;
+  float* Fp = F + mp;
+  float* G = Fp + mp;
+  float* la2 = G + mp;
+  float* lb2 = la2 + mp;
+  float* al = lb2 + mp;
   float* gL = d.logK;
-  float* gLT = gL + (size_t)m * m;
-  const float* galpha = gLT + (size_t)m * m;
+  float* gLT = gL + (size_t)m * mp;
+  const float* galpha = gLT + (size_t)m * mp;
   const float* gbeta = galpha + m;
-  const bool in_lds = (size_t)6 * m + (size_t)2 * m * m <= lds_floats;
+  const bool in_lds = (size_t)6 * mp + (size_t)2 * m * mp <= lds_floats;
   const float* L = gL;
   const float* LT = gLT;
   if (in_lds) {
-    float* Ls = al + m;
-    float* LTs = Ls + (size_t)m * m;
-    for (int e = tid; e < m * m; e += blockDim.x) { Ls[e] = gL[e]; LTs[e] = gLT[e]; }
+    float* Ls = al + mp;
+    float* LTs = Ls + (size_t)m * mp;
+    for (int e = tid; e < m * mp; e += blockDim.x) { Ls[e] = gL[e]; LTs[e] = gLT[e]; }
     L = Ls;
     LT = LTs;
   }
+  for (int i = m + tid; i < mp; i += blockDim.x) { F[i] = 0.0f; G[i] = 0.0f; }
   const float s2 = (float)(kLog2eD / d.eps);
   for (int i = tid; i < m; i += blockDim.x) {
     la2[i] = log2f(galpha[i]);
@@ -194,7 +231,7 @@ __device__ void solve_one(const ot_batch_desc& d, const BSolveArgs& a, float* ld
     // row update F^t from G^{t-1}; residual of the state after t-1
     float racc = 0.0f;
     for (int i = grp; i < m; i += ngrp) {
-      const float Fn = la2[i] - grp_lse2<LPR>(L + (size_t)i * m, G, m, gl);
+      const float Fn = la2[i] - grp_lse2<LPR>(L + (size_t)i * mp, G, mp, gl);
       if (gl == 0) {
         if (t >= 2) {
           const float rr = scaled_exp2m1(al[i], F[i] - Fn);
@@ -222,7 +259,7 @@ __device__ void solve_one(const ot_batch_desc& d, const BSolveArgs& a, float* ld
     __syncthreads();
     // column update G^t from F^t
     for (int j = grp; j < m; j += ngrp) {
-      const float Gn = lb2[j] - grp_lse2<LPR>(LT + (size_t)j * m, F, m, gl);
+      const float Gn = lb2[j] - grp_lse2<LPR>(LT + (size_t)j * mp, F, mp, gl);
       if (gl == 0) G[j] = Gn;
     }
     __syncthreads();
@@ -267,71 +304,108 @@ __global__ void __launch_bounds__(kBSolveThreads) batched_solve_kernel(BSolveArg
 }
 
 // ---- 3. values, gradients and float64 marginal sums ----------------------------------------
-// Tiles [0, nrow) of a problem are row tiles, [nrow, 2 nrow) column tiles (16 points each).
+// Tiles [0, nrow) of a problem are row tiles, [nrow, 2 nrow) column tiles (16 points each: a
+// wave owns 4 points and its lanes stride over the partner points, so one partner load feeds
+// four entries).
 // acc[p]: {P, <C,T>, mass, sum (rowsum - alpha)^2, sum (colsum - beta)^2, <f,alpha>, <g,beta>}
 template <int DIM, bool ROW>
 __device__ void values_tile(const ot_batch_desc& d, int a0, double* __restrict__ acc) {
-  const int m = bm(d), K = d.K;
+  constexpr int Q = 4;
+  const int m = bm(d), K = d.K, mp = bmp(m);
   const float* L = d.logK;
-  const float* LT = L + (size_t)m * m;
-  const float* al = LT + (size_t)m * m;
+  const float* LT = L + (size_t)m * mp;
+  const float* al = LT + (size_t)m * mp;
   const float* be = al + m;
   const float s2 = (float)(kLog2eD / d.eps);
   const float eps = (float)d.eps;
   const double ie = 1.0 / d.eps;
-  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;  // 4 waves x 4 points
-  double vP = 0.0, vC = 0.0, vM = 0.0, v2 = 0.0, vd = 0.0;
-  for (int q = 0; q < 4; ++q) {
-    const int A = a0 + wv * 4 + q;  // own point (row i or column j) in [0, m)
-    if (A >= m) break;
-    float po[DIM];
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const int A0 = a0 + wv * Q;  // first own point of this wave (row i or column j, < m)
+  if (A0 >= m) return;
+  const float* ownp = ROW ? d.x : d.y;
+  const float* othp = ROW ? d.y : d.x;
+  int Aq[Q];
+  float po[Q][DIM], pa[Q], gacc[Q][DIM], tP[Q], tC[Q], tM[Q];
 #pragma unroll
-    for (int dd = 0; dd < DIM; ++dd) po[dd] = (ROW ? d.x : d.y)[(int64_t)A * DIM + dd];
-    const float pa = ROW ? d.f[A] : d.g[A];
-    float gacc[DIM];
+  for (int q = 0; q < Q; ++q) {
+    Aq[q] = min(A0 + q, m - 1);
 #pragma unroll
-    for (int dd = 0; dd < DIM; ++dd) gacc[dd] = 0.0f;
-    float tP = 0.0f, tC = 0.0f, tM = 0.0f;
-    for (int k = 0; k < K; ++k) {
-      // ROW: partner column k m + b (block-row 0); COL: partner row r m + b with r = (K-k)%K
-      const int r = (K - k) % K;
-      for (int b = lane; b < m; b += kWave) {
-        const int i = ROW ? A : b, j = ROW ? b : A;
-        const float c = bcost<DIM, float>(d.x, i, d.y, k * m + j);
-        const float fg = pa + (ROW ? d.g[b] : d.f[b]);
+    for (int dd = 0; dd < DIM; ++dd) { po[q][dd] = ownp[(int64_t)Aq[q] * DIM + dd]; gacc[q][dd] = 0.0f; }
+    pa[q] = ROW ? d.f[Aq[q]] : d.g[Aq[q]];
+    tP[q] = tC[q] = tM[q] = 0.0f;
+  }
+  for (int k = 0; k < K; ++k) {
+    // ROW: partner column k m + b of block-row 0; COL: partner row r m + b, r = (K - k) mod K,
+    // whose entry with column j is T_{b j k}
+    const int r = (K - k) % K;
+    float yk[Q][DIM];  // COL: y_{k m + j} of the own columns j
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int dd = 0; dd < DIM; ++dd) yk[q][dd] = ROW ? 0.0f : d.y[(int64_t)(k * m + Aq[q]) * DIM + dd];
+    for (int b = lane; b < m; b += kWave) {
+      const int P = ROW ? k * m + b : r * m + b;
+      float pp[DIM], cb[DIM];
+#pragma unroll
+      for (int dd = 0; dd < DIM; ++dd) {
+        pp[dd] = othp[(int64_t)P * DIM + dd];
+        // COL: the cost uses block-row 0's row point x_b
+        cb[dd] = ROW ? pp[dd] : d.x[(int64_t)b * DIM + dd];
+      }
+      const float ob = ROW ? d.g[b] : d.f[b];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        float c = 0.0f;
+        if (ROW) {
+#pragma unroll
+          for (int dd = 0; dd < DIM; ++dd) { const float df = po[q][dd] - cb[dd]; c = fmaf(df, df, c); }
+        } else {
+          // C_{b, j, k} = |x_b - y_{k m + j}|^2
+#pragma unroll
+          for (int dd = 0; dd < DIM; ++dd) {
+            const float df = cb[dd] - yk[q][dd];
+            c = fmaf(df, df, c);
+          }
+        }
+        const float fg = pa[q] + ob;
         const float T = exp2_fast((fg - c) * s2);
-        const int P = ROW ? k * m + b : r * m + b;  // partner point for the gradient weight
 #pragma unroll
-        for (int dd = 0; dd < DIM; ++dd)
-          gacc[dd] = fmaf(T, po[dd] - (ROW ? d.y : d.x)[(int64_t)P * DIM + dd], gacc[dd]);
+        for (int dd = 0; dd < DIM; ++dd) gacc[q][dd] = fmaf(T, po[q][dd] - pp[dd], gacc[q][dd]);
         if (ROW) {
           const float z = (fg - c) / eps;
-          tP = fmaf(T, c + eps * (z - 1.0f), tP);
-          tC = fmaf(T, c, tC);
-          tM += T;
+          tP[q] = fmaf(T, c + eps * (z - 1.0f), tP[q]);
+          tC[q] = fmaf(T, c, tC[q]);
+          tM[q] += T;
         }
       }
     }
-    // float64 marginal sum of own point A from logK
+  }
+  double vP = 0.0, vC = 0.0, vM = 0.0, v2 = 0.0, vd = 0.0;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const bool ok = A0 + q < m;
+    // float64 marginal sum of own point from logK (base 2 in the scratch)
     double ms = 0.0;
-    const float* Lrow = (ROW ? L : LT) + (size_t)A * m;
+    const float* Lrow = (ROW ? L : LT) + (size_t)Aq[q] * mp;
     for (int b = lane; b < m; b += kWave)
-      ms += exp((double)Lrow[b] * kLn2D + ((double)pa + (double)(ROW ? d.g[b] : d.f[b])) * ie);
+      ms += exp((double)Lrow[b] * kLn2D + ((double)pa[q] + (double)(ROW ? d.g[b] : d.f[b])) * ie);
     ms = wave_sum_d(ms);
-    const double target = ROW ? (double)al[A] : (double)be[A];
+    const double target = ROW ? (double)al[Aq[q]] : (double)be[Aq[q]];
 #pragma unroll
     for (int dd = 0; dd < DIM; ++dd) {
-      const float gsum = wave_sum(gacc[dd]);
+      const float gsum = wave_sum(gacc[q][dd]);
       float* dst = ROW ? d.dx : d.dy;
-      if (lane == 0 && dst) dst[(int64_t)A * DIM + dd] = 2.0f * gsum;
+      if (lane == 0 && dst && ok) dst[(int64_t)Aq[q] * DIM + dd] = 2.0f * gsum;
     }
     if (ROW) {
-      vP += wave_sum_d((double)tP);
-      vC += wave_sum_d((double)tC);
-      vM += wave_sum_d((double)tM);
+      const double P = wave_sum_d((double)tP[q]), C = wave_sum_d((double)tC[q]),
+                   Ms = wave_sum_d((double)tM[q]);
+      if (ok) { vP += P; vC += C; vM += Ms; }
     }
-    v2 += (ms - target) * (ms - target);
-    vd += (double)pa * target;
+    if (ok) {
+      v2 += (ms - target) * (ms - target);
+      vd += (double)pa[q] * target;
+    }
   }
   if (lane == 0) {
     if (ROW) {
