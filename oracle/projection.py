@@ -42,3 +42,19 @@ def group_average(C, K):
         acc += Pl @ C @ Pl.T
         Pl = P @ Pl
     return acc / K
+
+
+def project_rows_from_points(x, y, K, rows):
+    """Rows ``rows`` (block-row-0 indices i in [0, m)) of the projected cost, as block-row 0:
+    entry ``(i, k m + j) = (1/K) sum_r |x_{r m + i} - y_{((r + k) mod K) m + j}|^2``.  The same
+    average as ``project_blocks`` without forming the n x n cost; shape ``[len(rows), n]``."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    n = x.shape[0]
+    m = n // K
+    out = np.empty((len(rows), n))
+    for t, i in enumerate(rows):
+        Ci = _cost.sq_euclidean(x[i::m][:K], y).reshape(K, K, m)   # [r, block c, j]
+        for k in range(K):
+            out[t, k * m:(k + 1) * m] = np.mean([Ci[r, (r + k) % K] for r in range(K)], axis=0)
+    return out

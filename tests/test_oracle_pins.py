@@ -339,3 +339,14 @@ def test_projection_is_exact_on_symmetric_input():
     blocks = projection.project_blocks(C, p.K)
     Cp = cost.block_circulant_from_blocks(blocks)
     assert np.abs(Cp - C).max() < 1e-6  # float32 coordinates: symmetric up to rounding
+
+
+def test_projection_rows_from_points_equal_group_average():
+    """The row-wise projection from coordinates (used at sizes where the n x n cost is not
+    formed) equals block-row 0 of Lemma 1's permutation average of the full cost."""
+    p = workloads.jittered_problem(60, 5, sigma=0.05, noise=0.1, dim=3, seed=13)
+    x, y = p.x.astype(np.float64), p.y.astype(np.float64)
+    avg = projection.group_average(cost.sq_euclidean(x, y), p.K)
+    rows = [0, 4, 11]
+    got = projection.project_rows_from_points(x, y, p.K, rows)
+    assert np.abs(got - avg[rows]).max() < 1e-13
