@@ -88,8 +88,13 @@ def main():
     prob = csot.Problem(T_(p.a), T_(p.b), p.eps, p.K, x=T_(p.x), y=T_(p.y))
     m = p.m
     o_tol = csot.make_opts(tol=TOL, max_iter=100000, fold_fp64=1)
-    o_fr = csot.make_opts(tol=0.0, max_iter=args.fixed_reduced, fold_fp64=1)
-    o_ff = csot.make_opts(tol=0.0, max_iter=args.fixed_full)
+    # the fixed-count legs also time their solver kernel alone (events recorded by the library
+    # right around that launch, on the stream it runs on)
+    kev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for k in ("red_fixed", "full_fixed")}
+    o_fr = csot.make_opts(tol=0.0, max_iter=args.fixed_reduced, fold_fp64=1,
+                          timing_events=kev["red_fixed"])
+    o_ff = csot.make_opts(tol=0.0, max_iter=args.fixed_full, timing_events=kev["full_fixed"])
     # preallocated outputs (nothing allocated inside the timed region)
     logK = torch.empty((m, m), device=dev)
     al, be = torch.empty(m, device=dev), torch.empty(m, device=dev)
@@ -132,13 +137,21 @@ def main():
                                                         out=(ff2, gf2), dstats=ds[3]))
         return ev
 
+    def kernel_ms():
+        torch.cuda.synchronize()
+        return {k: e[0].elapsed_time(e[1]) for k, e in kev.items()}
+
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    evs = [step(True) for _ in range(args.steps)]
+    evs, kms = [], []
+    for _ in range(args.steps):
+        evs.append(step(True))
+        kms.append(kernel_ms())   # after the step's last launch: no extra sync inside a step
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    kern = {k: sum(d[k] for d in kms) / args.steps for k in kev}
 
     ms = {k: sum(e[k][0].elapsed_time(e[k][1]) for e in evs) / args.steps for k in legs}
     st = [d.cpu().tolist() for d in ds]
@@ -152,10 +165,13 @@ def main():
 
     # roofline of the dominant kernel: the full-size solver (fixed-count leg)
     entries = 2.0 * N * N * args.fixed_full
-    achieved = entries * FLOPS_PER_ENTRY[DIM] / (ms["full_fixed"] * 1e-3) / 1e12
+    achieved = entries * FLOPS_PER_ENTRY[DIM] / (kern["full_fixed"] * 1e-3) / 1e12
     roof = {"bound": "alu", "kernel": "full_solver_kernel", "achieved": round(achieved, 3),
             "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-            "traffic": _traffic("full.hip", 1)}
+            "traffic": _traffic("full.hip", 1),
+            "kernel_ms_per_launch": round(kern["full_fixed"], 4),
+            "flops_per_launch": entries * FLOPS_PER_ENTRY[DIM]}
+    red_kernel_us = kern["red_fixed"] * 1e3 / args.fixed_reduced
 
     out = {
         "metric": "Sinkhorn iters/s & time-to-1e-6 marginal err, reduced vs full, n=8192 K=16",
@@ -174,6 +190,8 @@ def main():
                                f"m={m}, eps={EPS_FACTOR}*median(C), tol={TOL}",
                    "n": N, "K": K, "m": m, "dim": DIM, "eps": p.eps, "seed": SEED},
         "reduced_iters_per_s": round(red_ips, 1),
+        "reduced_kernel_us_per_iter": round(red_kernel_us, 3),
+        "full_kernel_us_per_iter": round(kern["full_fixed"] * 1e3 / args.fixed_full, 3),
         "full_iters_per_s": round(full_ips, 1),
         "iter_speedup": round(red_ips / full_ips, 2),
         "time_to_tol_ms": {"reduced_fold_plus_solve": round(ttt_red, 4),

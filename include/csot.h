@@ -76,6 +76,11 @@ typedef struct ot_problem {
  *   warm_start [0]     1: on entry g holds the initial column potential (natural units).
  *   validate   [0]     1: host-side checks of the marginals and of block-circulance (syncs).
  *   workgroups [0]     persistent solvers: number of cooperating workgroups (0 = automatic).
+ *   timing_events [NULL]  host pointer to two hipEvent_t owned by the caller.  The persistent
+ *                      solver calls (ot_sinkhorn_reduced, ot_sinkhorn_full) record the first on
+ *                      the stream immediately before their solver kernel and the second right
+ *                      after it, so the elapsed time between them is that kernel alone (no
+ *                      set-up or float64 check kernels).  Other calls ignore it.
  */
 typedef struct ot_opts {
   double tol;
@@ -84,7 +89,8 @@ typedef struct ot_opts {
   int32_t warm_start;
   int32_t validate;
   int32_t workgroups;
-  int32_t reserved[3];
+  int32_t reserved;      /* must be 0 */
+  void* timing_events;   /* hipEvent_t[2] or NULL */
 } ot_opts;
 
 /* [host] statistics of a solve.  err_row / err_col are recomputed in float64 on the GPU from
@@ -100,7 +106,9 @@ typedef struct ot_stats {
 } ot_stats;
 
 /* Device-side statistics: solvers write OT_DSTATS_LEN doubles to `dstats` (device) in the
- * layout {iters, converged, err_row, err_col, err_row32, flags, 0, 0}. */
+ * layout {iters, converged, err_row, err_col, err_row32, flags, redo, 0}.  redo (full-size
+ * solver only, else 0) counts the half-iterations of the first workgroup whose shifted
+ * log-sum-exp had to be recomputed with a running maximum. */
 #define OT_DSTATS_LEN 8
 
 /* Bytes of scratch space any call below needs for this problem and these options. */

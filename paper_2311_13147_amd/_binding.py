@@ -42,7 +42,7 @@ class OtOpts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("fold_fp64", ctypes.c_int32), ("warm_start", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("workgroups", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("reserved", ctypes.c_int32), ("timing_events", ctypes.c_void_p)]
 
 
 class OtStats(ctypes.Structure):
@@ -149,9 +149,22 @@ class Problem:
         return ctypes.byref(self._c)
 
 
-def make_opts(tol=1e-6, max_iter=10000, fold_fp64=-1, warm_start=0, validate=0, workgroups=0):
-    return OtOpts(float(tol), int(max_iter), int(fold_fp64), int(warm_start), int(validate),
-                  int(workgroups))
+def make_opts(tol=1e-6, max_iter=10000, fold_fp64=-1, warm_start=0, validate=0, workgroups=0,
+              timing_events=None):
+    """Solver options.  timing_events: a pair of torch.cuda.Event(enable_timing=True) that the
+    persistent solver calls record right around their solver kernel (elapsed_time between
+    them is that kernel alone)."""
+    o = OtOpts(float(tol), int(max_iter), int(fold_fp64), int(warm_start), int(validate),
+               int(workgroups), 0, None)
+    if timing_events is not None:
+        e0, e1 = timing_events
+        for e in (e0, e1):           # torch creates the native event on first record
+            if not e.cuda_event:
+                e.record()
+        arr = (ctypes.c_void_p * 2)(e0.cuda_event, e1.cuda_event)
+        o.timing_events = ctypes.cast(arr, ctypes.c_void_p)
+        o._events_keepalive = (arr, e0, e1)
+    return o
 
 
 _ws_cache = {}

@@ -73,6 +73,7 @@ int check_opts(const ot_opts& o) {
   if (o.max_iter < 1) return fail(OT_ERR_ARG, "max_iter must be >= 1");
   if (o.fold_fp64 < -1 || o.fold_fp64 > 1) return fail(OT_ERR_ARG, "fold_fp64 must be -1, 0 or 1");
   if (o.workgroups < 0) return fail(OT_ERR_ARG, "workgroups must be >= 0");
+  if (o.reserved != 0) return fail(OT_ERR_ARG, "reserved option field must be 0");
   return OT_OK;
 }
 
@@ -270,7 +271,8 @@ int ot_sinkhorn_reduced(const ot_problem* prob, const ot_opts* opts, const float
   if ((rc = check_ws(ws, ws_bytes, csot::reduced_ws_bytes(m, plan)))) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = csot::launch_sinkhorn_reduced(m, prob->K, prob->eps, logK, alpha, beta, f, g,
-                                               o.tol, o.max_iter, o.warm_start, dstats, ws, plan, s);
+                                               o.tol, o.max_iter, o.warm_start, dstats, ws, plan, s,
+                                               static_cast<hipEvent_t*>(o.timing_events));
   if (e != hipSuccess) return hip_fail(e, "reduced solver launch");
   if (hstats) return finish_stats(dstats, hstats, o.tol, s);
   return ok();
@@ -293,7 +295,7 @@ int ot_sinkhorn_full(const ot_problem* prob, const ot_opts* opts, float* f, floa
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (o.validate && (rc = validate_inputs(prob, s, false))) return rc;
   hipError_t e = csot::launch_sinkhorn_full(geo, f, g, o.tol, o.max_iter, o.warm_start, dstats,
-                                            ws, plan, s);
+                                            ws, plan, s, static_cast<hipEvent_t*>(o.timing_events));
   if (e != hipSuccess) return hip_fail(e, "full solver launch");
   if (hstats) return finish_stats(dstats, hstats, o.tol, s);
   return ok();

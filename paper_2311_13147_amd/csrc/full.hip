@@ -44,15 +44,30 @@ struct FullParams {
   double* dstats;
 };
 
+// Smallest shifted row sum the shifted mode accepts: every dropped term is below 2^-126, so
+// with n < 2^24 the lost mass stays below 2^-42 of the accepted sum.
+constexpr float kMinShiftedSum = 0x1p-60f;
+
 // One phase for this workgroup's rows: LSE2 over all other points of (pot_J - C_IJ s2).
-// Returns false on abort.  lse[rl] receives the result for local row rl.
-template <int DIM, int RT, int CQ>
-__device__ __forceinline__ bool full_phase(const FullParams& p, int r0, const float4* __restrict__ ownc,
-                                           const float* __restrict__ dense, int64_t ldd,
-                                           const float4* __restrict__ othc, uint64_t* oslots,
-                                           uint32_t epoch, float4* __restrict__ buf,
-                                           float2* __restrict__ part, float* __restrict__ lse,
-                                           int* s_bad) {
+// lse[rl] receives the result for local row rl.  Returns kPhaseOk, kPhaseAbort, or (shifted
+// mode only) kPhaseRedo when a row's shifted sum fell outside [2^-60, inf).
+//
+// Exact mode keeps a running (max, sum) per row, rescaled once per 4 columns.  Shifted mode
+// sums 2^(pot_J - C_IJ s2 + sh_I) with the row's own previous potential sh_I, and needs no
+// maximum: after the other side's last update every term of a row is at most that side's
+// marginal entry (the previous plan's column or row sums are exact), so the sum is at most 1
+// and cannot overflow; it is that plan's row sum, far from underflow unless the previous
+// plan left the row almost empty -- the caller then redoes the phase in exact mode.  The shift
+// enters the cost as the offset -sh_I / s2, so an entry costs 2 sub, 3 fma, 1 exp and 1 add.
+constexpr int kPhaseOk = 0, kPhaseAbort = 1, kPhaseRedo = 2;
+
+template <int DIM, int RT, int CQ, bool EXACT>
+__device__ __forceinline__ int full_phase(const FullParams& p, int r0, const float4* __restrict__ ownc,
+                                          const float* __restrict__ dense, int64_t ldd,
+                                          const float4* __restrict__ othc, uint64_t* oslots,
+                                          uint32_t epoch, const float* __restrict__ sh,
+                                          float4* __restrict__ buf, float2* __restrict__ part,
+                                          float* __restrict__ lse, int* s_bad, int* s_redo) {
   constexpr int RG = kFullWaves / CQ;
   constexpr int U = kNC / kWave / CQ;  // 64-column steps per wave per chunk
   constexpr int TU = U < 4 ? U : 4;     // columns per lane between running-max rescales
@@ -61,11 +76,12 @@ __device__ __forceinline__ bool full_phase(const FullParams& p, int r0, const fl
   const int wv = tid / kWave;
   const int rg = wv / CQ, cq = wv % CQ;
   float xr[RT][3];
-  float M[RT], S[RT];
+  float M[RT], S[RT], off[RT];
   const float* drow[RT];
 #pragma unroll
   for (int q = 0; q < RT; ++q) {
-    const int I = min(r0 + rg * RT + q, p.n - 1);
+    const int rl = rg * RT + q;
+    const int I = min(r0 + rl, p.n - 1);
     if constexpr (DIM > 0) {
       const float4 c = ownc[I];
       xr[q][0] = c.x; xr[q][1] = c.y; xr[q][2] = c.z;
@@ -73,7 +89,9 @@ __device__ __forceinline__ bool full_phase(const FullParams& p, int r0, const fl
     drow[q] = DIM == 0 ? dense + (int64_t)I * ldd : nullptr;
     M[q] = kNegBig;
     S[q] = 0.0f;
+    off[q] = EXACT ? 0.0f : -sh[rl] * p.to_nat;  // to_nat = 1 / s2
   }
+  if (tid == 0) *s_redo = 0;
   const int nchunks = p.np / kNC;
   bool ok = true;
   // prefetch chunk 0: coordinates and slots of points tid + k * kFullThreads
@@ -100,7 +118,7 @@ __device__ __forceinline__ bool full_phase(const FullParams& p, int r0, const fl
     }
     if (!ok) *s_bad = 1;
     __syncthreads();
-    if (*s_bad) return false;
+    if (*s_bad) return kPhaseAbort;
     if (c + 1 < nchunks) {
 #pragma unroll
       for (int k = 0; k < kPF; ++k) {
@@ -122,11 +140,11 @@ __device__ __forceinline__ bool full_phase(const FullParams& p, int r0, const fl
           float cst;
           if constexpr (DIM == 0) {
             const int Jc = c * kNC + lane + kWave * (u + cc);
-            cst = Jc < p.n ? drow[q][Jc] : 0.0f;
+            cst = (Jc < p.n ? drow[q][Jc] : 0.0f) + off[q];
           } else {
             const float dx = xr[q][0] - o[cc].x;
             const float dy = xr[q][1] - o[cc].y;
-            cst = dx * dx;
+            cst = fmaf(dx, dx, off[q]);
             cst = fmaf(dy, dy, cst);
             if constexpr (DIM == 3) {
               const float dz = xr[q][2] - o[cc].z;
@@ -135,15 +153,20 @@ __device__ __forceinline__ bool full_phase(const FullParams& p, int r0, const fl
           }
           t[cc] = fmaf(-cst, p.s2, o[cc].w);
         }
-        float tm = t[0];
+        if constexpr (EXACT) {
+          float tm = t[0];
 #pragma unroll
-        for (int cc = 1; cc < TU; ++cc) tm = fmaxf(tm, t[cc]);
-        const float Mn = fmaxf(M[q], tm);
-        float acc = S[q] * exp2_fast(M[q] - Mn);
+          for (int cc = 1; cc < TU; ++cc) tm = fmaxf(tm, t[cc]);
+          const float Mn = fmaxf(M[q], tm);
+          float acc = S[q] * exp2_fast(M[q] - Mn);
 #pragma unroll
-        for (int cc = 0; cc < TU; ++cc) acc += exp2_fast(t[cc] - Mn);
-        S[q] = acc;
-        M[q] = Mn;
+          for (int cc = 0; cc < TU; ++cc) acc += exp2_fast(t[cc] - Mn);
+          S[q] = acc;
+          M[q] = Mn;
+        } else {
+#pragma unroll
+          for (int cc = 0; cc < TU; ++cc) S[q] += exp2_fast(t[cc]);
+        }
       }
     }
   }
@@ -151,20 +174,51 @@ __device__ __forceinline__ bool full_phase(const FullParams& p, int r0, const fl
 #pragma unroll
   for (int q = 0; q < RT; ++q) {
     float m_ = M[q], s_ = S[q];
-    wave_lse_merge(m_, s_);
+    if constexpr (EXACT) {
+      wave_lse_merge(m_, s_);
+    } else {
+      s_ = wave_sum_all(s_);
+    }
     if (lane == 0) part[(rg * RT + q) * CQ + cq] = make_float2(m_, s_);
   }
   __syncthreads();
   for (int rl = tid; rl < RG * RT; rl += kFullThreads) {
-    float m_ = kNegBig, s_ = 0.0f;
-    for (int k = 0; k < CQ; ++k) {
-      const float2 v = part[rl * CQ + k];
-      lse_merge(m_, s_, v.x, v.y);
+    if constexpr (EXACT) {
+      float m_ = kNegBig, s_ = 0.0f;
+      for (int k = 0; k < CQ; ++k) {
+        const float2 v = part[rl * CQ + k];
+        lse_merge(m_, s_, v.x, v.y);
+      }
+      lse[rl] = m_ + log2_fast(s_);
+    } else {
+      float s_ = 0.0f;
+      for (int k = 0; k < CQ; ++k) s_ += part[rl * CQ + k].y;
+      if (r0 + rl < p.n && !(s_ >= kMinShiftedSum && s_ < INFINITY)) *s_redo = 1;
+      lse[rl] = log2_fast(s_) - sh[rl];
     }
-    lse[rl] = m_ + log2_fast(s_);
   }
   __syncthreads();
-  return true;
+  return (!EXACT && *s_redo) ? kPhaseRedo : kPhaseOk;
+}
+
+// A phase in shifted mode, redone in exact mode when the shifted sums are out of range.
+template <int DIM, int RT, int CQ>
+__device__ __forceinline__ int full_phase_auto(bool exact, const FullParams& p, int r0,
+                                               const float4* ownc, const float* dense,
+                                               int64_t ldd, const float4* othc,
+                                               uint64_t* oslots, uint32_t epoch,
+                                               const float* sh, float4* buf, float2* part,
+                                               float* lse, int* s_bad, int* s_redo,
+                                               int* redo_count) {
+  if (!exact) {
+    const int r = full_phase<DIM, RT, CQ, false>(p, r0, ownc, dense, ldd, othc, oslots, epoch,
+                                                 sh, buf, part, lse, s_bad, s_redo);
+    if (r != kPhaseRedo) return r;
+    ++*redo_count;
+    __syncthreads();  // every wave is done with the chunk buffers
+  }
+  return full_phase<DIM, RT, CQ, true>(p, r0, ownc, dense, ldd, othc, oslots, epoch, sh, buf,
+                                       part, lse, s_bad, s_redo);
 }
 
 template <int DIM, int RT, int CQ>
@@ -176,7 +230,7 @@ __global__ void __launch_bounds__(kFullThreads) full_solver_kernel(FullParams p)
   __shared__ float Fcur[R], Fprev[R], Gcur[R], la2[R], lb2[R];
   __shared__ float rsv[256];
   __shared__ double red[kFullWaves];
-  __shared__ int s_bad, s_stop;
+  __shared__ int s_bad, s_stop, s_redo;
   const int w = blockIdx.x, tid = threadIdx.x;
   const int r0 = w * R;
   const int nr = max(0, min(R, p.n - r0));
@@ -192,13 +246,17 @@ __global__ void __launch_bounds__(kFullThreads) full_solver_kernel(FullParams p)
   }
   if (tid == 0) s_bad = 0;
   __syncthreads();
-  int iters_done = 0, converged = 0, flags = 0;
+  int iters_done = 0, converged = 0, flags = 0, redos = 0;
   double err2 = 0.0;
 
   for (uint32_t t = 1;; ++t) {
     // ---- row phase: F^t from G^{t-1} ----------------------------------------------------
-    if (!full_phase<DIM, RT, CQ>(p, r0, p.xc, p.C, p.ldc, p.yc, p.gx, t - 1, buf, part, lse,
-                                 &s_bad)) { flags |= 2; break; }
+    // F^1 has no previous F to shift by: exact mode; later rows shift by F^{t-1}
+    if (full_phase_auto<DIM, RT, CQ>(t == 1, p, r0, p.xc, p.C, p.ldc, p.yc, p.gx, t - 1, Fcur,
+                                     buf, part, lse, &s_bad, &s_redo, &redos) != kPhaseOk) {
+      flags |= 2;
+      break;
+    }
     double rpart = 0.0;
     for (int rl = tid; rl < nr; rl += blockDim.x) {
       const int I = r0 + rl;
@@ -236,8 +294,12 @@ __global__ void __launch_bounds__(kFullThreads) full_solver_kernel(FullParams p)
       if (s_stop) { iters_done = (int)t - 1; break; }
     }
     // ---- column phase: G^t from F^t -------------------------------------------------------
-    if (!full_phase<DIM, RT, CQ>(p, r0, p.yc, p.CT, p.np, p.xc, p.fx, t, buf, part, lse,
-                                 &s_bad)) { flags |= 2; break; }
+    // shifted by G^{t-1}, which the row update of this iteration used
+    if (full_phase_auto<DIM, RT, CQ>(false, p, r0, p.yc, p.CT, p.np, p.xc, p.fx, t, Gcur, buf,
+                                     part, lse, &s_bad, &s_redo, &redos) != kPhaseOk) {
+      flags |= 2;
+      break;
+    }
     for (int cl = tid; cl < nr; cl += blockDim.x) {
       const float Gn = lb2[cl] - lse[cl];
       Gcur[cl] = Gn;
@@ -255,6 +317,8 @@ __global__ void __launch_bounds__(kFullThreads) full_solver_kernel(FullParams p)
     p.dstats[1] = (double)converged;
     p.dstats[4] = sqrt(err2);
     p.dstats[5] = (double)flags;
+    p.dstats[6] = (double)redos;
+    p.dstats[7] = 0.0;
   } else if (tid == 0 && flags) {
     p.dstats[5] = (double)flags;
   }
@@ -378,7 +442,7 @@ size_t full_ws_bytes(const Geom& g, const FullPlan& pl) {
 
 hipError_t launch_sinkhorn_full(const Geom& g, float* f, float* gpot, double tol, int max_iter,
                                 int warm, double* dstats, void* ws, const FullPlan& pl,
-                                hipStream_t s) {
+                                hipStream_t s, hipEvent_t* events) {
   const int np = full_np(g.n);
   char* base = static_cast<char*>(ws);
   uint32_t* ctl = reinterpret_cast<uint32_t*>(base);
@@ -418,8 +482,10 @@ hipError_t launch_sinkhorn_full(const Geom& g, float* f, float* gpot, double tol
   void* args[] = {&p};
   const void* k = pick_full_kernel(g.dim, pl.threads / 100, pl.threads % 100);
   if (!k) return hipErrorInvalidValue;
+  if (events && (e = hipEventRecord(events[0], s)) != hipSuccess) return e;
   e = hipLaunchCooperativeKernel(k, dim3(pl.W), dim3(kFullThreads), args, 0, s);
   if (e != hipSuccess) return e;
+  if (events && (e = hipEventRecord(events[1], s)) != hipSuccess) return e;
 
   // float64 check of the returned state
   return launch_check(g, 0, nullptr, f, gpot, g.a, g.b, sums, dstats, s);

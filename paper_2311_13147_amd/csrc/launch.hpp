@@ -41,7 +41,8 @@ size_t reduced_ws_bytes(int m, const ReducedPlan& p);
 hipError_t launch_sinkhorn_reduced(int m, int K, double eps, const float* logK,
                                    const float* alpha, const float* beta, float* f, float* g,
                                    double tol, int max_iter, int warm, double* dstats,
-                                   void* ws, const ReducedPlan& p, hipStream_t s);
+                                   void* ws, const ReducedPlan& p, hipStream_t s,
+                                   hipEvent_t* events = nullptr);
 
 // ---- full.hip ----------------------------------------------------------------------------
 struct FullPlan {
@@ -54,7 +55,7 @@ bool plan_full(const Geom& g, int workgroups_hint, FullPlan* plan);
 size_t full_ws_bytes(const Geom& g, const FullPlan& p);
 hipError_t launch_sinkhorn_full(const Geom& g, float* f, float* gpot, double tol, int max_iter,
                                 int warm, double* dstats, void* ws, const FullPlan& p,
-                                hipStream_t s);
+                                hipStream_t s, hipEvent_t* events = nullptr);
 
 // ---- expand.hip --------------------------------------------------------------------------
 hipError_t launch_expand(const Geom& g, const float* f, const float* gp, float* T, int64_t ldt,

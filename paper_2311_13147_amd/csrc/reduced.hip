@@ -262,6 +262,8 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
     p.dstats[1] = (double)converged;
     p.dstats[4] = sqrt((double)p.K * (double)err2);
     p.dstats[5] = (double)flags;
+    p.dstats[6] = 0.0;
+    p.dstats[7] = 0.0;
   } else if (tid == 0 && flags) {
     p.dstats[5] = (double)flags;
   }
@@ -344,7 +346,8 @@ size_t reduced_ws_bytes(int m, const ReducedPlan& p) {
 hipError_t launch_sinkhorn_reduced(int m, int K, double eps, const float* logK,
                                    const float* alpha, const float* beta, float* f, float* g,
                                    double tol, int max_iter, int warm, double* dstats,
-                                   void* ws, const ReducedPlan& pl, hipStream_t s) {
+                                   void* ws, const ReducedPlan& pl, hipStream_t s,
+                                   hipEvent_t* events) {
   const int mp = reduced_mp(m);
   char* base = static_cast<char*>(ws);
   uint32_t* ctl = reinterpret_cast<uint32_t*>(base);
@@ -367,9 +370,11 @@ hipError_t launch_sinkhorn_reduced(int m, int K, double eps, const float* logK,
   p.logK = logK; p.alpha = alpha; p.beta = beta; p.f_out = f; p.g_out = g;
   p.fx = fx; p.gx = gx; p.rsx = rsx; p.ctl = ctl; p.dstats = dstats;
   void* args[] = {&p};
+  if (events && (e = hipEventRecord(events[0], s)) != hipSuccess) return e;
   e = hipLaunchCooperativeKernel((const void*)reduced_solver_kernel, dim3(pl.W * pl.stride),
                                  dim3(pl.threads), args, (unsigned)pl.lds, s);
   if (e != hipSuccess) return e;
+  if (events && (e = hipEventRecord(events[1], s)) != hipSuccess) return e;
 
   // float64 check of the returned state: full-space row and column errors
   Geom geo;

@@ -146,3 +146,13 @@ def test_binding_requires_device_tensors(B):
     import torch
     with pytest.raises(TypeError):
         B.Problem(torch.ones(8), torch.ones(8), 0.1, 2, x=torch.ones(8, 2), y=torch.ones(8, 2))
+
+
+def test_reserved_option_must_be_zero_and_events_field_layout(B):
+    lib = B.raw_lib()
+    p = _prob(B)
+    o = B.make_opts()
+    assert B.OtOpts.timing_events.offset == 32 and o.timing_events is None
+    o.reserved = 1
+    assert lib.ot_fold_kernel(ctypes.byref(p), ctypes.byref(o), 8, 8, 8, None, 0, None) == B.OT_ERR_ARG
+    assert "reserved" in lib.ot_last_error().decode()
