@@ -45,7 +45,20 @@ def _args():
     ap.add_argument("--fixed-full", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy (the reference kernel "
+                         "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE) and exit")
     return ap.parse_args()
+
+
+def copy_calibration():
+    import torch
+    src = torch.ones(64 * 1024 * 1024, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": src.numel() * 4}), flush=True)
 
 
 def _source_hash(*names):
@@ -72,6 +85,9 @@ def _traffic(kernel_file, launches_per_call):
 
 def main():
     args = _args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
@@ -206,6 +222,7 @@ def main():
         "objective": {"reduced_P": vr["P"], "full_P": vf["P"],
                       "rel_gap": abs(vr["P"] - vf["P"]) / max(abs(vf["P"]), vf["CT"])},
         "leg_ms": {k: round(v, 4) for k, v in ms.items()},
+        "leg_ms_max": {k: round(max(e[k][0].elapsed_time(e[k][1]) for e in evs), 4) for k in legs},
         "expand_GBps": round(4.0 * N * N / (ms["expand"] * 1e-3) / 1e9, 1),
         "roofline": roof,
     }
