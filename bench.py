@@ -217,6 +217,7 @@ def main():
         "forward_backward_ms": {"reduced": round(ttt_red + ms["red_grad"], 4),
                                 "full": round(ttt_full + ms["full_grad"], 4)},
         "iterations_to_tol": {"reduced": it_red, "full": it_full},
+        "reduced_xcd_local_exchange": bool(st[1][7]),
         "marginal_err_fp64": {"reduced_row": st[0][2], "reduced_col": st[0][3],
                               "full_row": st[2][2], "full_col": st[2][3]},
         "objective": {"reduced_P": vr["P"], "full_P": vf["P"],

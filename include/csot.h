@@ -106,9 +106,11 @@ typedef struct ot_stats {
 } ot_stats;
 
 /* Device-side statistics: solvers write OT_DSTATS_LEN doubles to `dstats` (device) in the
- * layout {iters, converged, err_row, err_col, err_row32, flags, redo, 0}.  redo (full-size
- * solver only, else 0) counts the half-iterations of the first workgroup whose shifted
- * log-sum-exp had to be recomputed with a running maximum. */
+ * layout {iters, converged, err_row, err_col, err_row32, flags, redo, xcd_local}.  redo
+ * (full-size solver only, else 0) counts the half-iterations of the first workgroup whose
+ * shifted log-sum-exp had to be recomputed with a running maximum.  xcd_local (reduced solver
+ * only, else 0) is 1 when all its workgroups ran on one XCD and exchanged potentials through
+ * that XCD's L2. */
 #define OT_DSTATS_LEN 8
 
 /* Bytes of scratch space any call below needs for this problem and these options. */

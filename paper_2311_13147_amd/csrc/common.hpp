@@ -84,6 +84,36 @@ __device__ __forceinline__ float wave_sum_all(float v) {
   return a + b;
 }
 
+// Wave-wide sum / max on the vector unit alone, every lane receiving the bitwise-identical
+// result: DPP inside rows of 16 lanes, then v_permlane16_swap (row pairs) and
+// v_permlane32_swap (the two halves).  Each lane combines the two operands in the same order,
+// so all lanes (and all waves holding the same inputs) agree exactly.
+__device__ __forceinline__ float swap_sum16(float v) {
+  const auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(a[0]) + __uint_as_float(a[1]);
+}
+__device__ __forceinline__ float swap_sum32(float v) {
+  const auto a = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(a[0]) + __uint_as_float(a[1]);
+}
+__device__ __forceinline__ float wave_sum_v(float v) {
+  v += dpp_f32<kDppXor1>(v);
+  v += dpp_f32<kDppXor2>(v);
+  v += dpp_f32<kDppHalfMirror>(v);
+  v += dpp_f32<kDppMirror>(v);
+  return swap_sum32(swap_sum16(v));
+}
+__device__ __forceinline__ float wave_max_v(float v) {
+  v = fmaxf(v, dpp_f32<kDppXor1>(v));
+  v = fmaxf(v, dpp_f32<kDppXor2>(v));
+  v = fmaxf(v, dpp_f32<kDppHalfMirror>(v));
+  v = fmaxf(v, dpp_f32<kDppMirror>(v));
+  auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  v = fmaxf(__uint_as_float(a[0]), __uint_as_float(a[1]));
+  a = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return fmaxf(__uint_as_float(a[0]), __uint_as_float(a[1]));
+}
+
 // (max, sum) merge across the 64 lanes of a wave: DPP inside each row of 16 lanes, then a
 // lane swizzle across rows (xor 16) and a read of lane 32 for the last step.  The result is
 // valid in lane 0.
@@ -176,6 +206,23 @@ __device__ __forceinline__ bool grid_barrier(uint32_t* ctl, uint32_t target, int
 __device__ __forceinline__ void slot_publish(uint64_t* slot, float v, uint32_t epoch) {
   const uint64_t w = ((uint64_t)epoch << 32) | (uint64_t)__float_as_uint(v);
   __hip_atomic_store(slot, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Publication visible only through the L2 of the writer's XCD: a plain (workgroup-scope)
+// store, which the write-through L1 forwards to that L2, where agent-scope loads from CUs of
+// the same XCD find it.  Agent-scope stores are written through to memory as well and take
+// about twice as long to reach a poller.  Only for grids whose workgroups have been checked
+// to share one XCD (see xcc_id); across XCDs such a store stays in the writer's L2 and the
+// bounded polls of the other side would time out.
+__device__ __forceinline__ void slot_publish_local(uint64_t* slot, float v, uint32_t epoch) {
+  const uint64_t w = ((uint64_t)epoch << 32) | (uint64_t)__float_as_uint(v);
+  __hip_atomic_store(slot, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Index of the XCD (accelerator complex die) this wave runs on: hardware register XCC_ID,
+// bits [3:0].
+__device__ __forceinline__ uint32_t xcc_id() {
+  return (uint32_t)__builtin_amdgcn_s_getreg((3 << 11) | 20) & 15u;
 }
 
 __device__ __forceinline__ uint64_t slot_load(uint64_t* slot) {

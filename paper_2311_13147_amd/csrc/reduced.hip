@@ -47,6 +47,7 @@ struct RedParams {
   uint64_t* fx;    // [m] F exchange slots
   uint64_t* gx;    // [m] G exchange slots
   uint64_t* rsx;   // [2][W] residual-partial slots, double-buffered by iteration parity
+  uint64_t* xid;   // [W] XCD index of every workgroup (epoch 1)
   uint32_t* ctl;   // [0] abort flag
   double* dstats;
 };
@@ -67,16 +68,58 @@ __device__ __forceinline__ float wave_lse2(const float* __restrict__ row,
                         l1.x + v1.x, l1.y + v1.y, l1.z + v1.z, l1.w + v1.w};
     float mx = fmaxf(fmaxf(fmaxf(t[0], t[1]), fmaxf(t[2], t[3])),
                      fmaxf(fmaxf(t[4], t[5]), fmaxf(t[6], t[7])));
-    mx = wave_max_all(mx);
+    mx = wave_max_v(mx);
     const float Mn = fmaxf(M, mx);
     float s = 0.0f;
 #pragma unroll
     for (int k = 0; k < 8; ++k) s += exp2_fast(t[k] - Mn);
-    s = wave_sum_all(s);
+    s = wave_sum_v(s);
     S = S * exp2_fast(M - Mn) + s;
     M = Mn;
   }
   return M + log2_fast(S);
+}
+
+// Shifted sum over a padded LDS row: sum_j 2^(row_j + vec_j + sh), every lane receiving it.
+// With sh the row's own previous potential every term is at most the other side's marginal
+// entry (the previous plan's column or row sums are exact after the other side's update), so
+// the sum, the previous plan's row sum, is at most 1 and needs no maximum.
+constexpr float kMinShiftedSum = 0x1p-60f;  // below this the caller redoes the row exactly
+
+__device__ __forceinline__ float wave_shifted_sum(const float* __restrict__ row,
+                                                  const float* __restrict__ vec, int mp,
+                                                  int lane, float sh) {
+  float s = 0.0f;
+  for (int base = 0; base < mp; base += kSweep) {
+    const int q0 = base + 4 * lane, q1 = q0 + 4 * kWave;
+    const float4 l0 = *reinterpret_cast<const float4*>(row + q0);
+    const float4 v0 = *reinterpret_cast<const float4*>(vec + q0);
+    const float4 l1 = *reinterpret_cast<const float4*>(row + q1);
+    const float4 v1 = *reinterpret_cast<const float4*>(vec + q1);
+    s += exp2_fast(l0.x + (v0.x + sh)) + exp2_fast(l0.y + (v0.y + sh)) +
+         exp2_fast(l0.z + (v0.z + sh)) + exp2_fast(l0.w + (v0.w + sh)) +
+         exp2_fast(l1.x + (v1.x + sh)) + exp2_fast(l1.y + (v1.y + sh)) +
+         exp2_fast(l1.z + (v1.z + sh)) + exp2_fast(l1.w + (v1.w + sh));
+  }
+  return wave_sum_v(s);
+}
+
+// One potential update by one wave: the new potential lm - LSE2_j(row_j + vec_j) and the
+// previous plan's marginal sum.  Shifted by the previous potential `prev` when `shifted`,
+// falling back to the exact running-maximum form when the shifted sum is out of range.
+__device__ __forceinline__ float wave_update(const float* __restrict__ row,
+                                             const float* __restrict__ vec, int mp, int lane,
+                                             float lm, float prev, bool shifted, float* sum_out) {
+  if (shifted) {
+    const float S = wave_shifted_sum(row, vec, mp, lane, prev);
+    if (S >= kMinShiftedSum && S < INFINITY) {
+      *sum_out = S;
+      return lm - log2_fast(S) + prev;
+    }
+  }
+  const float Fn = lm - wave_lse2(row, vec, mp, lane);
+  *sum_out = -1.0f;  // not available: the caller uses the potential difference
+  return Fn;
 }
 
 // Stage the m slots of `src` carrying `epoch` into Vs (zero padding up to mp) and, when
@@ -123,8 +166,9 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
   const int R = p.R, mp = p.mp, m = p.m;
   float* Ls = lds;                      // [R][mp] row slab
   float* LTs = Ls + (size_t)R * mp;     // [R][mp] column slab (transposed)
-  float* Vs = LTs + (size_t)R * mp;     // [mp] staged potential
-  float* la2 = Vs + mp;                 // [R] log2 alpha (my rows)
+  float* VsG = LTs + (size_t)R * mp;    // [mp] staged G (read by row updates)
+  float* VsF = VsG + mp;                // [mp] staged F (read by column updates)
+  float* la2 = VsF + mp;                // [R] log2 alpha (my rows)
   float* lb2 = la2 + R;                 // [R] log2 beta (my columns)
   float* av = lb2 + R;                  // [R] alpha (my rows)
   float* Fcur = av + R;                 // [R] F^t
@@ -135,7 +179,7 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
   float* rsv = Fold + R;                // [W] residual partials of every workgroup
   __shared__ float wsum[kRedWaves];
   __shared__ int s_bad;
-  __shared__ int s_stop;
+  __shared__ int s_mixed;
 
   if (blockIdx.x % p.stride) return;  // placeholder block: frees its CU at once
   const int w = blockIdx.x / p.stride;
@@ -168,81 +212,112 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
     Fprev[rl] = 0.0f;
     Fold[rl] = 0.0f;
   }
-  for (int j = tid; j < mp; j += blockDim.x)
-    Vs[j] = (j < m && p.warm) ? p.g_out[j] * p.s2 : 0.0f;
-  if (tid == 0) s_bad = 0;
+  for (int j = tid; j < mp; j += blockDim.x) {
+    VsG[j] = (j < m && p.warm) ? p.g_out[j] * p.s2 : 0.0f;
+    VsF[j] = 0.0f;
+  }
+  if (tid == 0) {
+    s_bad = 0;
+    s_mixed = 0;
+  }
   __syncthreads();
 
   int iters_done = 0, converged = 0, flags = 0;
   float err2 = 0.0f;
 
-  // Iteration t: row update (F^t from G^{t-1}; the residual of the state after t-1 falls out
-  // of it), publication of F^t, then the stop test on the state after t-2 whose residual
-  // partials arrived with G^{t-1} (so it never delays a publication), exchange of F^t, column
-  // update (G^t), exchange of G^t together with the residual partials of iteration t.
-  for (uint32_t t = 1;; ++t) {
+  // When the launch placed every workgroup on one XCD (stride 8), confirm it: then the
+  // potentials can be published through that XCD's L2 alone (slot_publish_local), which
+  // halves the exchange latency.  Otherwise every publication is agent-scope.
+  bool local_pub = false;
+  if (p.stride > 1) {
+    const uint32_t me = xcc_id();
+    if (tid == 0) slot_publish(p.xid + w, __uint_as_float(me), 1u);
+    for (int v = tid; v < p.W; v += blockDim.x) {
+      uint64_t x = slot_load(p.xid + v);
+      if (!slot_wait(p.xid + v, x, 1u, abort_flag)) s_bad = 1;
+      else if (__float_as_uint(slot_value(x)) != me) s_mixed = 1;
+    }
+    __syncthreads();
+    local_pub = !s_mixed;
+  }
+  auto publish = [&](uint64_t* slot, float v, uint32_t epoch) {
+    if (local_pub) slot_publish_local(slot, v, epoch);
+    else slot_publish(slot, v, epoch);
+  };
+  // read once, before any wave can reach an exchange (which may set s_bad again)
+  const bool started = s_bad == 0;
+  if (!started) flags |= 2;
+
+  // Iteration t: row update (F^t from G^{t-1}; the row sums of the state after t-1 fall out of
+  // it), publication of F^t, the stop test on the state after t-2 whose residual partials
+  // arrived with G^{t-1} (every wave evaluates it from the same staged values, so no barrier
+  // is needed and it never delays a publication), exchange of F^t, publication of this
+  // workgroup's residual partial of iteration t, column update (G^t), exchange of G^t together
+  // with the residual partials of iteration t.  The two staged potentials have buffers of
+  // their own, so the two exchanges are the only barriers of an iteration.
+  for (uint32_t t = 1; started; ++t) {
     // ---- row update ----------------------------------------------------------------------
     float racc = 0.0f;
     for (int rl = wv; rl < nr; rl += kRedWaves) {
-      const float Fn = la2[rl] - wave_lse2(Ls + (size_t)rl * mp, Vs, mp, lane);
+      float S;
+      const float Fo = Fcur[rl];
+      const float Fn = wave_update(Ls + (size_t)rl * mp, VsG, mp, lane, la2[rl], Fo, t >= 2, &S);
       if (lane == 0) {
         if (t >= 2) {
-          const float rr = scaled_exp2m1(av[rl], Fcur[rl] - Fn);
+          // residual of the state after t-1: its row sum minus alpha
+          const float rr = S >= 0.0f ? S - av[rl] : scaled_exp2m1(av[rl], Fo - Fn);
           racc += rr * rr;
         }
         Fold[rl] = Fprev[rl];
-        Fprev[rl] = Fcur[rl];
+        Fprev[rl] = Fo;
         Fcur[rl] = Fn;
-        slot_publish(p.fx + r0 + rl, Fn, t);
+        publish(p.fx + r0 + rl, Fn, t);
       }
     }
     if (lane == 0) wsum[wv] = racc;
-    __syncthreads();  // every wave is done with Vs (G^{t-1}) and wrote its residual part
-    if (tid == 0) {
-      float s = 0.0f;
-      for (int k = 0; k < kRedWaves; ++k) s += wsum[k];
-      slot_publish(p.rsx + (t & 1u) * p.W + w, s, t);
-    }
 
     // ---- stop test on the state after iteration t-2 (its residual came with G^{t-1}) -------
     if (t >= 3) {
-      if (wv == 0) {  // fixed-order reduction: every workgroup gets the same sum
-        float s = 0.0f;
-        for (int v = lane; v < p.W; v += kWave) s += rsv[v];
-        s = wave_sum_all(s);
-        if (lane == 0) {
-          err2 = s;
-          const bool fin = s == s && s < 3.0e38f;
-          converged = fin && (double)s <= p.tol2;
-          // tol = 0 asks for exactly max_iter iterations, even if the residual underflows
-          s_stop = (converged && p.tol2 > 0.0) || !fin || (int)(t - 2) >= p.max_iter;
-          if (!fin) flags |= 1;
-        }
+      float s = 0.0f;  // fixed-order reduction: every wave of every workgroup gets this sum
+      for (int v = lane; v < p.W; v += kWave) s += rsv[v];
+      s = wave_sum_v(s);
+      err2 = s;
+      const bool fin = s == s && s < 3.0e38f;
+      converged = fin && (double)s <= p.tol2;
+      if (!fin) flags |= 1;
+      // tol = 0 asks for exactly max_iter iterations, even if the residual underflows
+      if ((converged && p.tol2 > 0.0) || !fin || (int)(t - 2) >= p.max_iter) {
+        iters_done = (int)t - 2;
+        break;
       }
-      __syncthreads();
-      if (s_stop) { iters_done = (int)t - 2; break; }
     }
 
-    // ---- exchange F^t, column update -------------------------------------------------------
-    if (!stage_slots(p.fx, m, mp, t, Vs, nullptr, 0, 0, nullptr, abort_flag, &s_bad)) {
+    // ---- exchange F^t (barrier), residual partial of iteration t, column update -----------
+    if (!stage_slots(p.fx, m, mp, t, VsF, nullptr, 0, 0, nullptr, abort_flag, &s_bad)) {
       flags |= 2;
       break;
     }
+    if (wv == 0 && t >= 2) {
+      float s = lane < kRedWaves ? wsum[lane] : 0.0f;
+      s = wave_sum_v(s);
+      if (lane == 0) publish(p.rsx + (t & 1u) * p.W + w, s, t);
+    }
     for (int cl = wv; cl < nr; cl += kRedWaves) {
-      const float Gn = lb2[cl] - wave_lse2(LTs + (size_t)cl * mp, Vs, mp, lane);
+      float S;
+      const float Go = Gcur[cl];
+      const float Gn = wave_update(LTs + (size_t)cl * mp, VsF, mp, lane, lb2[cl], Go, true, &S);
       if (lane == 0) {
-        Gprev[cl] = Gcur[cl];
+        Gprev[cl] = Go;
         Gcur[cl] = Gn;
-        slot_publish(p.gx + r0 + cl, Gn, t);
+        publish(p.gx + r0 + cl, Gn, t);
       }
     }
-    __syncthreads();  // everyone is done reading Vs (F^t)
 
-    // ---- exchange G^t and the residual partials of iteration t -------------------------------
+    // ---- exchange G^t and the residual partials of iteration t (barrier) ----------------------
     // A workgroup that is one iteration ahead may already publish its next residual partial
     // while this one still polls; the parity buffers keep the two apart.
     const int nres = t >= 2 ? p.W : 0;
-    if (!stage_slots(p.gx, m, mp, t, Vs, p.rsx + (t & 1u) * p.W, nres, t, rsv, abort_flag,
+    if (!stage_slots(p.gx, m, mp, t, VsG, p.rsx + (t & 1u) * p.W, nres, t, rsv, abort_flag,
                      &s_bad)) {
       flags |= 2;
       break;
@@ -263,7 +338,7 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
     p.dstats[4] = sqrt((double)p.K * (double)err2);
     p.dstats[5] = (double)flags;
     p.dstats[6] = 0.0;
-    p.dstats[7] = 0.0;
+    p.dstats[7] = local_pub ? 1.0 : 0.0;
   } else if (tid == 0 && flags) {
     p.dstats[5] = (double)flags;
   }
@@ -280,7 +355,7 @@ static int device_cu_count() {
 }
 
 static size_t reduced_lds_bytes(int R, int mp, int W) {
-  return sizeof(float) * ((size_t)2 * R * mp + mp + 9 * (size_t)R + W) + 16;
+  return sizeof(float) * ((size_t)2 * R * mp + 2 * (size_t)mp + 9 * (size_t)R + W) + 16;
 }
 
 static int reduced_mp(int m) { return (m + kSweep - 1) / kSweep * kSweep; }
@@ -331,12 +406,12 @@ bool plan_reduced(int m, int hint, ReducedPlan* plan) {
   return true;
 }
 
-// workspace: ctl[64 words] | fx[mp] | gx[mp] | rsx[W] (64-bit slots) | check partials
+// workspace: ctl[64 words] | fx[mp] | gx[mp] | rsx[2W] | xid[W] (64-bit slots) | check partials
 static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
 static size_t slots_bytes(int m, int W) {
   return align256(256) + 2 * align256(sizeof(uint64_t) * reduced_mp(m)) +
-         align256(sizeof(uint64_t) * 2 * W);
+         align256(sizeof(uint64_t) * 2 * W) + align256(sizeof(uint64_t) * W);
 }
 
 size_t reduced_ws_bytes(int m, const ReducedPlan& p) {
@@ -355,6 +430,7 @@ hipError_t launch_sinkhorn_reduced(int m, int K, double eps, const float* logK,
   uint64_t* fx = reinterpret_cast<uint64_t*>(base + off); off += align256(sizeof(uint64_t) * mp);
   uint64_t* gx = reinterpret_cast<uint64_t*>(base + off); off += align256(sizeof(uint64_t) * mp);
   uint64_t* rsx = reinterpret_cast<uint64_t*>(base + off); off += align256(sizeof(uint64_t) * 2 * pl.W);
+  uint64_t* xid = reinterpret_cast<uint64_t*>(base + off); off += align256(sizeof(uint64_t) * pl.W);
   double* part = reinterpret_cast<double*>(base + off);
 
   // epochs start at 1, so zeroed slots are never mistaken for current ones
@@ -368,7 +444,7 @@ hipError_t launch_sinkhorn_reduced(int m, int K, double eps, const float* logK,
   p.to_nat = (float)(eps * kLn2D);
   p.tol2 = tol * tol / (double)K;
   p.logK = logK; p.alpha = alpha; p.beta = beta; p.f_out = f; p.g_out = g;
-  p.fx = fx; p.gx = gx; p.rsx = rsx; p.ctl = ctl; p.dstats = dstats;
+  p.fx = fx; p.gx = gx; p.rsx = rsx; p.xid = xid; p.ctl = ctl; p.dstats = dstats;
   void* args[] = {&p};
   if (events && (e = hipEventRecord(events[0], s)) != hipSuccess) return e;
   e = hipLaunchCooperativeKernel((const void*)reduced_solver_kernel, dim3(pl.W * pl.stride),
