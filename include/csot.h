@@ -70,9 +70,11 @@ typedef struct ot_problem {
  *                      current plan is <= tol (the column marginal is exact after each column
  *                      update).  tol = 0 runs exactly max_iter iterations.
  *   max_iter   [10000] >= 1.
- *   fold_fp64  [-1]    fold's log-sum over the K shifts in float64: 1 yes, 0 or -1 no.  The
- *                      float32 fold's error grows with C/eps, not with K, so float64 is for
- *                      callers that know eps is small relative to the cost scale.
+ *   fold_fp64  [-1]    precision of the fold's log-sum over the K shifts.  1 or -1: costs,
+ *                      their minimum and the shifted exponents in float64, the exponentials
+ *                      of the shifted (non-positive) exponents in float32; logK is accurate
+ *                      to float32 rounding at the speed of the float32 fold.  0: everything
+ *                      in float32, whose error grows with C / eps.
  *   warm_start [0]     1: on entry g holds the initial column potential (natural units).
  *   validate   [0]     1: host-side checks of the marginals and of block-circulance (syncs).
  *   workgroups [0]     persistent solvers: number of cooperating workgroups (0 = automatic).

@@ -236,7 +236,7 @@ int ot_fold_kernel(const ot_problem* prob, const ot_opts* opts, float* logK, flo
   if (!logK || !alpha || !beta) return fail(OT_ERR_ARG, "fold outputs must be non-NULL");
   hipStream_t s = static_cast<hipStream_t>(stream);
   if (o.validate && (rc = validate_inputs(prob, s, true))) return rc;
-  const bool fp64 = o.fold_fp64 == 1;
+  const bool fp64 = o.fold_fp64 != 0;
   hipError_t e = csot::launch_fold(geom(prob), fp64, logK, alpha, beta, s);
   if (e != hipSuccess) return hip_fail(e, "fold launch");
   return ok();

@@ -61,7 +61,7 @@ __device__ void fold_tile(const ot_batch_desc& d, int i0, int fp64_mode) {
   const int m = bm(d), K = d.K, mp = bmp(m);
   float* L = d.logK;
   float* LT = L + (size_t)m * mp;
-  const bool fp64 = fp64_mode == 1;
+  const bool fp64 = fp64_mode != 0;  // -1 (default) and 1: float64 exponents
   const double ie = 1.0 / d.eps;
   const int rows = min(kBT, m - i0);
   for (int e = threadIdx.x; e < rows * mp; e += blockDim.x) {
@@ -71,12 +71,14 @@ __device__ void fold_tile(const ot_batch_desc& d, int i0, int fp64_mode) {
       continue;
     }
     float v;
-    if (fp64) {
+    if (fp64) {  // float64 costs and shifted exponents, float32 exponentials of those (<= 0)
+      const double s2d = kLog2eD * ie;
       double cmin = 1.0e300;
       for (int k = 0; k < K; ++k) cmin = fmin(cmin, bcost<DIM, double>(d.x, i, d.y, k * m + j));
-      double s = 0.0;
-      for (int k = 0; k < K; ++k) s += exp((cmin - bcost<DIM, double>(d.x, i, d.y, k * m + j)) * ie);
-      v = (float)((-cmin * ie + log(s)) * kLog2eD);
+      float s = 0.0f;
+      for (int k = 0; k < K; ++k)
+        s += exp2_fast((float)((cmin - bcost<DIM, double>(d.x, i, d.y, k * m + j)) * s2d));
+      v = (float)(-cmin * s2d + (double)log2_fast(s));
     } else {
       const float s2 = (float)(kLog2eD * ie);
       float cmin = 3.0e38f;

@@ -8,9 +8,10 @@
 // C_ijk is block-row 0 of the block-circulant cost (eq. blkstr_cost): the cost between point
 // i and point k*m + j, recomputed from the float32 coordinates or read from a dense C.  The
 // k-sum is a max-shifted log-sum-exp: two passes over k (minimum cost, then the shifted sum),
-// so no term overflows and the dominant term is exact.  In float64 mode the costs, the shift,
-// the exponentials and the logarithm are all float64 and only the result is rounded; in
-// float32 mode they use the transcendental unit in base 2.
+// so no term overflows and the dominant term is exact.  In float64 mode the costs and the
+// shifted exponents are float64 and only the exponentials of the (non-positive) shifted
+// exponents run in float32, which keeps the result accurate to float32 rounding; in float32
+// mode everything is float32, and the rounding of C / eps grows with its magnitude.
 //
 // Work per output entry: K cost evaluations twice and K exponentials; the output is m*m
 // floats, so the kernel is bound by exp throughput (float32) or float64 FMA throughput.
@@ -46,6 +47,10 @@ __device__ __forceinline__ Real pt_cost(const float* __restrict__ x, int I,
   return c;
 }
 
+// float64 costs, minimum and shifted exponents; the exponentials of the shifted exponents
+// (all <= 0, the largest exactly 0) in float32 on the transcendental unit, the sum of at most
+// K terms in [0, 1] in float32 (it lies in [1, K]) and the final sum in float64.  The result
+// is accurate to float32 rounding of logK: the shift removes the large magnitude exactly.
 template <int DIM>
 __device__ __forceinline__ void fold_entry_fp64(const Geom& g, int i, int j, float* out) {
   double cmin = 1.0e300;
@@ -55,15 +60,15 @@ __device__ __forceinline__ void fold_entry_fp64(const Geom& g, int i, int j, flo
     else c = pt_cost<DIM, double>(g.x, i, g.y, k * g.m + j);
     cmin = c < cmin ? c : cmin;
   }
-  const double inv_eps = 1.0 / g.eps;
-  double s = 0.0;
+  const double s2 = kLog2eD / g.eps;
+  float s = 0.0f;
   for (int k = 0; k < g.K; ++k) {
     double c;
     if constexpr (DIM == 0) c = (double)g.C[(int64_t)i * g.ldc + (int64_t)k * g.m + j];
     else c = pt_cost<DIM, double>(g.x, i, g.y, k * g.m + j);
-    s += exp((cmin - c) * inv_eps);
+    s += exp2_fast((float)((cmin - c) * s2));
   }
-  *out = (float)(-cmin * inv_eps + log(s));
+  *out = (float)(-cmin / g.eps + (double)log2_fast(s) * kLn2D);
 }
 
 template <int DIM>
