@@ -188,9 +188,10 @@ int ot_cost_and_grad(const ot_problem* prob, const float* f, const float* g, int
  *   n, K, dim (2 or 3), eps   as in ot_problem; points and marginals x, y [n, dim], a, b [n];
  *   tile_cfg   lanes cooperating on one row in the solve (16, 32, 64; 0 = by size) -- the
  *              value the autotuner picks per size bucket;
- *   logK       scratch of 2 m mp + 2 m floats, 16-byte aligned, mp = m rounded up to a
- *              multiple of 4 (folded kernel and its transpose with padded rows, folded
- *              marginals);
+ *   logK       scratch of 2 m mp + 2 m + 2 (2 mp + 64) floats, 16-byte aligned, mp = m
+ *              rounded up to a multiple of 4 (folded kernel and its transpose with padded
+ *              rows, folded marginals, then 2 mp + 64 64-bit exchange slots used when
+ *              several workgroups solve the problem together);
  *   f, g [m]   out: reduced potentials (g is also the warm-start input);
  *   dx, dy [m, dim] out or NULL: gradients of the full objective w.r.t. the first block's
  *              points, dP/dx_i = 2 sum_{k,j} T_ijk (x_i - y_{km+j}) and
@@ -215,8 +216,10 @@ typedef struct ot_batch_desc {
 /* Number of int32 entries of a batch plan for `count` problems. */
 size_t ot_batched_plan_len(int32_t count);
 
-/* [host] Plan a batch: the work-queue order (largest problems first) and the tile offsets of
- * the fold and value kernels.  `host_descs` is a host copy of the descriptor array; `plan`
+/* [host] Plan a batch: the work-queue order (largest problems first), the tile offsets of
+ * the fold and value kernels and the solve tasks (problems above m = 256 are solved by a gang
+ * of ceil(m / 128) workgroups, at most 32, that exchange potentials through the problem's
+ * scratch).  `host_descs` is a host copy of the descriptor array; `plan`
  * [host] receives ot_batched_plan_len(count) int32 values that the caller copies to the
  * device.  Errors: OT_ERR_ARG (bad descriptor), OT_ERR_UNSUPPORTED (too many tiles). */
 int ot_batched_plan(const ot_batch_desc* host_descs, int32_t count, int32_t* plan);
@@ -227,8 +230,9 @@ size_t ot_batched_workspace_bytes(int32_t count);
 /* Many independent cyclic problems of uneven size (the reduced path of Alg. 2 for each):
  * fold, cyclic Sinkhorn to tol (each problem stops on its own), objective values, float64
  * marginal errors and first-block gradients.  Four launches on `stream`: a tiled fold, ONE
- * persistent solve launch whose workgroups pop problems from a device work queue, a tiled
- * value/gradient kernel and a per-problem finalize.  No host synchronisation, memset or
+ * persistent solve launch (one workgroup per CU, all resident) whose workgroups pop tasks --
+ * a whole small problem or one member's share of a large one -- from a device work queue, a
+ * tiled value/gradient kernel and a per-problem finalize.  No host synchronisation, memset or
  * allocation, so the call can be captured in a HIP graph.  `plan` is the device copy of
  * ot_batched_plan's output for the same descriptors; fold_tiles and value_tiles are its first
  * two entries (plan[0], plan[1]), passed by value so that no device read is needed.  opts:

@@ -50,6 +50,13 @@ def _setup_lib():
 _lib = _setup_lib()
 
 
+def scratch_floats(m: int) -> int:
+    """Floats of per-problem scratch that ot_sinkhorn_reduced_batched expects (a multiple
+    of 4, so that consecutive scratches stay 16-byte aligned)."""
+    mp = (m + 3) // 4 * 4
+    return (2 * m * mp + 2 * m + 2 * (2 * mp + 64) + 3) // 4 * 4
+
+
 def size_bucket(m: int) -> str:
     """Power-of-two bucket of the block size used by the tuning table."""
     b = 1
@@ -91,8 +98,9 @@ class Batch:
         oxy = off([n * d for n, d in zip(ns, dims)])
         oab = off(ns)
         # scratch per problem: logK and its transpose with rows padded to mp = m rounded up
-        # to 4 floats, then alpha and beta; each problem's scratch starts 16-byte aligned
-        osc = off([(2 * m * ((m + 3) // 4 * 4) + 2 * m + 3) // 4 * 4 for m in ms])
+        # to 4 floats, alpha and beta, then the exchange slots of a gang solve (2 mp + 64
+        # 64-bit words); each problem's scratch starts 16-byte aligned
+        osc = off([scratch_floats(m) for m in ms])
         ofg = off(ms)
         ogr = off([m * d for m, d in zip(ms, dims)])
         f32 = dict(dtype=torch.float32, device=dev)

@@ -29,6 +29,7 @@ constexpr int kBT = 16;            // rows (or columns) per fold / values tile
 constexpr int kBSolveThreads = 1024;
 constexpr int kBSolveWaves = kBSolveThreads / kWave;
 constexpr int kBMaxLds = 148 * 1024;
+constexpr int kMaxGangF = 32;      // largest gang (workgroups cooperating on one problem)
 
 __device__ __forceinline__ int find_problem(const int32_t* __restrict__ start, int count, int b) {
   int lo = 0, hi = count - 1;  // largest p with start[p] <= b
@@ -56,39 +57,82 @@ __device__ __forceinline__ Real bcost(const float* __restrict__ x, int I,
 }
 
 // ---- 1. fold -------------------------------------------------------------------------------
+// A tile is 16 rows of one problem; a thread owns one column j and 4 of the rows, so each
+// y_{k m + j} it loads feeds 4 cost evaluations.  Two passes over k: the minimum cost per row,
+// then the shifted exponential sum.  fp64 (default): costs, minimum and shifted exponents in
+// float64, exponentials of the (non-positive) shifted exponents in float32 -- logK accurate
+// to float32 rounding; otherwise all float32.  Output in base 2 (log2 of the folded kernel).
+constexpr int kFoldQ = 4;  // rows per thread
+
+template <int DIM, typename Real>
+__device__ __forceinline__ void fold_cols(const ot_batch_desc& d, int i0, int rows, float* L,
+                                          float* LT) {
+  const int m = bm(d), K = d.K, mp = bmp(m);
+  const Real s2 = (Real)(kLog2eD / d.eps);
+  const int groups = (rows + kFoldQ - 1) / kFoldQ;
+  for (int e = threadIdx.x; e < groups * m; e += blockDim.x) {
+    const int g = e / m, j = e - g * m;
+    const int ib = i0 + g * kFoldQ;
+    Real xq[kFoldQ][DIM], cmin[kFoldQ];
+#pragma unroll
+    for (int q = 0; q < kFoldQ; ++q) {
+      const int i = min(ib + q, i0 + rows - 1);
+#pragma unroll
+      for (int dd = 0; dd < DIM; ++dd) xq[q][dd] = (Real)d.x[(int64_t)i * DIM + dd];
+      cmin[q] = (Real)3.0e38;
+    }
+    for (int k = 0; k < K; ++k) {
+      Real yv[DIM];
+#pragma unroll
+      for (int dd = 0; dd < DIM; ++dd) yv[dd] = (Real)d.y[(int64_t)(k * m + j) * DIM + dd];
+#pragma unroll
+      for (int q = 0; q < kFoldQ; ++q) {
+        Real c = 0;
+#pragma unroll
+        for (int dd = 0; dd < DIM; ++dd) { const Real df = xq[q][dd] - yv[dd]; c = fma(df, df, c); }
+        cmin[q] = c < cmin[q] ? c : cmin[q];
+      }
+    }
+    float sum[kFoldQ] = {};
+    for (int k = 0; k < K; ++k) {
+      Real yv[DIM];
+#pragma unroll
+      for (int dd = 0; dd < DIM; ++dd) yv[dd] = (Real)d.y[(int64_t)(k * m + j) * DIM + dd];
+#pragma unroll
+      for (int q = 0; q < kFoldQ; ++q) {
+        Real c = 0;
+#pragma unroll
+        for (int dd = 0; dd < DIM; ++dd) { const Real df = xq[q][dd] - yv[dd]; c = fma(df, df, c); }
+        sum[q] += exp2_fast((float)((cmin[q] - c) * s2));
+      }
+    }
+    float v[kFoldQ];
+#pragma unroll
+    for (int q = 0; q < kFoldQ; ++q) v[q] = (float)(-cmin[q] * s2 + (Real)log2_fast(sum[q]));
+#pragma unroll
+    for (int q = 0; q < kFoldQ; ++q)
+      if (ib + q < i0 + rows) L[(size_t)(ib + q) * mp + j] = v[q];
+    float* lt = LT + (size_t)j * mp + ib;  // ib is a multiple of 4 and mp too: 16-byte aligned
+    if (ib + kFoldQ <= i0 + rows) {
+      *reinterpret_cast<float4*>(lt) = make_float4(v[0], v[1], v[2], v[3]);
+    } else {
+      for (int q = 0; q < kFoldQ && ib + q < i0 + rows; ++q) lt[q] = v[q];
+    }
+  }
+}
+
 template <int DIM>
 __device__ void fold_tile(const ot_batch_desc& d, int i0, int fp64_mode) {
   const int m = bm(d), K = d.K, mp = bmp(m);
   float* L = d.logK;
   float* LT = L + (size_t)m * mp;
-  const bool fp64 = fp64_mode != 0;  // -1 (default) and 1: float64 exponents
-  const double ie = 1.0 / d.eps;
   const int rows = min(kBT, m - i0);
-  for (int e = threadIdx.x; e < rows * mp; e += blockDim.x) {
-    const int i = i0 + e / mp, j = e - (e / mp) * mp;
-    if (j >= m) {  // padding: -inf contributes nothing to a log-sum-exp
-      L[(size_t)i * mp + j] = -INFINITY;
-      continue;
-    }
-    float v;
-    if (fp64) {  // float64 costs and shifted exponents, float32 exponentials of those (<= 0)
-      const double s2d = kLog2eD * ie;
-      double cmin = 1.0e300;
-      for (int k = 0; k < K; ++k) cmin = fmin(cmin, bcost<DIM, double>(d.x, i, d.y, k * m + j));
-      float s = 0.0f;
-      for (int k = 0; k < K; ++k)
-        s += exp2_fast((float)((cmin - bcost<DIM, double>(d.x, i, d.y, k * m + j)) * s2d));
-      v = (float)(-cmin * s2d + (double)log2_fast(s));
-    } else {
-      const float s2 = (float)(kLog2eD * ie);
-      float cmin = 3.0e38f;
-      for (int k = 0; k < K; ++k) cmin = fminf(cmin, bcost<DIM, float>(d.x, i, d.y, k * m + j));
-      float s = 0.0f;
-      for (int k = 0; k < K; ++k) s += exp2_fast((cmin - bcost<DIM, float>(d.x, i, d.y, k * m + j)) * s2);
-      v = -cmin * s2 + log2_fast(s);
-    }
-    L[(size_t)i * mp + j] = v;
-    LT[(size_t)j * mp + i] = v;
+  if (fp64_mode != 0) fold_cols<DIM, double>(d, i0, rows, L, LT);
+  else fold_cols<DIM, float>(d, i0, rows, L, LT);
+  // padding: -inf contributes nothing to a log-sum-exp
+  for (int e = threadIdx.x; e < rows * (mp - m); e += blockDim.x) {
+    const int i = i0 + e / (mp - m), j = m + e % (mp - m);
+    L[(size_t)i * mp + j] = -INFINITY;
   }
   // padding columns of the transpose (rows j < m, columns i in [m, mp)) are written by the
   // first tile
@@ -97,6 +141,10 @@ __device__ void fold_tile(const ot_batch_desc& d, int i0, int fp64_mode) {
       const int j = e / (mp - m), i = m + e % (mp - m);
       LT[(size_t)j * mp + i] = -INFINITY;
     }
+  }
+  if (i0 == 0) {  // exchange slots of a gang solve: epochs start at 1, so zero means "none"
+    uint32_t* sw = reinterpret_cast<uint32_t*>(LT + (size_t)m * mp + 2 * (size_t)m);
+    for (int e = threadIdx.x; e < 2 * (2 * mp + 2 * kMaxGangF); e += blockDim.x) sw[e] = 0u;
   }
   if (i0 == 0) {  // folded marginals
     float* al = LT + (size_t)m * mp;
@@ -182,8 +230,9 @@ __device__ __forceinline__ float grp_lse2(const float* row, const float* vec, in
 struct BSolveArgs {
   const ot_batch_desc* descs;
   int count;
-  const int32_t* order;   // problems, largest first
-  uint32_t* queue;        // [0] next position, zeroed before the launch
+  const int32_t* ntasks;  // device: number of tasks (plan entry 3)
+  const uint32_t* tasks;  // work queue, largest problems first: problem | member << 20 | (G-1) << 26
+  uint32_t* queue;        // [0] next position, [1] abort flag; zeroed before the launch
   double tol;
   int max_iter;
   int warm;
@@ -280,22 +329,198 @@ __device__ void solve_one(const ot_batch_desc& d, const BSolveArgs& a, float* ld
   __syncthreads();
 }
 
+// Exchange area of a problem's scratch, after its folded kernel, transpose and marginals:
+// F and G slots (mp each) and residual-partial slots (2 x kMaxGang), 64-bit each.
+constexpr int kMaxGang = kMaxGangF;
+__device__ __forceinline__ uint64_t* gang_slots(const ot_batch_desc& d) {
+  const int m = bm(d), mp = bmp(m);
+  return reinterpret_cast<uint64_t*>(d.logK + 2 * (size_t)m * mp + 2 * (size_t)m);
+}
+
+// Shifted sum over j < mp of 2^(row_j + vec_j + sh) by one wave (rows padded with -inf up to
+// mp, a multiple of 4); every lane returns it.  See the reduced solver for why no maximum is
+// needed when sh is the row's previous potential.
+__device__ __forceinline__ float wave_shifted_sum_g(const float* __restrict__ row,
+                                                    const float* __restrict__ vec, int mp,
+                                                    int lane, float sh) {
+  float s = 0.0f;
+  for (int q = 4 * lane; q < mp; q += 4 * kWave) {
+    const float4 l = *reinterpret_cast<const float4*>(row + q);
+    const float4 v = *reinterpret_cast<const float4*>(vec + q);
+    s += exp2_fast(l.x + (v.x + sh)) + exp2_fast(l.y + (v.y + sh)) +
+         exp2_fast(l.z + (v.z + sh)) + exp2_fast(l.w + (v.w + sh));
+  }
+  return wave_sum_v(s);
+}
+
+constexpr float kMinShiftedSumB = 0x1p-60f;
+
+// One potential update of row (or column) `row` by one wave: lm - LSE2_j(row_j + vec_j),
+// shifted by the previous potential when `shifted`, exact otherwise or when the shifted sum
+// is out of range.  *S receives the previous plan's marginal sum, or -1 when not available.
+__device__ __forceinline__ float gang_update(const float* row, const float* vec, int mp,
+                                             int lane, float lm, float prev, bool shifted,
+                                             float* S) {
+  if (shifted) {
+    const float s = wave_shifted_sum_g(row, vec, mp, lane, prev);
+    if (s >= kMinShiftedSumB && s < INFINITY) {
+      *S = s;
+      return lm - log2_fast(s) + prev;
+    }
+  }
+  *S = -1.0f;
+  return lm - grp_lse2<64>(row, vec, mp, lane);
+}
+
+// A large problem solved by a gang of G workgroups (member k owns rows and columns
+// [k R, k R + R), R = ceil(m / G)); the rows of the folded kernel stream from the scratch in
+// global memory.  Same iteration, exchange and lagged stop test as the single-problem reduced
+// solver: potentials and residual partials travel in epoch-tagged slots (agent scope; the
+// members may sit on any XCD), two barriers per iteration, every member takes the same stop
+// decision from the same partials.
+__device__ void solve_gang(const ot_batch_desc& d, const BSolveArgs& a, int member, int G,
+                           float* lds, uint32_t* abort_flag) {
+  const int m = bm(d), K = d.K, mp = bmp(m);
+  const int R = (m + G - 1) / G;
+  const int r0 = member * R;
+  const int nr = max(0, min(R, m - r0));
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+  const float* gL = d.logK;
+  const float* gLT = gL + (size_t)m * mp;
+  const float* galpha = gLT + (size_t)m * mp;
+  const float* gbeta = galpha + m;
+  uint64_t* fx = gang_slots(d);
+  uint64_t* gx = fx + mp;
+  uint64_t* rsx = gx + mp;  // [2][kMaxGang]
+  float* VsG = lds;                 // [mp]
+  float* VsF = VsG + mp;            // [mp]
+  float* la2 = VsF + mp;            // [R] own rows / columns
+  float* lb2 = la2 + R;
+  float* av = lb2 + R;
+  float* Fcur = av + R;
+  float* Fprev = Fcur + R;
+  float* Fold = Fprev + R;
+  float* Gcur = Fold + R;
+  float* Gprev = Gcur + R;
+  float* rsv = Gprev + R;           // [kMaxGang]
+  float* wsum = rsv + kMaxGang;     // [kBSolveWaves]
+  int* flag = reinterpret_cast<int*>(wsum + kBSolveWaves);  // [0] s_bad
+  const float s2 = (float)(kLog2eD / d.eps);
+  for (int rl = tid; rl < R; rl += blockDim.x) {
+    const bool ok = rl < nr;
+    la2[rl] = ok ? log2f(galpha[r0 + rl]) : 0.0f;
+    lb2[rl] = ok ? log2f(gbeta[r0 + rl]) : 0.0f;
+    av[rl] = ok ? galpha[r0 + rl] : 0.0f;
+    Gcur[rl] = ok && a.warm ? d.g[r0 + rl] * s2 : 0.0f;
+    Gprev[rl] = Gcur[rl];
+    Fcur[rl] = Fprev[rl] = Fold[rl] = 0.0f;
+  }
+  for (int j = tid; j < mp; j += blockDim.x) {
+    VsG[j] = (j < m && a.warm) ? d.g[j] * s2 : 0.0f;
+    VsF[j] = 0.0f;
+  }
+  if (tid == 0) flag[0] = 0;
+  __syncthreads();
+  const double tol2 = a.tol * a.tol / (double)K;
+  int iters_done = 0, converged = 0, flags = 0;
+  for (uint32_t t = 1;; ++t) {
+    float racc = 0.0f;
+    for (int rl = wv; rl < nr; rl += kBSolveWaves) {
+      float S;
+      const float Fo = Fcur[rl];
+      const float Fn = gang_update(gL + (size_t)(r0 + rl) * mp, VsG, mp, lane, la2[rl], Fo,
+                                   t >= 2, &S);
+      if (lane == 0) {
+        if (t >= 2) {
+          const float rr = S >= 0.0f ? S - av[rl] : scaled_exp2m1(av[rl], Fo - Fn);
+          racc += rr * rr;
+        }
+        Fold[rl] = Fprev[rl];
+        Fprev[rl] = Fo;
+        Fcur[rl] = Fn;
+        slot_publish(fx + r0 + rl, Fn, t);
+      }
+    }
+    if (lane == 0) wsum[wv] = racc;
+    if (t >= 3) {  // stop test on the state after t-2, the same in every wave and member
+      float sres = 0.0f;
+      for (int v = lane; v < G; v += kWave) sres += rsv[v];
+      sres = wave_sum_v(sres);
+      const bool fin = sres == sres && sres < 3.0e38f;
+      converged = fin && (double)sres <= tol2;
+      if (!fin) flags |= 1;
+      if ((converged && tol2 > 0.0) || !fin || (int)(t - 2) >= a.max_iter) {
+        iters_done = (int)t - 2;
+        break;
+      }
+    }
+    if (!stage_slots(fx, m, mp, t, VsF, nullptr, 0, 0, nullptr, abort_flag, flag)) {
+      flags |= 2;
+      break;
+    }
+    if (wv == 0 && t >= 2) {
+      float sw = lane < kBSolveWaves ? wsum[lane] : 0.0f;
+      sw = wave_sum_v(sw);
+      if (lane == 0) slot_publish(rsx + (t & 1u) * kMaxGang + member, sw, t);
+    }
+    for (int cl = wv; cl < nr; cl += kBSolveWaves) {
+      float S;
+      const float Go = Gcur[cl];
+      const float Gn = gang_update(gLT + (size_t)(r0 + cl) * mp, VsF, mp, lane, lb2[cl], Go,
+                                   true, &S);
+      if (lane == 0) {
+        Gprev[cl] = Go;
+        Gcur[cl] = Gn;
+        slot_publish(gx + r0 + cl, Gn, t);
+      }
+    }
+    const int nres = t >= 2 ? G : 0;
+    if (!stage_slots(gx, m, mp, t, VsG, rsx + (t & 1u) * kMaxGang, nres, t, rsv, abort_flag,
+                     flag)) {
+      flags |= 2;
+      break;
+    }
+  }
+  // outputs: the state after iteration iters_done, (F^{t-2}, G^{t-2}) as in the reduced solver
+  __syncthreads();
+  const float to_nat = (float)(d.eps * kLn2D);
+  for (int rl = tid; rl < nr; rl += blockDim.x) {
+    d.f[r0 + rl] = Fold[rl] * to_nat;
+    d.g[r0 + rl] = Gprev[rl] * to_nat;
+  }
+  if (tid == 0 && (member == 0 || flags)) {
+    if (member == 0) {
+      d.out[5] = (double)iters_done;
+      d.out[6] = (double)converged;
+    }
+    if (member == 0 || flags) d.out[7] = (double)flags;
+  }
+  __syncthreads();
+}
+
 __global__ void __launch_bounds__(kBSolveThreads) batched_solve_kernel(BSolveArgs a) {
   extern __shared__ float4 lds4[];
   float* lds = reinterpret_cast<float*>(lds4);
   __shared__ float red[kBSolveWaves];
-  __shared__ int s_p;
+  __shared__ uint32_t s_task;
   const size_t lds_floats = (size_t)kBMaxLds / sizeof(float);
   for (;;) {
     if (threadIdx.x == 0) {
       const uint32_t pos = __hip_atomic_fetch_add(a.queue, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      s_p = pos < (uint32_t)a.count ? a.order[pos] : -1;
+      s_task = pos < (uint32_t)*a.ntasks ? a.tasks[pos] : 0xffffffffu;
     }
     __syncthreads();
-    const int p = s_p;
+    const uint32_t task = s_task;
     __syncthreads();
-    if (p < 0) return;  // queue drained: every workgroup reaches this
+    if (task == 0xffffffffu) return;  // queue drained: every workgroup reaches this
+    const int p = (int)(task & 0xfffffu);
+    const int member = (int)((task >> 20) & 63u);
+    const int G = (int)(task >> 26) + 1;
     const ot_batch_desc d = a.descs[p];
+    if (G > 1) {
+      solve_gang(d, a, member, G, lds, a.queue + 1);
+      continue;
+    }
     const int m = bm(d);
     const int lpr = d.tile_cfg == 16 || d.tile_cfg == 32 || d.tile_cfg == 64
                         ? d.tile_cfg : (m >= 512 ? 64 : m >= 128 ? 32 : 16);
@@ -310,8 +535,11 @@ __global__ void __launch_bounds__(kBSolveThreads) batched_solve_kernel(BSolveArg
 // wave owns 4 points and its lanes stride over the partner points, so one partner load feeds
 // four entries).
 // acc[p]: {P, <C,T>, mass, sum (rowsum - alpha)^2, sum (colsum - beta)^2, <f,alpha>, <g,beta>}
+constexpr int kVChunk = 1024;  // partner points staged in LDS at a time
+
 template <int DIM, bool ROW>
-__device__ void values_tile(const ot_batch_desc& d, int a0, double* __restrict__ acc) {
+__device__ void values_tile(const ot_batch_desc& d, int a0, double* __restrict__ acc,
+                           float4* __restrict__ sP, float4* __restrict__ sC) {
   constexpr int Q = 4;
   const int m = bm(d), K = d.K, mp = bmp(m);
   const float* L = d.logK;
@@ -319,11 +547,10 @@ __device__ void values_tile(const ot_batch_desc& d, int a0, double* __restrict__
   const float* al = LT + (size_t)m * mp;
   const float* be = al + m;
   const float s2 = (float)(kLog2eD / d.eps);
-  const float eps = (float)d.eps;
-  const double ie = 1.0 / d.eps;
+  const double s2d = kLog2eD / d.eps;
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-  const int A0 = a0 + wv * Q;  // first own point of this wave (row i or column j, < m)
-  if (A0 >= m) return;
+  const int A0 = a0 + wv * Q;  // first own point of this wave (row i or column j)
+  const bool active = A0 < m;  // inactive waves still stage partners and meet the barriers
   const float* ownp = ROW ? d.x : d.y;
   const float* othp = ROW ? d.y : d.x;
   int Aq[Q];
@@ -336,62 +563,91 @@ __device__ void values_tile(const ot_batch_desc& d, int a0, double* __restrict__
     pa[q] = ROW ? d.f[Aq[q]] : d.g[Aq[q]];
     tP[q] = tC[q] = tM[q] = 0.0f;
   }
-  for (int k = 0; k < K; ++k) {
-    // ROW: partner column k m + b of block-row 0; COL: partner row r m + b, r = (K - k) mod K,
-    // whose entry with column j is T_{b j k}
-    const int r = (K - k) % K;
-    float yk[Q][DIM];  // COL: y_{k m + j} of the own columns j
-#pragma unroll
-    for (int q = 0; q < Q; ++q)
-#pragma unroll
-      for (int dd = 0; dd < DIM; ++dd) yk[q][dd] = ROW ? 0.0f : d.y[(int64_t)(k * m + Aq[q]) * DIM + dd];
-    for (int b = lane; b < m; b += kWave) {
-      const int P = ROW ? k * m + b : r * m + b;
-      float pp[DIM], cb[DIM];
-#pragma unroll
-      for (int dd = 0; dd < DIM; ++dd) {
-        pp[dd] = othp[(int64_t)P * DIM + dd];
-        // COL: the cost uses block-row 0's row point x_b
-        cb[dd] = ROW ? pp[dd] : d.x[(int64_t)b * DIM + dd];
+  // Partner points b of a chunk are staged in LDS: sC[b] = {cost point, partner potential}
+  // once per chunk (ROW: nothing but g_b; COL: x_b of block-row 0 and f_b), sP[b] = the
+  // gradient partner of block k (ROW: y_{k m + b}; COL: x_{r m + b}, r = (K - k) mod K, whose
+  // entry with column j is T_{b j k}).
+  for (int c0 = 0; c0 < m; c0 += kVChunk) {
+    const int nc = min(kVChunk, m - c0);
+    __syncthreads();  // the previous chunk's readers are done
+    for (int b = threadIdx.x; b < nc; b += blockDim.x) {
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (!ROW) {
+        v.x = d.x[(int64_t)(c0 + b) * DIM];
+        v.y = d.x[(int64_t)(c0 + b) * DIM + 1];
+        if (DIM == 3) v.z = d.x[(int64_t)(c0 + b) * DIM + 2];
       }
-      const float ob = ROW ? d.g[b] : d.f[b];
+      v.w = ROW ? d.g[c0 + b] : d.f[c0 + b];
+      sC[b] = v;
+    }
+    for (int k = 0; k < K; ++k) {
+      const int r = (K - k) % K;
+      const int pbase = (ROW ? k : r) * m + c0;
+      __syncthreads();  // sP of the previous block is no longer read
+      for (int b = threadIdx.x; b < nc; b += blockDim.x) {
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        v.x = othp[(int64_t)(pbase + b) * DIM];
+        v.y = othp[(int64_t)(pbase + b) * DIM + 1];
+        if (DIM == 3) v.z = othp[(int64_t)(pbase + b) * DIM + 2];
+        sP[b] = v;
+      }
+      __syncthreads();
+      if (!active) continue;
+      float yk[Q][DIM];  // COL: y_{k m + j} of the own columns j
 #pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        float c = 0.0f;
-        if (ROW) {
+      for (int q = 0; q < Q; ++q)
 #pragma unroll
-          for (int dd = 0; dd < DIM; ++dd) { const float df = po[q][dd] - cb[dd]; c = fmaf(df, df, c); }
-        } else {
-          // C_{b, j, k} = |x_b - y_{k m + j}|^2
+        for (int dd = 0; dd < DIM; ++dd) yk[q][dd] = ROW ? 0.0f : d.y[(int64_t)(k * m + Aq[q]) * DIM + dd];
+      for (int b = lane; b < nc; b += kWave) {
+        const float4 P4 = sP[b];
+        const float4 C4 = sC[b];
+        const float pp[3] = {P4.x, P4.y, P4.z};
+        // ROW: the cost uses the partner itself; COL: block-row 0's row point x_b
+        const float cb[3] = {ROW ? P4.x : C4.x, ROW ? P4.y : C4.y, ROW ? P4.z : C4.z};
+        const float ob = C4.w;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          float c = 0.0f;
 #pragma unroll
           for (int dd = 0; dd < DIM; ++dd) {
-            const float df = cb[dd] - yk[q][dd];
+            // ROW: C_{i, b, k} = |x_i - y_{k m + b}|^2; COL: C_{b, j, k} = |x_b - y_{k m + j}|^2
+            const float df = ROW ? po[q][dd] - cb[dd] : cb[dd] - yk[q][dd];
             c = fmaf(df, df, c);
           }
-        }
-        const float fg = pa[q] + ob;
-        const float T = exp2_fast((fg - c) * s2);
+          const float T = exp2_fast((pa[q] + ob - c) * s2);
 #pragma unroll
-        for (int dd = 0; dd < DIM; ++dd) gacc[q][dd] = fmaf(T, po[q][dd] - pp[dd], gacc[q][dd]);
-        if (ROW) {
-          const float z = (fg - c) / eps;
-          tP[q] = fmaf(T, c + eps * (z - 1.0f), tP[q]);
-          tC[q] = fmaf(T, c, tC[q]);
-          tM[q] += T;
+          for (int dd = 0; dd < DIM; ++dd) gacc[q][dd] = fmaf(T, po[q][dd] - pp[dd], gacc[q][dd]);
+          if (ROW) {
+            // C + eps (Z - 1) = f_i + g_j - eps with Z = (f_i + g_j - C) / eps: the primal
+            // term needs only the plan's g-weighted sum besides its mass
+            tP[q] = fmaf(T, ob, tP[q]);
+            tC[q] = fmaf(T, c, tC[q]);
+            tM[q] += T;
+          }
         }
       }
     }
   }
+  if (!active) return;
   double vP = 0.0, vC = 0.0, vM = 0.0, v2 = 0.0, vd = 0.0;
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const bool ok = A0 + q < m;
-    // float64 marginal sum of own point from logK (base 2 in the scratch)
-    double ms = 0.0;
+    // marginal sum of the own point from logK (base 2 in the scratch): float64 exponents and
+    // sums, float32 exponentials of the exponents less the own potential's part, scaled back
+    // exactly (the terms of a converged row are at most the row's marginal, far from
+    // under- or overflow after the shift)
     const float* Lrow = (ROW ? L : LT) + (size_t)Aq[q] * mp;
+    const double own2 = (double)pa[q] * s2d;
+    const float* opot = ROW ? d.g : d.f;
+    float emax = -INFINITY;
     for (int b = lane; b < m; b += kWave)
-      ms += exp((double)Lrow[b] * kLn2D + ((double)pa[q] + (double)(ROW ? d.g[b] : d.f[b])) * ie);
-    ms = wave_sum_d(ms);
+      emax = fmaxf(emax, (float)((double)Lrow[b] + (double)opot[b] * s2d + own2));
+    const double sh2 = (double)wave_max_v(emax);
+    double ms = 0.0;
+    for (int b = lane; b < m; b += kWave)
+      ms += (double)exp2_fast((float)((double)Lrow[b] + (double)opot[b] * s2d + own2 - sh2));
+    ms = wave_sum_d(ms) * exp2(sh2);
     const double target = ROW ? (double)al[Aq[q]] : (double)be[Aq[q]];
 #pragma unroll
     for (int dd = 0; dd < DIM; ++dd) {
@@ -400,9 +656,10 @@ __device__ void values_tile(const ot_batch_desc& d, int a0, double* __restrict__
       if (lane == 0 && dst && ok) dst[(int64_t)Aq[q] * DIM + dd] = 2.0f * gsum;
     }
     if (ROW) {
-      const double P = wave_sum_d((double)tP[q]), C = wave_sum_d((double)tC[q]),
+      const double Tg = wave_sum_d((double)tP[q]), C = wave_sum_d((double)tC[q]),
                    Ms = wave_sum_d((double)tM[q]);
-      if (ok) { vP += P; vC += C; vM += Ms; }
+      // sum_{j,k} T_ijk (f_i + g_j - eps)
+      if (ok) { vP += ((double)pa[q] - d.eps) * Ms + Tg; vC += C; vM += Ms; }
     }
     if (ok) {
       v2 += (ms - target) * (ms - target);
@@ -434,8 +691,9 @@ __global__ void __launch_bounds__(256)
   double* acc = accs + 8 * (size_t)p;
   const bool row = t < nrow;
   const int a0 = (row ? t : t - nrow) * kBT;
-  if (d.dim == 3) { if (row) values_tile<3, true>(d, a0, acc); else values_tile<3, false>(d, a0, acc); }
-  else { if (row) values_tile<2, true>(d, a0, acc); else values_tile<2, false>(d, a0, acc); }
+  __shared__ float4 sP[kVChunk], sC[kVChunk];
+  if (d.dim == 3) { if (row) values_tile<3, true>(d, a0, acc, sP, sC); else values_tile<3, false>(d, a0, acc, sP, sC); }
+  else { if (row) values_tile<2, true>(d, a0, acc, sP, sC); else values_tile<2, false>(d, a0, acc, sP, sC); }
 }
 
 __global__ void batched_finalize_kernel(const ot_batch_desc* __restrict__ descs, int count,
@@ -461,10 +719,21 @@ __global__ void zero_d_words(double* p, int64_t count) {
 // ---- host ----------------------------------------------------------------------------------
 static size_t a256(size_t v) { return (v + 255) / 256 * 256; }
 
-size_t batched_plan_len(int count) { return 4 + 3 * (size_t)count; }
+size_t batched_plan_len(int count) { return 4 + (3 + (size_t)kMaxGangF) * (size_t)count; }
 
-// plan = {nfold, nval, count, 0, order[count], fold_start[count], val_start[count]}
+// Workgroups that solve one problem together: one up to m = 256 (logK then costs a single
+// workgroup at most ~0.1 ms per solve), about 128 rows per member above.
+static int gang_size(int m) {
+  if (m <= 256) return 1;
+  const int g = (m + 127) / 128;
+  return g < kMaxGangF ? g : kMaxGangF;
+}
+
+// plan = {nfold, nval, count, ntasks, order[count], fold_start[count], val_start[count],
+//         tasks[ntasks]}; a task is problem | member << 20 | (G - 1) << 26, largest problems
+// first, the G members of a gang consecutive.
 int batched_plan(const ot_batch_desc* h, int count, int32_t* plan) {
+  if (count >= (1 << 20)) return -1;
   std::vector<int> idx(count);
   for (int p = 0; p < count; ++p) idx[p] = p;
   auto cost = [&](int p) {
@@ -475,7 +744,9 @@ int batched_plan(const ot_batch_desc* h, int count, int32_t* plan) {
   int32_t* order = plan + 4;
   int32_t* fstart = order + count;
   int32_t* vstart = fstart + count;
+  uint32_t* tasks = reinterpret_cast<uint32_t*>(vstart + count);
   int64_t nf = 0, nv = 0;
+  int nt = 0;
   for (int p = 0; p < count; ++p) {
     order[p] = idx[p];
     const int m = h[p].n / h[p].K;
@@ -485,11 +756,16 @@ int batched_plan(const ot_batch_desc* h, int count, int32_t* plan) {
     nf += tiles;
     nv += 2 * tiles;
   }
+  for (int q = 0; q < count; ++q) {
+    const int p = idx[q];
+    const int G = gang_size(h[p].n / h[p].K);
+    for (int k = 0; k < G; ++k) tasks[nt++] = (uint32_t)p | ((uint32_t)k << 20) | ((uint32_t)(G - 1) << 26);
+  }
   if (nf > INT32_MAX || nv > INT32_MAX) return -1;
   plan[0] = (int32_t)nf;
   plan[1] = (int32_t)nv;
   plan[2] = count;
-  plan[3] = 0;
+  plan[3] = nt;
   return 0;
 }
 
@@ -521,8 +797,13 @@ hipError_t launch_batched(const ot_batch_desc* descs, int count, const int32_t* 
   int dev = 0, cus = 0;
   if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
   if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-  BSolveArgs a{descs, count, order, queue, tol, max_iter, warm};
-  const int grid = count < cus ? count : cus;
+  // the device copy of the plan: task count in entry 3, tasks after val_start
+  const uint32_t* tasks = reinterpret_cast<const uint32_t*>(vstart + count);
+  BSolveArgs a{descs, count, dplan + 3, tasks, queue, tol, max_iter, warm};
+  // one workgroup per CU (the LDS request allows no more), all resident at once, so the
+  // members of a gang never wait on a workgroup that cannot start; workgroups that find the
+  // queue empty leave at once
+  const int grid = cus;
   hipLaunchKernelGGL(batched_solve_kernel, dim3(grid), dim3(kBSolveThreads), kBMaxLds, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(batched_values_kernel, dim3(nval), dim3(256), 0, s, descs, count, vstart, accs);

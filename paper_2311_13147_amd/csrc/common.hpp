@@ -265,6 +265,44 @@ __device__ __forceinline__ float slot_value(uint64_t w) {
   return __uint_as_float((uint32_t)(w & 0xffffffffull));
 }
 
+// Stage the m slots of `src` carrying `epoch` into Vs (zero padding up to mp) and, when
+// `extra` is non-null, the `nextra` slots of `extra` into xv.  Every thread issues all its
+// loads first and then waits on the ones not yet current, so both sets cost one round trip.
+// Returns false on abort.
+__device__ __forceinline__ bool stage_slots(uint64_t* src, int m, int mp, uint32_t epoch,
+                                            float* Vs, uint64_t* extra, int nextra,
+                                            uint32_t xepoch, float* xv, uint32_t* abort_flag,
+                                            int* s_bad) {
+  constexpr int kB = 2;
+  bool ok = true;
+  const int total = mp + nextra;
+  for (int base = threadIdx.x; base < total; base += kB * (int)blockDim.x) {
+    uint64_t w[kB];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      const int j = base + u * (int)blockDim.x;
+      w[u] = j < m ? slot_load(src + j)
+                   : (j >= mp && j < total) ? slot_load(extra + (j - mp)) : 0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      const int j = base + u * (int)blockDim.x;
+      if (j < m) {
+        if (ok) ok = slot_wait(src + j, w[u], epoch, abort_flag);
+        Vs[j] = slot_value(w[u]);
+      } else if (j < mp) {
+        Vs[j] = 0.0f;
+      } else if (j < total) {
+        if (ok) ok = slot_wait(extra + (j - mp), w[u], xepoch, abort_flag);
+        xv[j - mp] = slot_value(w[u]);
+      }
+    }
+  }
+  if (!ok) *s_bad = 1;
+  __syncthreads();
+  return *s_bad == 0;
+}
+
 // Zero `count` 32-bit words (control blocks) -- a kernel rather than a memset so that a
 // captured graph holds no memset node.
 __global__ void zero_words_kernel(uint32_t* p, int count);

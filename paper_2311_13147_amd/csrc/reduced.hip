@@ -122,44 +122,6 @@ __device__ __forceinline__ float wave_update(const float* __restrict__ row,
   return Fn;
 }
 
-// Stage the m slots of `src` carrying `epoch` into Vs (zero padding up to mp) and, when
-// `extra` is non-null, the `nextra` slots of `extra` into xv.  Every thread issues all its
-// loads first and then waits on the ones not yet current, so both sets cost one round trip.
-// Returns false on abort.
-__device__ __forceinline__ bool stage_slots(uint64_t* src, int m, int mp, uint32_t epoch,
-                                            float* Vs, uint64_t* extra, int nextra,
-                                            uint32_t xepoch, float* xv, uint32_t* abort_flag,
-                                            int* s_bad) {
-  constexpr int kB = 2;
-  bool ok = true;
-  const int total = mp + nextra;
-  for (int base = threadIdx.x; base < total; base += kB * kRedThreads) {
-    uint64_t w[kB];
-#pragma unroll
-    for (int u = 0; u < kB; ++u) {
-      const int j = base + u * kRedThreads;
-      w[u] = j < m ? slot_load(src + j)
-                   : (j >= mp && j < total) ? slot_load(extra + (j - mp)) : 0ull;
-    }
-#pragma unroll
-    for (int u = 0; u < kB; ++u) {
-      const int j = base + u * kRedThreads;
-      if (j < m) {
-        if (ok) ok = slot_wait(src + j, w[u], epoch, abort_flag);
-        Vs[j] = slot_value(w[u]);
-      } else if (j < mp) {
-        Vs[j] = 0.0f;
-      } else if (j < total) {
-        if (ok) ok = slot_wait(extra + (j - mp), w[u], xepoch, abort_flag);
-        xv[j - mp] = slot_value(w[u]);
-      }
-    }
-  }
-  if (!ok) *s_bad = 1;
-  __syncthreads();
-  return *s_bad == 0;
-}
-
 __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p) {
   extern __shared__ float4 lds4[];
   float* lds = reinterpret_cast<float*>(lds4);

@@ -156,3 +156,24 @@ def test_reserved_option_must_be_zero_and_events_field_layout(B):
     o.reserved = 1
     assert lib.ot_fold_kernel(ctypes.byref(p), ctypes.byref(o), 8, 8, 8, None, 0, None) == B.OT_ERR_ARG
     assert "reserved" in lib.ot_last_error().decode()
+
+
+def test_batched_plan_gang_tasks(B):
+    """Problems above m = 256 become ceil(m / 128) consecutive tasks (members 0..G-1), the
+    largest problem first; smaller ones one task each."""
+    import numpy as np
+    from paper_2311_13147_amd.batched import BatchDesc, _lib
+    shapes = [(64 * 4, 4), (512 * 2, 2), (1000 * 3, 3)]  # m = 64, 512, 1000
+    descs = (BatchDesc * 3)()
+    for d, (n, K) in zip(descs, shapes):
+        d.n, d.K, d.dim, d.eps = n, K, 2, 0.1
+        d.x = d.y = d.a = d.b = d.logK = d.f = d.g = d.out = 8
+    plan = (ctypes.c_int32 * _lib.ot_batched_plan_len(3))()
+    assert _lib.ot_batched_plan(descs, 3, plan) == 0
+    nt = plan[3]
+    assert nt == 8 + 4 + 1
+    tasks = np.frombuffer(plan, dtype=np.uint32)[4 + 3 * 3:4 + 3 * 3 + nt]
+    prob, member, gang = tasks & 0xFFFFF, (tasks >> 20) & 63, (tasks >> 26) + 1
+    assert list(prob) == [2] * 8 + [1] * 4 + [0]
+    assert list(member) == list(range(8)) + list(range(4)) + [0]
+    assert list(gang) == [8] * 8 + [4] * 4 + [1]
