@@ -73,26 +73,35 @@ __device__ __forceinline__ void fold_cols(const ot_batch_desc& d, int i0, int ro
   for (int e = threadIdx.x; e < groups * m; e += blockDim.x) {
     const int g = e / m, j = e - g * m;
     const int ib = i0 + g * kFoldQ;
+    // pass 1 (float32): the shift, the minimum cost up to float32 rounding -- any shift that
+    // close to the minimum keeps every shifted exponent <= ~0, and the same value is added
+    // back exactly
     Real xq[kFoldQ][DIM], cmin[kFoldQ];
+    float xf[kFoldQ][DIM], cminf[kFoldQ];
 #pragma unroll
     for (int q = 0; q < kFoldQ; ++q) {
       const int i = min(ib + q, i0 + rows - 1);
 #pragma unroll
-      for (int dd = 0; dd < DIM; ++dd) xq[q][dd] = (Real)d.x[(int64_t)i * DIM + dd];
-      cmin[q] = (Real)3.0e38;
+      for (int dd = 0; dd < DIM; ++dd) {
+        xf[q][dd] = d.x[(int64_t)i * DIM + dd];
+        xq[q][dd] = (Real)xf[q][dd];
+      }
+      cminf[q] = 3.0e38f;
     }
     for (int k = 0; k < K; ++k) {
-      Real yv[DIM];
+      float yv[DIM];
 #pragma unroll
-      for (int dd = 0; dd < DIM; ++dd) yv[dd] = (Real)d.y[(int64_t)(k * m + j) * DIM + dd];
+      for (int dd = 0; dd < DIM; ++dd) yv[dd] = d.y[(int64_t)(k * m + j) * DIM + dd];
 #pragma unroll
       for (int q = 0; q < kFoldQ; ++q) {
-        Real c = 0;
+        float c = 0.0f;
 #pragma unroll
-        for (int dd = 0; dd < DIM; ++dd) { const Real df = xq[q][dd] - yv[dd]; c = fma(df, df, c); }
-        cmin[q] = c < cmin[q] ? c : cmin[q];
+        for (int dd = 0; dd < DIM; ++dd) { const float df = xf[q][dd] - yv[dd]; c = fmaf(df, df, c); }
+        cminf[q] = fminf(c, cminf[q]);
       }
     }
+#pragma unroll
+    for (int q = 0; q < kFoldQ; ++q) cmin[q] = (Real)cminf[q];
     float sum[kFoldQ] = {};
     for (int k = 0; k < K; ++k) {
       Real yv[DIM];

@@ -225,6 +225,7 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
       const float Fo = Fcur[rl];
       const float Fn = wave_update(Ls + (size_t)rl * mp, VsG, mp, lane, la2[rl], Fo, t >= 2, &S);
       if (lane == 0) {
+        publish(p.fx + r0 + rl, Fn, t);  // first: the other workgroups wait for it
         if (t >= 2) {
           // residual of the state after t-1: its row sum minus alpha
           const float rr = S >= 0.0f ? S - av[rl] : scaled_exp2m1(av[rl], Fo - Fn);
@@ -233,7 +234,6 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
         Fold[rl] = Fprev[rl];
         Fprev[rl] = Fo;
         Fcur[rl] = Fn;
-        publish(p.fx + r0 + rl, Fn, t);
       }
     }
     if (lane == 0) wsum[wv] = racc;
@@ -269,9 +269,9 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
       const float Go = Gcur[cl];
       const float Gn = wave_update(LTs + (size_t)cl * mp, VsF, mp, lane, lb2[cl], Go, true, &S);
       if (lane == 0) {
+        publish(p.gx + r0 + cl, Gn, t);
         Gprev[cl] = Go;
         Gcur[cl] = Gn;
-        publish(p.gx + r0 + cl, Gn, t);
       }
     }
 
