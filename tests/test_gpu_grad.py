@@ -125,3 +125,43 @@ def test_dense_cost_autograd(lib):
     got = C.grad.cpu().numpy().astype(np.float64)
     assert np.abs(got - want).max() / want.max() < 1e-4
     assert abs(got.sum() - 1.0) < 1e-4          # K times the reduced mass 1/K
+
+
+def _fd_golden():
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "fd_grad_n4096_K8.json")
+    with open(path) as fh:
+        return json.load(fh)
+
+
+@pytest.mark.parametrize("path", ["cyclic", "full"])
+def test_gradients_match_asymmetric_finite_differences(lib, path):
+    """Single-coordinate perturbations of the full problem (they break the symmetry): central
+    differences of the float64 full-size solver, stored by tests/golden/make_fd_grad.py, at
+    32 point coordinates and 16 e_I - e_J marginal directions, against the GPU gradients of
+    both paths (the cyclic path's dx, dy cover all n points)."""
+    g = _fd_golden()
+    wl = g["workload"]
+    p = workloads.symmetric_problem(wl["n"], wl["K"], wl["dim"], wl["eps_factor"], seed=wl["seed"])
+    assert abs(p.eps - wl["eps"]) <= 1e-12 * wl["eps"]
+    print(f"[grad] {path} vs stored central differences", flush=True)
+    x, y, a, b = _t(p.x, True), _t(p.y, True), _t(p.a, True), _t(p.b, True)
+    if path == "cyclic":
+        P = lib.CyclicOT.apply(x, y, a, b, p.eps, p.K, 1e-7, 100000, 1)
+    else:
+        P = lib.FullOT.apply(x, y, a, b, p.eps, p.K, 1e-7, 100000)
+    P.backward()
+    assert abs(P.item() - g["value_P"]) <= 1e-5 * abs(g["value_P"])
+    grads = {"x": x.grad.cpu().numpy(), "y": y.grad.cpu().numpy(),
+             "a": a.grad.cpu().numpy().astype(np.float64),
+             "b": b.grad.cpu().numpy().astype(np.float64)}
+    scale = max(abs(c["fd"]) for c in g["coords"])
+    for c in g["coords"]:
+        got = float(grads[c["which"]][c["index"], c["comp"]])
+        assert abs(got - c["fd"]) <= 2e-4 * abs(c["fd"]) + 1e-5 * scale, (c, got)
+    for c in g["marginals"]:
+        v = grads[c["which"]]
+        got = v[c["I"]] - v[c["J"]]
+        assert abs(got - c["fd"]) <= 1e-4 * abs(c["fd"]) + 1e-6, (c, got)

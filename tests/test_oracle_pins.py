@@ -350,3 +350,27 @@ def test_projection_rows_from_points_equal_group_average():
     rows = [0, 4, 11]
     got = projection.project_rows_from_points(x, y, p.K, rows)
     assert np.abs(got - avg[rows]).max() < 1e-13
+
+
+def test_envelope_gradients_match_stored_asymmetric_differences():
+    """The envelope gradients of the converged float64 full solution at n = 4096, K = 8 against
+    the central differences stored by tests/golden/make_fd_grad.py (each from two further
+    float64 solves with one coordinate or one e_I - e_J marginal direction perturbed)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fd_grad_n4096_K8.json")
+    with open(path) as fh:
+        gold = json.load(fh)
+    wl = gold["workload"]
+    p = workloads.symmetric_problem(wl["n"], wl["K"], wl["dim"], wl["eps_factor"], seed=wl["seed"])
+    x, y, a, b = (v.astype(np.float64) for v in (p.x, p.y, p.a, p.b))
+    P, out = grad.solve_value(x, y, a, b, p.eps, tol=1e-12)
+    assert abs(P - gold["value_P"]) <= 1e-12 * abs(P)
+    g = grad.envelope_grads(out["f"], out["g"], x, y, p.eps)
+    for c in gold["coords"]:
+        got = g["dx" if c["which"] == "x" else "dy"][c["index"], c["comp"]]
+        assert abs(got - c["fd"]) <= 1e-6 * abs(c["fd"]) + 1e-9, c
+    for c in gold["marginals"]:
+        v = g["da" if c["which"] == "a" else "db"]
+        # h = 1e-7 and solves to a 1e-12 residual leave ~1e-6 relative in these differences
+        assert abs((v[c["I"]] - v[c["J"]]) - c["fd"]) <= 1e-5 * abs(c["fd"]) + 1e-9, c
