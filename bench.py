@@ -49,10 +49,49 @@ def _args():
     ap.add_argument("--fixed-full", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--batched", action="store_true",
+                    help="only time the batched workload (1024 uneven cyclic problems) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (the reference kernel "
                          "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE) and exit")
     return ap.parse_args()
+
+
+def batched_only(steps, warmup):
+    """The batched workload: 1024 cyclic problems, m log-uniform in [32, 1024], K in
+    {4, 8, 16, 32}, 2-D or 3-D, eps = 0.05 median each, tol 1e-6; fold, solve, objective
+    values and first-block gradients of all of them per call, timed with HIP events."""
+    import numpy as np
+    import torch
+
+    import paper_2311_13147_amd as csot
+    import workloads
+
+    items = workloads.batched_problems(1024)
+    probs = [dict(x=p.x, y=p.y, a=p.a, b=p.b, eps=p.eps, K=p.K)
+             for p in (workloads.symmetric_problem(it.m * it.K, it.K, it.dim, 0.05, seed=it.seed)
+                       for it in items)]
+    batch = csot.Batch(probs, device="cuda:0")
+    opts = csot.make_opts(tol=1e-6, max_iter=20000)
+    for _ in range(warmup):
+        batch.run(opts)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        batch.run(opts)
+    e1.record()
+    torch.cuda.synchronize()
+    out = batch.OUT.cpu().numpy()
+    ms = e0.elapsed_time(e1) / steps
+    print(json.dumps({"workload": "batched: 1024 cyclic problems, m log-uniform [32, 1024], "
+                                  "K in {4,8,16,32}, dim 2/3, eps=0.05*median, tol=1e-6",
+                      "ms_per_call": round(ms, 3), "problems_per_s": round(1024 / ms * 1e3, 1),
+                      "sum_m2": int(sum(it.m * it.m for it in items)),
+                      "all_converged": bool((out[:, 6] == 1).all()),
+                      "max_err_row": float(out[:, 3].max()),
+                      "iterations_median_max": [float(np.median(out[:, 5])), float(out[:, 5].max())]}),
+          flush=True)
 
 
 def copy_calibration():
@@ -100,6 +139,9 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
+    if args.batched:
+        batched_only(args.steps, args.warmup)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
@@ -134,6 +176,10 @@ def main():
     ds = [torch.zeros(8, dtype=torch.float64, device=dev) for _ in range(4)]
     vals_r = torch.empty(8, dtype=torch.float64, device=dev)
     vals_f = torch.empty(8, dtype=torch.float64, device=dev)
+    f32 = dict(dtype=torch.float32, device=dev)
+    grads_r = {"dx": torch.empty((N, DIM), **f32), "dy": torch.empty((N, DIM), **f32),
+               "da": torch.empty(N, **f32), "db": torch.empty(N, **f32)}
+    grads_f = {k: torch.empty_like(v) for k, v in grads_r.items()}
     csot.workspace(prob, o_tol)
 
     E = lambda: torch.cuda.Event(enable_timing=True)
@@ -153,14 +199,16 @@ def main():
                                                           dstats=ds[0]))
         run("expand", lambda: csot.ot_expand_plan(prob, fr, gr, out=Tplan))
         res_r = run("red_grad", lambda: csot.ot_cost_and_grad(prob, fr, gr, True, want_dxy=True,
-                                                              want_dab=True, out=vals_r))
+                                                              want_dab=True, out=vals_r,
+                                                              grads=grads_r))
         run("red_fixed", lambda: csot.ot_sinkhorn_reduced(prob, logK, al, be, o_fr,
                                                           host_stats=False, out=(fr2, gr2),
                                                           dstats=ds[1]))
         run("full_solve", lambda: csot.ot_sinkhorn_full(prob, o_tol, host_stats=False,
                                                         out=(ff, gf), dstats=ds[2]))
         run("full_grad", lambda: csot.ot_cost_and_grad(prob, ff, gf, False, want_dxy=True,
-                                                       want_dab=True, out=vals_f))
+                                                       want_dab=True, out=vals_f,
+                                                       grads=grads_f))
         run("full_fixed", lambda: csot.ot_sinkhorn_full(prob, o_ff, host_stats=False,
                                                         out=(ff2, gf2), dstats=ds[3]))
         return ev

@@ -270,24 +270,31 @@ def ot_expand_plan(prob: Problem, f, g, out=None):
 
 
 def ot_cost_and_grad(prob: Problem, f, g, reduced: bool, want_dC=False, want_dxy=False,
-                     want_dab=False, out=None):
+                     want_dab=False, out=None, grads=None):
     """-> dict with 'values' (device double[8]: P, D, <C,T>, err_row, err_col, mass) and the
     requested gradients dC ([K, m, m] reduced or [n, n] full), dx, dy ([n, dim]), da, db
-    ([n])."""
+    ([n]).  `grads`: optional dict of preallocated float32 outputs (keys dC, dx, dy, da, db)
+    used instead of new tensors."""
     dev = prob.device
     n, m, K = prob.n, prob.m, prob.K
+    grads = grads or {}
     vals = out if out is not None else torch.empty(8, dtype=torch.float64, device=dev)
-    dC = None
-    if want_dC:
-        dC = torch.empty((K, m, m) if reduced else (n, n), dtype=torch.float32, device=dev)
+
+    def buf(key, shape):
+        t = grads.get(key)
+        if t is None:
+            return torch.empty(shape, dtype=torch.float32, device=dev)
+        return _dev_f32(t, key, shape)
+
+    dC = buf("dC", (K, m, m) if reduced else (n, n)) if want_dC else None
     dx = dy = None
     if want_dxy:
-        dx = torch.empty((n, prob.dim), dtype=torch.float32, device=dev)
-        dy = torch.empty((n, prob.dim), dtype=torch.float32, device=dev)
+        dx = buf("dx", (n, prob.dim))
+        dy = buf("dy", (n, prob.dim))
     da = db = None
     if want_dab:
-        da = torch.empty(n, dtype=torch.float32, device=dev)
-        db = torch.empty(n, dtype=torch.float32, device=dev)
+        da = buf("da", (n,))
+        db = buf("db", (n,))
     ws = workspace(prob)
     lddc = n if (dC is not None and not reduced) else 0
     _check(_lib.ot_cost_and_grad(prob.c(), _ptr(f), _ptr(g), 1 if reduced else 0, _ptr(vals),
