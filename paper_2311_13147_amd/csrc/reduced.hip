@@ -1,4 +1,4 @@
-// Cyclic Sinkhorn on the folded m x m problem (Alg. 2), one persistent cooperative launch.
+// Cyclic Sinkhorn on the folded m x m problem (Alg. 2), one persistent launch.
 //
 // Log-domain updates in base 2 (F = f log2(e) / eps, G = g log2(e) / eps, L = logK log2(e)):
 //   row    (eq. optimal_f_sinkhorn_logdomain):  F_i = log2 alpha_i - LSE2_j(L_ij + G_j)
@@ -6,23 +6,25 @@
 // starting from G = 0 (q = 1, Alg. 2 initialisation) or a warm start.
 //
 // Work split: workgroup w owns rows [w R, w R + R) and columns [w R, w R + R).  It keeps its
-// row slab of L and its column slab (a transposed copy) in LDS for the whole solve, so an
-// iteration reads no matrix data from memory.  The new potentials are published as
-// epoch-tagged 64-bit slots (value | iteration); each workgroup polls the m slots of the other
-// potential until they carry the current iteration and stages them in LDS.  The data is its
-// own ready flag, so there is no counter barrier and no cache flush; the dependency chain
-// (F^t needs every G^{t-1}, G^t needs every F^t) is what keeps workgroups in step.
+// row slab of logK and its column slab (a transposed copy) in LDS for the whole solve (natural
+// log as stored; one fma per entry turns it into L), so an iteration reads no matrix data from
+// memory.  The new potentials are published as epoch-tagged 64-bit slots (value | iteration);
+// each workgroup polls the m slots of the other potential until they carry the current
+// iteration and stages them in LDS.  The data is its own ready flag, so there is no counter
+// barrier and no cache flush; the dependency chain (F^t needs every G^{t-1}, G^t needs every
+// F^t) is what keeps workgroups in step.  When the 32 workgroups of m = 512 fit on one XCD
+// (blocks are dealt to XCDs round-robin, so every 8th block is launched as a real one), they
+// publish through that XCD's L2.
 //
-// Convergence (a reading of "until convergence"): the row residual of the plan after
-// iteration t-1 falls out of the row update of iteration t for free,
-//   r_i = alpha_i (2^(F_i^{t-1} - F_i^t) - 1),
-// because the row sums of that plan are alpha_i 2^(F^{t-1} - F^t).  Each workgroup publishes
-// its partial sum of r_i^2 in a slot next to F^t; every workgroup sums the W partials in the
-// same order before its column update, so all take the same stop decision.  The returned
-// state is (F^{t-1}, G^{t-1}); the full-space norm is sqrt(K) ||r||_2 (every block-row of the
-// expanded plan has these row sums).
-//
-// A separate check kernel recomputes both marginal errors in float64 from the returned f, g.
+// Convergence (a reading of "until convergence"): the row sums of the plan after iteration
+// t-1 fall out of the row update of iteration t -- with the row shifted by its previous
+// potential the shifted sum *is* that row sum -- so the residual r_i = rowsum_i - alpha_i is
+// free.  Each workgroup publishes its partial sum of r_i^2 in a slot; every wave sums the W
+// partials in the same order one iteration later, so all take the same stop decision without
+// delaying a publication.  The returned state is (F^{t-2}, G^{t-2}) at the stop test of
+// iteration t; the full-space norm is sqrt(K) ||r||_2 (every block-row of the expanded plan
+// has these row sums).  At exit the workgroups exchange the returned f, g once more and
+// recompute both marginal errors in float64.
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -38,6 +40,7 @@ struct RedParams {
   int stride;      // launched blocks per workgroup slot (8: keep all workgroups on one XCD)
   float s2;        // log2(e) / eps
   float to_nat;    // eps ln 2
+  double eps;
   double tol2;     // tol^2 / K  (compared with sum r_i^2)
   const float* logK;
   const float* alpha;
@@ -48,7 +51,9 @@ struct RedParams {
   uint64_t* gx;    // [m] G exchange slots
   uint64_t* rsx;   // [2][W] residual-partial slots, double-buffered by iteration parity
   uint64_t* xid;   // [W] XCD index of every workgroup (epoch 1)
-  uint32_t* ctl;   // [0] abort flag
+  uint64_t* ffin;  // [mp] returned f (natural units) for the float64 check (epoch 1)
+  uint64_t* gfin;  // [mp] returned g
+  uint32_t* ctl;   // [0] abort flag, [8..11] two float64 sums, [12] finished workgroups
   double* dstats;
 };
 
@@ -64,8 +69,11 @@ __device__ __forceinline__ float wave_lse2(const float* __restrict__ row,
     const float4 v0 = *reinterpret_cast<const float4*>(vec + q0);
     const float4 l1 = *reinterpret_cast<const float4*>(row + q1);
     const float4 v1 = *reinterpret_cast<const float4*>(vec + q1);
-    const float t[8] = {l0.x + v0.x, l0.y + v0.y, l0.z + v0.z, l0.w + v0.w,
-                        l1.x + v1.x, l1.y + v1.y, l1.z + v1.z, l1.w + v1.w};
+    // row holds the natural logK: base 2 by one fma per entry
+    const float t[8] = {fmaf(l0.x, kLog2e, v0.x), fmaf(l0.y, kLog2e, v0.y),
+                        fmaf(l0.z, kLog2e, v0.z), fmaf(l0.w, kLog2e, v0.w),
+                        fmaf(l1.x, kLog2e, v1.x), fmaf(l1.y, kLog2e, v1.y),
+                        fmaf(l1.z, kLog2e, v1.z), fmaf(l1.w, kLog2e, v1.w)};
     float mx = fmaxf(fmaxf(fmaxf(t[0], t[1]), fmaxf(t[2], t[3])),
                      fmaxf(fmaxf(t[4], t[5]), fmaxf(t[6], t[7])));
     mx = wave_max_v(mx);
@@ -96,10 +104,10 @@ __device__ __forceinline__ float wave_shifted_sum(const float* __restrict__ row,
     const float4 v0 = *reinterpret_cast<const float4*>(vec + q0);
     const float4 l1 = *reinterpret_cast<const float4*>(row + q1);
     const float4 v1 = *reinterpret_cast<const float4*>(vec + q1);
-    s += exp2_fast(l0.x + (v0.x + sh)) + exp2_fast(l0.y + (v0.y + sh)) +
-         exp2_fast(l0.z + (v0.z + sh)) + exp2_fast(l0.w + (v0.w + sh)) +
-         exp2_fast(l1.x + (v1.x + sh)) + exp2_fast(l1.y + (v1.y + sh)) +
-         exp2_fast(l1.z + (v1.z + sh)) + exp2_fast(l1.w + (v1.w + sh));
+    s += exp2_fast(fmaf(l0.x, kLog2e, v0.x + sh)) + exp2_fast(fmaf(l0.y, kLog2e, v0.y + sh)) +
+         exp2_fast(fmaf(l0.z, kLog2e, v0.z + sh)) + exp2_fast(fmaf(l0.w, kLog2e, v0.w + sh)) +
+         exp2_fast(fmaf(l1.x, kLog2e, v1.x + sh)) + exp2_fast(fmaf(l1.y, kLog2e, v1.y + sh)) +
+         exp2_fast(fmaf(l1.z, kLog2e, v1.z + sh)) + exp2_fast(fmaf(l1.w, kLog2e, v1.w + sh));
   }
   return wave_sum_v(s);
 }
@@ -156,12 +164,12 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
   for (int e = tid; e < R * mp; e += blockDim.x) {
     const int rl = e / mp, j = e - rl * mp;
     const bool ok = rl < nr && j < m;
-    Ls[e] = ok ? p.logK[(int64_t)(r0 + rl) * m + j] * kLog2e : -INFINITY;
+    Ls[e] = ok ? p.logK[(int64_t)(r0 + rl) * m + j] : -INFINITY;  // natural log
   }
   for (int e = tid; e < R * mp; e += blockDim.x) {
     const int i = e / R, cl = e - i * R;  // consecutive threads read consecutive columns
     const bool ok = cl < nr && i < m;
-    LTs[(size_t)cl * mp + i] = ok ? p.logK[(int64_t)i * m + r0 + cl] * kLog2e : -INFINITY;
+    LTs[(size_t)cl * mp + i] = ok ? p.logK[(int64_t)i * m + r0 + cl] : -INFINITY;
   }
   for (int rl = tid; rl < R; rl += blockDim.x) {
     const bool ok = rl < nr;
@@ -291,8 +299,11 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
   // Fold = F^{t-2}) and the column update of t has not (Gcur = G^{t-1}, Gprev = G^{t-2}).
   __syncthreads();
   for (int rl = tid; rl < nr; rl += blockDim.x) {
-    p.f_out[r0 + rl] = Fold[rl] * p.to_nat;
-    p.g_out[r0 + rl] = Gprev[rl] * p.to_nat;
+    const float fo = Fold[rl] * p.to_nat, go = Gprev[rl] * p.to_nat;
+    p.f_out[r0 + rl] = fo;
+    p.g_out[r0 + rl] = go;
+    publish(p.ffin + r0 + rl, fo, 1u);
+    publish(p.gfin + r0 + rl, go, 1u);
   }
   if (w == 0 && tid == 0) {
     p.dstats[0] = (double)iters_done;
@@ -303,6 +314,59 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
     p.dstats[7] = local_pub ? 1.0 : 0.0;
   } else if (tid == 0 && flags) {
     p.dstats[5] = (double)flags;
+  }
+
+  // ---- float64 check of the returned state: full-space L2 marginal errors --------------------
+  // Every workgroup stages all returned f and g (natural units, as written) and sums its own
+  // rows and columns of the reduced plan T_ij = exp(logK_ij + (f_i + g_j) / eps) from the
+  // stored logK in float64; the squared residuals meet in two float64 accumulators and the last
+  // workgroup to finish writes sqrt(K sum).
+  double* acc = reinterpret_cast<double*>(p.ctl + 8);
+  uint32_t* done = p.ctl + 12;
+  const bool staged = stage_slots(p.ffin, m, mp, 1u, VsF, p.gfin, m, 1u, VsG, abort_flag, &s_bad);
+  const double inv_eps = 1.0 / p.eps;
+  double part_r = 0.0, part_c = 0.0;
+  if (staged) {
+    for (int q = wv; q < 2 * nr; q += kRedWaves) {
+      const bool row = q < nr;
+      const int o = r0 + (row ? q : q - nr);         // own row i or own column j
+      const double po = (double)(row ? VsF[o] : VsG[o]);
+      const float* opot = row ? VsG : VsF;
+      double sum = 0.0;
+      const float* slab = (row ? Ls : LTs) + (size_t)(o - r0) * mp;  // stored logK, natural
+      for (int b = lane; b < m; b += kWave)
+        sum += exp((double)slab[b] + (po + (double)opot[b]) * inv_eps);
+      sum = wave_sum_d(sum);
+      const double d = sum - (double)(row ? p.alpha[o] : p.beta[o]);
+      if (lane == 0) {
+        if (row) part_r += d * d;
+        else part_c += d * d;
+      }
+    }
+  }
+  __shared__ double s_acc[2 * kRedWaves];
+  if (lane == 0) {
+    s_acc[wv] = part_r;
+    s_acc[kRedWaves + wv] = part_c;
+  }
+  __syncthreads();
+  __shared__ int s_last;
+  if (tid == 0) {
+    double r = 0.0, c = 0.0;
+    for (int k = 0; k < kRedWaves; ++k) { r += s_acc[k]; c += s_acc[kRedWaves + k]; }
+    atomicAdd(&acc[0], r);
+    atomicAdd(&acc[1], c);
+    __threadfence();
+    s_last = atomicAdd(done, 1u) == (uint32_t)(p.W - 1);
+  }
+  __syncthreads();
+  if (s_last && tid == 0) {
+    __threadfence();
+    const double r = __hip_atomic_load(&acc[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const double c = __hip_atomic_load(&acc[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const bool ok = staged && s_bad == 0;
+    p.dstats[2] = ok ? sqrt((double)p.K * r) : NAN;
+    p.dstats[3] = ok ? sqrt((double)p.K * c) : NAN;
   }
 }
 
@@ -368,17 +432,15 @@ bool plan_reduced(int m, int hint, ReducedPlan* plan) {
   return true;
 }
 
-// workspace: ctl[64 words] | fx[mp] | gx[mp] | rsx[2W] | xid[W] (64-bit slots) | check partials
+// workspace: ctl[64 words] | fx[mp] | gx[mp] | rsx[2W] | xid[W] | ffin[mp] | gfin[mp] (64-bit slots)
 static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
 static size_t slots_bytes(int m, int W) {
-  return align256(256) + 2 * align256(sizeof(uint64_t) * reduced_mp(m)) +
+  return align256(256) + 4 * align256(sizeof(uint64_t) * reduced_mp(m)) +
          align256(sizeof(uint64_t) * 2 * W) + align256(sizeof(uint64_t) * W);
 }
 
-size_t reduced_ws_bytes(int m, const ReducedPlan& p) {
-  return slots_bytes(m, p.W) + align256(sizeof(double) * 2 * m);
-}
+size_t reduced_ws_bytes(int m, const ReducedPlan& p) { return slots_bytes(m, p.W); }
 
 hipError_t launch_sinkhorn_reduced(int m, int K, double eps, const float* logK,
                                    const float* alpha, const float* beta, float* f, float* g,
@@ -393,7 +455,8 @@ hipError_t launch_sinkhorn_reduced(int m, int K, double eps, const float* logK,
   uint64_t* gx = reinterpret_cast<uint64_t*>(base + off); off += align256(sizeof(uint64_t) * mp);
   uint64_t* rsx = reinterpret_cast<uint64_t*>(base + off); off += align256(sizeof(uint64_t) * 2 * pl.W);
   uint64_t* xid = reinterpret_cast<uint64_t*>(base + off); off += align256(sizeof(uint64_t) * pl.W);
-  double* part = reinterpret_cast<double*>(base + off);
+  uint64_t* ffin = reinterpret_cast<uint64_t*>(base + off); off += align256(sizeof(uint64_t) * mp);
+  uint64_t* gfin = reinterpret_cast<uint64_t*>(base + off); off += align256(sizeof(uint64_t) * mp);
 
   // epochs start at 1, so zeroed slots are never mistaken for current ones
   hipError_t e = launch_zero_words(ctl, (int)(slots_bytes(m, pl.W) / 4), s);
@@ -406,19 +469,22 @@ hipError_t launch_sinkhorn_reduced(int m, int K, double eps, const float* logK,
   p.to_nat = (float)(eps * kLn2D);
   p.tol2 = tol * tol / (double)K;
   p.logK = logK; p.alpha = alpha; p.beta = beta; p.f_out = f; p.g_out = g;
-  p.fx = fx; p.gx = gx; p.rsx = rsx; p.xid = xid; p.ctl = ctl; p.dstats = dstats;
+  p.fx = fx; p.gx = gx; p.rsx = rsx; p.xid = xid; p.ffin = ffin; p.gfin = gfin; p.ctl = ctl;
+  p.dstats = dstats;
+  p.eps = eps;
   void* args[] = {&p};
   if (events && (e = hipEventRecord(events[0], s)) != hipSuccess) return e;
-  e = hipLaunchCooperativeKernel((const void*)reduced_solver_kernel, dim3(pl.W * pl.stride),
-                                 dim3(pl.threads), args, (unsigned)pl.lds, s);
+  // An ordinary launch: the plan admits at most one block per CU and no more blocks than CUs,
+  // so on a device with no concurrent kernels every block is resident at once (the cooperative
+  // launch API guarantees the same but adds ~10 us of dispatch overhead on each side).  Should a
+  // block not be resident, the others' bounded waits end in the abort flag, not in a hang.
+  hipLaunchKernelGGL(reduced_solver_kernel, dim3(pl.W * pl.stride), dim3(pl.threads),
+                     (unsigned)pl.lds, s, p);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (events && (e = hipEventRecord(events[1], s)) != hipSuccess) return e;
 
-  // float64 check of the returned state: full-space row and column errors
-  Geom geo;
-  geo.n = m * K; geo.K = K; geo.m = m; geo.dim = 2; geo.x = geo.y = geo.C = nullptr; geo.ldc = 0;
-  geo.a = alpha; geo.b = beta; geo.eps = eps;
-  return launch_check(geo, 1, logK, f, g, alpha, beta, part, dstats, s);
+  return hipSuccess;
 }
 
 }  // namespace csot
