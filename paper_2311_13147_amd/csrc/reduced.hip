@@ -161,15 +161,27 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
   uint32_t* abort_flag = p.ctl;
 
   // ---- load the slabs (once) ------------------------------------------------------------
-  for (int e = tid; e < R * mp; e += blockDim.x) {
-    const int rl = e / mp, j = e - rl * mp;
-    const bool ok = rl < nr && j < m;
-    Ls[e] = ok ? p.logK[(int64_t)(r0 + rl) * m + j] : -INFINITY;  // natural log
-  }
-  for (int e = tid; e < R * mp; e += blockDim.x) {
-    const int i = e / R, cl = e - i * R;  // consecutive threads read consecutive columns
-    const bool ok = cl < nr && i < m;
-    LTs[(size_t)cl * mp + i] = ok ? p.logK[(int64_t)i * m + r0 + cl] : -INFINITY;
+  // 8 loads in flight per thread before the first store (one memory round trip per 8)
+  constexpr int kLd = 8;
+  for (int e0 = tid; e0 < R * mp; e0 += kLd * blockDim.x) {
+    float v[kLd], vt[kLd];
+#pragma unroll
+    for (int u = 0; u < kLd; ++u) {
+      const int e = e0 + u * blockDim.x;
+      const int rl = e / mp, j = e - rl * mp;
+      v[u] = (e < R * mp && rl < nr && j < m) ? p.logK[(int64_t)(r0 + rl) * m + j] : -INFINITY;
+      const int i = e / R, cl = e - i * R;  // consecutive threads read consecutive columns
+      vt[u] = (e < R * mp && cl < nr && i < m) ? p.logK[(int64_t)i * m + r0 + cl] : -INFINITY;
+    }
+#pragma unroll
+    for (int u = 0; u < kLd; ++u) {
+      const int e = e0 + u * blockDim.x;
+      if (e < R * mp) {
+        Ls[e] = v[u];  // natural log
+        const int i = e / R, cl = e - i * R;
+        LTs[(size_t)cl * mp + i] = vt[u];
+      }
+    }
   }
   for (int rl = tid; rl < R; rl += blockDim.x) {
     const bool ok = rl < nr;
@@ -354,14 +366,16 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
   if (tid == 0) {
     double r = 0.0, c = 0.0;
     for (int k = 0; k < kRedWaves; ++k) { r += s_acc[k]; c += s_acc[kRedWaves + k]; }
-    atomicAdd(&acc[0], r);
-    atomicAdd(&acc[1], c);
-    __threadfence();
-    s_last = atomicAdd(done, 1u) == (uint32_t)(p.W - 1);
+    // agent-scope atomics are performed at the point of coherence; waiting for them to return
+    // orders them before the counter increment, so no cache-flushing fence is needed
+    __hip_atomic_fetch_add(&acc[0], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(&acc[1], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_s_waitcnt(0);  // both adds have returned before the counter moves
+    s_last = __hip_atomic_fetch_add(done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+             (uint32_t)(p.W - 1);
   }
   __syncthreads();
   if (s_last && tid == 0) {
-    __threadfence();
     const double r = __hip_atomic_load(&acc[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const double c = __hip_atomic_load(&acc[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const bool ok = staged && s_bad == 0;
