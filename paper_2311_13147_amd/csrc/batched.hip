@@ -88,6 +88,7 @@ __device__ __forceinline__ void fold_cols(const ot_batch_desc& d, int i0, int ro
       }
       cminf[q] = 3.0e38f;
     }
+#pragma unroll 4
     for (int k = 0; k < K; ++k) {
       float yv[DIM];
 #pragma unroll
@@ -103,6 +104,7 @@ __device__ __forceinline__ void fold_cols(const ot_batch_desc& d, int i0, int ro
 #pragma unroll
     for (int q = 0; q < kFoldQ; ++q) cmin[q] = (Real)cminf[q];
     float sum[kFoldQ] = {};
+#pragma unroll 4
     for (int k = 0; k < K; ++k) {
       Real yv[DIM];
 #pragma unroll
@@ -236,6 +238,43 @@ __device__ __forceinline__ float grp_lse2(const float* row, const float* vec, in
   return M + log2_fast(S);
 }
 
+constexpr float kMinShiftedSumB = 0x1p-60f;  // below this a shifted sum is redone exactly
+
+// Shifted sum of 2^(row_j + vec_j + sh) over j < mp by a group of LPR lanes (rows padded
+// with -inf); with sh the row's previous potential no maximum is needed (see the reduced
+// solver).  Every lane of the group returns it.
+template <int LPR>
+__device__ __forceinline__ float grp_shifted_sum(const float* row, const float* vec, int mp,
+                                                 int gl, float sh) {
+  constexpr int kU = 4;  // loads in flight per lane (rows may stream from global memory)
+  float s = 0.0f;
+  for (int base = 4 * gl; base < mp; base += 4 * LPR * kU) {
+    float4 l[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int q = base + 4 * LPR * u;
+      l[u] = q < mp ? *reinterpret_cast<const float4*>(row + q)
+                    : make_float4(-INFINITY, -INFINITY, -INFINITY, -INFINITY);
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int q = base + 4 * LPR * u;
+      if (q < mp) {
+        const float4 v = *reinterpret_cast<const float4*>(vec + q);
+        s += exp2_fast(l[u].x + (v.x + sh)) + exp2_fast(l[u].y + (v.y + sh)) +
+             exp2_fast(l[u].z + (v.z + sh)) + exp2_fast(l[u].w + (v.w + sh));
+      }
+    }
+  }
+  s += dpp_f32<kDppXor1>(s);
+  s += dpp_f32<kDppXor2>(s);
+  s += dpp_f32<kDppHalfMirror>(s);
+  s += dpp_f32<kDppMirror>(s);
+  if constexpr (LPR >= 32) s = swap_sum16(s);
+  if constexpr (LPR == 64) s = swap_sum32(s);
+  return s;
+}
+
 struct BSolveArgs {
   const ot_batch_desc* descs;
   int count;
@@ -291,13 +330,21 @@ __device__ void solve_one(const ot_batch_desc& d, const BSolveArgs& a, float* ld
     // row update F^t from G^{t-1}; residual of the state after t-1
     float racc = 0.0f;
     for (int i = grp; i < m; i += ngrp) {
-      const float Fn = la2[i] - grp_lse2<LPR>(L + (size_t)i * mp, G, mp, gl);
+      const float Fo = F[i];
+      float Fn, S = -1.0f;
+      if (t >= 2) {  // shifted by the row's previous potential; exact when out of range
+        S = grp_shifted_sum<LPR>(L + (size_t)i * mp, G, mp, gl, Fo);
+        if (S >= kMinShiftedSumB && S < INFINITY) Fn = la2[i] - log2_fast(S) + Fo;
+        else S = -1.0f;
+      }
+      if (S < 0.0f) Fn = la2[i] - grp_lse2<LPR>(L + (size_t)i * mp, G, mp, gl);
       if (gl == 0) {
         if (t >= 2) {
-          const float rr = scaled_exp2m1(al[i], F[i] - Fn);
+          // residual of the state after t-1: its row sum (the shifted sum) minus alpha
+          const float rr = S >= 0.0f ? S - al[i] : scaled_exp2m1(al[i], Fo - Fn);
           racc += rr * rr;
         }
-        Fp[i] = F[i];
+        Fp[i] = Fo;
         F[i] = Fn;
       }
     }
@@ -319,7 +366,11 @@ __device__ void solve_one(const ot_batch_desc& d, const BSolveArgs& a, float* ld
     __syncthreads();
     // column update G^t from F^t
     for (int j = grp; j < m; j += ngrp) {
-      const float Gn = lb2[j] - grp_lse2<LPR>(LT + (size_t)j * mp, F, mp, gl);
+      const float Go = G[j];
+      const float S = grp_shifted_sum<LPR>(LT + (size_t)j * mp, F, mp, gl, Go);
+      const float Gn = (S >= kMinShiftedSumB && S < INFINITY)
+                           ? lb2[j] - log2_fast(S) + Go
+                           : lb2[j] - grp_lse2<LPR>(LT + (size_t)j * mp, F, mp, gl);
       if (gl == 0) G[j] = Gn;
     }
     __syncthreads();
@@ -349,20 +400,34 @@ __device__ __forceinline__ uint64_t* gang_slots(const ot_batch_desc& d) {
 // Shifted sum over j < mp of 2^(row_j + vec_j + sh) by one wave (rows padded with -inf up to
 // mp, a multiple of 4); every lane returns it.  See the reduced solver for why no maximum is
 // needed when sh is the row's previous potential.
+// The row streams from global memory (L2 / MALL): eight float4 loads per lane are issued
+// before any is used, so a wave keeps 8 KB in flight instead of waiting once per float4.
 __device__ __forceinline__ float wave_shifted_sum_g(const float* __restrict__ row,
                                                     const float* __restrict__ vec, int mp,
                                                     int lane, float sh) {
+  constexpr int kU = 8;
   float s = 0.0f;
-  for (int q = 4 * lane; q < mp; q += 4 * kWave) {
-    const float4 l = *reinterpret_cast<const float4*>(row + q);
-    const float4 v = *reinterpret_cast<const float4*>(vec + q);
-    s += exp2_fast(l.x + (v.x + sh)) + exp2_fast(l.y + (v.y + sh)) +
-         exp2_fast(l.z + (v.z + sh)) + exp2_fast(l.w + (v.w + sh));
+  for (int base = 4 * lane; base < mp; base += 4 * kWave * kU) {
+    float4 l[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int q = base + 4 * kWave * u;
+      l[u] = q < mp ? *reinterpret_cast<const float4*>(row + q)
+                    : make_float4(-INFINITY, -INFINITY, -INFINITY, -INFINITY);
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int q = base + 4 * kWave * u;
+      if (q < mp) {
+        const float4 v = *reinterpret_cast<const float4*>(vec + q);
+        s += exp2_fast(l[u].x + (v.x + sh)) + exp2_fast(l[u].y + (v.y + sh)) +
+             exp2_fast(l[u].z + (v.z + sh)) + exp2_fast(l[u].w + (v.w + sh));
+      }
+    }
   }
   return wave_sum_v(s);
 }
 
-constexpr float kMinShiftedSumB = 0x1p-60f;
 
 // One potential update of row (or column) `row` by one wave: lm - LSE2_j(row_j + vec_j),
 // shifted by the previous potential when `shifted`, exact otherwise or when the shifted sum
