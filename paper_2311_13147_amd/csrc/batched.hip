@@ -609,7 +609,7 @@ __global__ void __launch_bounds__(kBSolveThreads) batched_solve_kernel(BSolveArg
 // wave owns 4 points and its lanes stride over the partner points, so one partner load feeds
 // four entries).
 // acc[p]: {P, <C,T>, mass, sum (rowsum - alpha)^2, sum (colsum - beta)^2, <f,alpha>, <g,beta>}
-constexpr int kVChunk = 1024;  // partner points staged in LDS at a time
+constexpr int kVChunk = 1024;  // partner points staged in LDS at a time (4 per thread)
 
 template <int DIM, bool ROW>
 __device__ void values_tile(const ot_batch_desc& d, int a0, double* __restrict__ acc,
@@ -641,6 +641,11 @@ __device__ void values_tile(const ot_batch_desc& d, int a0, double* __restrict__
   // once per chunk (ROW: nothing but g_b; COL: x_b of block-row 0 and f_b), sP[b] = the
   // gradient partner of block k (ROW: y_{k m + b}; COL: x_{r m + b}, r = (K - k) mod K, whose
   // entry with column j is T_{b j k}).
+  // potentials enter the exponent scaled to base 2: pas (own) and sC.w (partner)
+  float pas[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) pas[q] = pa[q] * s2;
+  constexpr int kPre = kVChunk / 256;  // partners per thread per block (256 threads)
   for (int c0 = 0; c0 < m; c0 += kVChunk) {
     const int nc = min(kVChunk, m - c0);
     __syncthreads();  // the previous chunk's readers are done
@@ -651,21 +656,37 @@ __device__ void values_tile(const ot_batch_desc& d, int a0, double* __restrict__
         v.y = d.x[(int64_t)(c0 + b) * DIM + 1];
         if (DIM == 3) v.z = d.x[(int64_t)(c0 + b) * DIM + 2];
       }
-      v.w = ROW ? d.g[c0 + b] : d.f[c0 + b];
+      v.w = (ROW ? d.g[c0 + b] : d.f[c0 + b]) * s2;
       sC[b] = v;
     }
+    // the partners of block k + 1 are loaded into registers while block k is processed
+    float4 pre[kPre];
+#pragma unroll
+    for (int u = 0; u < kPre; ++u) {
+      const int b = threadIdx.x + 256 * u;
+      const int64_t P = (int64_t)c0 + b;  // block 0 (k = 0, r = 0)
+      pre[u] = b < nc ? make_float4(othp[P * DIM], othp[P * DIM + 1], DIM == 3 ? othp[P * DIM + 2] : 0.f, 0.f)
+                      : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
     for (int k = 0; k < K; ++k) {
-      const int r = (K - k) % K;
-      const int pbase = (ROW ? k : r) * m + c0;
       __syncthreads();  // sP of the previous block is no longer read
-      for (int b = threadIdx.x; b < nc; b += blockDim.x) {
-        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-        v.x = othp[(int64_t)(pbase + b) * DIM];
-        v.y = othp[(int64_t)(pbase + b) * DIM + 1];
-        if (DIM == 3) v.z = othp[(int64_t)(pbase + b) * DIM + 2];
-        sP[b] = v;
+#pragma unroll
+      for (int u = 0; u < kPre; ++u) {
+        const int b = threadIdx.x + 256 * u;
+        if (b < nc) sP[b] = pre[u];
       }
       __syncthreads();
+      if (k + 1 < K) {
+        const int kn = k + 1, rn = (K - kn) % K;
+        const int64_t pbase = (int64_t)(ROW ? kn : rn) * m + c0;
+#pragma unroll
+        for (int u = 0; u < kPre; ++u) {
+          const int b = threadIdx.x + 256 * u;
+          const int64_t P = pbase + b;
+          if (b < nc)
+            pre[u] = make_float4(othp[P * DIM], othp[P * DIM + 1], DIM == 3 ? othp[P * DIM + 2] : 0.f, 0.f);
+        }
+      }
       if (!active) continue;
       float yk[Q][DIM];  // COL: y_{k m + j} of the own columns j
 #pragma unroll
@@ -678,7 +699,7 @@ __device__ void values_tile(const ot_batch_desc& d, int a0, double* __restrict__
         const float pp[3] = {P4.x, P4.y, P4.z};
         // ROW: the cost uses the partner itself; COL: block-row 0's row point x_b
         const float cb[3] = {ROW ? P4.x : C4.x, ROW ? P4.y : C4.y, ROW ? P4.z : C4.z};
-        const float ob = C4.w;
+        const float obs = C4.w;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
           float c = 0.0f;
@@ -688,13 +709,13 @@ __device__ void values_tile(const ot_batch_desc& d, int a0, double* __restrict__
             const float df = ROW ? po[q][dd] - cb[dd] : cb[dd] - yk[q][dd];
             c = fmaf(df, df, c);
           }
-          const float T = exp2_fast((pa[q] + ob - c) * s2);
+          const float T = exp2_fast(fmaf(-c, s2, pas[q] + obs));
 #pragma unroll
           for (int dd = 0; dd < DIM; ++dd) gacc[q][dd] = fmaf(T, po[q][dd] - pp[dd], gacc[q][dd]);
           if (ROW) {
             // C + eps (Z - 1) = f_i + g_j - eps with Z = (f_i + g_j - C) / eps: the primal
-            // term needs only the plan's g-weighted sum besides its mass
-            tP[q] = fmaf(T, ob, tP[q]);
+            // term needs only the plan's g-weighted sum (kept scaled by s2) besides its mass
+            tP[q] = fmaf(T, obs, tP[q]);
             tC[q] = fmaf(T, c, tC[q]);
             tM[q] += T;
           }
@@ -730,7 +751,7 @@ __device__ void values_tile(const ot_batch_desc& d, int a0, double* __restrict__
       if (lane == 0 && dst && ok) dst[(int64_t)Aq[q] * DIM + dd] = 2.0f * gsum;
     }
     if (ROW) {
-      const double Tg = wave_sum_d((double)tP[q]), C = wave_sum_d((double)tC[q]),
+      const double Tg = wave_sum_d((double)tP[q]) / (double)s2, C = wave_sum_d((double)tC[q]),
                    Ms = wave_sum_d((double)tM[q]);
       // sum_{j,k} T_ijk (f_i + g_j - eps)
       if (ok) { vP += ((double)pa[q] - d.eps) * Ms + Tg; vC += C; vM += Ms; }
