@@ -31,7 +31,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 N, K, DIM, SEED, EPS_FACTOR, TOL = 8192, 16, 2, 100, 0.01, 1e-6
-FLOPS_PER_ENTRY = {2: 11, 3: 14}  # algorithmic fp32 ops per (I, J) entry of a half-step
+# Algorithmic flops per (I, J) entry of a half-step, counted on the definition of the update
+# (an fma is 2 flops, exp2 is 1): |x_I - y_J|^2 is dim subtractions, dim multiplies and dim - 1
+# adds; then the scale by log2(e)/eps, the potential, the shift, the exp2 and the accumulation
+# (dim 2: 5 + 5 = 10; dim 3: 8 + 5 = 13)
+FLOPS_PER_ENTRY = {2: 10, 3: 13}
 # fp32 vector peak without packed-FP32 instructions (this build does not emit them):
 # 256 CUs x 4 SIMDs x 16 lanes x 2 flops per FMA x 2.4 GHz.  The published 157.3 TFLOP/s
 # counts packed FMAs and is reported beside it.

@@ -9,9 +9,9 @@
 // row phase the whole other side streams through LDS in chunks of kNC points -- static
 // coordinates (packed once per solve) plus the current potential, read from epoch-tagged
 // 64-bit slots and polled until they carry the current iteration -- double-buffered with the
-// next chunk prefetched into registers.  Every lane evaluates costs on the fly, keeping a
-// running (max, sum) per row that is rescaled once per 4 columns; lanes, then column parts,
-// are merged at the end.  Dense costs (dim = 0) are streamed from HBM instead: C for row
+// next chunk prefetched into registers.  Every lane evaluates costs on the fly from
+// coordinates pre-scaled by sqrt(log2(e)/eps), so that an exponent is G_J - |x'_I - y'_J|^2;
+// lanes, then column parts, are merged at the end.  Dense costs (dim = 0) are streamed from HBM instead: C for row
 // phases, a transposed copy for column phases.  Exchange and stop test are those of the
 // reduced solver (slots as their own ready flags, no counter barrier, no cache flushes).
 #include "common.hpp"
@@ -53,12 +53,14 @@ constexpr float kMinShiftedSum = 0x1p-60f;
 // mode only) kPhaseRedo when a row's shifted sum fell outside [2^-60, inf).
 //
 // Exact mode keeps a running (max, sum) per row, rescaled once per 4 columns.  Shifted mode
-// sums 2^(pot_J - C_IJ s2 + sh_I) with the row's own previous potential sh_I, and needs no
-// maximum: after the other side's last update every term of a row is at most that side's
-// marginal entry (the previous plan's column or row sums are exact), so the sum is at most 1
-// and cannot overflow; it is that plan's row sum, far from underflow unless the previous
-// plan left the row almost empty -- the caller then redoes the phase in exact mode.  The shift
-// enters the cost as the offset -sh_I / s2, so an entry costs 2 sub, 3 fma, 1 exp and 1 add.
+// needs no maximum: it sums 2^(pot_J + sig - C_IJ s2) with one shift sig per workgroup, the
+// largest previous potential sh_I of its rows.  With sh_I in place of sig the sum would be the
+// previous plan's row sum (every term of a row is at most the other side's marginal entry
+// after that side's last update), at most 1; the common shift scales it by 2^(sig - sh_I) >= 1,
+// so it cannot underflow where the row's own shift would not, and overflows only when the
+// workgroup's previous potentials spread over more than ~127 (base 2).  Either case (a sum
+// outside [2^-60, inf)) makes the caller redo the phase in exact mode.  The shift is added to
+// the staged potentials, so an entry costs 2 sub, 2 fma, 1 exp and 1 add (dim 2).
 constexpr int kPhaseOk = 0, kPhaseAbort = 1, kPhaseRedo = 2;
 
 template <int DIM, int RT, int CQ, bool EXACT>
@@ -76,7 +78,7 @@ __device__ __forceinline__ int full_phase(const FullParams& p, int r0, const flo
   const int wv = tid / kWave;
   const int rg = wv / CQ, cq = wv % CQ;
   float xr[RT][3];
-  float M[RT], S[RT], off[RT];
+  float M[RT], S[RT];
   const float* drow[RT];
 #pragma unroll
   for (int q = 0; q < RT; ++q) {
@@ -89,7 +91,14 @@ __device__ __forceinline__ int full_phase(const FullParams& p, int r0, const flo
     drow[q] = DIM == 0 ? dense + (int64_t)I * ldd : nullptr;
     M[q] = kNegBig;
     S[q] = 0.0f;
-    off[q] = EXACT ? 0.0f : -sh[rl] * p.to_nat;  // to_nat = 1 / s2
+  }
+  // the workgroup's common shift: its rows' largest previous potential (written before the
+  // barrier that ended the previous update; R <= 64 rows, one per lane, and every wave gets
+  // the bitwise-identical maximum)
+  float sig = 0.0f;
+  if constexpr (!EXACT) {
+    static_assert(RG * RT <= kWave, "one row per lane");
+    sig = wave_max_v(lane < RG * RT && r0 + lane < p.n ? sh[lane] : kNegBig);
   }
   if (tid == 0) *s_redo = 0;
   const int nchunks = p.np / kNC;
@@ -110,7 +119,7 @@ __device__ __forceinline__ int full_phase(const FullParams& p, int r0, const flo
       const int J = c * kNC + tid + k * kFullThreads;
       if (J < p.n) {
         if (ok) ok = slot_wait(oslots + J, ps[k], epoch, p.ctl);
-        pc[k].w = slot_value(ps[k]);
+        pc[k].w = slot_value(ps[k]) + sig;
       } else {
         pc[k].w = -INFINITY;
       }
@@ -137,21 +146,21 @@ __device__ __forceinline__ int full_phase(const FullParams& p, int r0, const flo
         float t[TU];
 #pragma unroll
         for (int cc = 0; cc < TU; ++cc) {
-          float cst;
           if constexpr (DIM == 0) {
             const int Jc = c * kNC + lane + kWave * (u + cc);
-            cst = (Jc < p.n ? drow[q][Jc] : 0.0f) + off[q];
+            t[cc] = fmaf(-(Jc < p.n ? drow[q][Jc] : 0.0f), p.s2, o[cc].w);
           } else {
+            // scaled coordinates: -C_IJ s2 = -|x'_I - y'_J|^2
             const float dx = xr[q][0] - o[cc].x;
             const float dy = xr[q][1] - o[cc].y;
-            cst = fmaf(dx, dx, off[q]);
-            cst = fmaf(dy, dy, cst);
+            float e = fmaf(-dx, dx, o[cc].w);
+            e = fmaf(-dy, dy, e);
             if constexpr (DIM == 3) {
               const float dz = xr[q][2] - o[cc].z;
-              cst = fmaf(dz, dz, cst);
+              e = fmaf(-dz, dz, e);
             }
+            t[cc] = e;
           }
-          t[cc] = fmaf(-cst, p.s2, o[cc].w);
         }
         if constexpr (EXACT) {
           float tm = t[0];
@@ -194,7 +203,7 @@ __device__ __forceinline__ int full_phase(const FullParams& p, int r0, const flo
       float s_ = 0.0f;
       for (int k = 0; k < CQ; ++k) s_ += part[rl * CQ + k].y;
       if (r0 + rl < p.n && !(s_ >= kMinShiftedSum && s_ < INFINITY)) *s_redo = 1;
-      lse[rl] = log2_fast(s_) - sh[rl];
+      lse[rl] = log2_fast(s_) - sig;
     }
   }
   __syncthreads();
@@ -224,13 +233,13 @@ __device__ __forceinline__ int full_phase_auto(bool exact, const FullParams& p, 
 template <int DIM, int RT, int CQ>
 __global__ void __launch_bounds__(kFullThreads) full_solver_kernel(FullParams p) {
   constexpr int R = (kFullWaves / CQ) * RT;
+  static_assert(R <= kWave, "a workgroup's rows are one per lane of wave 0");
   __shared__ float4 buf[2 * kNC];
   __shared__ float2 part[R * CQ];
   __shared__ float lse[R];
-  __shared__ float Fcur[R], Fprev[R], Gcur[R], la2[R], lb2[R];
-  __shared__ float rsv[256];
-  __shared__ double red[kFullWaves];
-  __shared__ int s_bad, s_stop, s_redo;
+  __shared__ float Fcur[R], Fprev[R], Gcur[R], Gprev[R], la2[R], lb2[R];
+  __shared__ int s_bad, s_stop, s_redo, s_conv, s_fin;
+  __shared__ double s_err2;
   const int w = blockIdx.x, tid = threadIdx.x;
   const int r0 = w * R;
   const int nr = max(0, min(R, p.n - r0));
@@ -243,12 +252,18 @@ __global__ void __launch_bounds__(kFullThreads) full_solver_kernel(FullParams p)
     Fcur[rl] = 0.0f;
     Fprev[rl] = 0.0f;
     Gcur[rl] = ok ? slot_value(slot_load(p.gx + I)) : 0.0f;  // initial G (epoch 0)
+    Gprev[rl] = Gcur[rl];
   }
   if (tid == 0) s_bad = 0;
   __syncthreads();
   int iters_done = 0, converged = 0, flags = 0, redos = 0;
   double err2 = 0.0;
 
+  // Iteration t: row phase (F^t from G^{t-1}), then column phase (G^t from F^t).  The row
+  // update also yields the residual of the state after iteration t-1; every workgroup
+  // publishes its partial and reads all of them only after the column phase, when they have
+  // long been visible, so the stop test never holds up the exchange.  A stop at iteration t
+  // returns the state after t-1 (F^{t-1}, G^{t-1}) and discards the column phase just done.
   for (uint32_t t = 1;; ++t) {
     // ---- row phase: F^t from G^{t-1} ----------------------------------------------------
     // F^1 has no previous F to shift by: exact mode; later rows shift by F^{t-1}
@@ -257,41 +272,21 @@ __global__ void __launch_bounds__(kFullThreads) full_solver_kernel(FullParams p)
       flags |= 2;
       break;
     }
-    double rpart = 0.0;
-    for (int rl = tid; rl < nr; rl += blockDim.x) {
-      const int I = r0 + rl;
-      const float Fn = la2[rl] - lse[rl];
-      if (t >= 2) {
-        const float rr = p.a[I] * expm1f((Fcur[rl] - Fn) * kLn2);
-        rpart += (double)rr * (double)rr;
+    if (tid < kWave) {  // wave 0: one row per lane
+      double rr2 = 0.0;
+      if (tid < nr) {
+        const int I = r0 + tid;
+        const float Fn = la2[tid] - lse[tid];
+        if (t >= 2) {
+          const float rr = p.a[I] * expm1f((Fcur[tid] - Fn) * kLn2);
+          rr2 = (double)rr * (double)rr;
+        }
+        Fprev[tid] = Fcur[tid];
+        Fcur[tid] = Fn;
+        slot_publish(p.fx + I, Fn, t);
       }
-      Fprev[rl] = Fcur[rl];
-      Fcur[rl] = Fn;
-      slot_publish(p.fx + I, Fn, t);
-    }
-    const double rtot = block_sum_d(rpart, red);
-    if (tid == 0) slot_publish(p.rsx + w, (float)rtot, t);
-    // ---- stop test on the state after iteration t-1 --------------------------------------
-    if (t >= 2) {
-      for (int v = tid; v < p.W; v += blockDim.x) {
-        uint64_t wv = slot_load(p.rsx + v);
-        if (!slot_wait(p.rsx + v, wv, t, p.ctl)) s_bad = 1;
-        rsv[v] = slot_value(wv);
-      }
-      __syncthreads();
-      if (s_bad) { flags |= 2; break; }
-      if (tid == 0) {
-        double s = 0.0;
-        for (int v = 0; v < p.W; ++v) s += (double)rsv[v];
-        err2 = s;
-        const bool fin = s == s && s < 1.0e300;
-        converged = fin && s <= p.tol2;
-        // tol = 0 asks for exactly max_iter iterations, even if the residual underflows to 0
-        s_stop = (converged && p.tol2 > 0.0) || !fin || (int)(t - 1) >= p.max_iter;
-        if (!fin) flags |= 1;
-      }
-      __syncthreads();
-      if (s_stop) { iters_done = (int)t - 1; break; }
+      rr2 = wave_sum_d(rr2);
+      if (tid == 0) slot_publish(p.rsx + w, (float)rr2, t);
     }
     // ---- column phase: G^t from F^t -------------------------------------------------------
     // shifted by G^{t-1}, which the row update of this iteration used
@@ -300,17 +295,53 @@ __global__ void __launch_bounds__(kFullThreads) full_solver_kernel(FullParams p)
       flags |= 2;
       break;
     }
-    for (int cl = tid; cl < nr; cl += blockDim.x) {
-      const float Gn = lb2[cl] - lse[cl];
-      Gcur[cl] = Gn;
-      slot_publish(p.gx + r0 + cl, Gn, t);
+    if (tid < kWave) {
+      if (tid < nr) {
+        const float Gn = lb2[tid] - lse[tid];
+        Gprev[tid] = Gcur[tid];
+        Gcur[tid] = Gn;
+        slot_publish(p.gx + r0 + tid, Gn, t);
+      }
+      // ---- stop test on the state after iteration t-1: every workgroup sums the same
+      // partials in the same order, so all take the same decision
+      if (t >= 2) {
+        double s = 0.0;
+        bool ok = true;
+        for (int v = tid; v < p.W; v += kWave) {
+          uint64_t wv = slot_load(p.rsx + v);
+          if (ok) ok = slot_wait(p.rsx + v, wv, t, p.ctl);
+          s += (double)slot_value(wv);
+        }
+        s = wave_sum_d(s);
+        if (!ok) s_bad = 1;
+        if (tid == 0) {
+          const bool fin = s == s && s < 1.0e300;
+          // tol = 0 asks for exactly max_iter iterations, even if the residual underflows to 0
+          const bool conv = fin && s <= p.tol2;
+          s_stop = (conv && p.tol2 > 0.0) || !fin || (int)(t - 1) >= p.max_iter;
+          s_err2 = s;
+          s_conv = conv;
+          s_fin = fin;
+        }
+      }
+    }
+    __syncthreads();
+    if (t >= 2) {
+      if (s_bad) { flags |= 2; break; }
+      if (s_stop) {
+        err2 = s_err2;
+        converged = s_conv;
+        if (!s_fin) flags |= 1;
+        iters_done = (int)t - 1;
+        break;
+      }
     }
   }
 
   __syncthreads();
   for (int rl = tid; rl < nr; rl += blockDim.x) {
     p.f_out[r0 + rl] = Fprev[rl] * p.to_nat;
-    p.g_out[r0 + rl] = Gcur[rl] * p.to_nat;
+    p.g_out[r0 + rl] = Gprev[rl] * p.to_nat;
   }
   if (w == 0 && tid == 0) {
     p.dstats[0] = (double)iters_done;
@@ -324,19 +355,20 @@ __global__ void __launch_bounds__(kFullThreads) full_solver_kernel(FullParams p)
   }
 }
 
-// Per-solve setup: pack coordinates, publish the initial column potential as epoch 0.
+// Per-solve setup: pack coordinates scaled by sq = sqrt(log2(e)/eps), publish the initial
+// column potential as epoch 0.
 template <int DIM>
 __global__ void full_init_kernel(int n, int np, const float* __restrict__ x,
                                  const float* __restrict__ y, const float* __restrict__ g0,
-                                 int warm, float s2, float4* __restrict__ xc,
+                                 int warm, float s2, float sq, float4* __restrict__ xc,
                                  float4* __restrict__ yc, uint64_t* __restrict__ gx) {
   for (int I = blockIdx.x * blockDim.x + threadIdx.x; I < np; I += gridDim.x * blockDim.x) {
     float4 vx = make_float4(0.f, 0.f, 0.f, 0.f), vy = vx;
     if (I < n) {
       if constexpr (DIM > 0) {
-        vx.x = x[(int64_t)I * DIM]; vx.y = x[(int64_t)I * DIM + 1];
-        vy.x = y[(int64_t)I * DIM]; vy.y = y[(int64_t)I * DIM + 1];
-        if constexpr (DIM == 3) { vx.z = x[(int64_t)I * 3 + 2]; vy.z = y[(int64_t)I * 3 + 2]; }
+        vx.x = x[(int64_t)I * DIM] * sq; vx.y = x[(int64_t)I * DIM + 1] * sq;
+        vy.x = y[(int64_t)I * DIM] * sq; vy.y = y[(int64_t)I * DIM + 1] * sq;
+        if constexpr (DIM == 3) { vx.z = x[(int64_t)I * 3 + 2] * sq; vy.z = y[(int64_t)I * 3 + 2] * sq; }
       }
       const float G0 = warm ? g0[I] * s2 : 0.0f;
       gx[I] = (uint64_t)__float_as_uint(G0);  // epoch 0
@@ -459,11 +491,12 @@ hipError_t launch_sinkhorn_full(const Geom& g, float* f, float* gpot, double tol
   hipError_t e = launch_zero_words(ctl, (int)(zero_bytes / 4), s);
   if (e != hipSuccess) return e;
   const float s2 = (float)(kLog2eD / g.eps);
+  const float sq = (float)sqrt(kLog2eD / g.eps);
   const int ib = (np + 255) / 256 < 1024 ? (np + 255) / 256 : 1024;
   switch (g.dim) {
-    case 0: hipLaunchKernelGGL(full_init_kernel<0>, dim3(ib), dim3(256), 0, s, g.n, np, g.x, g.y, gpot, warm, s2, xc, yc, gx); break;
-    case 2: hipLaunchKernelGGL(full_init_kernel<2>, dim3(ib), dim3(256), 0, s, g.n, np, g.x, g.y, gpot, warm, s2, xc, yc, gx); break;
-    case 3: hipLaunchKernelGGL(full_init_kernel<3>, dim3(ib), dim3(256), 0, s, g.n, np, g.x, g.y, gpot, warm, s2, xc, yc, gx); break;
+    case 0: hipLaunchKernelGGL(full_init_kernel<0>, dim3(ib), dim3(256), 0, s, g.n, np, g.x, g.y, gpot, warm, s2, sq, xc, yc, gx); break;
+    case 2: hipLaunchKernelGGL(full_init_kernel<2>, dim3(ib), dim3(256), 0, s, g.n, np, g.x, g.y, gpot, warm, s2, sq, xc, yc, gx); break;
+    case 3: hipLaunchKernelGGL(full_init_kernel<3>, dim3(ib), dim3(256), 0, s, g.n, np, g.x, g.y, gpot, warm, s2, sq, xc, yc, gx); break;
     default: return hipErrorInvalidValue;
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;
