@@ -69,13 +69,15 @@ __device__ __forceinline__ int full_phase(const FullParams& p, int r0, const flo
                                           const float4* __restrict__ othc, uint64_t* oslots,
                                           uint32_t epoch, const float* __restrict__ sh,
                                           float4* __restrict__ buf, float2* __restrict__ part,
-                                          float* __restrict__ lse, int* s_bad, int* s_redo) {
+                                          float* __restrict__ lse, int* s_bad, int* s_redo,
+                                          uint64_t* xs, int nx, uint32_t xepoch,
+                                          float* __restrict__ xdst) {
   constexpr int RG = kFullWaves / CQ;
   constexpr int U = kNC / kWave / CQ;  // 64-column steps per wave per chunk
   constexpr int TU = U < 4 ? U : 4;     // columns per lane between running-max rescales
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
-  const int wv = tid / kWave;
+  const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
   const int rg = wv / CQ, cq = wv % CQ;
   float xr[RT][3];
   float M[RT], S[RT];
@@ -103,15 +105,18 @@ __device__ __forceinline__ int full_phase(const FullParams& p, int r0, const flo
   if (tid == 0) *s_redo = 0;
   const int nchunks = p.np / kNC;
   bool ok = true;
-  // prefetch chunk 0: coordinates and slots of points tid + k * kFullThreads
+  // prefetch chunk 0: coordinates and slots of points tid + k * kFullThreads; the nx extra
+  // slots xs[] (another exchange, long published) are staged into xdst with the last chunk
   float4 pc[kPF];
   uint64_t ps[kPF];
+  uint64_t xw = 0;
 #pragma unroll
   for (int k = 0; k < kPF; ++k) {
     const int J = tid + k * kFullThreads;
     pc[k] = DIM > 0 ? othc[J] : make_float4(0.f, 0.f, 0.f, 0.f);
     ps[k] = J < p.n ? slot_load(oslots + J) : 0ull;
   }
+  if (nchunks == 1 && tid < nx) xw = slot_load(xs + tid);
   for (int c = 0; c < nchunks; ++c) {
     float4* cur = buf + (c & 1) * kNC;
 #pragma unroll
@@ -125,6 +130,10 @@ __device__ __forceinline__ int full_phase(const FullParams& p, int r0, const flo
       }
       cur[tid + k * kFullThreads] = pc[k];
     }
+    if (c == nchunks - 1 && tid < nx) {
+      if (ok) ok = slot_wait(xs + tid, xw, xepoch, p.ctl);
+      xdst[tid] = slot_value(xw);
+    }
     if (!ok) *s_bad = 1;
     __syncthreads();
     if (*s_bad) return kPhaseAbort;
@@ -135,6 +144,7 @@ __device__ __forceinline__ int full_phase(const FullParams& p, int r0, const flo
         pc[k] = DIM > 0 ? othc[Jn] : make_float4(0.f, 0.f, 0.f, 0.f);
         ps[k] = Jn < p.n ? slot_load(oslots + Jn) : 0ull;
       }
+      if (c + 2 == nchunks && tid < nx) xw = slot_load(xs + tid);
     }
 #pragma unroll 1
     for (int u = cq * U; u < (cq + 1) * U; u += TU) {
@@ -218,16 +228,19 @@ __device__ __forceinline__ int full_phase_auto(bool exact, const FullParams& p, 
                                                uint64_t* oslots, uint32_t epoch,
                                                const float* sh, float4* buf, float2* part,
                                                float* lse, int* s_bad, int* s_redo,
-                                               int* redo_count) {
+                                               int* redo_count, uint64_t* xs = nullptr,
+                                               int nx = 0, uint32_t xepoch = 0,
+                                               float* xdst = nullptr) {
   if (!exact) {
     const int r = full_phase<DIM, RT, CQ, false>(p, r0, ownc, dense, ldd, othc, oslots, epoch,
-                                                 sh, buf, part, lse, s_bad, s_redo);
+                                                 sh, buf, part, lse, s_bad, s_redo, xs, nx,
+                                                 xepoch, xdst);
     if (r != kPhaseRedo) return r;
     ++*redo_count;
     __syncthreads();  // every wave is done with the chunk buffers
   }
   return full_phase<DIM, RT, CQ, true>(p, r0, ownc, dense, ldd, othc, oslots, epoch, sh, buf,
-                                       part, lse, s_bad, s_redo);
+                                       part, lse, s_bad, s_redo, xs, nx, xepoch, xdst);
 }
 
 template <int DIM, int RT, int CQ>
@@ -237,9 +250,9 @@ __global__ void __launch_bounds__(kFullThreads) full_solver_kernel(FullParams p)
   __shared__ float4 buf[2 * kNC];
   __shared__ float2 part[R * CQ];
   __shared__ float lse[R];
-  __shared__ float Fcur[R], Fprev[R], Gcur[R], Gprev[R], la2[R], lb2[R];
-  __shared__ int s_bad, s_stop, s_redo, s_conv, s_fin;
-  __shared__ double s_err2;
+  __shared__ float Fcur[R], Fprev[R], Gcur[R], Gprev[R], la2[R], lb2[R], aa[R];
+  __shared__ float rsl[kFullThreads];  // residual partials of all workgroups (W <= 1024)
+  __shared__ int s_bad, s_redo;
   const int w = blockIdx.x, tid = threadIdx.x;
   const int r0 = w * R;
   const int nr = max(0, min(R, p.n - r0));
@@ -247,6 +260,7 @@ __global__ void __launch_bounds__(kFullThreads) full_solver_kernel(FullParams p)
   for (int rl = tid; rl < R; rl += blockDim.x) {
     const bool ok = rl < nr;
     const int I = r0 + rl;
+    aa[rl] = ok ? p.a[I] : 0.0f;
     la2[rl] = ok ? log2f(p.a[I]) : 0.0f;
     lb2[rl] = ok ? log2f(p.b[I]) : 0.0f;
     Fcur[rl] = 0.0f;
@@ -261,9 +275,11 @@ __global__ void __launch_bounds__(kFullThreads) full_solver_kernel(FullParams p)
 
   // Iteration t: row phase (F^t from G^{t-1}), then column phase (G^t from F^t).  The row
   // update also yields the residual of the state after iteration t-1; every workgroup
-  // publishes its partial and reads all of them only after the column phase, when they have
-  // long been visible, so the stop test never holds up the exchange.  A stop at iteration t
-  // returns the state after t-1 (F^{t-1}, G^{t-1}) and discards the column phase just done.
+  // publishes its partial, and the column phase stages all of them into LDS with its last
+  // chunk, when they have long been visible, so the stop test never holds up the exchange.
+  // Every wave then sums the same partials in the same order and takes the same decision; a
+  // stop at iteration t returns the state after t-1 (F^{t-1}, G^{t-1}) and discards the
+  // column phase just done.
   for (uint32_t t = 1;; ++t) {
     // ---- row phase: F^t from G^{t-1} ----------------------------------------------------
     // F^1 has no previous F to shift by: exact mode; later rows shift by F^{t-1}
@@ -278,7 +294,7 @@ __global__ void __launch_bounds__(kFullThreads) full_solver_kernel(FullParams p)
         const int I = r0 + tid;
         const float Fn = la2[tid] - lse[tid];
         if (t >= 2) {
-          const float rr = p.a[I] * expm1f((Fcur[tid] - Fn) * kLn2);
+          const float rr = aa[tid] * expm1f((Fcur[tid] - Fn) * kLn2);
           rr2 = (double)rr * (double)rr;
         }
         Fprev[tid] = Fcur[tid];
@@ -291,47 +307,30 @@ __global__ void __launch_bounds__(kFullThreads) full_solver_kernel(FullParams p)
     // ---- column phase: G^t from F^t -------------------------------------------------------
     // shifted by G^{t-1}, which the row update of this iteration used
     if (full_phase_auto<DIM, RT, CQ>(false, p, r0, p.yc, p.CT, p.np, p.xc, p.fx, t, Gcur, buf,
-                                     part, lse, &s_bad, &s_redo, &redos) != kPhaseOk) {
+                                     part, lse, &s_bad, &s_redo, &redos, p.rsx,
+                                     t >= 2 ? p.W : 0, t, rsl) != kPhaseOk) {
       flags |= 2;
       break;
     }
-    if (tid < kWave) {
-      if (tid < nr) {
-        const float Gn = lb2[tid] - lse[tid];
-        Gprev[tid] = Gcur[tid];
-        Gcur[tid] = Gn;
-        slot_publish(p.gx + r0 + tid, Gn, t);
-      }
-      // ---- stop test on the state after iteration t-1: every workgroup sums the same
-      // partials in the same order, so all take the same decision
-      if (t >= 2) {
-        double s = 0.0;
-        bool ok = true;
-        for (int v = tid; v < p.W; v += kWave) {
-          uint64_t wv = slot_load(p.rsx + v);
-          if (ok) ok = slot_wait(p.rsx + v, wv, t, p.ctl);
-          s += (double)slot_value(wv);
-        }
-        s = wave_sum_d(s);
-        if (!ok) s_bad = 1;
-        if (tid == 0) {
-          const bool fin = s == s && s < 1.0e300;
-          // tol = 0 asks for exactly max_iter iterations, even if the residual underflows to 0
-          const bool conv = fin && s <= p.tol2;
-          s_stop = (conv && p.tol2 > 0.0) || !fin || (int)(t - 1) >= p.max_iter;
-          s_err2 = s;
-          s_conv = conv;
-          s_fin = fin;
-        }
-      }
+    if (tid < nr) {  // wave 0
+      const float Gn = lb2[tid] - lse[tid];
+      Gprev[tid] = Gcur[tid];
+      Gcur[tid] = Gn;
+      slot_publish(p.gx + r0 + tid, Gn, t);
     }
-    __syncthreads();
+    // ---- stop test on the state after iteration t-1 (partials staged by the column phase)
     if (t >= 2) {
-      if (s_bad) { flags |= 2; break; }
-      if (s_stop) {
-        err2 = s_err2;
-        converged = s_conv;
-        if (!s_fin) flags |= 1;
+      const int lane = tid & (kWave - 1);
+      double s = 0.0;
+      for (int v = lane; v < p.W; v += kWave) s += (double)rsl[v];
+      s = wave_sum_d(s);
+      const bool fin = s == s && s < 1.0e300;
+      // tol = 0 asks for exactly max_iter iterations, even if the residual underflows to 0
+      const bool conv = fin && s <= p.tol2;
+      if ((conv && p.tol2 > 0.0) || !fin || (int)(t - 1) >= p.max_iter) {
+        err2 = s;
+        converged = conv;
+        if (!fin) flags |= 1;
         iters_done = (int)t - 1;
         break;
       }
@@ -445,6 +444,7 @@ bool plan_full(const Geom& g, int hint, FullPlan* plan) {
   const int RT = kVariants[best].RT, CQ = kVariants[best].CQ;
   const int R = (kFullWaves / CQ) * RT;
   const int W = (g.n + R - 1) / R;
+  if (W > kFullThreads) return false;  // residual partials are staged one per thread
   const void* k = pick_full_kernel(g.dim, RT, CQ);
   if (!k) return false;
   hipFuncAttributes attr;
