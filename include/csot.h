@@ -152,6 +152,8 @@ int ot_sinkhorn_reduced(const ot_problem* prob, const ot_opts* opts, const float
 /* Plain full-size log-domain Sinkhorn on the n x n problem (Alg. 3, stage 2; the paper's
  * baseline), costs recomputed per tile from the coordinates (dim 2/3) or streamed from the
  * dense C (dim 0).  Same stopping rule, statistics and launch structure as the reduced call.
+ * Workgroups (one per CU) own up to 4 blocks of at most 64 rows each, so n <= 256 x the CU
+ * count (65536 on a 256-CU device); larger n fails with OT_ERR_UNSUPPORTED.
  *   f, g [n] out (g is also the warm-start input). */
 int ot_sinkhorn_full(const ot_problem* prob, const ot_opts* opts, float* f, float* g,
                      double* dstats, ot_stats* hstats, void* ws, size_t ws_bytes,

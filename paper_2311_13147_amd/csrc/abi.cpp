@@ -217,6 +217,7 @@ size_t ot_workspace_bytes(const ot_problem* prob, const ot_opts* opts) {
     csot::FullPlan fp;
     fp.W = g.n;
     fp.R = 1;
+    fp.P = 1;
     fp.threads = 256;
     fp.lds = 0;
     if (g.dim == 2 || g.dim == 3 || g.dim == 0) need = std::max(need, csot::full_ws_bytes(g, fp));

@@ -25,7 +25,7 @@ constexpr int kNC = 2048;           // points per LDS chunk (two per thread)
 constexpr int kPF = kNC / kFullThreads;
 
 struct FullParams {
-  int n, np, W, R, max_iter;
+  int n, np, W, R, P, max_iter;  // P row blocks of R rows per workgroup
   float s2, to_nat;
   double tol2;
   const float4* xc;  // [np] packed x coordinates
@@ -62,6 +62,20 @@ constexpr float kMinShiftedSum = 0x1p-60f;
 // outside [2^-60, inf)) makes the caller redo the phase in exact mode.  The shift is added to
 // the staged potentials, so an entry costs 2 sub, 2 fma, 1 exp and 1 add (dim 2).
 constexpr int kPhaseOk = 0, kPhaseAbort = 1, kPhaseRedo = 2;
+
+// The used coordinates of a packed point, loaded at their own width: a full float4 load would
+// also write the register that the staged potential later takes, and a register written by a
+// load still in flight cannot be reused before the load completes.
+template <int DIM>
+__device__ __forceinline__ float4 load_coords(const float4* __restrict__ c) {
+  if constexpr (DIM == 0) {
+    return make_float4(0.f, 0.f, 0.f, 0.f);
+  } else {
+    const float2 v = *reinterpret_cast<const float2*>(c);
+    const float z = DIM == 3 ? reinterpret_cast<const float*>(c)[2] : 0.0f;
+    return make_float4(v.x, v.y, z, 0.0f);
+  }
+}
 
 template <int DIM, int RT, int CQ, bool EXACT>
 __device__ __forceinline__ int full_phase(const FullParams& p, int r0, const float4* __restrict__ ownc,
@@ -113,7 +127,7 @@ __device__ __forceinline__ int full_phase(const FullParams& p, int r0, const flo
 #pragma unroll
   for (int k = 0; k < kPF; ++k) {
     const int J = tid + k * kFullThreads;
-    pc[k] = DIM > 0 ? othc[J] : make_float4(0.f, 0.f, 0.f, 0.f);
+    pc[k] = load_coords<DIM>(othc + J);
     ps[k] = J < p.n ? slot_load(oslots + J) : 0ull;
   }
   if (nchunks == 1 && tid < nx) xw = slot_load(xs + tid);
@@ -141,7 +155,7 @@ __device__ __forceinline__ int full_phase(const FullParams& p, int r0, const flo
 #pragma unroll
       for (int k = 0; k < kPF; ++k) {
         const int Jn = (c + 1) * kNC + tid + k * kFullThreads;
-        pc[k] = DIM > 0 ? othc[Jn] : make_float4(0.f, 0.f, 0.f, 0.f);
+        pc[k] = load_coords<DIM>(othc + Jn);
         ps[k] = Jn < p.n ? slot_load(oslots + Jn) : 0ull;
       }
       if (c + 2 == nchunks && tid < nx) xw = slot_load(xs + tid);
@@ -243,23 +257,30 @@ __device__ __forceinline__ int full_phase_auto(bool exact, const FullParams& p, 
                                        part, lse, s_bad, s_redo, xs, nx, xepoch, xdst);
 }
 
+constexpr int kMaxRowBlocks = 4;  // row blocks per workgroup (n up to 4 x 64 x workgroups)
+
 template <int DIM, int RT, int CQ>
 __global__ void __launch_bounds__(kFullThreads) full_solver_kernel(FullParams p) {
   constexpr int R = (kFullWaves / CQ) * RT;
-  static_assert(R <= kWave, "a workgroup's rows are one per lane of wave 0");
+  static_assert(R <= kWave, "a row block's rows are one per lane of wave 0");
+  constexpr int RM = kMaxRowBlocks * R;
   __shared__ float4 buf[2 * kNC];
   __shared__ float2 part[R * CQ];
-  __shared__ float lse[R];
-  __shared__ float Fcur[R], Fprev[R], Gcur[R], Gprev[R], la2[R], lb2[R], aa[R];
+  __shared__ float lse[RM];
+  __shared__ float Fcur[RM], Fprev[RM], Gcur[RM], Gprev[RM], la2[RM], lb2[RM], aa[RM];
   __shared__ float rsl[kFullThreads];  // residual partials of all workgroups (W <= 1024)
   __shared__ int s_bad, s_redo;
   const int w = blockIdx.x, tid = threadIdx.x;
-  const int r0 = w * R;
-  const int nr = max(0, min(R, p.n - r0));
+  const int P = p.P;
+  // workgroup w owns rows [w P R, (w + 1) P R): P blocks of R rows, each a pass over the
+  // other side
+  const int rbase = w * P * R;
+  const int nr = max(0, min(P * R, p.n - rbase));
+  const int nb = (nr + R - 1) / R;  // row blocks holding rows
 
-  for (int rl = tid; rl < R; rl += blockDim.x) {
+  for (int rl = tid; rl < P * R; rl += blockDim.x) {
     const bool ok = rl < nr;
-    const int I = r0 + rl;
+    const int I = rbase + rl;
     aa[rl] = ok ? p.a[I] : 0.0f;
     la2[rl] = ok ? log2f(p.a[I]) : 0.0f;
     lb2[rl] = ok ? log2f(p.b[I]) : 0.0f;
@@ -283,40 +304,50 @@ __global__ void __launch_bounds__(kFullThreads) full_solver_kernel(FullParams p)
   for (uint32_t t = 1;; ++t) {
     // ---- row phase: F^t from G^{t-1} ----------------------------------------------------
     // F^1 has no previous F to shift by: exact mode; later rows shift by F^{t-1}
-    if (full_phase_auto<DIM, RT, CQ>(t == 1, p, r0, p.xc, p.C, p.ldc, p.yc, p.gx, t - 1, Fcur,
-                                     buf, part, lse, &s_bad, &s_redo, &redos) != kPhaseOk) {
+    int st = kPhaseOk;
+    for (int b = 0; b < nb && st == kPhaseOk; ++b)
+      st = full_phase_auto<DIM, RT, CQ>(t == 1, p, rbase + b * R, p.xc, p.C, p.ldc, p.yc, p.gx,
+                                        t - 1, Fcur + b * R, buf, part, lse + b * R, &s_bad,
+                                        &s_redo, &redos);
+    if (st != kPhaseOk) {
       flags |= 2;
       break;
     }
-    if (tid < kWave) {  // wave 0: one row per lane
+    if (tid < kWave) {  // wave 0: one row per lane and block
       double rr2 = 0.0;
-      if (tid < nr) {
-        const int I = r0 + tid;
-        const float Fn = la2[tid] - lse[tid];
+      for (int rl = tid; rl < nr; rl += kWave) {
+        const float Fn = la2[rl] - lse[rl];
         if (t >= 2) {
-          const float rr = aa[tid] * expm1f((Fcur[tid] - Fn) * kLn2);
-          rr2 = (double)rr * (double)rr;
+          const float rr = aa[rl] * expm1f((Fcur[rl] - Fn) * kLn2);
+          rr2 += (double)rr * (double)rr;
         }
-        Fprev[tid] = Fcur[tid];
-        Fcur[tid] = Fn;
-        slot_publish(p.fx + I, Fn, t);
+        Fprev[rl] = Fcur[rl];
+        Fcur[rl] = Fn;
+        slot_publish(p.fx + rbase + rl, Fn, t);
       }
       rr2 = wave_sum_d(rr2);
       if (tid == 0) slot_publish(p.rsx + w, (float)rr2, t);
     }
     // ---- column phase: G^t from F^t -------------------------------------------------------
-    // shifted by G^{t-1}, which the row update of this iteration used
-    if (full_phase_auto<DIM, RT, CQ>(false, p, r0, p.yc, p.CT, p.np, p.xc, p.fx, t, Gcur, buf,
-                                     part, lse, &s_bad, &s_redo, &redos, p.rsx,
-                                     t >= 2 ? p.W : 0, t, rsl) != kPhaseOk) {
+    // shifted by G^{t-1}, which the row update of this iteration used; the last block also
+    // stages the residual partials
+    for (int b = 0; b < nb && st == kPhaseOk; ++b) {
+      const bool last = b == nb - 1;
+      st = full_phase_auto<DIM, RT, CQ>(false, p, rbase + b * R, p.yc, p.CT, p.np, p.xc, p.fx, t,
+                                        Gcur + b * R, buf, part, lse + b * R, &s_bad, &s_redo,
+                                        &redos, p.rsx, last && t >= 2 ? p.W : 0, t, rsl);
+    }
+    if (st != kPhaseOk) {
       flags |= 2;
       break;
     }
-    if (tid < nr) {  // wave 0
-      const float Gn = lb2[tid] - lse[tid];
-      Gprev[tid] = Gcur[tid];
-      Gcur[tid] = Gn;
-      slot_publish(p.gx + r0 + tid, Gn, t);
+    if (tid < kWave) {  // wave 0
+      for (int rl = tid; rl < nr; rl += kWave) {
+        const float Gn = lb2[rl] - lse[rl];
+        Gprev[rl] = Gcur[rl];
+        Gcur[rl] = Gn;
+        slot_publish(p.gx + rbase + rl, Gn, t);
+      }
     }
     // ---- stop test on the state after iteration t-1 (partials staged by the column phase)
     if (t >= 2) {
@@ -339,8 +370,8 @@ __global__ void __launch_bounds__(kFullThreads) full_solver_kernel(FullParams p)
 
   __syncthreads();
   for (int rl = tid; rl < nr; rl += blockDim.x) {
-    p.f_out[r0 + rl] = Fprev[rl] * p.to_nat;
-    p.g_out[r0 + rl] = Gprev[rl] * p.to_nat;
+    p.f_out[rbase + rl] = Fprev[rl] * p.to_nat;
+    p.g_out[rbase + rl] = Gprev[rl] * p.to_nat;
   }
   if (w == 0 && tid == 0) {
     p.dstats[0] = (double)iters_done;
@@ -434,7 +465,8 @@ bool plan_full(const Geom& g, int hint, FullPlan* plan) {
   const int cus = cu_count();
   if (cus <= 0) return false;
   const int Wmax = hint > 0 ? hint : cus;  // one 16-wave workgroup per CU
-  // smallest R (most parallelism) such that W = ceil(n / R) <= Wmax
+  // smallest R (most parallelism) such that W = ceil(n / R) <= Wmax; beyond 64 Wmax rows,
+  // the largest R with several row blocks per workgroup
   int best = -1;
   for (int v = (int)(sizeof(kVariants) / sizeof(kVariants[0])) - 1; v >= 0; --v) {
     const int R = (kFullWaves / kVariants[v].CQ) * kVariants[v].RT;
@@ -443,7 +475,10 @@ bool plan_full(const Geom& g, int hint, FullPlan* plan) {
   if (best < 0) best = 0;
   const int RT = kVariants[best].RT, CQ = kVariants[best].CQ;
   const int R = (kFullWaves / CQ) * RT;
-  const int W = (g.n + R - 1) / R;
+  const int blocks = (g.n + R - 1) / R;
+  const int P = (blocks + Wmax - 1) / Wmax;
+  if (P > kMaxRowBlocks) return false;
+  const int W = (blocks + P - 1) / P;
   if (W > kFullThreads) return false;  // residual partials are staged one per thread
   const void* k = pick_full_kernel(g.dim, RT, CQ);
   if (!k) return false;
@@ -456,6 +491,7 @@ bool plan_full(const Geom& g, int hint, FullPlan* plan) {
   if (per_cu * cus < W) return false;
   plan->W = W;
   plan->R = R;
+  plan->P = P;
   plan->threads = RT * 100 + CQ;  // variant code (threads per block is always kFullThreads)
   plan->lds = 0;
   return true;
@@ -506,7 +542,7 @@ hipError_t launch_sinkhorn_full(const Geom& g, float* f, float* gpot, double tol
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   FullParams p;
-  p.n = g.n; p.np = np; p.W = pl.W; p.R = pl.R; p.max_iter = max_iter;
+  p.n = g.n; p.np = np; p.W = pl.W; p.R = pl.R; p.P = pl.P; p.max_iter = max_iter;
   p.s2 = s2;
   p.to_nat = (float)(g.eps * kLn2D);
   p.tol2 = tol * tol;

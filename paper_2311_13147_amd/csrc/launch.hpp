@@ -48,6 +48,7 @@ hipError_t launch_sinkhorn_reduced(int m, int K, double eps, const float* logK,
 struct FullPlan {
   int W;
   int R;
+  int P;  // row blocks of R rows per workgroup
   int threads;
   size_t lds;
 };

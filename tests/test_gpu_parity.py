@@ -221,6 +221,37 @@ def test_full_fixed_and_tolerance(lib, name, mk):
         assert np.abs(got - G[key]).max() / np.abs(G[key]).max() < 1e-4
 
 
+def test_full_multi_block_workgroups(lib):
+    """n = 20000 > 64 rows x 256 workgroups: every workgroup owns two row blocks (the last one
+    a ragged 32-row block).  K = 4 rotates by exact quarter turns, so the float32 problem is
+    exactly block-circulant and the tiled float64 reduced iterates are the reference (iterate
+    equivalence); the oracle never forms the 20000 x 20000 cost."""
+    p = workloads.symmetric_problem(20000, 4, 2, 0.05, seed=13)
+    m = p.n // p.K
+    x0 = p.x[:m].astype(np.float64)
+    for r in range(1, p.K):  # the copies are exact quarter turns of block 0
+        rot = x0 @ np.linalg.matrix_power(np.array([[0.0, 1.0], [-1.0, 0.0]]), r)
+        assert np.array_equal(np.abs(rot), np.abs(p.x[r * m:(r + 1) * m].astype(np.float64)))
+    prob = _problem(lib, p)
+    for its in (1, 4):
+        print(f"[full multi-block] n20000 K4 iters={its}", flush=True)
+        f, g, st = lib.ot_sinkhorn_full(prob, lib.make_opts(tol=0.0, max_iter=its))
+        ref = _reduced_ref(p, 0.0, its)
+        assert st["iters"] == its
+        assert np.abs(f.cpu().numpy() - np.tile(ref["f"], p.K)).max() / p.eps < 2e-5
+        assert np.abs(g.cpu().numpy() - np.tile(ref["g"], p.K)).max() / p.eps < 2e-5
+    print("[full multi-block] n20000 K4 tol=1e-6", flush=True)
+    f, g, st = lib.ot_sinkhorn_full(prob, lib.make_opts(tol=1e-6, max_iter=20000))
+    ref = _reduced_ref(p, 1e-6, 20000)
+    assert st["converged"] and abs(st["iters"] - ref["iters"]) <= 1, (st["iters"], ref["iters"])
+    fh, gh = _f64(f.cpu()), _f64(g.cpu())
+    vg = objective.reduced_values(fh[:m], gh[:m], ref["Ck"], p.eps, ref["alpha"], ref["beta"])
+    vr = objective.reduced_values(ref["f"], ref["g"], ref["Ck"], p.eps, ref["alpha"], ref["beta"])
+    assert abs(vg["P"] - vr["P"]) / max(abs(vr["P"]), vr["CT"]) < REL
+    # block-circulance of the full-size solution (shift invariance)
+    assert np.abs(fh.reshape(p.K, m) - fh[:m]).max() / p.eps < 2e-5
+
+
 def test_full_dense(lib):
     p = workloads.dense_appd_problem(600, 6, seed=1)
     print("[full dense] appd n600", flush=True)
