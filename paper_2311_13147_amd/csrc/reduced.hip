@@ -53,7 +53,8 @@ struct RedParams {
   uint64_t* xid;   // [W] XCD index of every workgroup (epoch 1)
   uint64_t* ffin;  // [mp] returned f (natural units) for the float64 check (epoch 1)
   uint64_t* gfin;  // [mp] returned g
-  uint32_t* ctl;   // [0] abort flag, [8..11] two float64 sums, [12] finished workgroups
+  uint64_t* chk;   // [4][W] float64 check partials of every workgroup (two 32-bit halves each)
+  uint32_t* ctl;   // [0] abort flag
   double* dstats;
 };
 
@@ -160,26 +161,72 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
   const int wv = tid / kWave;
   uint32_t* abort_flag = p.ctl;
 
+  // announce this workgroup's XCD before the slab load, so that the check after it rarely waits
+  if (p.stride > 1 && tid == 0) slot_publish(p.xid + w, __uint_as_float(xcc_id()), 1u);
+
   // ---- load the slabs (once) ------------------------------------------------------------
-  // 8 loads in flight per thread before the first store (one memory round trip per 8)
+  // Row slab Ls[rl][j] = logK[r0 + rl][j], column slab LTs[cl][i] = logK[i][r0 + cl], -inf in
+  // the padding.  With m and R multiples of 4 both read float4 (four consecutive columns);
+  // 8 loads in flight per thread before the first store (one memory round trip per 8).
   constexpr int kLd = 8;
-  for (int e0 = tid; e0 < R * mp; e0 += kLd * blockDim.x) {
-    float v[kLd], vt[kLd];
+  if ((m & 3) == 0 && (R & 3) == 0 && (reinterpret_cast<uintptr_t>(p.logK) & 15) == 0) {
+    const float4 ninf = make_float4(-INFINITY, -INFINITY, -INFINITY, -INFINITY);
+    const int q4 = mp / 4, r4 = R / 4;
+    const int nrow = R * q4, ncol = mp * r4;  // quads of the row slab, of the column slab
+    for (int e0 = tid; e0 < nrow + ncol; e0 += kLd * blockDim.x) {
+      float4 v[kLd];
 #pragma unroll
-    for (int u = 0; u < kLd; ++u) {
-      const int e = e0 + u * blockDim.x;
-      const int rl = e / mp, j = e - rl * mp;
-      v[u] = (e < R * mp && rl < nr && j < m) ? p.logK[(int64_t)(r0 + rl) * m + j] : -INFINITY;
-      const int i = e / R, cl = e - i * R;  // consecutive threads read consecutive columns
-      vt[u] = (e < R * mp && cl < nr && i < m) ? p.logK[(int64_t)i * m + r0 + cl] : -INFINITY;
+      for (int u = 0; u < kLd; ++u) {
+        const int e = e0 + u * blockDim.x;
+        v[u] = ninf;
+        if (e < nrow) {
+          const int rl = e / q4, j = 4 * (e - rl * q4);
+          if (rl < nr && j < m) v[u] = *reinterpret_cast<const float4*>(p.logK + (int64_t)(r0 + rl) * m + j);
+        } else if (e < nrow + ncol) {
+          const int ec = e - nrow;
+          const int i = ec / r4, cl = 4 * (ec - i * r4);
+          if (i < m && cl < nr) {
+            v[u] = *reinterpret_cast<const float4*>(p.logK + (int64_t)i * m + r0 + cl);
+            if (cl + 1 >= nr) v[u].y = -INFINITY;
+            if (cl + 2 >= nr) v[u].z = -INFINITY;
+            if (cl + 3 >= nr) v[u].w = -INFINITY;
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kLd; ++u) {
+        const int e = e0 + u * blockDim.x;
+        if (e < nrow) {
+          *reinterpret_cast<float4*>(Ls + 4 * (size_t)e) = v[u];  // natural log
+        } else if (e < nrow + ncol) {
+          const int ec = e - nrow;
+          const int i = ec / r4, cl = 4 * (ec - i * r4);
+          LTs[(size_t)cl * mp + i] = v[u].x;
+          LTs[(size_t)(cl + 1) * mp + i] = v[u].y;
+          LTs[(size_t)(cl + 2) * mp + i] = v[u].z;
+          LTs[(size_t)(cl + 3) * mp + i] = v[u].w;
+        }
+      }
     }
+  } else {
+    for (int e0 = tid; e0 < R * mp; e0 += kLd * blockDim.x) {
+      float v[kLd], vt[kLd];
 #pragma unroll
-    for (int u = 0; u < kLd; ++u) {
-      const int e = e0 + u * blockDim.x;
-      if (e < R * mp) {
-        Ls[e] = v[u];  // natural log
-        const int i = e / R, cl = e - i * R;
-        LTs[(size_t)cl * mp + i] = vt[u];
+      for (int u = 0; u < kLd; ++u) {
+        const int e = e0 + u * blockDim.x;
+        const int rl = e / mp, j = e - rl * mp;
+        v[u] = (e < R * mp && rl < nr && j < m) ? p.logK[(int64_t)(r0 + rl) * m + j] : -INFINITY;
+        const int i = e / R, cl = e - i * R;  // consecutive threads read consecutive columns
+        vt[u] = (e < R * mp && cl < nr && i < m) ? p.logK[(int64_t)i * m + r0 + cl] : -INFINITY;
+      }
+#pragma unroll
+      for (int u = 0; u < kLd; ++u) {
+        const int e = e0 + u * blockDim.x;
+        if (e < R * mp) {
+          Ls[e] = v[u];  // natural log
+          const int i = e / R, cl = e - i * R;
+          LTs[(size_t)cl * mp + i] = vt[u];
+        }
       }
     }
   }
@@ -213,7 +260,6 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
   bool local_pub = false;
   if (p.stride > 1) {
     const uint32_t me = xcc_id();
-    if (tid == 0) slot_publish(p.xid + w, __uint_as_float(me), 1u);
     for (int v = tid; v < p.W; v += blockDim.x) {
       uint64_t x = slot_load(p.xid + v);
       if (!slot_wait(p.xid + v, x, 1u, abort_flag)) s_bad = 1;
@@ -331,10 +377,9 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
   // ---- float64 check of the returned state: full-space L2 marginal errors --------------------
   // Every workgroup stages all returned f and g (natural units, as written) and sums its own
   // rows and columns of the reduced plan T_ij = exp(logK_ij + (f_i + g_j) / eps) from the
-  // stored logK in float64; the squared residuals meet in two float64 accumulators and the last
-  // workgroup to finish writes sqrt(K sum).
-  double* acc = reinterpret_cast<double*>(p.ctl + 8);
-  uint32_t* done = p.ctl + 12;
+  // stored logK in float64; it publishes its two squared-residual partials (each as two 32-bit
+  // halves in epoch-tagged slots), and workgroup 0 sums all of them in a fixed order and
+  // writes sqrt(K sum).
   const bool staged = stage_slots(p.ffin, m, mp, 1u, VsF, p.gfin, m, 1u, VsG, abort_flag, &s_bad);
   const double inv_eps = 1.0 / p.eps;
   double part_r = 0.0, part_c = 0.0;
@@ -362,25 +407,35 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
     s_acc[kRedWaves + wv] = part_c;
   }
   __syncthreads();
-  __shared__ int s_last;
-  if (tid == 0) {
-    double r = 0.0, c = 0.0;
-    for (int k = 0; k < kRedWaves; ++k) { r += s_acc[k]; c += s_acc[kRedWaves + k]; }
-    // agent-scope atomics are performed at the point of coherence; waiting for them to return
-    // orders them before the counter increment, so no cache-flushing fence is needed
-    __hip_atomic_fetch_add(&acc[0], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_fetch_add(&acc[1], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __builtin_amdgcn_s_waitcnt(0);  // both adds have returned before the counter moves
-    s_last = __hip_atomic_fetch_add(done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
-             (uint32_t)(p.W - 1);
+  if (tid < 2) {
+    double v = 0.0;
+    for (int k = 0; k < kRedWaves; ++k) v += s_acc[tid * kRedWaves + k];
+    const uint64_t bits = (uint64_t)__double_as_longlong(v);
+    publish(p.chk + (2 * tid) * p.W + w, __uint_as_float((uint32_t)(bits >> 32)), 1u);
+    publish(p.chk + (2 * tid + 1) * p.W + w, __uint_as_float((uint32_t)bits), 1u);
   }
-  __syncthreads();
-  if (s_last && tid == 0) {
-    const double r = __hip_atomic_load(&acc[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const double c = __hip_atomic_load(&acc[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const bool ok = staged && s_bad == 0;
-    p.dstats[2] = ok ? sqrt((double)p.K * r) : NAN;
-    p.dstats[3] = ok ? sqrt((double)p.K * c) : NAN;
+  if (w == 0 && wv == 0) {
+    double r = 0.0, c = 0.0;
+    bool ok = staged;
+    for (int v = lane; v < p.W; v += kWave) {
+      uint64_t h[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) h[k] = slot_load(p.chk + k * p.W + v);
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (ok) ok = slot_wait(p.chk + k * p.W + v, h[k], 1u, abort_flag);
+      r += __longlong_as_double((long long)(((uint64_t)__float_as_uint(slot_value(h[0])) << 32) |
+                                            __float_as_uint(slot_value(h[1]))));
+      c += __longlong_as_double((long long)(((uint64_t)__float_as_uint(slot_value(h[2])) << 32) |
+                                            __float_as_uint(slot_value(h[3]))));
+    }
+    r = wave_sum_d(r);
+    c = wave_sum_d(c);
+    ok = __all(ok) && s_bad == 0;  // s_bad: an abort seen by this workgroup's exchanges
+    if (lane == 0) {
+      p.dstats[2] = ok ? sqrt((double)p.K * r) : NAN;
+      p.dstats[3] = ok ? sqrt((double)p.K * c) : NAN;
+    }
   }
 }
 
@@ -446,12 +501,14 @@ bool plan_reduced(int m, int hint, ReducedPlan* plan) {
   return true;
 }
 
-// workspace: ctl[64 words] | fx[mp] | gx[mp] | rsx[2W] | xid[W] | ffin[mp] | gfin[mp] (64-bit slots)
+// workspace: ctl[64 words] | fx[mp] | gx[mp] | rsx[2W] | xid[W] | ffin[mp] | gfin[mp] | chk[4W]
+// (64-bit slots)
 static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
 static size_t slots_bytes(int m, int W) {
   return align256(256) + 4 * align256(sizeof(uint64_t) * reduced_mp(m)) +
-         align256(sizeof(uint64_t) * 2 * W) + align256(sizeof(uint64_t) * W);
+         align256(sizeof(uint64_t) * 2 * W) + align256(sizeof(uint64_t) * W) +
+         align256(sizeof(uint64_t) * 4 * W);
 }
 
 size_t reduced_ws_bytes(int m, const ReducedPlan& p) { return slots_bytes(m, p.W); }
@@ -471,6 +528,7 @@ hipError_t launch_sinkhorn_reduced(int m, int K, double eps, const float* logK,
   uint64_t* xid = reinterpret_cast<uint64_t*>(base + off); off += align256(sizeof(uint64_t) * pl.W);
   uint64_t* ffin = reinterpret_cast<uint64_t*>(base + off); off += align256(sizeof(uint64_t) * mp);
   uint64_t* gfin = reinterpret_cast<uint64_t*>(base + off); off += align256(sizeof(uint64_t) * mp);
+  uint64_t* chk = reinterpret_cast<uint64_t*>(base + off); off += align256(sizeof(uint64_t) * 4 * pl.W);
 
   // epochs start at 1, so zeroed slots are never mistaken for current ones
   hipError_t e = launch_zero_words(ctl, (int)(slots_bytes(m, pl.W) / 4), s);
@@ -483,7 +541,7 @@ hipError_t launch_sinkhorn_reduced(int m, int K, double eps, const float* logK,
   p.to_nat = (float)(eps * kLn2D);
   p.tol2 = tol * tol / (double)K;
   p.logK = logK; p.alpha = alpha; p.beta = beta; p.f_out = f; p.g_out = g;
-  p.fx = fx; p.gx = gx; p.rsx = rsx; p.xid = xid; p.ffin = ffin; p.gfin = gfin; p.ctl = ctl;
+  p.fx = fx; p.gx = gx; p.rsx = rsx; p.xid = xid; p.ffin = ffin; p.gfin = gfin; p.chk = chk; p.ctl = ctl;
   p.dstats = dstats;
   p.eps = eps;
   void* args[] = {&p};
