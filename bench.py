@@ -223,9 +223,41 @@ def main():
     grads_f = {k: torch.empty_like(v) for k, v in grads_r.items()}
     csot.workspace(prob, o_tol)
 
+    # The time-to-tolerance work also recorded once in graphs (kernels only; the stopping
+    # decision is made on the GPU), so that a replay shows the GPU time without the host's
+    # per-call dispatch: fold + reduced solve, and the full-size solve.
+    fr3, gr3 = torch.empty(m, device=dev), torch.empty(m, device=dev)
+    ff3, gf3 = torch.empty(N, device=dev), torch.empty(N, device=dev)
+    ds_g = [torch.zeros(8, dtype=torch.float64, device=dev) for _ in range(2)]
+    logK3 = torch.empty((m, m), device=dev)
+    al3, be3 = torch.empty(m, device=dev), torch.empty(m, device=dev)
+
+    def red_tol():
+        csot.ot_fold_kernel(prob, o_tol, out=(logK3, al3, be3))
+        csot.ot_sinkhorn_reduced(prob, logK3, al3, be3, o_tol, host_stats=False, out=(fr3, gr3),
+                                 dstats=ds_g[0])
+
+    def full_tol():
+        csot.ot_sinkhorn_full(prob, o_tol, host_stats=False, out=(ff3, gf3), dstats=ds_g[1])
+
+    graphs = {}
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        red_tol()
+        full_tol()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    for name, fn in (("red_graph", red_tol), ("full_graph", full_tol)):
+        gr_ = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gr_):
+            fn()
+        graphs[name] = gr_
+    torch.cuda.synchronize()
+
     E = lambda: torch.cuda.Event(enable_timing=True)
     legs = ["fold", "red_solve", "expand", "red_grad", "red_fixed", "full_solve", "full_grad",
-            "full_fixed"]
+            "full_fixed", "red_graph", "full_graph"]
 
     def step(record):
         ev = {k: (E(), E()) for k in legs}
@@ -252,6 +284,8 @@ def main():
                                                        grads=grads_f))
         run("full_fixed", lambda: csot.ot_sinkhorn_full(prob, o_ff, host_stats=False,
                                                         out=(ff2, gf2), dstats=ds[3]))
+        run("red_graph", graphs["red_graph"].replay)
+        run("full_graph", graphs["full_graph"].replay)
         return ev
 
     def kernel_ms():
@@ -273,6 +307,10 @@ def main():
     ms = {k: sum(e[k][0].elapsed_time(e[k][1]) for e in evs) / args.steps for k in legs}
     st = [d.cpu().tolist() for d in ds]
     it_red, it_full = int(st[0][0]), int(st[2][0])
+    stg = [d.cpu().tolist() for d in ds_g]
+    # a replay must reproduce the eager solve: same iteration count, converged, same potentials
+    graph_ok = (int(stg[0][0]) == it_red and int(stg[1][0]) == it_full and stg[0][1] == 1.0
+                and stg[1][1] == 1.0 and torch.equal(fr3, fr) and torch.equal(ff3, ff))
     vr, vf = csot.values_dict(vals_r), csot.values_dict(vals_f)
     red_ips = args.fixed_reduced / (ms["red_fixed"] * 1e-3)
     full_ips = args.fixed_full / (ms["full_fixed"] * 1e-3)
@@ -316,6 +354,10 @@ def main():
                            "reduced_end_to_end_with_expand": round(ttt_red + ms["expand"], 4),
                            "full_solve": round(ttt_full, 4),
                            "speedup_solve": round(ttt_full / ttt_red, 2)},
+        "time_to_tol_graph_ms": {"reduced_fold_plus_solve": round(ms["red_graph"], 4),
+                                 "full_solve": round(ms["full_graph"], 4),
+                                 "speedup_solve": round(ms["full_graph"] / ms["red_graph"], 2),
+                                 "replays_match_eager": bool(graph_ok)},
         "forward_backward_ms": {"reduced": round(ttt_red + ms["red_grad"], 4),
                                 "full": round(ttt_full + ms["full_grad"], 4)},
         "iterations_to_tol": {"reduced": it_red, "full": it_full},

@@ -142,8 +142,9 @@ int ot_symmetrize_cost(const ot_problem* prob, float* Csym, int64_t ldcs, void* 
  * sqrt(K) ||T_red 1 - alpha||_2 <= tol.  Only prob->n, K and eps are read.
  *   f, g [m] out (g is also the warm-start input); dstats [OT_DSTATS_LEN] device out or NULL;
  *   hstats [host] out or NULL (non-NULL synchronises and enables OT_ERR_NOCONV/NONFINITE).
- * One persistent cooperative launch: workgroups own row/column slabs of logK in LDS and meet
- * at device-wide barriers; no host round trip per iteration. */
+ * One persistent launch (every workgroup resident at once, at most one per CU): workgroups
+ * own row/column slabs of logK in LDS and exchange potentials through epoch-tagged slots in
+ * device memory; no host round trip per iteration, and the launch can be captured in a graph. */
 int ot_sinkhorn_reduced(const ot_problem* prob, const ot_opts* opts, const float* logK,
                         const float* alpha, const float* beta, float* f, float* g,
                         double* dstats, ot_stats* hstats, void* ws, size_t ws_bytes,

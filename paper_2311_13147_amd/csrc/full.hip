@@ -1,5 +1,5 @@
 // Plain full-size log-domain Sinkhorn on the n x n problem (the baseline the paper compares
-// against: Alg. 3, stage 2, i.e. Cuturi's iteration), one persistent cooperative launch.
+// against: Alg. 3, stage 2, i.e. Cuturi's iteration), one persistent launch.
 //
 //   row    : F_I = log2 a_I - LSE2_J(G_J - C_IJ log2(e)/eps)
 //   column : G_J = log2 b_J - LSE2_I(F_I - C_IJ log2(e)/eps)
@@ -552,7 +552,10 @@ hipError_t launch_sinkhorn_full(const Geom& g, float* f, float* gpot, double tol
   const void* k = pick_full_kernel(g.dim, pl.threads / 100, pl.threads % 100);
   if (!k) return hipErrorInvalidValue;
   if (events && (e = hipEventRecord(events[0], s)) != hipSuccess) return e;
-  e = hipLaunchCooperativeKernel(k, dim3(pl.W), dim3(kFullThreads), args, 0, s);
+  // An ordinary launch: the plan admits no more blocks than CUs and checked that the kernel
+  // fits once per CU, so on a device with no concurrent kernels every block is resident at
+  // once; should one not be, the others' bounded waits end in the abort flag, not in a hang.
+  e = hipLaunchKernel(k, dim3(pl.W), dim3(kFullThreads), args, 0, s);
   if (e != hipSuccess) return e;
   if (events && (e = hipEventRecord(events[1], s)) != hipSuccess) return e;
 

@@ -485,7 +485,7 @@ bool plan_reduced(int m, int hint, ReducedPlan* plan) {
       return false;
     attr_set = true;
   }
-  // co-residency: the cooperative launch needs all W workgroups resident at once
+  // co-residency: the persistent launch needs all W workgroups resident at once
   int per_cu = 0;
   const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
       &per_cu, reduced_solver_kernel, kRedThreads, lds);
