@@ -76,6 +76,9 @@ typedef struct ot_problem {
  *                      to float32 rounding at the speed of the float32 fold.  0: everything
  *                      in float32, whose error grows with C / eps.
  *   warm_start [0]     1: on entry g holds the initial column potential (natural units).
+ *                      2 (ot_sinkhorn_full): on entry g[0..m) holds one block of a block-periodic
+ *                      initial column potential, e.g. a reduced solution, and the solve starts
+ *                      from it tiled K times (the second stage of Alg. 3); elsewhere as 1.
  *   validate   [0]     1: host-side checks of the marginals and of block-circulance (syncs).
  *   workgroups [0]     persistent solvers: number of cooperating workgroups (0 = automatic).
  *   timing_events [NULL]  host pointer to two hipEvent_t owned by the caller.  The persistent

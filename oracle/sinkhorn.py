@@ -24,6 +24,11 @@ fold_marginals, fold_kernel, reduced_sinkhorn, expand_plan
       phi*(y) = eps exp(y / eps)) laid out block-circulantly (Lemma 1, eq.
       blkstr_optimal_solution).
 
+two_stage_sinkhorn
+    Alg. 3 for approximately symmetric data: stage 1 solves the symmetrized (block-averaged)
+    problem by the cyclic algorithm, stage 2 runs full_sinkhorn on the data as given from the
+    tiled stage-1 column potential.
+
 Stopping rule (a reading: the paper only says "until convergence"): after each full iteration
 (row update then column update) the row-marginal residual of the current plan,
 ``err = ||T 1 - a||_2`` on the full n-vector, is compared with ``tol``; the column marginal is
@@ -168,3 +173,20 @@ def cyclic_sinkhorn(a, b, Ck, eps, tol=1e-9, max_iter=100000):
     out = reduced_sinkhorn(alpha, beta, logK, eps, K, tol=tol, max_iter=max_iter)
     out.update(alpha=alpha, beta=beta, logK=logK)
     return out
+
+
+def two_stage_sinkhorn(a, b, C, K, eps, tol=1e-9, max_iter=100000, tol_stage1=None):
+    """Alg. 3 for approximately symmetric data, in the paper's order.  Stage 1: average the
+    marginals over the K blocks (``fold_marginals``) and the cost over the K shifts (the
+    block-circulant projection ``projection.project_blocks``) and solve that reduced problem
+    (Alg. 2).  Stage 2: plain full-size Sinkhorn on the data as given, started from the stage-1
+    column potential tiled K times.  Both stages use the stopping rule of this module; stage 1
+    may use a looser tolerance."""
+    from .projection import project_blocks
+
+    C = np.asarray(C, dtype=np.float64)
+    stage1 = cyclic_sinkhorn(a, b, project_blocks(C, K), eps,
+                             tol=tol if tol_stage1 is None else tol_stage1, max_iter=max_iter)
+    stage2 = full_sinkhorn(a, b, C, eps, tol=tol, max_iter=max_iter,
+                           g0=np.tile(stage1["g"], K))
+    return {"f": stage2["f"], "g": stage2["g"], "stage1": stage1, "stage2": stage2}

@@ -26,3 +26,4 @@ from ._binding import (  # noqa: F401
 )
 from .autograd import CyclicOT, CyclicOTCost, FullOT  # noqa: F401
 from .batched import Batch, BatchDesc  # noqa: F401
+from .two_stage import two_stage_sinkhorn  # noqa: F401

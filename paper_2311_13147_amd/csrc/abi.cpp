@@ -73,6 +73,7 @@ int check_opts(const ot_opts& o) {
   if (o.max_iter < 1) return fail(OT_ERR_ARG, "max_iter must be >= 1");
   if (o.fold_fp64 < -1 || o.fold_fp64 > 1) return fail(OT_ERR_ARG, "fold_fp64 must be -1, 0 or 1");
   if (o.workgroups < 0) return fail(OT_ERR_ARG, "workgroups must be >= 0");
+  if (o.warm_start < 0 || o.warm_start > 2) return fail(OT_ERR_ARG, "warm_start must be 0, 1 or 2");
   if (o.reserved != 0) return fail(OT_ERR_ARG, "reserved option field must be 0");
   return OT_OK;
 }

@@ -386,11 +386,12 @@ __global__ void __launch_bounds__(kFullThreads) full_solver_kernel(FullParams p)
 }
 
 // Per-solve setup: pack coordinates scaled by sq = sqrt(log2(e)/eps), publish the initial
-// column potential as epoch 0.
+// column potential as epoch 0: 0, or g0[I mod wm] (wm = n: a full warm start; wm = m: a
+// block-periodic one tiled from its first block, the second stage of Alg. 3).
 template <int DIM>
 __global__ void full_init_kernel(int n, int np, const float* __restrict__ x,
                                  const float* __restrict__ y, const float* __restrict__ g0,
-                                 int warm, float s2, float sq, float4* __restrict__ xc,
+                                 int warm, int wm, float s2, float sq, float4* __restrict__ xc,
                                  float4* __restrict__ yc, uint64_t* __restrict__ gx) {
   for (int I = blockIdx.x * blockDim.x + threadIdx.x; I < np; I += gridDim.x * blockDim.x) {
     float4 vx = make_float4(0.f, 0.f, 0.f, 0.f), vy = vx;
@@ -400,7 +401,7 @@ __global__ void full_init_kernel(int n, int np, const float* __restrict__ x,
         vy.x = y[(int64_t)I * DIM] * sq; vy.y = y[(int64_t)I * DIM + 1] * sq;
         if constexpr (DIM == 3) { vx.z = x[(int64_t)I * 3 + 2] * sq; vy.z = y[(int64_t)I * 3 + 2] * sq; }
       }
-      const float G0 = warm ? g0[I] * s2 : 0.0f;
+      const float G0 = warm ? g0[I % wm] * s2 : 0.0f;
       gx[I] = (uint64_t)__float_as_uint(G0);  // epoch 0
     }
     xc[I] = vx;
@@ -530,9 +531,9 @@ hipError_t launch_sinkhorn_full(const Geom& g, float* f, float* gpot, double tol
   const float sq = (float)sqrt(kLog2eD / g.eps);
   const int ib = (np + 255) / 256 < 1024 ? (np + 255) / 256 : 1024;
   switch (g.dim) {
-    case 0: hipLaunchKernelGGL(full_init_kernel<0>, dim3(ib), dim3(256), 0, s, g.n, np, g.x, g.y, gpot, warm, s2, sq, xc, yc, gx); break;
-    case 2: hipLaunchKernelGGL(full_init_kernel<2>, dim3(ib), dim3(256), 0, s, g.n, np, g.x, g.y, gpot, warm, s2, sq, xc, yc, gx); break;
-    case 3: hipLaunchKernelGGL(full_init_kernel<3>, dim3(ib), dim3(256), 0, s, g.n, np, g.x, g.y, gpot, warm, s2, sq, xc, yc, gx); break;
+    case 0: hipLaunchKernelGGL(full_init_kernel<0>, dim3(ib), dim3(256), 0, s, g.n, np, g.x, g.y, gpot, warm, warm == 2 ? g.m : g.n, s2, sq, xc, yc, gx); break;
+    case 2: hipLaunchKernelGGL(full_init_kernel<2>, dim3(ib), dim3(256), 0, s, g.n, np, g.x, g.y, gpot, warm, warm == 2 ? g.m : g.n, s2, sq, xc, yc, gx); break;
+    case 3: hipLaunchKernelGGL(full_init_kernel<3>, dim3(ib), dim3(256), 0, s, g.n, np, g.x, g.y, gpot, warm, warm == 2 ? g.m : g.n, s2, sq, xc, yc, gx); break;
     default: return hipErrorInvalidValue;
   }
   if ((e = hipGetLastError()) != hipSuccess) return e;

@@ -84,3 +84,30 @@ def test_exact_symmetry_gives_zero_gap(lib):
     Pf, Pr = r["vf"]["P"], r["vr"]["P"]
     assert abs(Pf - Pr) / max(abs(Pf), r["vf"]["CT"]) < 1e-5
     assert abs(r["sf"]["iters"] - r["sr"]["iters"]) <= 1
+
+
+def test_two_stage_on_jittered_data(lib):
+    """Alg. 3 at n = 16384, K = 32: the two-stage result solves the given (jittered) problem --
+    converged under the float64 check, at the objective of a cold full-size solve, g the column
+    update of f at sampled columns -- and stage 2 needs no more iterations than the cold start."""
+    p = workloads.jittered_problem(N, K, sigma=1e-3, noise=0.01, seed=200)
+    print(f"[two-stage] jittered n={N} K={K}", flush=True)
+    prob = lib.Problem(_t(p.a), _t(p.b), p.eps, K, x=_t(p.x), y=_t(p.y))
+    out = lib.two_stage_sinkhorn(prob, tol=1e-6)
+    s1, s2 = out["stage1"], out["stage2"]
+    ff, gf, sf = lib.ot_sinkhorn_full(prob, lib.make_opts(tol=1e-6, max_iter=20000))
+    v2 = lib.values_dict(lib.ot_cost_and_grad(prob, out["f"], out["g"], reduced=False)["values"])
+    vf = lib.values_dict(lib.ot_cost_and_grad(prob, ff, gf, reduced=False)["values"])
+    print(f"[two-stage] stage1 {s1['iters']} + stage2 {s2['iters']} iterations; cold full "
+          f"{sf['iters']}; P {v2['P']:.9g} vs cold {vf['P']:.9g}", flush=True)
+    assert s1["converged"] and s2["converged"] and s2["err_row"] <= 1e-6 * 1.05
+    assert s2["iters"] <= sf["iters"]
+    assert abs(v2["P"] - vf["P"]) / max(abs(vf["P"]), vf["CT"]) < 1e-5
+    f = out["f"].cpu().numpy().astype(np.float64)
+    x, y, b = p.x.astype(np.float64), p.y.astype(np.float64), p.b.astype(np.float64)
+    g = out["g"].cpu().numpy().astype(np.float64)
+    J = np.random.default_rng(4).choice(N, size=64, replace=False)
+    z = (f[:, None] - cost.sq_euclidean(x, y[J])) / p.eps
+    zmax = z.max(axis=0)
+    g_ref = p.eps * np.log(b[J]) - p.eps * (zmax + np.log(np.exp(z - zmax).sum(axis=0)))
+    assert np.abs(g[J] - g_ref).max() / p.eps < 2e-5

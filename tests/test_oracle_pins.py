@@ -375,3 +375,43 @@ def test_envelope_gradients_match_stored_asymmetric_differences():
         # the value's curvature in a marginal entry grows like 1 / entry, so h = 1e-7 leaves a
         # truncation error up to ~1e-4 relative where b_J or a_J is small (most agree to 1e-7)
         assert abs((v[c["I"]] - v[c["J"]]) - c["fd"]) <= 1e-4 * abs(c["fd"]) + 1e-9, c
+
+
+# ---------------------------------------------------------------- two-stage (Alg. 3) -------
+
+def _plan(f, g, C, eps):
+    return np.exp((f[:, None] + g[None, :] - C) / eps)
+
+
+def test_two_stage_on_exact_symmetry_needs_one_full_iteration():
+    """On exactly block-circulant data the stage-1 solution tiled is already the full solution
+    (Lemma 1 with iterate equivalence), so stage 2 stops after its first iteration, at the plan
+    of a cold full-size solve (the EROT solution is unique)."""
+    m, K, eps = 12, 4, 0.15
+    x, y, a, b = _exact_cloud(m, K, 2, seed=31)
+    C = cost.sq_euclidean(x, y)
+    out = sinkhorn.two_stage_sinkhorn(a, b, C, K, eps, tol=1e-10)
+    assert out["stage1"]["converged"] and out["stage2"]["iters"] == 1
+    cold = sinkhorn.full_sinkhorn(a, b, C, eps, tol=1e-10)
+    T2, Tc = _plan(out["f"], out["g"], C, eps), _plan(cold["f"], cold["g"], C, eps)
+    assert np.abs(T2 - Tc).sum() / Tc.sum() < 1e-8
+
+
+def test_two_stage_reaches_the_unique_solution_on_jittered_data():
+    """Jittered copies and perturbed marginals: stage 2 starts from the symmetrized solution and
+    ends at the unique EROT plan of the given data (equal to a cold solve's, marginals met,
+    primal = dual), in no more full-size iterations than the cold start.  (The saving is small:
+    the slow modes of the full iteration come from the symmetry breaking itself, and a cold
+    start from g = 0, which is block-periodic too, carries them with the same amplitude.)"""
+    p = workloads.jittered_problem(96, 4, sigma=1e-2, noise=0.05, seed=41)
+    x, y, a, b = (v.astype(np.float64) for v in (p.x, p.y, p.a, p.b))
+    C = cost.sq_euclidean(x, y)
+    out = sinkhorn.two_stage_sinkhorn(a, b, C, 4, p.eps, tol=1e-11)
+    cold = sinkhorn.full_sinkhorn(a, b, C, p.eps, tol=1e-11)
+    assert out["stage2"]["converged"] and cold["converged"]
+    T2, Tc = _plan(out["f"], out["g"], C, p.eps), _plan(cold["f"], cold["g"], C, p.eps)
+    assert np.abs(T2 - Tc).sum() / Tc.sum() < 1e-8
+    assert np.abs(T2.sum(axis=0) - b).max() < 1e-12
+    v = objective.full_values(out["f"], out["g"], C, p.eps, a, b)
+    assert abs(v["P"] - v["D"]) <= 1e-9 * max(abs(v["P"]), v["CT"])
+    assert out["stage2"]["iters"] <= cold["iters"]
