@@ -55,6 +55,8 @@ def _args():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--batched", action="store_true",
                     help="only time the batched workload (1024 uneven cyclic problems) and exit")
+    ap.add_argument("--two-stage", action="store_true",
+                    help="only the approximate-symmetry workload: cold full vs two-stage")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (the reference kernel "
                          "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE) and exit")
@@ -135,6 +137,48 @@ def batched_only(steps, warmup):
           flush=True)
 
 
+def two_stage_only(steps, warmup):
+    """The approximate-symmetry workload (n=16384, K=32, m=512, jitter 1e-3, marginal noise 1%,
+    eps = 0.05 median of the symmetric cloud, tol 1e-6): plain full-size Sinkhorn from g = 0 on
+    the given data beside the two-stage method (Alg. 3: reduced solve of the block-averaged
+    problem, then the full-size solve from its tiled potential), each timed with HIP events."""
+    import numpy as np
+    import torch
+
+    import paper_2311_13147_amd as csot
+    import workloads
+
+    p = workloads.jittered_problem(16384, 32, sigma=1e-3, noise=0.01, seed=200)
+    T_ = lambda v: torch.from_numpy(np.ascontiguousarray(v)).to("cuda:0")
+    prob = csot.Problem(T_(p.a), T_(p.b), p.eps, p.K, x=T_(p.x), y=T_(p.y))
+    opts = csot.make_opts(tol=1e-6, max_iter=20000)
+    E = lambda: torch.cuda.Event(enable_timing=True)
+    t_cold, t_two = [], []
+    for it in range(warmup + steps):
+        e = [E() for _ in range(3)]
+        e[0].record()
+        ff, gf, sf = csot.ot_sinkhorn_full(prob, opts, host_stats=False)
+        e[1].record()
+        out = csot.two_stage_sinkhorn(prob, tol=1e-6)
+        e[2].record()
+        torch.cuda.synchronize()
+        if it >= warmup:
+            t_cold.append(e[0].elapsed_time(e[1]))
+            t_two.append(e[1].elapsed_time(e[2]))
+    sf = sf.cpu().tolist()
+    vf = csot.values_dict(csot.ot_cost_and_grad(prob, ff, gf, reduced=False)["values"])
+    v2 = csot.values_dict(csot.ot_cost_and_grad(prob, out["f"], out["g"], reduced=False)["values"])
+    print(json.dumps({"workload": "approximate symmetry: n=16384, K=32, m=512, jitter 1e-3, "
+                                  "marginal noise 1%, eps=0.05*median, tol=1e-6",
+                      "cold_full_ms": round(sum(t_cold) / steps, 3),
+                      "two_stage_ms": round(sum(t_two) / steps, 3),
+                      "iterations": {"cold_full": int(sf[0]), "stage1": out["stage1"]["iters"],
+                                     "stage2": out["stage2"]["iters"]},
+                      "err_row_fp64": {"cold_full": sf[2], "two_stage": out["stage2"]["err_row"]},
+                      "objective_rel_diff": abs(v2["P"] - vf["P"]) / max(abs(vf["P"]), vf["CT"])}),
+          flush=True)
+
+
 def copy_calibration():
     import torch
     src = torch.ones(64 * 1024 * 1024, device="cuda:0")
@@ -182,6 +226,9 @@ def main():
         return
     if args.batched:
         batched_only(args.steps, args.warmup)
+        return
+    if args.two_stage:
+        two_stage_only(args.steps, args.warmup)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
