@@ -314,19 +314,19 @@ __global__ void __launch_bounds__(kFullThreads) full_solver_kernel(FullParams p)
       break;
     }
     if (tid < kWave) {  // wave 0: one row per lane and block
-      double rr2 = 0.0;
+      float rr2 = 0.0f;
       for (int rl = tid; rl < nr; rl += kWave) {
         const float Fn = la2[rl] - lse[rl];
         if (t >= 2) {
-          const float rr = aa[rl] * expm1f((Fcur[rl] - Fn) * kLn2);
-          rr2 += (double)rr * (double)rr;
+          const float rr = scaled_exp2m1(aa[rl], Fcur[rl] - Fn);
+          rr2 = fmaf(rr, rr, rr2);
         }
         Fprev[rl] = Fcur[rl];
         Fcur[rl] = Fn;
         slot_publish(p.fx + rbase + rl, Fn, t);
       }
-      rr2 = wave_sum_d(rr2);
-      if (tid == 0) slot_publish(p.rsx + w, (float)rr2, t);
+      rr2 = wave_sum_v(rr2);  // vector-unit reduction (DPP, lane swaps)
+      if (tid == 0) slot_publish(p.rsx + w, rr2, t);
     }
     // ---- column phase: G^t from F^t -------------------------------------------------------
     // shifted by G^{t-1}, which the row update of this iteration used; the last block also
@@ -352,12 +352,12 @@ __global__ void __launch_bounds__(kFullThreads) full_solver_kernel(FullParams p)
     // ---- stop test on the state after iteration t-1 (partials staged by the column phase)
     if (t >= 2) {
       const int lane = tid & (kWave - 1);
-      double s = 0.0;
-      for (int v = lane; v < p.W; v += kWave) s += (double)rsl[v];
-      s = wave_sum_d(s);
-      const bool fin = s == s && s < 1.0e300;
+      float s = 0.0f;  // fixed order: every wave of every workgroup gets this very sum
+      for (int v = lane; v < p.W; v += kWave) s += rsl[v];
+      s = wave_sum_v(s);
+      const bool fin = s == s && s < 3.0e38f;
       // tol = 0 asks for exactly max_iter iterations, even if the residual underflows to 0
-      const bool conv = fin && s <= p.tol2;
+      const bool conv = fin && (double)s <= p.tol2;
       if ((conv && p.tol2 > 0.0) || !fin || (int)(t - 1) >= p.max_iter) {
         err2 = s;
         converged = conv;
