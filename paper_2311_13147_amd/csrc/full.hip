@@ -210,7 +210,7 @@ __device__ __forceinline__ int full_phase(const FullParams& p, int r0, const flo
     if constexpr (EXACT) {
       wave_lse_merge(m_, s_);
     } else {
-      s_ = wave_sum_all(s_);
+      s_ = wave_sum_v(s_);
     }
     if (lane == 0) part[(rg * RT + q) * CQ + cq] = make_float2(m_, s_);
   }
