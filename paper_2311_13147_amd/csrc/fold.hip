@@ -15,6 +15,8 @@
 //
 // Work per output entry: K cost evaluations twice and K exponentials; the output is m*m
 // floats, so the kernel is bound by exp throughput (float32) or float64 FMA throughput.
+#include <type_traits>
+
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -91,7 +93,13 @@ __device__ __forceinline__ void fold_entry_fp32(const Geom& g, int i, int j, flo
   *out = (-cmin * s2 + log2_fast(s)) * kLn2;
 }
 
+constexpr int kFoldKC = 32;  // shifts k whose target points are staged in LDS at a time
+
 // Blocks with blockIdx.y < ceil(m / TI) fold logK; the last row of blocks folds a and b.
+// Point clouds: the block's 64 target columns j of up to 32 shifts k (points k m + j) are
+// staged in LDS and every thread keeps its x_i in registers, so each cost is two LDS reads and
+// a few FMAs; with K <= 32 one staging serves both passes over k.  Dense costs are read
+// straight from C (no reuse across the block).
 template <int DIM, bool FP64>
 __global__ void __launch_bounds__(kFoldTJ* kFoldTI)
     fold_kernel(Geom g, float* __restrict__ logK, float* __restrict__ alpha,
@@ -110,15 +118,73 @@ __global__ void __launch_bounds__(kFoldTJ* kFoldTI)
     }
     return;
   }
-  const int j = blockIdx.x * kFoldTJ + tj;
+  const int j0 = blockIdx.x * kFoldTJ;
+  const int j = j0 + tj;
   const int i = blockIdx.y * kFoldTI + ti;
-  if (i >= g.m || j >= g.m) return;
-  float* out = logK + (int64_t)i * g.m + j;
-  if constexpr (FP64) {
-    fold_entry_fp64<DIM>(g, i, j, out);
+  if constexpr (DIM == 0) {
+    if (i >= g.m || j >= g.m) return;
+    float* out = logK + (int64_t)i * g.m + j;
+    if constexpr (FP64) fold_entry_fp64<DIM>(g, i, j, out);
+    else fold_entry_fp32<DIM>(g, i, j, (float)(kLog2eD / g.eps), out);
   } else {
-    const float s2 = (float)(kLog2eD / g.eps);
-    fold_entry_fp32<DIM>(g, i, j, s2, out);
+    using Real = typename std::conditional<FP64, double, float>::type;
+    __shared__ float ys[kFoldKC][DIM][kFoldTJ];
+    const bool active = i < g.m && j < g.m;  // inactive threads still stage and meet barriers
+    Real xi[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) xi[d] = active ? (Real)g.x[(int64_t)i * DIM + d] : Real(0);
+    const int nkc = (g.K + kFoldKC - 1) / kFoldKC;
+    auto stage = [&](int kc) {
+      const int kb = kc * kFoldKC;
+      const int nk = min(kFoldKC, g.K - kb);
+      for (int e = threadIdx.x; e < nk * kFoldTJ; e += blockDim.x) {
+        const int kk = e / kFoldTJ, t = e - kk * kFoldTJ;
+        const int jj = j0 + t;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d)
+          ys[kk][d][t] = jj < g.m ? g.y[((int64_t)(kb + kk) * g.m + jj) * DIM + d] : 0.0f;
+      }
+    };
+    // C_ijk = |x_i - y_{k m + j}|^2 (exact in float64 for float32 inputs)
+    auto cost = [&](int kk) {
+      Real c = 0;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const Real df = xi[d] - (Real)ys[kk][d][tj];
+        c += df * df;
+      }
+      return c;
+    };
+    // pass 1: the minimum cost over k; pass 2: the shifted sum (one staging when K <= 32)
+    Real cmin = FP64 ? Real(1.0e300) : Real(3.0e38f);
+    for (int kc = 0; kc < nkc; ++kc) {
+      if (kc > 0) __syncthreads();  // the previous chunk's readers are done
+      stage(kc);
+      __syncthreads();
+      const int nk = min(kFoldKC, g.K - kc * kFoldKC);
+      if (active)
+        for (int kk = 0; kk < nk; ++kk) {
+          const Real c = cost(kk);
+          cmin = c < cmin ? c : cmin;
+        }
+    }
+    const Real s2 = (Real)(kLog2eD / g.eps);
+    float sum = 0.0f;
+    for (int kc = 0; kc < nkc; ++kc) {
+      if (nkc > 1) {
+        __syncthreads();
+        stage(kc);
+        __syncthreads();
+      }
+      const int nk = min(kFoldKC, g.K - kc * kFoldKC);
+      if (active)
+        for (int kk = 0; kk < nk; ++kk) sum += exp2_fast((float)((cmin - cost(kk)) * s2));
+    }
+    if (active) {
+      float* out = logK + (int64_t)i * g.m + j;
+      if constexpr (FP64) *out = (float)(-cmin / g.eps + (double)log2_fast(sum) * kLn2D);
+      else *out = (-cmin * s2 + log2_fast(sum)) * kLn2;
+    }
   }
 }
 
