@@ -389,11 +389,18 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
       const int o = r0 + (row ? q : q - nr);         // own row i or own column j
       const double po = (double)(row ? VsF[o] : VsG[o]);
       const float* opot = row ? VsG : VsF;
-      double sum = 0.0;
       const float* slab = (row ? Ls : LTs) + (size_t)(o - r0) * mp;  // stored logK, natural
-      for (int b = lane; b < m; b += kWave)
-        sum += exp((double)slab[b] + (po + (double)opot[b]) * inv_eps);
-      sum = wave_sum_d(sum);
+      // four independent float64 exponentials in flight per lane (one wave per SIMD here)
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int b = lane;
+      for (; b + 3 * kWave < m; b += 4 * kWave) {
+        s0 += exp((double)slab[b] + (po + (double)opot[b]) * inv_eps);
+        s1 += exp((double)slab[b + kWave] + (po + (double)opot[b + kWave]) * inv_eps);
+        s2 += exp((double)slab[b + 2 * kWave] + (po + (double)opot[b + 2 * kWave]) * inv_eps);
+        s3 += exp((double)slab[b + 3 * kWave] + (po + (double)opot[b + 3 * kWave]) * inv_eps);
+      }
+      for (; b < m; b += kWave) s0 += exp((double)slab[b] + (po + (double)opot[b]) * inv_eps);
+      const double sum = wave_sum_d((s0 + s1) + (s2 + s3));
       const double d = sum - (double)(row ? p.alpha[o] : p.beta[o]);
       if (lane == 0) {
         if (row) part_r += d * d;
