@@ -275,6 +275,29 @@ def test_two_stage_parity(lib):
     assert np.abs((f[I] + g[J]) - (ref["f"][I] + ref["g"][J])).max() / p.eps < 2e-5
 
 
+def test_full_shift_overflow_redoes_in_exact_mode(lib):
+    """Rows whose costs carry offsets of 0 or 100 eps alternate, so the previous potentials of
+    a workgroup's rows spread by ~144 (base 2): the common shift of the shifted phase would
+    overflow float32, the phase is redone in exact mode (counted in dstats[6]) and the result
+    still matches the float64 oracle."""
+    n = 2048
+    rng = np.random.default_rng(17)
+    eps = 0.05
+    C = rng.uniform(0.0, 1.0, size=(n, n)) + (np.arange(n) % 2)[:, None] * (100.0 * eps)
+    C = C.astype(np.float32)
+    a = rng.uniform(0.5, 1.5, size=n)
+    b = rng.uniform(0.5, 1.5, size=n)
+    a, b = workloads.equal_mass_pair(a / a.sum(), b / b.sum())
+    print("[full redo] dense n2048 row offsets", flush=True)
+    prob = lib.Problem(T_(a), T_(b), eps, 1, C=T_(C))
+    f, g, ds = lib.ot_sinkhorn_full(prob, lib.make_opts(tol=0.0, max_iter=6), host_stats=False)
+    dsh = ds.cpu().numpy()
+    assert dsh[0] == 6 and dsh[5] == 0 and dsh[6] > 0, dsh
+    ref = sinkhorn.full_sinkhorn(_f64(a), _f64(b), _f64(C), eps, tol=0.0, max_iter=6)
+    assert np.abs(f.cpu().numpy() - ref["f"]).max() / eps < 2e-5
+    assert np.abs(g.cpu().numpy() - ref["g"]).max() / eps < 2e-5
+
+
 def test_full_dense(lib):
     p = workloads.dense_appd_problem(600, 6, seed=1)
     print("[full dense] appd n600", flush=True)
