@@ -93,6 +93,28 @@ def test_reduced_fixed_iterations(lib, name, mk):
         assert df < 2e-5 and dg < 2e-5, (df, dg)
 
 
+def test_reduced_near_empty_rows_take_the_exact_path(lib):
+    """Block position 5 carries a marginal of 1e-25 in every block: that row's plan sum, which
+    is the shifted sum the row update starts from, stays near 1e-25 (below 2^-60), so the row
+    is recomputed with a running maximum every iteration; potentials still match the oracle."""
+    p = workloads.symmetric_problem(256, 4, 2, 0.05, seed=23)
+    a = p.a.astype(np.float64).copy()
+    a.reshape(p.K, p.m)[:, 5] = 1e-25
+    a = (a / a.sum()).astype(np.float32)
+    print("[reduced tiny row] n256 K4", flush=True)
+    prob = lib.Problem(T_(a), T_(p.b), p.eps, p.K, x=T_(p.x), y=T_(p.y))
+    q = workloads.Problem(n=p.n, K=p.K, dim=p.dim, x=p.x, y=p.y, a=a, b=p.b, eps=p.eps,
+                          seed=p.seed, name="tiny")
+    for its in (2, 10):
+        opts = lib.make_opts(tol=0.0, max_iter=its, fold_fp64=1)
+        logK, alpha, beta = lib.ot_fold_kernel(prob, opts)
+        f, g, st = lib.ot_sinkhorn_reduced(prob, logK, alpha, beta, opts)
+        ref = _reduced_ref(q, 0.0, its)
+        assert st["iters"] == its
+        assert np.abs(f.cpu().numpy() - ref["f"]).max() / p.eps < 2e-5
+        assert np.abs(g.cpu().numpy() - ref["g"]).max() / p.eps < 2e-5
+
+
 @pytest.mark.parametrize("name,mk", CASES, ids=[c[0] for c in CASES])
 def test_reduced_to_tolerance(lib, name, mk):
     p = mk()
