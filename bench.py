@@ -79,6 +79,9 @@ def batched_only(steps, warmup):
                        for it in items)]
     batch = csot.Batch(probs, device="cuda:0")
     opts = csot.make_opts(tol=1e-6, max_iter=20000)
+    # the solve kernel alone, timed by events the library records right around its launch
+    sev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    opts_ev = csot.make_opts(tol=1e-6, max_iter=20000, timing_events=sev)
     for _ in range(warmup):
         batch.run(opts)
     torch.cuda.synchronize()
@@ -90,6 +93,29 @@ def batched_only(steps, warmup):
     torch.cuda.synchronize()
     out = batch.OUT.cpu().numpy()
     ms = e0.elapsed_time(e1) / steps
+    solve_ms = []
+    for _ in range(steps):
+        batch.run(opts_ev)
+        torch.cuda.synchronize()
+        solve_ms.append(sev[0].elapsed_time(sev[1]))
+    solve_ms = sum(solve_ms) / steps
+    # Algorithmic bytes of the solve: every pass over a problem's folded kernel that is not kept
+    # in LDS reads m * mp floats (logK rows in the row pass, its transpose in the column pass).
+    # One workgroup stops at the row pass of iteration iters + 1 (2 iters + 1 passes); a gang
+    # tests the state two iterations back (2 iters + 3 passes); LDS-resident problems read
+    # logK and its transpose once.
+    lds_floats = 148 * 1024 // 4
+    solve_bytes = 0
+    for m_, it_ in zip(batch.ms, out[:, 5]):
+        mp_ = (m_ + 3) // 4 * 4
+        it_ = int(it_)
+        if m_ > 256:
+            passes = 2 * it_ + 3
+        elif 6 * mp_ + 2 * m_ * mp_ <= lds_floats:
+            passes = 2
+        else:
+            passes = 2 * it_ + 1
+        solve_bytes += passes * m_ * mp_ * 4
 
     # The same problems solved one at a time at full size (n = K m points per side) on the GPU:
     # full-size Sinkhorn to the same tolerance, then values and coordinate gradients of all n
@@ -128,6 +154,12 @@ def batched_only(steps, warmup):
                       "all_converged": bool((out[:, 6] == 1).all()),
                       "max_err_row": float(out[:, 3].max()),
                       "iterations_median_max": [float(np.median(out[:, 5])), float(out[:, 5].max())],
+                      "solve_kernel_ms": round(solve_ms, 3),
+                      "solve_roofline": {"bound": "hbm", "unit": "GB/s",
+                                         "achieved": round(solve_bytes / (solve_ms * 1e-3) / 1e9, 1),
+                                         "peak": HBM_PEAK_GBS,
+                                         "frac": round(solve_bytes / (solve_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                         "bytes_per_launch": solve_bytes},
                       "full_size_one_by_one": {
                           "ms": round(full_ms, 3),
                           "all_converged": bool((fit[:, 1] == 1).all()),

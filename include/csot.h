@@ -82,10 +82,11 @@ typedef struct ot_problem {
  *   validate   [0]     1: host-side checks of the marginals and of block-circulance (syncs).
  *   workgroups [0]     persistent solvers: number of cooperating workgroups (0 = automatic).
  *   timing_events [NULL]  host pointer to two hipEvent_t owned by the caller.  The persistent
- *                      solver calls (ot_sinkhorn_reduced, ot_sinkhorn_full) record the first on
- *                      the stream immediately before their solver kernel and the second right
- *                      after it, so the elapsed time between them is that kernel alone (no
- *                      set-up or float64 check kernels).  Other calls ignore it.
+ *                      solver calls (ot_sinkhorn_reduced, ot_sinkhorn_full,
+ *                      ot_sinkhorn_reduced_batched) record the first on the stream immediately
+ *                      before their solver kernel and the second right after it, so the elapsed
+ *                      time between them is that kernel alone (no set-up, fold, values or
+ *                      float64 check kernels).  Other calls ignore it.
  */
 typedef struct ot_opts {
   double tol;

@@ -371,7 +371,8 @@ int ot_sinkhorn_reduced_batched(const ot_batch_desc* descs, int32_t count, const
   if (nfold < count || nval < 2 * count)
     return fail(OT_ERR_ARG, "fold_tiles / value_tiles must be plan[0] / plan[1]");
   hipError_t e = csot::launch_batched(descs, count, plan, nfold, nval, o.tol, o.max_iter,
-                                      o.fold_fp64, o.warm_start, ws, static_cast<hipStream_t>(stream));
+                                      o.fold_fp64, o.warm_start, ws, static_cast<hipStream_t>(stream),
+                                      static_cast<hipEvent_t*>(o.timing_events));
   if (e != hipSuccess) return hip_fail(e, "batched launch");
   return ok();
 }

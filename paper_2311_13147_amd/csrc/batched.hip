@@ -868,7 +868,7 @@ size_t batched_ws_bytes(int count) { return a256(256) + a256(sizeof(double) * 8 
 
 hipError_t launch_batched(const ot_batch_desc* descs, int count, const int32_t* dplan,
                           int nfold, int nval, double tol, int max_iter, int fold_fp64,
-                          int warm, void* ws, hipStream_t s) {
+                          int warm, void* ws, hipStream_t s, hipEvent_t* events) {
   char* base = static_cast<char*>(ws);
   uint32_t* queue = reinterpret_cast<uint32_t*>(base);
   double* accs = reinterpret_cast<double*>(base + a256(256));
@@ -899,8 +899,10 @@ hipError_t launch_batched(const ot_batch_desc* descs, int count, const int32_t* 
   // members of a gang never wait on a workgroup that cannot start; workgroups that find the
   // queue empty leave at once
   const int grid = cus;
+  if (events && (e = hipEventRecord(events[0], s)) != hipSuccess) return e;
   hipLaunchKernelGGL(batched_solve_kernel, dim3(grid), dim3(kBSolveThreads), kBMaxLds, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (events && (e = hipEventRecord(events[1], s)) != hipSuccess) return e;
   hipLaunchKernelGGL(batched_values_kernel, dim3(nval), dim3(256), 0, s, descs, count, vstart, accs);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(batched_finalize_kernel, dim3((count + 255) / 256), dim3(256), 0, s, descs,
