@@ -32,15 +32,6 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
   return v;
 }
-// max / sum over groups of `width` consecutive lanes (width a power of two <= 64)
-__device__ __forceinline__ float group_max(float v, int width) {
-  for (int o = width >> 1; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
-  return v;
-}
-__device__ __forceinline__ float group_sum(float v, int width) {
-  for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
-}
 
 // Cross-lane moves on the VALU (DPP) within a row of 16 lanes: lane i reads lane i^1, i^2,
 // the mirror within its half-row (7 - i) and the mirror within its row (15 - i).  Applied in
@@ -61,18 +52,8 @@ __device__ __forceinline__ void lse_merge(float& M, float& S, float M2, float S2
   M = Mn;
 }
 
-// Wave-wide max / sum with every lane receiving the result: DPP inside rows of 16 lanes,
-// a swizzle across rows (xor 16), then the two half-waves combined through lanes 0 and 32.
-__device__ __forceinline__ float wave_max_all(float v) {
-  v = fmaxf(v, dpp_f32<kDppXor1>(v));
-  v = fmaxf(v, dpp_f32<kDppXor2>(v));
-  v = fmaxf(v, dpp_f32<kDppHalfMirror>(v));
-  v = fmaxf(v, dpp_f32<kDppMirror>(v));
-  v = fmaxf(v, __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F)));
-  const float a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
-  const float b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
-  return fmaxf(a, b);
-}
+// Wave-wide sum with every lane receiving the result: DPP inside rows of 16 lanes, a swizzle
+// across rows (xor 16), then the two half-waves combined through lanes 0 and 32.
 __device__ __forceinline__ float wave_sum_all(float v) {
   v += dpp_f32<kDppXor1>(v);
   v += dpp_f32<kDppXor2>(v);
@@ -151,45 +132,9 @@ __device__ __forceinline__ double block_sum_d(double v, double* scratch) {
   return t;
 }
 
-// ----------------------------------------------------------------------------------------
-// Device-wide barrier for cooperative (co-resident) grids.
-//
-// `ctl[0]` is a monotonically increasing arrival counter, zeroed by the host-ordered init
-// kernel before the launch; barrier number b (1, 2, ...) completes when the counter reaches
-// nblocks * b.  Every thread publishes its own global writes with an agent-scope release
-// fence, one thread per block arrives and polls, then an agent-scope acquire fence makes the
-// other blocks' writes visible to the whole block.  The wait is bounded: after `kSpinLimit`
-// polls the block raises the abort flag `ctl[1]`; every other waiter sees it and gives up, so
-// the grid always drains.  Returns false when the barrier was abandoned.
-// ----------------------------------------------------------------------------------------
+// Bound on the polls of a bounded wait (seconds of polling); after it the waiter raises the abort
+// flag, which every other waiter checks, so a grid always drains.
 constexpr uint32_t kSpinLimit = 1u << 22;
-
-__device__ __forceinline__ bool grid_barrier(uint32_t* ctl, uint32_t target, int* s_flag) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int ok = 1;
-    __hip_atomic_fetch_add(&ctl[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    uint32_t spins = 0;
-    while (__hip_atomic_load(&ctl[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(1);
-      if (++spins >= kSpinLimit) {
-        __hip_atomic_store(&ctl[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ok = 0;
-        break;
-      }
-      if ((spins & 63u) == 0 &&
-          __hip_atomic_load(&ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-        ok = 0;
-        break;
-      }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    *s_flag = ok;
-  }
-  __syncthreads();
-  return *s_flag != 0;
-}
 
 // ----------------------------------------------------------------------------------------
 // Epoch-tagged exchange slots.
