@@ -236,14 +236,14 @@ size_t ot_batched_workspace_bytes(int32_t count);
 
 /* Many independent cyclic problems of uneven size (the reduced path of Alg. 2 for each):
  * fold, cyclic Sinkhorn to tol (each problem stops on its own), objective values, float64
- * marginal errors and first-block gradients.  Four launches on `stream`: a tiled fold, ONE
- * persistent solve launch (one workgroup per CU, all resident) whose workgroups pop tasks --
+ * marginal errors and first-block gradients.  Launches on `stream`: two small clearing
+ * kernels (queue and accumulators), a tiled fold, ONE persistent solve launch (one workgroup per CU, all resident) whose workgroups pop tasks --
  * a whole small problem or one member's share of a large one -- from a device work queue, a
  * tiled value/gradient kernel and a per-problem finalize.  No host synchronisation, memset or
  * allocation, so the call can be captured in a HIP graph.  `plan` is the device copy of
  * ot_batched_plan's output for the same descriptors; fold_tiles and value_tiles are its first
  * two entries (plan[0], plan[1]), passed by value so that no device read is needed.  opts:
- * tol, max_iter, fold_fp64, warm_start are honoured.
+ * tol, max_iter, fold_fp64, warm_start and timing_events are honoured.
  * Errors: OT_ERR_ARG, OT_ERR_WORKSPACE, OT_ERR_HIP. */
 int ot_sinkhorn_reduced_batched(const ot_batch_desc* descs, int32_t count, const int32_t* plan,
                                 int32_t fold_tiles, int32_t value_tiles, const ot_opts* opts,
