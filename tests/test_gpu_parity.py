@@ -320,6 +320,34 @@ def test_full_shift_overflow_redoes_in_exact_mode(lib):
     assert np.abs(g.cpu().numpy() - ref["g"]).max() / eps < 2e-5
 
 
+def test_validate_option_reports_bad_inputs(lib):
+    """validate = 1: the host-side checks reject a non-positive marginal, unequal masses and
+    (for the reduced path) data that is not block-circulant, and accept valid inputs."""
+    p = workloads.symmetric_problem(512, 8, 2, 0.05, seed=0)
+    opts = lib.make_opts(validate=1)
+    print("[validate] n512 K8", flush=True)
+    lib.ot_fold_kernel(_problem(lib, p), opts)                       # valid: no error
+
+    def code_of(fn):
+        with pytest.raises(lib.CsotError) as ei:
+            fn()
+        return ei.value.code
+
+    a_neg = p.a.copy()
+    a_neg[3] = -a_neg[3]
+    pn = lib.Problem(T_(a_neg), T_(p.b), p.eps, p.K, x=T_(p.x), y=T_(p.y))
+    assert code_of(lambda: lib.ot_fold_kernel(pn, opts)) == 2          # OT_ERR_MASS
+    a_more = (p.a * np.float32(1.01)).astype(np.float32)
+    pm = lib.Problem(T_(a_more), T_(p.b), p.eps, p.K, x=T_(p.x), y=T_(p.y))
+    assert code_of(lambda: lib.ot_fold_kernel(pm, opts)) == 2
+    j = workloads.jittered_problem(512, 8, sigma=1e-3, noise=0.0, seed=200)
+    pj = _problem(lib, j)
+    assert code_of(lambda: lib.ot_fold_kernel(pj, opts)) == 3          # OT_ERR_NOT_SYMMETRIC
+    # the full-size solver needs no symmetry
+    f, g, st = lib.ot_sinkhorn_full(pj, lib.make_opts(validate=1, tol=1e-6))
+    assert st["converged"]
+
+
 def test_full_dense(lib):
     p = workloads.dense_appd_problem(600, 6, seed=1)
     print("[full dense] appd n600", flush=True)
