@@ -64,70 +64,113 @@ __device__ __forceinline__ Real bcost(const float* __restrict__ x, int I,
 // to float32 rounding; otherwise all float32.  Output in base 2 (log2 of the folded kernel).
 constexpr int kFoldQ = 4;  // rows per thread
 
+constexpr int kFoldJC = 64;  // target columns j per LDS staging (one per lane of a wave)
+constexpr int kFoldKC = 32;  // shifts k per LDS staging
+
+// A fold tile: rows [i0, i0 + rows) (four groups of kFoldQ rows, one group per wave) against
+// every column j.  For each chunk of 64 columns the target points y_{k m + j} of up to 32
+// shifts are staged in LDS (K <= 32: one staging serves both passes), so each cost is an LDS
+// read and a few FMAs and every staged point serves the tile's 16 rows.
 template <int DIM, typename Real>
 __device__ __forceinline__ void fold_cols(const ot_batch_desc& d, int i0, int rows, float* L,
-                                          float* LT) {
+                                          float* LT, float* __restrict__ ys) {
   const int m = bm(d), K = d.K, mp = bmp(m);
   const Real s2 = (Real)(kLog2eD / d.eps);
-  const int groups = (rows + kFoldQ - 1) / kFoldQ;
-  for (int e = threadIdx.x; e < groups * m; e += blockDim.x) {
-    const int g = e / m, j = e - g * m;
-    const int ib = i0 + g * kFoldQ;
+  const int tj = threadIdx.x % kFoldJC, grp = threadIdx.x / kFoldJC;
+  const int ib = i0 + grp * kFoldQ;
+  const bool grp_active = ib < i0 + rows;  // inactive groups still stage and meet barriers
+  float xf[kFoldQ][DIM];
+  Real xq[kFoldQ][DIM];
+#pragma unroll
+  for (int q = 0; q < kFoldQ; ++q) {
+    const int i = min(ib + q, i0 + rows - 1);
+#pragma unroll
+    for (int dd = 0; dd < DIM; ++dd) {
+      xf[q][dd] = d.x[(int64_t)i * DIM + dd];
+      xq[q][dd] = (Real)xf[q][dd];
+    }
+  }
+  const int nkc = (K + kFoldKC - 1) / kFoldKC;
+  auto Y = [&](int kk, int dd, int t) -> float& { return ys[(kk * DIM + dd) * kFoldJC + t]; };
+  auto stage = [&](int kc, int j0) {
+    const int kb = kc * kFoldKC, nk = min(kFoldKC, K - kb);
+    for (int e = threadIdx.x; e < nk * kFoldJC; e += blockDim.x) {
+      const int kk = e / kFoldJC, t = e - kk * kFoldJC, jj = j0 + t;
+#pragma unroll
+      for (int dd = 0; dd < DIM; ++dd)
+        Y(kk, dd, t) = jj < m ? d.y[((int64_t)(kb + kk) * m + jj) * DIM + dd] : 0.0f;
+    }
+  };
+  for (int j0 = 0; j0 < m; j0 += kFoldJC) {
+    const int j = j0 + tj;
+    const bool active = grp_active && j < m;
     // pass 1 (float32): the shift, the minimum cost up to float32 rounding -- any shift that
     // close to the minimum keeps every shifted exponent <= ~0, and the same value is added
     // back exactly
-    Real xq[kFoldQ][DIM], cmin[kFoldQ];
-    float xf[kFoldQ][DIM], cminf[kFoldQ];
+    float cminf[kFoldQ];
 #pragma unroll
-    for (int q = 0; q < kFoldQ; ++q) {
-      const int i = min(ib + q, i0 + rows - 1);
-#pragma unroll
-      for (int dd = 0; dd < DIM; ++dd) {
-        xf[q][dd] = d.x[(int64_t)i * DIM + dd];
-        xq[q][dd] = (Real)xf[q][dd];
-      }
-      cminf[q] = 3.0e38f;
-    }
+    for (int q = 0; q < kFoldQ; ++q) cminf[q] = 3.0e38f;
+    for (int kc = 0; kc < nkc; ++kc) {
+      __syncthreads();  // the previous staging's readers are done
+      stage(kc, j0);
+      __syncthreads();
+      const int nk = min(kFoldKC, K - kc * kFoldKC);
+      if (active) {
 #pragma unroll 4
-    for (int k = 0; k < K; ++k) {
-      float yv[DIM];
+        for (int kk = 0; kk < nk; ++kk) {
+          float yv[DIM];
 #pragma unroll
-      for (int dd = 0; dd < DIM; ++dd) yv[dd] = d.y[(int64_t)(k * m + j) * DIM + dd];
+          for (int dd = 0; dd < DIM; ++dd) yv[dd] = Y(kk, dd, tj);
 #pragma unroll
-      for (int q = 0; q < kFoldQ; ++q) {
-        float c = 0.0f;
+          for (int q = 0; q < kFoldQ; ++q) {
+            float c = 0.0f;
 #pragma unroll
-        for (int dd = 0; dd < DIM; ++dd) { const float df = xf[q][dd] - yv[dd]; c = fmaf(df, df, c); }
-        cminf[q] = fminf(c, cminf[q]);
+            for (int dd = 0; dd < DIM; ++dd) { const float df = xf[q][dd] - yv[dd]; c = fmaf(df, df, c); }
+            cminf[q] = fminf(c, cminf[q]);
+          }
+        }
       }
     }
+    Real cmin[kFoldQ];
 #pragma unroll
     for (int q = 0; q < kFoldQ; ++q) cmin[q] = (Real)cminf[q];
     float sum[kFoldQ] = {};
+    for (int kc = 0; kc < nkc; ++kc) {
+      if (nkc > 1) {
+        __syncthreads();
+        stage(kc, j0);
+        __syncthreads();
+      }
+      const int nk = min(kFoldKC, K - kc * kFoldKC);
+      if (active) {
 #pragma unroll 4
-    for (int k = 0; k < K; ++k) {
-      Real yv[DIM];
+        for (int kk = 0; kk < nk; ++kk) {
+          Real yv[DIM];
 #pragma unroll
-      for (int dd = 0; dd < DIM; ++dd) yv[dd] = (Real)d.y[(int64_t)(k * m + j) * DIM + dd];
+          for (int dd = 0; dd < DIM; ++dd) yv[dd] = (Real)Y(kk, dd, tj);
 #pragma unroll
-      for (int q = 0; q < kFoldQ; ++q) {
-        Real c = 0;
+          for (int q = 0; q < kFoldQ; ++q) {
+            Real c = 0;
 #pragma unroll
-        for (int dd = 0; dd < DIM; ++dd) { const Real df = xq[q][dd] - yv[dd]; c = fma(df, df, c); }
-        sum[q] += exp2_fast((float)((cmin[q] - c) * s2));
+            for (int dd = 0; dd < DIM; ++dd) { const Real df = xq[q][dd] - yv[dd]; c = fma(df, df, c); }
+            sum[q] += exp2_fast((float)((cmin[q] - c) * s2));
+          }
+        }
       }
     }
-    float v[kFoldQ];
+    if (active) {
+      float v[kFoldQ];
 #pragma unroll
-    for (int q = 0; q < kFoldQ; ++q) v[q] = (float)(-cmin[q] * s2 + (Real)log2_fast(sum[q]));
+      for (int q = 0; q < kFoldQ; ++q) v[q] = (float)(-cmin[q] * s2 + (Real)log2_fast(sum[q]));
 #pragma unroll
-    for (int q = 0; q < kFoldQ; ++q)
-      if (ib + q < i0 + rows) L[(size_t)(ib + q) * mp + j] = v[q];
-    float* lt = LT + (size_t)j * mp + ib;  // ib is a multiple of 4 and mp too: 16-byte aligned
-    if (ib + kFoldQ <= i0 + rows) {
-      *reinterpret_cast<float4*>(lt) = make_float4(v[0], v[1], v[2], v[3]);
-    } else {
-      for (int q = 0; q < kFoldQ && ib + q < i0 + rows; ++q) lt[q] = v[q];
+      for (int q = 0; q < kFoldQ; ++q)
+        if (ib + q < i0 + rows) L[(size_t)(ib + q) * mp + j] = v[q];
+      float* lt = LT + (size_t)j * mp + ib;  // ib is a multiple of 4 and mp too: 16-byte aligned
+      if (ib + kFoldQ <= i0 + rows) {
+        *reinterpret_cast<float4*>(lt) = make_float4(v[0], v[1], v[2], v[3]);
+      } else {
+        for (int q = 0; q < kFoldQ && ib + q < i0 + rows; ++q) lt[q] = v[q];
+      }
     }
   }
 }
@@ -138,8 +181,9 @@ __device__ void fold_tile(const ot_batch_desc& d, int i0, int fp64_mode) {
   float* L = d.logK;
   float* LT = L + (size_t)m * mp;
   const int rows = min(kBT, m - i0);
-  if (fp64_mode != 0) fold_cols<DIM, double>(d, i0, rows, L, LT);
-  else fold_cols<DIM, float>(d, i0, rows, L, LT);
+  __shared__ float ys[kFoldKC * DIM * kFoldJC];
+  if (fp64_mode != 0) fold_cols<DIM, double>(d, i0, rows, L, LT, ys);
+  else fold_cols<DIM, float>(d, i0, rows, L, LT, ys);
   // padding: -inf contributes nothing to a log-sum-exp
   for (int e = threadIdx.x; e < rows * (mp - m); e += blockDim.x) {
     const int i = i0 + e / (mp - m), j = m + e % (mp - m);
