@@ -84,6 +84,15 @@ __global__ void __launch_bounds__(kPassThreads)
   }
   const int nblk = RED ? g.K : 1;
   const int bl = RED ? g.m : g.n;
+  // RED with coordinates: the cost uses block-row 0's points -- ROW: x_i (own, fixed) against
+  // y_{k m + b}; COL: x_b (the partner itself) against y_{k m + j} (own, fixed per block)
+  float xc[kPassRT][DIM > 0 ? DIM : 1];
+  if constexpr (RED && ROW && DIM > 0) {
+#pragma unroll
+    for (int q = 0; q < kPassRT; ++q)
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) xc[q][d] = g.x[(int64_t)ai[q] * DIM + d];
+  }
   for (int cb = 0; cb < nblk; ++cb) {
     int kk[kPassRT];
 #pragma unroll
@@ -92,12 +101,28 @@ __global__ void __launch_bounds__(kPassThreads)
       int k = ROW ? cb - ab[q] : ab[q] - cb;
       kk[q] = k < 0 ? k + g.K : k;
     }
+    if constexpr (RED && !ROW && DIM > 0) {
+#pragma unroll
+      for (int q = 0; q < kPassRT; ++q)
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) xc[q][d] = g.y[((int64_t)kk[q] * g.m + ai[q]) * DIM + d];
+    }
+    // the own points of a wave usually share one block: then one cost point serves all four
+    const bool same_k = kk[0] == kk[kPassRT - 1] && kk[1] == kk[0] && kk[2] == kk[0];
+#pragma unroll 2
     for (int b = lane; b < bl; b += kWave) {
       const int B = cb * bl + b;  // other point (global index)
       float pb[DIM > 0 ? DIM : 1];
       if constexpr (DIM > 0) {
 #pragma unroll
         for (int d = 0; d < DIM; ++d) pb[d] = othp[(int64_t)B * DIM + d];
+      }
+      float yc[DIM > 0 ? DIM : 1];  // RED ROW: y_{k m + b} of the common block
+      if constexpr (RED && ROW && DIM > 0) {
+        if (same_k) {
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) yc[d] = g.y[((int64_t)kk[0] * g.m + b) * DIM + d];
+        }
       }
       const float opot = RED ? (ROW ? gp[b] : f[b]) : (ROW ? gp[B] : f[B]);
 #pragma unroll
@@ -107,8 +132,19 @@ __global__ void __launch_bounds__(kPassThreads)
           // block-row 0 cost between point i (row) and point k m + j (column)
           const int i = ROW ? ai[q] : b;
           const int j = ROW ? b : ai[q];
-          if constexpr (DIM == 0) c = g.C[(int64_t)i * g.ldc + (int64_t)kk[q] * g.m + j];
-          else c = pt_cost_f<DIM>(g.x, i, g.y, kk[q] * g.m + j);
+          if constexpr (DIM == 0) {
+            c = g.C[(int64_t)i * g.ldc + (int64_t)kk[q] * g.m + j];
+          } else {
+            c = 0.0f;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+              float other;
+              if constexpr (ROW) other = same_k ? yc[d] : g.y[((int64_t)kk[q] * g.m + b) * DIM + d];
+              else other = g.x[(int64_t)b * DIM + d];
+              const float df = (ROW ? xc[q][d] : other) - (ROW ? other : xc[q][d]);
+              c = fmaf(df, df, c);
+            }
+          }
         } else {
           if constexpr (DIM == 0) {
             const int I = ROW ? ax[q] : B, J = ROW ? B : ax[q];
@@ -126,8 +162,8 @@ __global__ void __launch_bounds__(kPassThreads)
         const float T = exp2_fast((fg - c) * s2);
         tsum[q] += T;
         if constexpr (ROW) {
-          const float z = (fg - c) / eps;
-          vP[q] = fmaf(T, c + eps * (z - 1.0f), vP[q]);
+          // T (C + eps (Z - 1)) with Z = (f + g - C) / eps is T (f + g - eps)
+          vP[q] = fmaf(T, fg - eps, vP[q]);
           vC[q] = fmaf(T, c, vC[q]);
           if (out.dC && a0 + q < own_count) {
             if constexpr (RED) {
