@@ -25,8 +25,9 @@
 namespace csot {
 
 constexpr int kPassThreads = 256;
-constexpr int kPassRT = 4;  // own points per wave
-constexpr int kPassPts = kPassThreads / kWave * kPassRT;
+constexpr int kPassRT = 4;  // own points per workgroup, shared by its waves
+constexpr int kPassWaves = kPassThreads / kWave;
+constexpr int kPassPts = kPassRT;
 
 template <int DIM>
 __device__ __forceinline__ float pt_cost_f(const float* __restrict__ x, int I,
@@ -55,9 +56,11 @@ template <int DIM, bool RED, bool ROW>
 __global__ void __launch_bounds__(kPassThreads)
     pass_kernel(Geom g, const float* __restrict__ f, const float* __restrict__ gp, float s2,
                 float eps, int own_count, PassOut out) {
-  __shared__ double red[kPassThreads / kWave][3];
+  // the workgroup's waves share its four own points and split the other side among them
+  __shared__ double sh_d[kPassWaves][3][kPassRT];
+  __shared__ float sh_g[kPassWaves][kPassRT][DIM > 0 ? DIM : 1];
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-  const int a0 = (blockIdx.x * (kPassThreads / kWave) + wv) * kPassRT;
+  const int a0 = blockIdx.x * kPassRT;
   const float* ownp = ROW ? g.x : g.y;
   const float* othp = ROW ? g.y : g.x;
   float po[kPassRT][DIM > 0 ? DIM : 1];
@@ -110,7 +113,7 @@ __global__ void __launch_bounds__(kPassThreads)
     // the own points of a wave usually share one block: then one cost point serves all four
     const bool same_k = kk[0] == kk[kPassRT - 1] && kk[1] == kk[0] && kk[2] == kk[0];
 #pragma unroll 2
-    for (int b = lane; b < bl; b += kWave) {
+    for (int b = lane + wv * kWave; b < bl; b += kPassThreads) {
       const int B = cb * bl + b;  // other point (global index)
       float pb[DIM > 0 ? DIM : 1];
       if constexpr (DIM > 0) {
@@ -182,36 +185,46 @@ __global__ void __launch_bounds__(kPassThreads)
       }
     }
   }
-  double bp = 0.0, bc = 0.0, bm = 0.0;
+  // lanes, then the waves (fixed order) of each own point
 #pragma unroll
   for (int q = 0; q < kPassRT; ++q) {
-    const bool ok = a0 + q < own_count;
     const double ts = wave_sum_d((double)tsum[q]);
-    if (ROW) {
-      const double P = wave_sum_d((double)vP[q]);
-      const double C = wave_sum_d((double)vC[q]);
-      if (ok) { bp += P; bc += C; bm += ts; }
-    }
-    if (lane == 0 && ok) out.sums[a0 + q] = ts;
+    const double P = ROW ? wave_sum_d((double)vP[q]) : 0.0;
+    const double C = ROW ? wave_sum_d((double)vC[q]) : 0.0;
+    if (lane == 0) { sh_d[wv][0][q] = ts; sh_d[wv][1][q] = P; sh_d[wv][2][q] = C; }
     if constexpr (DIM > 0) {
       if (out.grad) {
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
           const float v = wave_sum(gacc[q][d]);
-          if (lane == 0 && ok) out.grad[(int64_t)(a0 + q) * DIM + d] = 2.0f * v;
+          if (lane == 0) sh_g[wv][q][d] = v;
         }
       }
     }
   }
-  if (ROW && out.part) {
-    if (lane == 0) { red[wv][0] = bp; red[wv][1] = bc; red[wv][2] = bm; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double P = 0, C = 0, M = 0;
-      for (int w = 0; w < kPassThreads / kWave; ++w) { P += red[w][0]; C += red[w][1]; M += red[w][2]; }
-      out.part[3 * blockIdx.x + 0] = P;
-      out.part[3 * blockIdx.x + 1] = C;
-      out.part[3 * blockIdx.x + 2] = M;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double bp = 0.0, bc = 0.0, bm = 0.0;
+    for (int q = 0; q < kPassRT; ++q) {
+      if (a0 + q >= own_count) break;
+      double ts = 0.0, P = 0.0, C = 0.0;
+      for (int w = 0; w < kPassWaves; ++w) { ts += sh_d[w][0][q]; P += sh_d[w][1][q]; C += sh_d[w][2][q]; }
+      out.sums[a0 + q] = ts;
+      bp += P; bc += C; bm += ts;
+      if constexpr (DIM > 0) {
+        if (out.grad) {
+          for (int d = 0; d < DIM; ++d) {
+            float v = 0.0f;
+            for (int w = 0; w < kPassWaves; ++w) v += sh_g[w][q][d];
+            out.grad[(int64_t)(a0 + q) * DIM + d] = 2.0f * v;
+          }
+        }
+      }
+    }
+    if (ROW && out.part) {
+      out.part[3 * blockIdx.x + 0] = bp;
+      out.part[3 * blockIdx.x + 1] = bc;
+      out.part[3 * blockIdx.x + 2] = bm;
     }
   }
 }
@@ -256,12 +269,16 @@ __global__ void __launch_bounds__(kPassThreads)
 
 // norms of (rowsum - ra), (colsum - rb) over N entries; `scale` (K for reduced sums) turns
 // them into full-space norms.
-__global__ void __launch_bounds__(256)
+// One workgroup of kFinThreads threads; loops keep four iterations' loads in flight.
+constexpr int kFinThreads = 1024;
+
+__global__ void __launch_bounds__(kFinThreads)
     check_finalize_kernel(int N, double scale, const double* __restrict__ rowsum,
                           const double* __restrict__ colsum, const float* __restrict__ ra,
                           const float* __restrict__ rb, double* __restrict__ dstats) {
-  __shared__ double red[8];
+  __shared__ double red[kFinThreads / kWave];
   double er = 0.0, ec = 0.0;
+#pragma unroll 4
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
     const double dr = rowsum[i] - (double)ra[i], dc = colsum[i] - (double)rb[i];
     er += dr * dr;
@@ -276,15 +293,16 @@ __global__ void __launch_bounds__(256)
 }
 
 // ---- finalize: scalars, marginal errors, da / db ----------------------------------------
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kFinThreads)
     finalize_kernel(Geom g, int red_mode, double scale, const float* __restrict__ f,
                     const float* __restrict__ gp, const double* __restrict__ part, int nparts,
                     const double* __restrict__ rowsum, const double* __restrict__ colsum,
                     double* __restrict__ out, float* __restrict__ da, float* __restrict__ db) {
-  __shared__ double red[8];
+  __shared__ double red[kFinThreads / kWave];
   const int N = red_mode ? g.m : g.n;
   const double K = red_mode ? (double)g.K : 1.0;
   double P = 0.0, CT = 0.0, mass = 0.0;
+#pragma unroll 4
   for (int b = threadIdx.x; b < nparts; b += blockDim.x) {
     P += part[3 * b];
     CT += part[3 * b + 1];
@@ -294,12 +312,14 @@ __global__ void __launch_bounds__(256)
   CT = block_sum_d(CT, red);
   mass = block_sum_d(mass, red);
   double fa = 0.0, gb = 0.0, er = 0.0, ec = 0.0, fs = 0.0, gs = 0.0;
+#pragma unroll 4
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
     double ai, bi;
     if (red_mode) {
       ai = 0.0;
       bi = 0.0;
-      for (int r = 0; r < g.K; ++r) {
+#pragma unroll 8
+      for (int r = 0; r < g.K; ++r) {  // eight blocks' loads in flight
         ai += (double)g.a[(int64_t)r * g.m + i];
         bi += (double)g.b[(int64_t)r * g.m + i];
       }
@@ -334,6 +354,7 @@ __global__ void __launch_bounds__(256)
     out[7] = 0.0;
   }
   const double fm = fs / N, gm = gs / N;
+#pragma unroll 4
   for (int I = threadIdx.x; I < g.n; I += blockDim.x) {
     const int i = red_mode ? I % g.m : I;
     if (da) da[I] = (float)((double)f[i] - fm);
@@ -394,7 +415,7 @@ hipError_t launch_cost_and_grad(const Geom& g, const float* f, const float* gp, 
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, s, g, reduced, scale, f, gp, part,
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kFinThreads), 0, s, g, reduced, scale, f, gp, part,
                      pass_blocks(rows), rowsum, colsum, out, da, db);
   return hipGetLastError();
 }
@@ -430,7 +451,7 @@ hipError_t launch_check(const Geom& g, int reduced, const float* logK, const flo
       default: return hipErrorInvalidValue;
     }
   }
-  hipLaunchKernelGGL(check_finalize_kernel, dim3(1), dim3(256), 0, s, N,
+  hipLaunchKernelGGL(check_finalize_kernel, dim3(1), dim3(kFinThreads), 0, s, N,
                      reduced ? (double)g.K : 1.0, rowsum, colsum, ra, rb, dstats);
   return hipGetLastError();
 }
