@@ -298,7 +298,6 @@ __global__ void __launch_bounds__(kFinThreads)
                     const float* __restrict__ gp, const double* __restrict__ part, int nparts,
                     const double* __restrict__ rowsum, const double* __restrict__ colsum,
                     double* __restrict__ out, float* __restrict__ da, float* __restrict__ db) {
-  __shared__ double red[kFinThreads / kWave];
   const int N = red_mode ? g.m : g.n;
   const double K = red_mode ? (double)g.K : 1.0;
   double P = 0.0, CT = 0.0, mass = 0.0;
@@ -308,9 +307,6 @@ __global__ void __launch_bounds__(kFinThreads)
     CT += part[3 * b + 1];
     mass += part[3 * b + 2];
   }
-  P = block_sum_d(P, red);
-  CT = block_sum_d(CT, red);
-  mass = block_sum_d(mass, red);
   double fa = 0.0, gb = 0.0, er = 0.0, ec = 0.0, fs = 0.0, gs = 0.0;
 #pragma unroll 4
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
@@ -337,12 +333,29 @@ __global__ void __launch_bounds__(kFinThreads)
     fs += f[i];
     gs += gp[i];
   }
-  fa = block_sum_d(fa, red);
-  gb = block_sum_d(gb, red);
-  er = block_sum_d(er, red);
-  ec = block_sum_d(ec, red);
-  fs = block_sum_d(fs, red);
-  gs = block_sum_d(gs, red);
+  // the nine block sums in one pass: interleaved lane shuffles, one LDS round
+  double v[9] = {P, CT, mass, fa, gb, er, ec, fs, gs};
+  {
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) v[k] += __shfl_xor(v[k], o, kWave);
+    }
+    __shared__ double sums9[kFinThreads / kWave][9];
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) sums9[wid][k] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      double t = 0.0;
+      for (int w = 0; w < kFinThreads / kWave; ++w) t += sums9[w][k];
+      v[k] = t;
+    }
+  }
+  P = v[0]; CT = v[1]; mass = v[2]; fa = v[3]; gb = v[4]; er = v[5]; ec = v[6]; fs = v[7];
+  gs = v[8];
   if (threadIdx.x == 0) {
     out[0] = scale * P;
     out[1] = K * (fa + gb) - g.eps * scale * mass;
