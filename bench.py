@@ -319,15 +319,32 @@ def main():
     def full_tol():
         csot.ot_sinkhorn_full(prob, o_tol, host_stats=False, out=(ff3, gf3), dstats=ds_g[1])
 
+    # forward + backward: the same solves followed by values and all gradients
+    vals_rg = torch.empty(8, dtype=torch.float64, device=dev)
+    vals_fg = torch.empty(8, dtype=torch.float64, device=dev)
+    grads_rg = {k: torch.empty_like(v) for k, v in grads_r.items()}
+    grads_fg = {k: torch.empty_like(v) for k, v in grads_r.items()}
+
+    def red_fb():
+        red_tol()
+        csot.ot_cost_and_grad(prob, fr3, gr3, True, want_dxy=True, want_dab=True, out=vals_rg,
+                              grads=grads_rg)
+
+    def full_fb():
+        full_tol()
+        csot.ot_cost_and_grad(prob, ff3, gf3, False, want_dxy=True, want_dab=True, out=vals_fg,
+                              grads=grads_fg)
+
     graphs = {}
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
-        red_tol()
-        full_tol()
+        red_fb()
+        full_fb()
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
-    for name, fn in (("red_graph", red_tol), ("full_graph", full_tol)):
+    for name, fn in (("red_graph", red_tol), ("full_graph", full_tol), ("red_fb_graph", red_fb),
+                     ("full_fb_graph", full_fb)):
         gr_ = torch.cuda.CUDAGraph()
         with torch.cuda.graph(gr_):
             fn()
@@ -336,7 +353,7 @@ def main():
 
     E = lambda: torch.cuda.Event(enable_timing=True)
     legs = ["fold", "red_solve", "expand", "red_grad", "red_fixed", "full_solve", "full_grad",
-            "full_fixed", "red_graph", "full_graph"]
+            "full_fixed", "red_graph", "full_graph", "red_fb_graph", "full_fb_graph"]
 
     def step(record):
         ev = {k: (E(), E()) for k in legs}
@@ -365,6 +382,8 @@ def main():
                                                         out=(ff2, gf2), dstats=ds[3]))
         run("red_graph", graphs["red_graph"].replay)
         run("full_graph", graphs["full_graph"].replay)
+        run("red_fb_graph", graphs["red_fb_graph"].replay)
+        run("full_fb_graph", graphs["full_fb_graph"].replay)
         return ev
 
     def kernel_ms():
@@ -439,6 +458,9 @@ def main():
                                  "replays_match_eager": bool(graph_ok)},
         "forward_backward_ms": {"reduced": round(ttt_red + ms["red_grad"], 4),
                                 "full": round(ttt_full + ms["full_grad"], 4)},
+        "forward_backward_graph_ms": {"reduced": round(ms["red_fb_graph"], 4),
+                                      "full": round(ms["full_fb_graph"], 4),
+                                      "speedup": round(ms["full_fb_graph"] / ms["red_fb_graph"], 2)},
         "iterations_to_tol": {"reduced": it_red, "full": it_full},
         "reduced_xcd_local_exchange": bool(st[1][7]),
         "marginal_err_fp64": {"reduced_row": st[0][2], "reduced_col": st[0][3],
