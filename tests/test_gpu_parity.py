@@ -93,6 +93,29 @@ def test_reduced_fixed_iterations(lib, name, mk):
         assert df < 2e-5 and dg < 2e-5, (df, dg)
 
 
+def test_reduced_more_workgroups_than_one_xcd(lib):
+    """m = 1000 needs 63 workgroups, more than one XCD holds: the solver is launched without
+    the one-XCD placement and publishes with agent-scope stores (dstats[7] = 0); fixed
+    iterations and the tolerance solve still match the oracle."""
+    p = workloads.symmetric_problem(2000, 2, 2, 0.05, seed=29)
+    print("[reduced many WGs] n2000 K2 m1000", flush=True)
+    prob = _problem(lib, p)
+    for its in (3, 12):
+        opts = lib.make_opts(tol=0.0, max_iter=its, fold_fp64=1)
+        logK, alpha, beta = lib.ot_fold_kernel(prob, opts)
+        f, g, ds = lib.ot_sinkhorn_reduced(prob, logK, alpha, beta, opts, host_stats=False)
+        dsh = ds.cpu().numpy()
+        ref = _reduced_ref(p, 0.0, its)
+        assert dsh[0] == its and dsh[7] == 0.0, dsh
+        assert np.abs(f.cpu().numpy() - ref["f"]).max() / p.eps < 2e-5
+        assert np.abs(g.cpu().numpy() - ref["g"]).max() / p.eps < 2e-5
+    opts = lib.make_opts(tol=1e-6, max_iter=20000, fold_fp64=1)
+    logK, alpha, beta = lib.ot_fold_kernel(prob, opts)
+    f, g, st = lib.ot_sinkhorn_reduced(prob, logK, alpha, beta, opts)
+    ref = _reduced_ref(p, 1e-6, 20000)
+    assert st["converged"] and abs(st["iters"] - ref["iters"]) <= 1
+
+
 def test_reduced_near_empty_rows_take_the_exact_path(lib):
     """Block position 5 carries a marginal of 1e-25 in every block: that row's plan sum, which
     is the shifted sum the row update starts from, stays near 1e-25 (below 2^-60), so the row
