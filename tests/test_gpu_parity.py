@@ -116,6 +116,18 @@ def test_reduced_more_workgroups_than_one_xcd(lib):
     assert st["converged"] and abs(st["iters"] - ref["iters"]) <= 1
 
 
+def test_reduced_too_large_is_unsupported(lib):
+    """m = 4096 slabs do not fit in LDS even with one workgroup per CU: the call returns
+    OT_ERR_UNSUPPORTED before any launch."""
+    p = workloads.symmetric_problem(8192, 2, 2, 0.05, seed=31)
+    prob = _problem(lib, p)
+    opts = lib.make_opts(tol=1e-6, fold_fp64=1)
+    logK, alpha, beta = lib.ot_fold_kernel(prob, opts)
+    with pytest.raises(lib.CsotError) as ei:
+        lib.ot_sinkhorn_reduced(prob, logK, alpha, beta, opts)
+    assert ei.value.code == 8  # OT_ERR_UNSUPPORTED
+
+
 def test_reduced_near_empty_rows_take_the_exact_path(lib):
     """Block position 5 carries a marginal of 1e-25 in every block: that row's plan sum, which
     is the shifted sum the row update starts from, stays near 1e-25 (below 2^-60), so the row
