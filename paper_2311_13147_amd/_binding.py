@@ -140,6 +140,7 @@ class Problem:
         self.device = a.device
         self._c = OtProblem(self.n, self.K, self.dim, _ptr(self.x), _ptr(self.y), _ptr(self.C),
                             self.ldc, _ptr(self.a), _ptr(self.b), self.eps)
+        self._ws_bytes = {}
 
     @property
     def m(self):
@@ -170,9 +171,18 @@ def make_opts(tol=1e-6, max_iter=10000, fold_fp64=-1, warm_start=0, validate=0, 
 _ws_cache = {}
 
 
-def workspace(prob: Problem, opts: Optional[OtOpts] = None) -> torch.Tensor:
-    nbytes = int(_lib.ot_workspace_bytes(prob.c(), ctypes.byref(opts) if opts else None))
-    key = (prob.device, torch.cuda.current_stream().cuda_stream)
+def workspace(prob: Problem, opts: Optional[OtOpts] = None,
+              stream: Optional[int] = None) -> torch.Tensor:
+    """The scratch buffer for calls on `stream` (default: the current stream), grown to what
+    `prob` with `opts` needs and kept for later calls on that stream."""
+    wg = opts.workgroups if opts else 0
+    nbytes = prob._ws_bytes.get(wg)
+    if nbytes is None:  # a problem's sizes never change: ask the library once per option set
+        nbytes = int(_lib.ot_workspace_bytes(prob.c(), ctypes.byref(opts) if opts else None))
+        prob._ws_bytes[wg] = nbytes
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    key = (prob.device, stream)
     ws = _ws_cache.get(key)
     if ws is None or ws.numel() < nbytes:
         ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=prob.device)
@@ -192,9 +202,10 @@ def ot_fold_kernel(prob: Problem, opts: Optional[OtOpts] = None, out=None):
                torch.empty(m, dtype=torch.float32, device=prob.device),
                torch.empty(m, dtype=torch.float32, device=prob.device))
     logK, alpha, beta = out
-    ws = workspace(prob, opts)
+    st = torch.cuda.current_stream().cuda_stream
+    ws = workspace(prob, opts, st)
     _check(_lib.ot_fold_kernel(prob.c(), ctypes.byref(opts) if opts else None, _ptr(logK),
-                               _ptr(alpha), _ptr(beta), _ptr(ws), ws.numel(), _stream()))
+                               _ptr(alpha), _ptr(beta), _ptr(ws), ws.numel(), ctypes.c_void_p(st)))
     return logK, alpha, beta
 
 
@@ -229,12 +240,13 @@ def ot_sinkhorn_reduced(prob: Problem, logK, alpha, beta, opts: Optional[OtOpts]
         opts.warm_start = 1
     if dstats is None:
         dstats = torch.zeros(OT_DSTATS_LEN, dtype=torch.float64, device=prob.device)
-    ws = workspace(prob, opts)
+    st = torch.cuda.current_stream().cuda_stream
+    ws = workspace(prob, opts, st)
     hs = OtStats() if host_stats else None
     _check(_lib.ot_sinkhorn_reduced(prob.c(), ctypes.byref(opts), _ptr(logK), _ptr(alpha),
                                     _ptr(beta), _ptr(f), _ptr(g), _ptr(dstats),
                                     ctypes.byref(hs) if hs is not None else None, _ptr(ws),
-                                    ws.numel(), _stream()), allow=(OT_ERR_NOCONV,))
+                                    ws.numel(), ctypes.c_void_p(st)), allow=(OT_ERR_NOCONV,))
     return f, g, (_stats_dict(hs) if hs is not None else dstats)
 
 
@@ -252,11 +264,12 @@ def ot_sinkhorn_full(prob: Problem, opts: Optional[OtOpts] = None, g0=None, host
         opts.warm_start = 1
     if dstats is None:
         dstats = torch.zeros(OT_DSTATS_LEN, dtype=torch.float64, device=prob.device)
-    ws = workspace(prob, opts)
+    st = torch.cuda.current_stream().cuda_stream
+    ws = workspace(prob, opts, st)
     hs = OtStats() if host_stats else None
     _check(_lib.ot_sinkhorn_full(prob.c(), ctypes.byref(opts), _ptr(f), _ptr(g), _ptr(dstats),
                                  ctypes.byref(hs) if hs is not None else None, _ptr(ws),
-                                 ws.numel(), _stream()), allow=(OT_ERR_NOCONV,))
+                                 ws.numel(), ctypes.c_void_p(st)), allow=(OT_ERR_NOCONV,))
     return f, g, (_stats_dict(hs) if hs is not None else dstats)
 
 
@@ -295,11 +308,12 @@ def ot_cost_and_grad(prob: Problem, f, g, reduced: bool, want_dC=False, want_dxy
     if want_dab:
         da = buf("da", (n,))
         db = buf("db", (n,))
-    ws = workspace(prob)
+    st = torch.cuda.current_stream().cuda_stream
+    ws = workspace(prob, None, st)
     lddc = n if (dC is not None and not reduced) else 0
     _check(_lib.ot_cost_and_grad(prob.c(), _ptr(f), _ptr(g), 1 if reduced else 0, _ptr(vals),
                                  _ptr(dC), lddc, _ptr(dx), _ptr(dy), _ptr(da), _ptr(db),
-                                 _ptr(ws), ws.numel(), _stream()))
+                                 _ptr(ws), ws.numel(), ctypes.c_void_p(st)))
     return {"values": vals, "dC": dC, "dx": dx, "dy": dy, "da": da, "db": db}
 
 
