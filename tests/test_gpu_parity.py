@@ -45,6 +45,10 @@ CASES = [
     ("sym_n600_K8_d3_ragged", lambda: workloads.symmetric_problem(600, 8, 3, 0.05, seed=7)),
     ("sym_n390_K6_d2_ragged", lambda: workloads.symmetric_problem(390, 6, 2, 0.01, seed=9)),
     ("appd_n700_K7_dense", lambda: workloads.dense_appd_problem(700, 7, seed=0)),
+    # the method's degenerate orders: K = 1 (the reduced problem is the full one) and m = 1
+    # (one point per block: logK is a scalar and one iteration reaches the fixed point)
+    ("sym_n300_K1_d2_order1", lambda: workloads.symmetric_problem(300, 1, 2, 0.05, seed=41)),
+    ("sym_n64_K64_d2_m1", lambda: workloads.symmetric_problem(64, 64, 2, 0.05, seed=43)),
 ]
 
 
