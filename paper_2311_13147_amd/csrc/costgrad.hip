@@ -49,6 +49,90 @@ struct PassOut {
   int64_t lddc;
 };
 
+// The inner loop of a pass when the workgroup's own points are all valid and, for reduced
+// potentials, lie in one block: the cost's block index is then uniform per partner block and
+// the flags (values and sums, plan entries, gradients) are compile-time, so the loop holds no
+// branches.  VALS: row / column sums (and, in the row pass, P and <C, T>) -- for reduced
+// potentials only block 0's points carry them (every block of the expanded plan holds the
+// same values, Lemma 1).  DC: store the plan entries.  GRAD: coordinate gradients.
+template <int DIM, bool RED, bool ROW, bool VALS, bool DC, bool GRAD>
+__device__ __forceinline__ void pass_fast(const Geom& g, const float* __restrict__ f,
+                                          const float* __restrict__ gp, float s2, float eps,
+                                          const PassOut& out, int a0, int wv, int lane,
+                                          const int (&ab)[kPassRT], const int (&ai)[kPassRT],
+                                          const float (&po)[kPassRT][DIM],
+                                          const float (&pot)[kPassRT],
+                                          const float (&xc)[kPassRT][DIM],
+                                          float (&tsum)[kPassRT], float (&gacc)[kPassRT][DIM],
+                                          float (&vP)[kPassRT], float (&vC)[kPassRT]) {
+  const int nblk = RED ? g.K : 1;
+  const int bl = RED ? g.m : g.n;
+  const float* othp = ROW ? g.y : g.x;
+  for (int cb = 0; cb < nblk; ++cb) {
+    int kk = 0;  // block of the cost: ROW (c - r) mod K with c = cb; COL (own c - r), r = cb
+    if constexpr (RED) {
+      kk = ROW ? cb - ab[0] : ab[0] - cb;
+      if (kk < 0) kk += g.K;
+    }
+    // reduced column pass: the own column's block-row 0 partner y_{k m + j} is fixed per block
+    float xq[kPassRT][DIM];
+#pragma unroll
+    for (int q = 0; q < kPassRT; ++q)
+#pragma unroll
+      for (int d = 0; d < DIM; ++d)
+        xq[q][d] = !RED ? 0.0f : ROW ? xc[q][d] : g.y[((int64_t)kk * g.m + ai[q]) * DIM + d];
+    // per partner b: the cost partner (reduced: block-row 0's point) and the actual partner
+    const float* costp = RED ? (ROW ? g.y + (int64_t)kk * g.m * DIM : g.x) : othp;
+    const float* gradp = othp + (int64_t)cb * bl * DIM;
+    float* dcrow[kPassRT];
+#pragma unroll
+    for (int q = 0; q < kPassRT; ++q)
+      dcrow[q] = !(DC && ROW) ? nullptr
+                 : RED ? out.dC + ((int64_t)kk * g.m + ai[q]) * g.m
+                       : out.dC + (int64_t)(a0 + q) * out.lddc;
+#pragma unroll 2
+    for (int b = lane + wv * kWave; b < bl; b += kPassThreads) {
+      float pb[DIM], cp[DIM];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) pb[d] = gradp[(int64_t)b * DIM + d];
+      if constexpr (RED) {
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) cp[d] = costp[(int64_t)b * DIM + d];
+      }
+      const float op = ROW ? gp[b] : f[b];  // reduced: index b of block 0; full: cb = 0
+#pragma unroll
+      for (int q = 0; q < kPassRT; ++q) {
+        float df[DIM];
+        float c = 0.0f;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+          df[d] = po[q][d] - pb[d];
+          if constexpr (RED) {
+            const float e = ROW ? xq[q][d] - cp[d] : cp[d] - xq[q][d];
+            c = fmaf(e, e, c);
+          } else {
+            c = fmaf(df[d], df[d], c);
+          }
+        }
+        const float fg = pot[q] + op;
+        const float T = exp2_fast((fg - c) * s2);
+        if constexpr (VALS) {
+          tsum[q] += T;
+          if constexpr (ROW) {
+            vP[q] = fmaf(T, fg - eps, vP[q]);  // T (C + eps (Z - 1)) = T (f + g - eps)
+            vC[q] = fmaf(T, c, vC[q]);
+          }
+        }
+        if constexpr (DC && ROW) dcrow[q][b] = T;
+        if constexpr (GRAD) {
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) gacc[q][d] = fmaf(T, df[d], gacc[q][d]);
+        }
+      }
+    }
+  }
+}
+
 // One pass in float32 (values / gradients).  ROW: own = rows I (x), other = columns J (y).
 // RED: potentials f, g have length m and the cost is block-row 0's.  `own_count` limits the
 // own points (m when only block 0 is needed, n otherwise).
@@ -96,7 +180,27 @@ __global__ void __launch_bounds__(kPassThreads)
 #pragma unroll
       for (int d = 0; d < DIM; ++d) xc[q][d] = g.x[(int64_t)ai[q] * DIM + d];
   }
-  for (int cb = 0; cb < nblk; ++cb) {
+  bool fast = false;
+  if constexpr (DIM > 0) {
+    if (a0 + kPassRT <= own_count && (!RED || ab[0] == ab[kPassRT - 1])) {
+      fast = true;
+      const bool vals = !RED || ab[0] == 0;
+      const bool dc = ROW && out.dC != nullptr && vals;
+      const bool gr = out.grad != nullptr;
+#define CSOT_PF(V, D, G)                                                                    \
+  pass_fast<DIM, RED, ROW, V, D, G>(g, f, gp, s2, eps, out, a0, wv, lane, ab, ai, po, pot, xc, \
+                                    tsum, gacc, vP, vC)
+      if (vals && dc) {
+        if (gr) CSOT_PF(true, true, true); else CSOT_PF(true, true, false);
+      } else if (vals) {
+        if (gr) CSOT_PF(true, false, true); else CSOT_PF(true, false, false);
+      } else {
+        if (gr) CSOT_PF(false, false, true); else CSOT_PF(false, false, false);
+      }
+#undef CSOT_PF
+    }
+  }
+  for (int cb = 0; cb < (fast ? 0 : nblk); ++cb) {
     int kk[kPassRT];
 #pragma unroll
     for (int q = 0; q < kPassRT; ++q) {
@@ -163,11 +267,17 @@ __global__ void __launch_bounds__(kPassThreads)
         }
         const float fg = pot[q] + opot;
         const float T = exp2_fast((fg - c) * s2);
-        tsum[q] += T;
+        // reduced potentials: every block-row (column) of the expanded plan holds the same
+        // values (Lemma 1), so sums and values come from block 0's points alone (x K)
+        if (!RED || ab[q] == 0) {
+          tsum[q] += T;
+          if constexpr (ROW) {
+            // T (C + eps (Z - 1)) with Z = (f + g - C) / eps is T (f + g - eps)
+            vP[q] = fmaf(T, fg - eps, vP[q]);
+            vC[q] = fmaf(T, c, vC[q]);
+          }
+        }
         if constexpr (ROW) {
-          // T (C + eps (Z - 1)) with Z = (f + g - C) / eps is T (f + g - eps)
-          vP[q] = fmaf(T, fg - eps, vP[q]);
-          vC[q] = fmaf(T, c, vC[q]);
           if (out.dC && a0 + q < own_count) {
             if constexpr (RED) {
               if (ab[q] == 0) out.dC[((int64_t)kk[q] * g.m + ai[q]) * g.m + b] = T;
@@ -409,13 +519,13 @@ hipError_t launch_cost_and_grad(const Geom& g, const float* f, const float* gp, 
   double* rowsum = reinterpret_cast<double*>(base);
   double* colsum = reinterpret_cast<double*>(base + align256(sizeof(double) * g.n));
   double* part = reinterpret_cast<double*>(base + 2 * align256(sizeof(double) * g.n));
-  // Reduced potentials: the values need block 0 only (K m^2 terms, scaled by K); the
-  // coordinate gradients need every point (n^2 terms, exact sums, scale 1).
+  // Reduced potentials: the values and marginal sums come from block 0's points only (K m^2
+  // terms, scaled by K); the coordinate gradients need every point (n^2 terms).
   const bool all_rows = !reduced || dx != nullptr;
   const bool all_cols = !reduced || dy != nullptr;
   const int rows = all_rows ? g.n : g.m;
   const int cols = all_cols ? g.n : g.m;
-  const double scale = (reduced && !all_rows) ? (double)g.K : 1.0;
+  const double scale = reduced ? (double)g.K : 1.0;
   PassOut ro{rowsum, part, dx, dC, lddc};
   PassOut co{colsum, nullptr, dy, nullptr, 0};
   const float s2 = (float)(kLog2eD / g.eps);
