@@ -149,7 +149,7 @@ int ot_symmetrize_cost(const ot_problem* prob, float* Csym, int64_t ldcs, void* 
  * One persistent launch (every workgroup resident at once, at most one per CU): workgroups
  * own row/column slabs of logK in LDS and exchange potentials through epoch-tagged slots in
  * device memory; no host round trip per iteration, and the launch can be captured in a graph.
- * The slabs of at most one workgroup per CU must fit in LDS: m up to ~2200 on a 256-CU device;
+ * The slabs of at most one workgroup per CU must fit in LDS: m up to 2048 on a 256-CU device;
  * larger m fails with OT_ERR_UNSUPPORTED (the batched call takes m up to 4096). */
 int ot_sinkhorn_reduced(const ot_problem* prob, const ot_opts* opts, const float* logK,
                         const float* alpha, const float* beta, float* f, float* g,

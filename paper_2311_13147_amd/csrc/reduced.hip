@@ -478,13 +478,16 @@ bool plan_reduced(int m, int hint, ReducedPlan* plan) {
   int R = (m + W - 1) / W;
   W = (m + R - 1) / R;  // no empty workgroups
   size_t lds = reduced_lds_bytes(R, mp, W);
-  while (lds > (size_t)kMaxLds && W < cus && W < m) {
-    ++W;
-    R = (m + W - 1) / W;
+  // slabs too large for LDS: fewer rows per workgroup, more workgroups.  R drops by at least
+  // one per step (W = ceil(m / (R - 1)) gives ceil(m / W) <= R - 1), so the loop ends.
+  while (lds > (size_t)kMaxLds && R > 1) {
+    --R;
     W = (m + R - 1) / R;
+    if (W > cus) break;
+    R = (m + W - 1) / W;  // no empty workgroups
     lds = reduced_lds_bytes(R, mp, W);
   }
-  if (lds > (size_t)kMaxLds) return false;
+  if (lds > (size_t)kMaxLds || W > cus) return false;
   static bool attr_set = false;
   if (!attr_set) {
     if (hipFuncSetAttribute((const void*)reduced_solver_kernel,

@@ -120,10 +120,12 @@ def test_reduced_more_workgroups_than_one_xcd(lib):
     assert st["converged"] and abs(st["iters"] - ref["iters"]) <= 1
 
 
-def test_reduced_too_large_is_unsupported(lib):
-    """m = 4096 slabs do not fit in LDS even with one workgroup per CU: the call returns
-    OT_ERR_UNSUPPORTED before any launch."""
-    p = workloads.symmetric_problem(8192, 2, 2, 0.05, seed=31)
+@pytest.mark.parametrize("n", [8192, 4400])
+def test_reduced_too_large_is_unsupported(lib, n):
+    """m = 4096 and m = 2200 slabs do not fit in LDS even with one workgroup per CU: the call
+    returns OT_ERR_UNSUPPORTED before any launch (the planner's search over rows per
+    workgroup ends)."""
+    p = workloads.symmetric_problem(n, 2, 2, 0.05, seed=31)
     prob = _problem(lib, p)
     opts = lib.make_opts(tol=1e-6, fold_fp64=1)
     logK, alpha, beta = lib.ot_fold_kernel(prob, opts)
