@@ -57,6 +57,9 @@ def _args():
                     help="only time the batched workload (1024 uneven cyclic problems) and exit")
     ap.add_argument("--two-stage", action="store_true",
                     help="only the approximate-symmetry workload: cold full vs two-stage")
+    ap.add_argument("--images", action="store_true",
+                    help="only the image workloads (64 x 64 pixels, mirror K=2 and quarter-turn "
+                         "K=4, pixel Euclidean distance, lambda 0.5): cyclic vs full")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (the reference kernel "
                          "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE) and exit")
@@ -211,6 +214,82 @@ def two_stage_only(steps, warmup):
           flush=True)
 
 
+def images_only(steps, warmup):
+    """Image workloads (Example 1; synthetic 64 x 64 grayscale images stand in for the paper's
+    real ones): pixel-wise Euclidean cost between pixel positions, lambda = 0.5, tol 1e-6, the
+    dense-cost path.  Exact symmetry (mirror K=2, quarter turn K=4): the cyclic solve (fold +
+    reduced solve) against the full-size solve on the dense n x n cost.  Approximate symmetry
+    (5 % pixel noise, mirror): the cyclic solve of the averaged problem, the two-stage method
+    and the full-size solve, with the objective gap and the marginal error of each against the
+    given marginals.  One line of JSON per workload; times from HIP events."""
+    import numpy as np
+    import torch
+
+    import paper_2311_13147_amd as csot
+    import workloads
+
+    T_ = lambda v: torch.from_numpy(np.ascontiguousarray(v)).to("cuda:0")
+    E = lambda: torch.cuda.Event(enable_timing=True)
+
+    def full_cost(p):
+        m, n, K = p.m, p.n, p.K
+        C = np.empty((n, n), dtype=np.float32)
+        for r in range(K):  # block (r, c) = C_{(c - r) mod K}
+            for c in range(K):
+                k = (c - r) % K
+                C[r * m:(r + 1) * m, c * m:(c + 1) * m] = p.C_row0[:, k * m:(k + 1) * m]
+        return C
+
+    for K, noise in ((2, 0.0), (4, 0.0), (2, 0.05)):
+        p = workloads.image_problem(64, K, "euclidean", noise=noise)
+        rprob = csot.Problem(T_(p.a), T_(p.b), p.eps, K, C=T_(p.C_row0))
+        fprob = csot.Problem(T_(p.a), T_(p.b), p.eps, K, C=T_(full_cost(p)))
+        opts = csot.make_opts(tol=1e-6, max_iter=20000)
+        t_red, t_full, t_two = [], [], []
+        for it in range(warmup + steps):
+            e = [E() for _ in range(4)]
+            e[0].record()
+            logK, al, be = csot.ot_fold_kernel(rprob, opts)
+            fr, gr, sr = csot.ot_sinkhorn_reduced(rprob, logK, al, be, opts, host_stats=False)
+            e[1].record()
+            ff, gf, sf = csot.ot_sinkhorn_full(fprob, opts, host_stats=False)
+            e[2].record()
+            if noise > 0.0:
+                two = csot.two_stage_sinkhorn(fprob, tol=1e-6)
+            e[3].record()
+            torch.cuda.synchronize()
+            if it >= warmup:
+                t_red.append(e[0].elapsed_time(e[1]))
+                t_full.append(e[1].elapsed_time(e[2]))
+                t_two.append(e[2].elapsed_time(e[3]))
+        sr, sf = sr.cpu().tolist(), sf.cpu().tolist()
+        vf = csot.values_dict(csot.ot_cost_and_grad(fprob, ff, gf, reduced=False)["values"])
+        # the cyclic solution tiled to full size, measured against the given marginals
+        vr = csot.values_dict(csot.ot_cost_and_grad(fprob, fr.repeat(K), gr.repeat(K),
+                                                    reduced=False)["values"])
+        gap = lambda v: abs(v["P"] - vf["P"]) / max(abs(vf["P"]), vf["CT"])
+        rec = {"workload": f"images 64x64, {'mirror' if K == 2 else 'quarter turn'} K={K}, "
+                           f"pixel Euclidean cost, lambda=0.5, tol=1e-6"
+                           + (f", pixel noise {noise:g} (approximate symmetry)" if noise else ""),
+               "n": p.n, "m": p.m,
+               "cyclic_ms": round(sum(t_red) / steps, 3),
+               "full_ms": round(sum(t_full) / steps, 3),
+               "speedup": round(sum(t_full) / sum(t_red), 2),
+               "iterations": {"cyclic": int(sr[0]), "full": int(sf[0])},
+               "err_row_fp64": {"full": sf[2]},
+               "cyclic_objective_rel_gap": gap(vr),
+               "cyclic_err_vs_given_marginals": {"row": vr["err_row"], "col": vr["err_col"]}}
+        if noise > 0.0:
+            v2 = csot.values_dict(csot.ot_cost_and_grad(fprob, two["f"], two["g"],
+                                                        reduced=False)["values"])
+            rec.update(two_stage_ms=round(sum(t_two) / steps, 3),
+                       two_stage_iterations={"stage1": two["stage1"]["iters"],
+                                             "stage2": two["stage2"]["iters"]},
+                       two_stage_objective_rel_gap=gap(v2),
+                       two_stage_err_row_fp64=two["stage2"]["err_row"])
+        print(json.dumps(rec), flush=True)
+
+
 def copy_calibration():
     import torch
     src = torch.ones(64 * 1024 * 1024, device="cuda:0")
@@ -261,6 +340,9 @@ def main():
         return
     if args.two_stage:
         two_stage_only(args.steps, args.warmup)
+        return
+    if args.images:
+        images_only(args.steps, args.warmup)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "

@@ -43,6 +43,9 @@ __all__ = [
     "dense_appd_problem",
     "batched_problems",
     "BatchItem",
+    "image_pixel_order",
+    "synthetic_image",
+    "image_problem",
 ]
 
 
@@ -196,3 +199,111 @@ def batched_problems(count: int = 1024, m_lo: int = 32, m_hi: int = 1024,
     ks = rng.choice(np.asarray(Ks), size=count)
     dims = rng.choice(np.asarray([2, 3]), size=count)
     return [BatchItem(int(ms[p]), int(ks[p]), int(dims[p]), seed + 10 * p) for p in range(count)]
+
+
+# ---- images with mirror or 90-degree rotational symmetry (Example 1 of the paper) ----------
+#
+# Readings (listed in the design notes): the paper orders the pixels of an h x w image with
+# mirror symmetry about the vertical axis column by column over the left half, then the
+# mirrored columns in the same order (its eq. vectorization_mirror); for 90-degree rotational
+# symmetry it only says "appropriately ordering", read here as the top-left quadrant column by
+# column, then its images under one, two and three quarter turns about the image centre.  The
+# cost is a distance between pixel positions (row, column) in pixel units -- the paper names
+# Manhattan, Euclidean and Chebyshev; its real-data experiment uses Euclidean and lambda = 0.5.
+# The paper's images (a public symmetry database, resized to 64 x 64 and 96 x 96, normalised to
+# unit mass) are not available; seeded synthetic grayscale images stand in for them.
+
+
+def image_pixel_order(h: int, w: int, K: int) -> np.ndarray:
+    """Pixel (row, col) of every position I = r*m + i, int64 ``[h*w, 2]``: K = 2 is the mirror
+    order (block 1 = block 0 mirrored about the vertical axis), K = 4 the quarter-turn order
+    (block r = block 0 turned r quarter turns; needs h == w)."""
+    if K == 2:
+        if w % 2:
+            raise ValueError("mirror symmetry needs an even width")
+        k = np.arange(h * w)
+        half = h * w // 2
+        col = np.where(k < half, k // h, (3 * w) // 2 - k // h - 1)
+        return np.stack([k % h, col], axis=1).astype(np.int64)
+    if K == 4:
+        if h != w or h % 2:
+            raise ValueError("quarter-turn symmetry needs an even square image")
+        q = h // 2
+        k = np.arange(q * q)
+        base = np.stack([k % q, k // q], axis=1)  # top-left quadrant, column by column
+        blocks = [base]
+        for _ in range(3):
+            i, j = blocks[-1][:, 0], blocks[-1][:, 1]
+            blocks.append(np.stack([j, h - 1 - i], axis=1))  # a quarter turn about the centre
+        return np.concatenate(blocks, axis=0).astype(np.int64)
+    raise ValueError("image symmetry: K must be 2 (mirror) or 4 (quarter turn)")
+
+
+def synthetic_image(h: int, w: int, rng: np.random.Generator, blobs: int = 6) -> np.ndarray:
+    """A smooth nonnegative grayscale image: a faint background plus Gaussian blobs of random
+    position, width and brightness (float64 ``[h, w]``)."""
+    ii, jj = np.meshgrid(np.arange(h), np.arange(w), indexing="ij")
+    img = np.full((h, w), 0.05)
+    for _ in range(blobs):
+        ci, cj = rng.uniform(0, h), rng.uniform(0, w)
+        sd = rng.uniform(0.05, 0.2) * min(h, w)
+        img += rng.uniform(0.3, 1.0) * np.exp(-((ii - ci) ** 2 + (jj - cj) ** 2) / (2 * sd * sd))
+    return img
+
+
+def _symmetrise_image(img: np.ndarray, K: int) -> np.ndarray:
+    if K == 2:
+        return 0.5 * (img + img[:, ::-1])
+    return 0.25 * sum(np.rot90(img, r) for r in range(4))
+
+
+def image_problem(side: int, K: int, metric: str = "euclidean", noise: float = 0.0,
+                  lam: float = 0.5, seed: int = 600, name: str = "") -> Problem:
+    """Transport between two side x side grayscale images with mirror (K = 2) or quarter-turn
+    (K = 4) symmetry, pixels in the block order of ``image_pixel_order``.  Both images are
+    exactly symmetric when ``noise = 0``; otherwise every pixel is multiplied by
+    ``exp(noise * xi)``, xi ~ N(0, 1), so the symmetry holds only approximately.  Images are
+    normalised to unit mass.
+
+    ``metric`` "euclidean", "manhattan" or "chebyshev" gives a dense-cost problem (block-row 0
+    ``C_row0[i, k*m + j]`` = the distance between pixels i and k*m + j, in pixel units);
+    "sqeuclidean" gives a point problem (x = y = the pixel positions, float32), whose cost is
+    the squared distance.  The cost is exactly block-circulant in every case: the mirror and
+    the quarter turns permute pixel positions and preserve all four distances.  Sub-seeds: image
+    a = seed, image b = seed + 1, noise = seed + 2."""
+    pix = image_pixel_order(side, side, K)
+    n = side * side
+    m = n // K
+    imgs = []
+    for t in range(2):
+        img = _symmetrise_image(synthetic_image(side, side, np.random.default_rng(seed + t)), K)
+        imgs.append(img)
+    if noise > 0.0:
+        rng = np.random.default_rng(seed + 2)
+        imgs = [img * np.exp(noise * rng.standard_normal(img.shape)) for img in imgs]
+        a = imgs[0][pix[:, 0], pix[:, 1]]
+        b = imgs[1][pix[:, 0], pix[:, 1]]
+        a, b = equal_mass_pair(a / a.sum(), b / b.sum())
+    else:
+        # exactly periodic: block 0's pixels, equal-mass on a common grid, tiled K times
+        a0 = imgs[0][pix[:m, 0], pix[:m, 1]]
+        b0 = imgs[1][pix[:m, 0], pix[:m, 1]]
+        a0, b0 = equal_mass_pair(a0 / (K * a0.sum()), b0 / (K * b0.sum()))
+        a, b = np.tile(a0, K), np.tile(b0, K)
+    pos = pix.astype(np.float64)
+    tag = f"img{side}_K{K}_{metric}" + (f"_noise{noise:g}" if noise > 0.0 else "")
+    if metric == "sqeuclidean":
+        xy = pos.astype(np.float32)
+        return Problem(n=n, K=K, dim=2, x=xy, y=xy.copy(), a=a, b=b, eps=lam, seed=seed,
+                       name=name or tag)
+    d = np.abs(pos[:m, None, :] - pos[None, :, :])  # [m, n, 2] coordinate differences
+    if metric == "euclidean":
+        C = np.sqrt((d ** 2).sum(-1))
+    elif metric == "manhattan":
+        C = d.sum(-1)
+    elif metric == "chebyshev":
+        C = d.max(-1)
+    else:
+        raise ValueError(f"unknown metric {metric!r}")
+    return Problem(n=n, K=K, dim=0, x=None, y=None, a=a, b=b, eps=lam,
+                   C_row0=C.astype(np.float32), seed=seed, name=name or tag)
