@@ -58,7 +58,7 @@ def _args():
     ap.add_argument("--two-stage", action="store_true",
                     help="only the approximate-symmetry workload: cold full vs two-stage")
     ap.add_argument("--images", action="store_true",
-                    help="only the image workloads (64 x 64 pixels, mirror K=2 and quarter-turn "
+                    help="only the image workloads (64 x 64 and 96 x 96 pixels, mirror K=2 and quarter-turn "
                          "K=4, pixel Euclidean distance, lambda 0.5): cyclic vs full")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (the reference kernel "
@@ -215,8 +215,8 @@ def two_stage_only(steps, warmup):
 
 
 def images_only(steps, warmup):
-    """Image workloads (Example 1; synthetic 64 x 64 grayscale images stand in for the paper's
-    real ones): pixel-wise Euclidean cost between pixel positions, lambda = 0.5, tol 1e-6, the
+    """Image workloads (Example 1; synthetic 64 x 64 and 96 x 96 grayscale images stand in for
+    the paper's real ones): pixel-wise Euclidean cost between pixel positions, lambda = 0.5, tol 1e-6, the
     dense-cost path.  Exact symmetry (mirror K=2, quarter turn K=4): the cyclic solve (fold +
     reduced solve) against the full-size solve on the dense n x n cost.  Approximate symmetry
     (5 % pixel noise, mirror): the cyclic solve of the averaged problem, the two-stage method
@@ -240,8 +240,9 @@ def images_only(steps, warmup):
                 C[r * m:(r + 1) * m, c * m:(c + 1) * m] = p.C_row0[:, k * m:(k + 1) * m]
         return C
 
-    for K, noise in ((2, 0.0), (4, 0.0), (2, 0.05)):
-        p = workloads.image_problem(64, K, "euclidean", noise=noise)
+    for side, K, noise in ((64, 2, 0.0), (64, 4, 0.0), (64, 2, 0.05), (96, 2, 0.0), (96, 4, 0.0),
+                           (96, 2, 0.05)):
+        p = workloads.image_problem(side, K, "euclidean", noise=noise)
         rprob = csot.Problem(T_(p.a), T_(p.b), p.eps, K, C=T_(p.C_row0))
         fprob = csot.Problem(T_(p.a), T_(p.b), p.eps, K, C=T_(full_cost(p)))
         opts = csot.make_opts(tol=1e-6, max_iter=20000)
@@ -268,7 +269,7 @@ def images_only(steps, warmup):
         vr = csot.values_dict(csot.ot_cost_and_grad(fprob, fr.repeat(K), gr.repeat(K),
                                                     reduced=False)["values"])
         gap = lambda v: abs(v["P"] - vf["P"]) / max(abs(vf["P"]), vf["CT"])
-        rec = {"workload": f"images 64x64, {'mirror' if K == 2 else 'quarter turn'} K={K}, "
+        rec = {"workload": f"images {side}x{side}, {'mirror' if K == 2 else 'quarter turn'} K={K}, "
                            f"pixel Euclidean cost, lambda=0.5, tol=1e-6"
                            + (f", pixel noise {noise:g} (approximate symmetry)" if noise else ""),
                "n": p.n, "m": p.m,

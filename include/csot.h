@@ -149,8 +149,10 @@ int ot_symmetrize_cost(const ot_problem* prob, float* Csym, int64_t ldcs, void* 
  * One persistent launch (every workgroup resident at once, at most one per CU): workgroups
  * own row/column slabs of logK in LDS and exchange potentials through epoch-tagged slots in
  * device memory; no host round trip per iteration, and the launch can be captured in a graph.
- * The slabs of at most one workgroup per CU must fit in LDS: m up to 2048 on a 256-CU device;
- * larger m fails with OT_ERR_UNSUPPORTED (the batched call takes m up to 4096). */
+ * Up to m = 2048 on a 256-CU device the slabs of one workgroup per CU are held in LDS; above,
+ * padded copies of logK and its transpose are written to the workspace and read every
+ * half-step (ot_workspace_bytes includes them for m > 1024).  Beyond m ~ 18900 even the staged
+ * potentials exceed LDS and the call fails with OT_ERR_UNSUPPORTED. */
 int ot_sinkhorn_reduced(const ot_problem* prob, const ot_opts* opts, const float* logK,
                         const float* alpha, const float* beta, float* f, float* g,
                         double* dstats, ot_stats* hstats, void* ws, size_t ws_bytes,

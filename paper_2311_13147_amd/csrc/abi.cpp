@@ -212,6 +212,9 @@ size_t ot_workspace_bytes(const ot_problem* prob, const ot_opts* opts) {
     rp.stride = 1;
     rp.threads = 256;
     rp.lds = 0;
+    // padded logK copies of the large-m mode: needed above m = 2048 on 256 CUs; sized in from
+    // m = 1024 so that devices down to 64 CUs are covered
+    rp.gslab = g.m > 1024 ? 1 : 0;
     need = std::max(need, csot::reduced_ws_bytes(g.m, rp));
   }
   {

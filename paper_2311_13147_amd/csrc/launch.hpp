@@ -35,6 +35,7 @@ struct ReducedPlan {
   int R;        // rows (and columns) per workgroup
   int threads;  // threads per workgroup
   size_t lds;   // dynamic LDS bytes
+  int gslab = 0;  // 1: logK slabs read from padded copies in the workspace (large m)
 };
 bool plan_reduced(int m, int workgroups_hint, ReducedPlan* plan);
 size_t reduced_ws_bytes(int m, const ReducedPlan& p);

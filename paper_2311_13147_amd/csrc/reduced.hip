@@ -54,6 +54,8 @@ struct RedParams {
   uint64_t* ffin;  // [mp] returned f (natural units) for the float64 check (epoch 1)
   uint64_t* gfin;  // [mp] returned g
   uint64_t* chk;   // [4][W] float64 check partials of every workgroup (two 32-bit halves each)
+  const float* Lg;   // [m][mp] padded logK rows in device memory, or NULL: slabs held in LDS
+  const float* LTg;  // [m][mp] padded logK columns (transposed), with Lg
   uint32_t* ctl;   // [0] abort flag
   double* dstats;
 };
@@ -131,13 +133,20 @@ __device__ __forceinline__ float wave_update(const float* __restrict__ row,
   return Fn;
 }
 
+// GSLAB: the slabs are read from the padded copies in device memory (large m); otherwise they
+// are loaded into LDS once.  A template parameter, so that either way the compiler knows the
+// slabs' address space (LDS reads stay ds_read, not flat loads).
+template <bool GSLAB>
 __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p) {
   extern __shared__ float4 lds4[];
   float* lds = reinterpret_cast<float*>(lds4);
   const int R = p.R, mp = p.mp, m = p.m;
-  float* Ls = lds;                      // [R][mp] row slab
-  float* LTs = Ls + (size_t)R * mp;     // [R][mp] column slab (transposed)
-  float* VsG = LTs + (size_t)R * mp;    // [mp] staged G (read by row updates)
+  // slabs in LDS, or (large m) read from the padded copies in device memory every half-step
+  constexpr bool gslab = GSLAB;
+  const size_t slab = gslab ? 0 : (size_t)R * mp;
+  float* Ls_l = lds;                    // [R][mp] row slab
+  float* LTs_l = Ls_l + slab;           // [R][mp] column slab (transposed)
+  float* VsG = LTs_l + slab;            // [mp] staged G (read by row updates)
   float* VsF = VsG + mp;                // [mp] staged F (read by column updates)
   float* la2 = VsF + mp;                // [R] log2 alpha (my rows)
   float* lb2 = la2 + R;                 // [R] log2 beta (my columns)
@@ -155,6 +164,8 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
   if (blockIdx.x % p.stride) return;  // placeholder block: frees its CU at once
   const int w = blockIdx.x / p.stride;
   const int r0 = w * R;
+  const float* Ls = GSLAB ? p.Lg + (size_t)r0 * mp : Ls_l;
+  const float* LTs = GSLAB ? p.LTg + (size_t)r0 * mp : LTs_l;
   const int nr = max(0, min(R, m - r0));  // rows (= columns) this workgroup owns
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
@@ -169,7 +180,9 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
   // the padding.  With m and R multiples of 4 both read float4 (four consecutive columns);
   // 8 loads in flight per thread before the first store (one memory round trip per 8).
   constexpr int kLd = 8;
-  if ((m & 3) == 0 && (R & 3) == 0 && (reinterpret_cast<uintptr_t>(p.logK) & 15) == 0) {
+  if constexpr (GSLAB) {
+    // nothing to load: the padded copies are read in place
+  } else if ((m & 3) == 0 && (R & 3) == 0 && (reinterpret_cast<uintptr_t>(p.logK) & 15) == 0) {
     const float4 ninf = make_float4(-INFINITY, -INFINITY, -INFINITY, -INFINITY);
     const int q4 = mp / 4, r4 = R / 4;
     const int nrow = R * q4, ncol = mp * r4;  // quads of the row slab, of the column slab
@@ -197,14 +210,14 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
       for (int u = 0; u < kLd; ++u) {
         const int e = e0 + u * blockDim.x;
         if (e < nrow) {
-          *reinterpret_cast<float4*>(Ls + 4 * (size_t)e) = v[u];  // natural log
+          *reinterpret_cast<float4*>(Ls_l + 4 * (size_t)e) = v[u];  // natural log
         } else if (e < nrow + ncol) {
           const int ec = e - nrow;
           const int i = ec / r4, cl = 4 * (ec - i * r4);
-          LTs[(size_t)cl * mp + i] = v[u].x;
-          LTs[(size_t)(cl + 1) * mp + i] = v[u].y;
-          LTs[(size_t)(cl + 2) * mp + i] = v[u].z;
-          LTs[(size_t)(cl + 3) * mp + i] = v[u].w;
+          LTs_l[(size_t)cl * mp + i] = v[u].x;
+          LTs_l[(size_t)(cl + 1) * mp + i] = v[u].y;
+          LTs_l[(size_t)(cl + 2) * mp + i] = v[u].z;
+          LTs_l[(size_t)(cl + 3) * mp + i] = v[u].w;
         }
       }
     }
@@ -223,9 +236,9 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
       for (int u = 0; u < kLd; ++u) {
         const int e = e0 + u * blockDim.x;
         if (e < R * mp) {
-          Ls[e] = v[u];  // natural log
+          Ls_l[e] = v[u];  // natural log
           const int i = e / R, cl = e - i * R;
-          LTs[(size_t)cl * mp + i] = vt[u];
+          LTs_l[(size_t)cl * mp + i] = vt[u];
         }
       }
     }
@@ -456,8 +469,31 @@ static int device_cu_count() {
   return cus;
 }
 
-static size_t reduced_lds_bytes(int R, int mp, int W) {
-  return sizeof(float) * ((size_t)2 * R * mp + 2 * (size_t)mp + 9 * (size_t)R + W) + 16;
+static size_t reduced_lds_bytes(int R, int mp, int W, bool gslab = false) {
+  return sizeof(float) * ((gslab ? 0 : (size_t)2 * R * mp) + 2 * (size_t)mp + 9 * (size_t)R + W) +
+         16;
+}
+
+// Padded copies of logK for the large-m mode: Lg[i][j] = logK[i][j], LTg[j][i] = logK[i][j],
+// rows of mp floats with -inf beyond m.  32 x 32 tiles through LDS; the grid covers mp x mp so
+// that the padding of both copies is written too.
+__global__ void __launch_bounds__(256)
+    pad_slabs_kernel(const float* __restrict__ logK, int m, int mp, float* __restrict__ Lg,
+                     float* __restrict__ LTg) {
+  __shared__ float tile[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;  // columns j, rows i of logK
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int k = ty; k < 32; k += 8) {
+    const int i = by + k, j = bx + tx;
+    const float v = (i < m && j < m) ? logK[(int64_t)i * m + j] : -INFINITY;
+    if (i < m) Lg[(int64_t)i * mp + j] = v;
+    tile[k][tx] = v;
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int j = bx + k, i = by + tx;  // LTg[j][i] = logK[i][j]
+    if (j < m) LTg[(int64_t)j * mp + i] = tile[tx][k];
+  }
 }
 
 static int reduced_mp(int m) { return (m + kSweep - 1) / kSweep * kSweep; }
@@ -487,10 +523,24 @@ bool plan_reduced(int m, int hint, ReducedPlan* plan) {
     R = (m + W - 1) / W;  // no empty workgroups
     lds = reduced_lds_bytes(R, mp, W);
   }
-  if (lds > (size_t)kMaxLds || W > cus) return false;
+  bool gslab = false;
+  if (lds > (size_t)kMaxLds || W > cus) {
+    // large m: the slabs stay in device memory (padded copies, read every half-step from the
+    // L2 / last-level cache) and LDS holds only the staged potentials
+    gslab = true;
+    W = hint > 0 ? hint : (m + kRedWaves - 1) / kRedWaves;
+    if (W > cus) W = cus;
+    if (W > m) W = m;
+    R = (m + W - 1) / W;
+    W = (m + R - 1) / R;
+    lds = reduced_lds_bytes(R, mp, W, true);
+    if (lds > (size_t)kMaxLds) return false;
+  }
   static bool attr_set = false;
   if (!attr_set) {
-    if (hipFuncSetAttribute((const void*)reduced_solver_kernel,
+    if (hipFuncSetAttribute((const void*)reduced_solver_kernel<false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds) != hipSuccess ||
+        hipFuncSetAttribute((const void*)reduced_solver_kernel<true>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds) != hipSuccess)
       return false;
     attr_set = true;
@@ -498,12 +548,14 @@ bool plan_reduced(int m, int hint, ReducedPlan* plan) {
   // co-residency: the persistent launch needs all W workgroups resident at once
   int per_cu = 0;
   const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      &per_cu, reduced_solver_kernel, kRedThreads, lds);
+      &per_cu, gslab ? reduced_solver_kernel<true> : reduced_solver_kernel<false>, kRedThreads,
+      lds);
   // keep every workgroup on one XCD (blocks are dealt to the 8 XCDs round-robin) when the
   // placeholder blocks still fit in one co-resident grid: polls then stay within one L2
   const int stride = (8 * W <= cus && cus % 8 == 0) ? 8 : 1;
   if (e != hipSuccess || per_cu * cus < W * stride) return false;
   plan->stride = stride;
+  plan->gslab = gslab ? 1 : 0;
   plan->W = W;
   plan->R = R;
   plan->threads = kRedThreads;
@@ -521,7 +573,10 @@ static size_t slots_bytes(int m, int W) {
          align256(sizeof(uint64_t) * 4 * W);
 }
 
-size_t reduced_ws_bytes(int m, const ReducedPlan& p) { return slots_bytes(m, p.W); }
+size_t reduced_ws_bytes(int m, const ReducedPlan& p) {
+  const size_t slabs = p.gslab ? 2 * align256(sizeof(float) * (size_t)m * reduced_mp(m)) : 0;
+  return slots_bytes(m, p.W) + slabs;
+}
 
 hipError_t launch_sinkhorn_reduced(int m, int K, double eps, const float* logK,
                                    const float* alpha, const float* beta, float* f, float* g,
@@ -539,10 +594,22 @@ hipError_t launch_sinkhorn_reduced(int m, int K, double eps, const float* logK,
   uint64_t* ffin = reinterpret_cast<uint64_t*>(base + off); off += align256(sizeof(uint64_t) * mp);
   uint64_t* gfin = reinterpret_cast<uint64_t*>(base + off); off += align256(sizeof(uint64_t) * mp);
   uint64_t* chk = reinterpret_cast<uint64_t*>(base + off); off += align256(sizeof(uint64_t) * 4 * pl.W);
+  const size_t slots_end = off;
+  float* Lg = nullptr;
+  float* LTg = nullptr;
+  if (pl.gslab) {
+    Lg = reinterpret_cast<float*>(base + off); off += align256(sizeof(float) * (size_t)m * mp);
+    LTg = reinterpret_cast<float*>(base + off); off += align256(sizeof(float) * (size_t)m * mp);
+  }
 
   // epochs start at 1, so zeroed slots are never mistaken for current ones
-  hipError_t e = launch_zero_words(ctl, (int)(slots_bytes(m, pl.W) / 4), s);
+  hipError_t e = launch_zero_words(ctl, (int)(slots_end / 4), s);
   if (e != hipSuccess) return e;
+  if (pl.gslab) {
+    hipLaunchKernelGGL(pad_slabs_kernel, dim3(mp / 32, mp / 32), dim3(256), 0, s, logK, m, mp,
+                       Lg, LTg);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
 
   RedParams p;
   p.m = m; p.mp = mp; p.K = K; p.W = pl.W; p.R = pl.R; p.max_iter = max_iter; p.warm = warm;
@@ -552,6 +619,7 @@ hipError_t launch_sinkhorn_reduced(int m, int K, double eps, const float* logK,
   p.tol2 = tol * tol / (double)K;
   p.logK = logK; p.alpha = alpha; p.beta = beta; p.f_out = f; p.g_out = g;
   p.fx = fx; p.gx = gx; p.rsx = rsx; p.xid = xid; p.ffin = ffin; p.gfin = gfin; p.chk = chk; p.ctl = ctl;
+  p.Lg = Lg; p.LTg = LTg;
   p.dstats = dstats;
   p.eps = eps;
   void* args[] = {&p};
@@ -560,7 +628,8 @@ hipError_t launch_sinkhorn_reduced(int m, int K, double eps, const float* logK,
   // so on a device with no concurrent kernels every block is resident at once (the cooperative
   // launch API guarantees the same but adds ~10 us of dispatch overhead on each side).  Should a
   // block not be resident, the others' bounded waits end in the abort flag, not in a hang.
-  hipLaunchKernelGGL(reduced_solver_kernel, dim3(pl.W * pl.stride), dim3(pl.threads),
+  auto kern = pl.gslab ? reduced_solver_kernel<true> : reduced_solver_kernel<false>;
+  hipLaunchKernelGGL(kern, dim3(pl.W * pl.stride), dim3(pl.threads),
                      (unsigned)pl.lds, s, p);
   e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -120,18 +120,52 @@ def test_reduced_more_workgroups_than_one_xcd(lib):
     assert st["converged"] and abs(st["iters"] - ref["iters"]) <= 1
 
 
-@pytest.mark.parametrize("n", [8192, 4400])
-def test_reduced_too_large_is_unsupported(lib, n):
-    """m = 4096 and m = 2200 slabs do not fit in LDS even with one workgroup per CU: the call
-    returns OT_ERR_UNSUPPORTED before any launch (the planner's search over rows per
-    workgroup ends)."""
-    p = workloads.symmetric_problem(n, 2, 2, 0.05, seed=31)
-    prob = _problem(lib, p)
-    opts = lib.make_opts(tol=1e-6, fold_fp64=1)
-    logK, alpha, beta = lib.ot_fold_kernel(prob, opts)
+def test_reduced_too_large_is_unsupported(lib):
+    """m = 19968: even with the slabs left in device memory, the staged potentials of one
+    workgroup per CU exceed LDS; the call returns OT_ERR_UNSUPPORTED before any launch (the
+    planner's searches end).  Inputs are placeholders: nothing is read."""
+    m, K = 19968, 2
+    n = m * K
+    rng = np.random.default_rng(3)
+    xy = T_(rng.uniform(-1, 1, size=(n, 2)).astype(np.float32))
+    a = T_(np.full(n, 1.0 / n, dtype=np.float32))
+    prob = lib.Problem(a, a, 0.05, K, x=xy, y=xy)
+    logK = torch.empty((m, m), dtype=torch.float32, device=DEV)
+    alpha = torch.full((m,), 1.0 / n, dtype=torch.float32, device=DEV)
     with pytest.raises(lib.CsotError) as ei:
-        lib.ot_sinkhorn_reduced(prob, logK, alpha, beta, opts)
+        lib.ot_sinkhorn_reduced(prob, logK, alpha, alpha, lib.make_opts(tol=1e-6))
     assert ei.value.code == 8  # OT_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("n,its", [(4608, (1, 5)), (8192, (2,))])
+def test_reduced_large_m_reads_slabs_from_device_memory(lib, n, its):
+    """m = 2304 and m = 4096 (K = 2): the slabs no longer fit in LDS, so the solver reads padded
+    copies of logK from device memory every half-step; fixed iterations against the float64
+    oracle, and (m = 2304) the tolerance solve with its float64 check."""
+    p = workloads.symmetric_problem(n, 2, 2, 0.05, seed=37)
+    prob = _problem(lib, p)
+    ref0 = _reduced_ref(p, 0.0, 1)
+    for k in its:
+        print(f"[reduced large m] m={p.m} iters={k}", flush=True)
+        opts = lib.make_opts(tol=0.0, max_iter=k, fold_fp64=1)
+        logK, alpha, beta = lib.ot_fold_kernel(prob, opts)
+        f, g, st = lib.ot_sinkhorn_reduced(prob, logK, alpha, beta, opts)
+        ref = sinkhorn.reduced_sinkhorn(ref0["alpha"], ref0["beta"], ref0["logK"], p.eps, p.K,
+                                        tol=0.0, max_iter=k)
+        assert st["iters"] == k
+        assert np.abs(f.cpu().numpy() - ref["f"]).max() / p.eps < 2e-5
+        assert np.abs(g.cpu().numpy() - ref["g"]).max() / p.eps < 2e-5
+    if p.m <= 2304:
+        print(f"[reduced large m] m={p.m} tol=1e-6", flush=True)
+        opts = lib.make_opts(tol=1e-6, max_iter=20000, fold_fp64=1)
+        logK, alpha, beta = lib.ot_fold_kernel(prob, opts)
+        f, g, st = lib.ot_sinkhorn_reduced(prob, logK, alpha, beta, opts)
+        ref = sinkhorn.reduced_sinkhorn(ref0["alpha"], ref0["beta"], ref0["logK"], p.eps, p.K,
+                                        tol=1e-6, max_iter=20000)
+        assert st["converged"] and abs(st["iters"] - ref["iters"]) <= 1
+        er, ec = sinkhorn.reduced_marginal_errors(_f64(f.cpu()), _f64(g.cpu()), ref0["logK"],
+                                                  p.eps, ref0["alpha"], ref0["beta"], p.K)
+        assert abs(st["err_row"] - er) <= 1e-3 * er + 1e-12
 
 
 def test_reduced_near_empty_rows_take_the_exact_path(lib):
