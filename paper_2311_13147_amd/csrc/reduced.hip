@@ -97,11 +97,38 @@ __device__ __forceinline__ float wave_lse2(const float* __restrict__ row,
 // the sum, the previous plan's row sum, is at most 1 and needs no maximum.
 constexpr float kMinShiftedSum = 0x1p-60f;  // below this the caller redoes the row exactly
 
+template <bool GSLAB>
 __device__ __forceinline__ float wave_shifted_sum(const float* __restrict__ row,
                                                   const float* __restrict__ vec, int mp,
                                                   int lane, float sh) {
   float s = 0.0f;
-  for (int base = 0; base < mp; base += kSweep) {
+  int base0 = 0;
+  if constexpr (GSLAB) {
+    // row in device memory: the loads of four sweeps are issued together, so that a row costs
+    // one memory round trip per four sweeps rather than one per sweep
+    constexpr int kG = 4;
+    for (; base0 + kG * kSweep <= mp; base0 += kG * kSweep) {
+      float4 l[2 * kG];
+#pragma unroll
+      for (int u = 0; u < kG; ++u) {
+        const int q0 = base0 + u * kSweep + 4 * lane;
+        l[2 * u] = *reinterpret_cast<const float4*>(row + q0);
+        l[2 * u + 1] = *reinterpret_cast<const float4*>(row + q0 + 4 * kWave);
+      }
+#pragma unroll
+      for (int u = 0; u < kG; ++u) {
+        const int q0 = base0 + u * kSweep + 4 * lane;
+        const float4 v0 = *reinterpret_cast<const float4*>(vec + q0);
+        const float4 v1 = *reinterpret_cast<const float4*>(vec + q0 + 4 * kWave);
+        const float4 l0 = l[2 * u], l1 = l[2 * u + 1];
+        s += exp2_fast(fmaf(l0.x, kLog2e, v0.x + sh)) + exp2_fast(fmaf(l0.y, kLog2e, v0.y + sh)) +
+             exp2_fast(fmaf(l0.z, kLog2e, v0.z + sh)) + exp2_fast(fmaf(l0.w, kLog2e, v0.w + sh)) +
+             exp2_fast(fmaf(l1.x, kLog2e, v1.x + sh)) + exp2_fast(fmaf(l1.y, kLog2e, v1.y + sh)) +
+             exp2_fast(fmaf(l1.z, kLog2e, v1.z + sh)) + exp2_fast(fmaf(l1.w, kLog2e, v1.w + sh));
+      }
+    }
+  }
+  for (int base = base0; base < mp; base += kSweep) {
     const int q0 = base + 4 * lane, q1 = q0 + 4 * kWave;
     const float4 l0 = *reinterpret_cast<const float4*>(row + q0);
     const float4 v0 = *reinterpret_cast<const float4*>(vec + q0);
@@ -118,11 +145,12 @@ __device__ __forceinline__ float wave_shifted_sum(const float* __restrict__ row,
 // One potential update by one wave: the new potential lm - LSE2_j(row_j + vec_j) and the
 // previous plan's marginal sum.  Shifted by the previous potential `prev` when `shifted`,
 // falling back to the exact running-maximum form when the shifted sum is out of range.
+template <bool GSLAB>
 __device__ __forceinline__ float wave_update(const float* __restrict__ row,
                                              const float* __restrict__ vec, int mp, int lane,
                                              float lm, float prev, bool shifted, float* sum_out) {
   if (shifted) {
-    const float S = wave_shifted_sum(row, vec, mp, lane, prev);
+    const float S = wave_shifted_sum<GSLAB>(row, vec, mp, lane, prev);
     if (S >= kMinShiftedSum && S < INFINITY) {
       *sum_out = S;
       return lm - log2_fast(S) + prev;
@@ -302,7 +330,8 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
     for (int rl = wv; rl < nr; rl += kRedWaves) {
       float S;
       const float Fo = Fcur[rl];
-      const float Fn = wave_update(Ls + (size_t)rl * mp, VsG, mp, lane, la2[rl], Fo, t >= 2, &S);
+      const float Fn =
+          wave_update<GSLAB>(Ls + (size_t)rl * mp, VsG, mp, lane, la2[rl], Fo, t >= 2, &S);
       if (lane == 0) {
         publish(p.fx + r0 + rl, Fn, t);  // first: the other workgroups wait for it
         if (t >= 2) {
@@ -346,7 +375,8 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
     for (int cl = wv; cl < nr; cl += kRedWaves) {
       float S;
       const float Go = Gcur[cl];
-      const float Gn = wave_update(LTs + (size_t)cl * mp, VsF, mp, lane, lb2[cl], Go, true, &S);
+      const float Gn =
+          wave_update<GSLAB>(LTs + (size_t)cl * mp, VsF, mp, lane, lb2[cl], Go, true, &S);
       if (lane == 0) {
         publish(p.gx + r0 + cl, Gn, t);
         Gprev[cl] = Go;
