@@ -60,6 +60,9 @@ def _args():
     ap.add_argument("--images", action="store_true",
                     help="only the image workloads (64 x 64 and 96 x 96 pixels, mirror K=2 and quarter-turn "
                          "K=4, pixel Euclidean distance, lambda 0.5): cyclic vs full")
+    ap.add_argument("--lot", action="store_true",
+                    help="only the cyclic linear OT steps on the GPU (min-fold, plan scatter) at "
+                         "n=8192, K=16")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (the reference kernel "
                          "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE) and exit")
@@ -291,6 +294,45 @@ def images_only(steps, warmup):
         print(json.dumps(rec), flush=True)
 
 
+def lot_only(steps, warmup):
+    """Cyclic linear OT (Thm. 1, Alg. 1) at n=8192, K=16, m=512: the GPU steps around the
+    small LP -- the min-fold (G = min_k C_ijk and the minimising k, float64 costs) and the
+    scatter of an m x m solution into the n x n plan (HBM-write bound) -- timed with HIP
+    events.  The small LP itself (m^2 variables) is the caller's and is not timed here."""
+    import numpy as np
+    import torch
+
+    import paper_2311_13147_amd as csot
+    import workloads
+
+    p = workloads.symmetric_problem(8192, 16, 2, 0.01, seed=100)
+    T_ = lambda v: torch.from_numpy(np.ascontiguousarray(v)).to("cuda:0")
+    prob = csot.Problem(T_(p.a), T_(p.b), p.eps, p.K, x=T_(p.x), y=T_(p.y))
+    G, kmin, al, be = csot.ot_lot_fold(prob)
+    S = torch.rand((p.m, p.m), device="cuda:0", dtype=torch.float32)
+    T = torch.empty((p.n, p.n), device="cuda:0", dtype=torch.float32)
+    E = lambda: torch.cuda.Event(enable_timing=True)
+    tf, te = [], []
+    for it in range(warmup + steps):
+        e = [E() for _ in range(3)]
+        e[0].record()
+        csot.ot_lot_fold(prob, out=(G, kmin, al, be))
+        e[1].record()
+        csot.ot_lot_expand(prob, S, kmin, out=T)
+        e[2].record()
+        torch.cuda.synchronize()
+        if it >= warmup:
+            tf.append(e[0].elapsed_time(e[1]))
+            te.append(e[1].elapsed_time(e[2]))
+    fold_ms, exp_ms = sum(tf) / steps, sum(te) / steps
+    gbps = p.n * p.n * 4 / (exp_ms * 1e-3) / 1e9
+    print(json.dumps({"workload": "cyclic linear OT steps, n=8192, K=16, m=512, 2-D clouds",
+                      "min_fold_ms": round(fold_ms, 4),
+                      "min_fold_cost_evals_per_s": p.K * p.m * p.m / (fold_ms * 1e-3),
+                      "plan_scatter_ms": round(exp_ms, 4), "plan_scatter_GBps": round(gbps, 1),
+                      "plan_scatter_frac_of_hbm": round(gbps / HBM_PEAK_GBS, 3)}), flush=True)
+
+
 def copy_calibration():
     import torch
     src = torch.ones(64 * 1024 * 1024, device="cuda:0")
@@ -344,6 +386,9 @@ def main():
         return
     if args.images:
         images_only(args.steps, args.warmup)
+        return
+    if args.lot:
+        lot_only(args.steps, args.warmup)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "

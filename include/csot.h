@@ -175,6 +175,26 @@ int ot_sinkhorn_full(const ot_problem* prob, const ot_opts* opts, float* f, floa
 int ot_expand_plan(const ot_problem* prob, const float* f, const float* g, float* T,
                    int64_t ldt, void* stream);
 
+/* Cyclic linear OT (Thm. 1, eq. definition_G; Alg. 1, first step): for the unregularised
+ * problem (eps is not used, but must be positive to pass validation), the min-fold of the cost
+ * and the folded marginals:
+ *   G[i, j] = min_k C_{ijk},  kmin[i, j] = the smallest k attaining it,  G, kmin [m, m];
+ *   alpha_i = (1/K) sum_r a_{r m + i},  beta likewise,  [m].
+ * Costs from coordinates are evaluated in float64 without fused multiply-adds (the same
+ * arithmetic as a plain float64 evaluation, so ties and near-ties resolve identically); G is
+ * stored in float32.  The small LP  min <G, S>, S 1 = alpha, S^T 1 = beta  (m^2 variables) is
+ * the caller's: it is not data-parallel.  Errors: OT_ERR_ARG, OT_ERR_HIP. */
+int ot_lot_fold(const ot_problem* prob, float* G, int32_t* kmin, float* alpha, float* beta,
+                void* stream);
+
+/* The full plan of the cyclic linear OT from the small LP's solution S [m, m] (eq.
+ * optimal_solution_problem_CLOT placed by Lemma 1; Alg. 1, last steps):
+ *   T[r*m + i, c*m + j] = S[i, j] if (c - r) mod K == kmin[i, j], else 0,  T [n, ldt], ldt >= n.
+ * Its value <C, T> is K <G, S>, the optimum of the full problem when S is optimal.
+ * Errors: OT_ERR_ARG, OT_ERR_HIP. */
+int ot_lot_expand(const ot_problem* prob, const float* S, const int32_t* kmin, float* T,
+                  int64_t ldt, void* stream);
+
 /* Objective values and gradients from converged potentials.
  *   reduced = 1: f, g [m] (plan T_ijk = exp((f_i + g_j - C_ijk)/eps) expanded by Lemma 1);
  *   reduced = 0: f, g [n] (plan T_IJ = exp((f_I + g_J - C_IJ)/eps)).

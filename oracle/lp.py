@@ -6,6 +6,11 @@
   ``LP - eps - 2 eps log n <= P_eps <= LP - eps`` and ``LP <= <C, T_eps> <= LP + 2 eps log n``.
 * ``small_lot_value``: Thm. 1 -- the cyclic LOT equals K times a small LOT on
   ``G_ij = min_k C_ijk`` (eq. definition_G) with marginals alpha, beta.
+* ``min_fold``: G and the smallest minimising k (eq. definition_G and the tie rule stated with
+  Thm. 1).
+* ``lot_plan``: the full plan of Thm. 1 (eq. optimal_solution_problem_CLOT) placed in the
+  block-circulant layout of Lemma 1, written out block by block.  Pinned by the brute-force LP:
+  the plan is feasible and its cost equals the full problem's optimum.
 
 These solve tiny problems only (n <= 40).  Parity unpinned by themselves: they are the pins.
 """
@@ -38,10 +43,27 @@ def lot_value(a, b, C):
     return float(res.fun), res.x.reshape(n1, n2)
 
 
+def min_fold(Ck):
+    """``G_ij = min_k C_ijk`` and the smallest k attaining it (``[m, m]`` each)."""
+    Ck = np.asarray(Ck, dtype=np.float64)
+    return Ck.min(axis=0), Ck.argmin(axis=0)  # argmin returns the first of equal minima
+
+
 def small_lot_value(alpha, beta, Ck):
     """Thm. 1: value of the small LOT on ``G = min_k C_k`` (returns value, S, argmin k)."""
-    Ck = np.asarray(Ck, dtype=np.float64)
-    G = Ck.min(axis=0)
-    kstar = Ck.argmin(axis=0)  # smallest k among ties, as the theorem prescribes
+    G, kstar = min_fold(Ck)
     val, S = lot_value(alpha, beta, G)
     return val, S, kstar
+
+
+def lot_plan(S, kstar, K):
+    """Full ``n x n`` plan: block (r, c) holds ``S_ij`` where ``kstar_ij == (c - r) mod K``
+    and 0 elsewhere."""
+    S = np.asarray(S, dtype=np.float64)
+    m = S.shape[0]
+    T = np.zeros((K * m, K * m))
+    for r in range(K):
+        for c in range(K):
+            k = (c - r) % K
+            T[r * m:(r + 1) * m, c * m:(c + 1) * m] = np.where(kstar == k, S, 0.0)
+    return T

@@ -16,6 +16,8 @@ from ._binding import (  # noqa: F401
     ot_cost_and_grad,
     ot_expand_plan,
     ot_fold_kernel,
+    ot_lot_expand,
+    ot_lot_fold,
     ot_sinkhorn_full,
     ot_sinkhorn_reduced,
     ot_symmetrize_cost,

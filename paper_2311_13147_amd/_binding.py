@@ -67,6 +67,8 @@ def _load():
         "ot_sinkhorn_reduced": (ctypes.c_int, [P, PO, VP, VP, VP, VP, VP, VP, PS, VP, SZ, VP]),
         "ot_sinkhorn_full": (ctypes.c_int, [P, PO, VP, VP, VP, PS, VP, SZ, VP]),
         "ot_expand_plan": (ctypes.c_int, [P, VP, VP, VP, I64, VP]),
+        "ot_lot_fold": (ctypes.c_int, [P, VP, VP, VP, VP, VP]),
+        "ot_lot_expand": (ctypes.c_int, [P, VP, VP, VP, I64, VP]),
         "ot_cost_and_grad": (ctypes.c_int, [P, VP, VP, I32, VP, VP, I64, VP, VP, VP, VP, VP, SZ, VP]),
         "ot_last_error": (ctypes.c_char_p, []),
         "ot_version": (ctypes.c_char_p, []),
@@ -81,7 +83,8 @@ def _load():
 _lib = _load()
 LIB_PATH = _LIB_PATH
 EXPORTED = ("ot_workspace_bytes", "ot_fold_kernel", "ot_symmetrize_cost", "ot_sinkhorn_reduced",
-            "ot_sinkhorn_full", "ot_expand_plan", "ot_cost_and_grad", "ot_batched_plan_len",
+            "ot_sinkhorn_full", "ot_expand_plan", "ot_lot_fold", "ot_lot_expand",
+            "ot_cost_and_grad", "ot_batched_plan_len",
             "ot_batched_plan", "ot_batched_workspace_bytes", "ot_sinkhorn_reduced_batched",
             "ot_last_error", "ot_version")
 
@@ -279,6 +282,39 @@ def ot_expand_plan(prob: Problem, f, g, out=None):
         out = torch.empty((prob.n, prob.n), dtype=torch.float32, device=prob.device)
     _check(_lib.ot_expand_plan(prob.c(), _ptr(f), _ptr(g), _ptr(out), int(out.stride(0)),
                                _stream()))
+    return out
+
+
+def ot_lot_fold(prob: Problem, out=None):
+    """Cyclic linear OT, first step -> (G [m, m] float32, kmin [m, m] int32, alpha [m],
+    beta [m]): G = min_k C_ijk, kmin the smallest minimising k, the folded marginals."""
+    m = prob.m
+    if out is None:
+        out = (torch.empty((m, m), dtype=torch.float32, device=prob.device),
+               torch.empty((m, m), dtype=torch.int32, device=prob.device),
+               torch.empty(m, dtype=torch.float32, device=prob.device),
+               torch.empty(m, dtype=torch.float32, device=prob.device))
+    G, kmin, alpha, beta = out
+    _dev_f32(G, "G", (m, m))
+    if not (kmin.is_cuda and kmin.dtype == torch.int32 and kmin.is_contiguous()
+            and tuple(kmin.shape) == (m, m)):
+        raise ValueError(f"kmin must be a contiguous int32 CUDA tensor of shape {(m, m)}")
+    _check(_lib.ot_lot_fold(prob.c(), _ptr(G), _ptr(kmin), _ptr(alpha), _ptr(beta), _stream()))
+    return G, kmin, alpha, beta
+
+
+def ot_lot_expand(prob: Problem, S, kmin, out=None):
+    """Cyclic linear OT, last steps -> T [n, n]: S (the small LP's solution, [m, m] float32)
+    placed at k = kmin in every block row (Thm. 1 with Lemma 1)."""
+    m = prob.m
+    _dev_f32(S, "S", (m, m))
+    if not (kmin.is_cuda and kmin.dtype == torch.int32 and kmin.is_contiguous()
+            and tuple(kmin.shape) == (m, m)):
+        raise ValueError(f"kmin must be a contiguous int32 CUDA tensor of shape {(m, m)}")
+    if out is None:
+        out = torch.empty((prob.n, prob.n), dtype=torch.float32, device=prob.device)
+    _check(_lib.ot_lot_expand(prob.c(), _ptr(S), _ptr(kmin), _ptr(out), int(out.stride(0)),
+                              _stream()))
     return out
 
 

@@ -317,6 +317,30 @@ int ot_expand_plan(const ot_problem* prob, const float* f, const float* g, float
   return ok();
 }
 
+int ot_lot_fold(const ot_problem* prob, float* G, int32_t* kmin, float* alpha, float* beta,
+                void* stream) {
+  int rc = check_problem(prob);
+  if (rc) return rc;
+  if (!G || !kmin || !alpha || !beta)
+    return fail(OT_ERR_ARG, "G, kmin, alpha and beta must be non-NULL");
+  hipError_t e = csot::launch_lot_fold(geom(prob), G, kmin, alpha, beta,
+                                       static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "lot fold launch");
+  return ok();
+}
+
+int ot_lot_expand(const ot_problem* prob, const float* S, const int32_t* kmin, float* T,
+                  int64_t ldt, void* stream) {
+  int rc = check_problem(prob);
+  if (rc) return rc;
+  if (!S || !kmin || !T) return fail(OT_ERR_ARG, "S, kmin and T must be non-NULL");
+  if (ldt < prob->n) return fail(OT_ERR_ARG, "ldt (%lld) < n (%d)", (long long)ldt, prob->n);
+  hipError_t e = csot::launch_lot_expand(prob->n / prob->K, prob->K, S, kmin, T, ldt,
+                                         static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "lot expand launch");
+  return ok();
+}
+
 int ot_cost_and_grad(const ot_problem* prob, const float* f, const float* g, int32_t reduced,
                      double* out, float* dC, int64_t lddc, float* dx, float* dy, float* da,
                      float* db, void* ws, size_t ws_bytes, void* stream) {

@@ -22,6 +22,12 @@ struct Geom {
   double eps;
 };
 
+// ---- lot.hip -----------------------------------------------------------------------------
+hipError_t launch_lot_fold(const Geom& g, float* G, int32_t* kmin, float* alpha, float* beta,
+                           hipStream_t s);
+hipError_t launch_lot_expand(int m, int K, const float* S, const int32_t* kmin, float* T,
+                             int64_t ldt, hipStream_t s);
+
 // ---- fold.hip ----------------------------------------------------------------------------
 hipError_t launch_fold(const Geom& g, bool fp64, float* logK, float* alpha, float* beta,
                        hipStream_t s);

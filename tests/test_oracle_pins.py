@@ -261,6 +261,31 @@ def test_theorem1_small_lp():
     assert abs(full - K * small) < 1e-12
 
 
+def test_lot_plan_is_feasible_and_optimal():
+    """Thm. 1 with Lemma 1: the plan built from the small LP's solution meets the full
+    marginals and its cost is the optimum of the full LP (brute force)."""
+    K, m = 4, 4
+    rng = np.random.default_rng(73)
+    Ck = rng.uniform(0, 1, size=(K, m, m))
+    al = rng.dirichlet(np.ones(m)) / K
+    be = rng.dirichlet(np.ones(m)) / K
+    C = cost.block_circulant_from_blocks(Ck)
+    full, _ = lp.lot_value(np.tile(al, K), np.tile(be, K), C)
+    small, S, kstar = lp.small_lot_value(al, be, Ck)
+    T = lp.lot_plan(S, kstar, K)
+    assert np.abs(T.sum(1) - np.tile(al, K)).max() < 1e-12
+    assert np.abs(T.sum(0) - np.tile(be, K)).max() < 1e-12
+    assert T.min() >= 0.0
+    assert abs((C * T).sum() - full) < 1e-12
+
+
+def test_min_fold_takes_the_smallest_k_among_ties():
+    Ck = np.array([[[2.0, 1.0]], [[1.0, 1.0]], [[1.0, 3.0]]])  # K = 3, m = 1 x 2 entries
+    G, kstar = lp.min_fold(Ck.reshape(3, 1, 2))
+    assert np.array_equal(G, [[1.0, 1.0]])
+    assert np.array_equal(kstar, [[1, 0]])
+
+
 def test_counter_example_single_block_is_not_the_answer():
     """App. A: solving OT on one symmetric block alone and tiling it is wrong in general;
     the cyclic solution differs from the block-diagonal tiling."""
