@@ -77,7 +77,10 @@ __device__ __forceinline__ float4 load_coords(const float4* __restrict__ c) {
   }
 }
 
-template <int DIM, int RT, int CQ, bool EXACT>
+// WIDE (shifted mode only): the workgroup's previous potentials spread too far for one common
+// shift; each row group (the RT rows of a wave) then shifts by its own largest previous
+// potential, added to the staged value once per column and wave (an add per RT entries).
+template <int DIM, int RT, int CQ, bool EXACT, bool WIDE = false>
 __device__ __forceinline__ int full_phase(const FullParams& p, int r0, const float4* __restrict__ ownc,
                                           const float* __restrict__ dense, int64_t ldd,
                                           const float4* __restrict__ othc, uint64_t* oslots,
@@ -111,10 +114,17 @@ __device__ __forceinline__ int full_phase(const FullParams& p, int r0, const flo
   // the workgroup's common shift: its rows' largest previous potential (written before the
   // barrier that ended the previous update; R <= 64 rows, one per lane, and every wave gets
   // the bitwise-identical maximum)
-  float sig = 0.0f;
+  float sig = 0.0f, dsig = 0.0f;
   if constexpr (!EXACT) {
     static_assert(RG * RT <= kWave, "one row per lane");
     sig = wave_max_v(lane < RG * RT && r0 + lane < p.n ? sh[lane] : kNegBig);
+    if constexpr (WIDE) {
+      float gs = kNegBig;  // this row group's largest previous potential
+#pragma unroll
+      for (int q = 0; q < RT; ++q)
+        if (r0 + rg * RT + q < p.n) gs = fmaxf(gs, sh[rg * RT + q]);
+      dsig = gs - sig;  // <= 0
+    }
   }
   if (tid == 0) *s_redo = 0;
   const int nchunks = p.np / kNC;
@@ -164,7 +174,10 @@ __device__ __forceinline__ int full_phase(const FullParams& p, int r0, const flo
     for (int u = cq * U; u < (cq + 1) * U; u += TU) {
       float4 o[TU];
 #pragma unroll
-      for (int cc = 0; cc < TU; ++cc) o[cc] = cur[lane + kWave * (u + cc)];
+      for (int cc = 0; cc < TU; ++cc) {
+        o[cc] = cur[lane + kWave * (u + cc)];
+        if constexpr (WIDE) o[cc].w += dsig;
+      }
 #pragma unroll
       for (int q = 0; q < RT; ++q) {
         float t[TU];
@@ -226,8 +239,15 @@ __device__ __forceinline__ int full_phase(const FullParams& p, int r0, const flo
     } else {
       float s_ = 0.0f;
       for (int k = 0; k < CQ; ++k) s_ += part[rl * CQ + k].y;
+      float rs = sig;  // the shift this row's sums carry
+      if constexpr (WIDE) {
+        const int g0 = rl / RT * RT;
+        rs = kNegBig;
+        for (int q = 0; q < RT; ++q)
+          if (r0 + g0 + q < p.n) rs = fmaxf(rs, sh[g0 + q]);
+      }
       if (r0 + rl < p.n && !(s_ >= kMinShiftedSum && s_ < INFINITY)) *s_redo = 1;
-      lse[rl] = log2_fast(s_) - sig;
+      lse[rl] = log2_fast(s_) - rs;
     }
   }
   __syncthreads();
@@ -246,9 +266,21 @@ __device__ __forceinline__ int full_phase_auto(bool exact, const FullParams& p, 
                                                int nx = 0, uint32_t xepoch = 0,
                                                float* xdst = nullptr) {
   if (!exact) {
-    const int r = full_phase<DIM, RT, CQ, false>(p, r0, ownc, dense, ldd, othc, oslots, epoch,
-                                                 sh, buf, part, lse, s_bad, s_redo, xs, nx,
-                                                 xepoch, xdst);
+    // spread of the rows' previous potentials: beyond ~100 (base 2) the common shift (the
+    // largest of them) would scale the sums of the lowest rows towards float32 overflow, so
+    // each row group shifts by its own largest
+    constexpr int NR = (kFullWaves / CQ) * RT;
+    const int lane = threadIdx.x & (kWave - 1);
+    const bool in = lane < NR && r0 + lane < p.n;
+    const float hi = wave_max_v(in ? sh[lane] : kNegBig);
+    const float lo = -wave_max_v(in ? -sh[lane] : kNegBig);
+    const int r = hi - lo > 100.0f
+                      ? full_phase<DIM, RT, CQ, false, true>(p, r0, ownc, dense, ldd, othc,
+                                                             oslots, epoch, sh, buf, part, lse,
+                                                             s_bad, s_redo, xs, nx, xepoch, xdst)
+                      : full_phase<DIM, RT, CQ, false>(p, r0, ownc, dense, ldd, othc, oslots,
+                                                       epoch, sh, buf, part, lse, s_bad, s_redo,
+                                                       xs, nx, xepoch, xdst);
     if (r != kPhaseRedo) return r;
     ++*redo_count;
     __syncthreads();  // every wave is done with the chunk buffers
