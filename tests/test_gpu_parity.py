@@ -395,6 +395,29 @@ def test_full_shift_overflow_redoes_in_exact_mode(lib):
     assert np.abs(g.cpu().numpy() - ref["g"]).max() / eps < 2e-5
 
 
+def test_full_wide_potentials_shift_per_row_group(lib):
+    """Groups of 4 consecutive rows carry cost offsets of 0 or 100 eps in turn: a workgroup's
+    previous potentials spread by ~144 (base 2), but each wave's 4 rows share one offset, so the
+    shifted phase shifts every row group by its own potential and nothing is redone in exact
+    mode (dstats[6] = 0); the result matches the float64 oracle."""
+    n = 2048
+    rng = np.random.default_rng(19)
+    eps = 0.05
+    C = rng.uniform(0.0, 1.0, size=(n, n)) + ((np.arange(n) // 4) % 2)[:, None] * (100.0 * eps)
+    C = C.astype(np.float32)
+    a = rng.uniform(0.5, 1.5, size=n)
+    b = rng.uniform(0.5, 1.5, size=n)
+    a, b = workloads.equal_mass_pair(a / a.sum(), b / b.sum())
+    print("[full wide] dense n2048 row-group offsets", flush=True)
+    prob = lib.Problem(T_(a), T_(b), eps, 1, C=T_(C))
+    f, g, ds = lib.ot_sinkhorn_full(prob, lib.make_opts(tol=0.0, max_iter=6), host_stats=False)
+    dsh = ds.cpu().numpy()
+    assert dsh[0] == 6 and dsh[5] == 0 and dsh[6] == 0, dsh
+    ref = sinkhorn.full_sinkhorn(_f64(a), _f64(b), _f64(C), eps, tol=0.0, max_iter=6)
+    assert np.abs(f.cpu().numpy() - ref["f"]).max() / eps < 2e-5
+    assert np.abs(g.cpu().numpy() - ref["g"]).max() / eps < 2e-5
+
+
 def test_validate_option_reports_bad_inputs(lib):
     """validate = 1: the host-side checks reject a non-positive marginal, unequal masses and
     (for the reduced path) data that is not block-circulant, and accept valid inputs."""
