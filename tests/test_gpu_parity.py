@@ -482,3 +482,52 @@ def test_reduced_matches_full_on_symmetric_data(lib):
     vr = lib.values_dict(lib.ot_cost_and_grad(prob, f, g, reduced=True)["values"])
     vf = lib.values_dict(lib.ot_cost_and_grad(prob, ff, gf, reduced=False)["values"])
     assert abs(vr["P"] - vf["P"]) / max(abs(vf["P"]), vf["CT"]) < 1e-4
+
+
+def test_padded_leading_dimensions(lib):
+    """Dense costs with a leading dimension beyond n (ldc = n + 13, the extra columns holding a
+    huge sentinel that must never be read) and plans written with ldt = n + 7 (the rows'
+    padding must stay untouched): fold, reduced solve, expand, the linear OT steps and the
+    dense full-size solve against the oracle."""
+    from oracle import lp
+    p = workloads.dense_appd_problem(600, 6, seed=3)
+    n, m, K = p.n, p.m, p.K
+    print("[padded strides] appd n600 K6", flush=True)
+    Cp = np.full((m, n + 13), 1.0e6, dtype=np.float32)
+    Cp[:, :n] = p.C_row0
+    prob = lib.Problem(T_(p.a), T_(p.b), p.eps, K, C=T_(Cp))
+    opts = lib.make_opts(tol=0.0, max_iter=5, fold_fp64=1)
+    logK, alpha, beta = lib.ot_fold_kernel(prob, opts)
+    ref = _reduced_ref(p, 0.0, 5)
+    assert (np.abs(logK.cpu().numpy() - ref["logK"]) / (np.abs(ref["logK"]) + 1.0)).max() < 2e-7
+    f, g, st = lib.ot_sinkhorn_reduced(prob, logK, alpha, beta, opts)
+    assert st["iters"] == 5
+    assert np.abs(f.cpu().numpy() - ref["f"]).max() / p.eps < 2e-5
+    # expand into rows of stride n + 7: the plan in the first n columns, the padding untouched
+    Tbuf = torch.full((n, n + 7), -7.0, dtype=torch.float32, device=DEV)
+    lib.ot_expand_plan(prob, f, g, out=Tbuf[:, :n])
+    Tb = Tbuf.cpu().numpy()
+    Tref = sinkhorn.expand_plan(_f64(f.cpu()), _f64(g.cpu()), ref["Ck"], p.eps)
+    assert np.abs(Tb[:, :n] - Tref).sum() / Tref.sum() < REL
+    assert (Tb[:, n:] == -7.0).all()
+    # linear OT steps on the padded cost
+    G, kmin, _, _ = lib.ot_lot_fold(prob)
+    Gref, kref = lp.min_fold(ref["Ck"])
+    assert np.array_equal(kmin.cpu().numpy(), kref)
+    assert np.array_equal(G.cpu().numpy(), Gref.astype(np.float32))
+    S = np.random.default_rng(4).uniform(0, 1, size=(m, m)).astype(np.float32)
+    Tbuf.fill_(-7.0)
+    lib.ot_lot_expand(prob, T_(S), kmin, out=Tbuf[:, :n])
+    Tb = Tbuf.cpu().numpy()
+    assert np.array_equal(Tb[:, :n].astype(np.float64), lp.lot_plan(S, kref, K))
+    assert (Tb[:, n:] == -7.0).all()
+    # the dense full-size solver on a padded n x (n + 13) cost
+    Cf = np.full((n, n + 13), 1.0e6, dtype=np.float32)
+    Cf[:, :n] = cost.block_circulant_from_row0(p.C_row0, K).astype(np.float32)
+    fprob = lib.Problem(T_(p.a), T_(p.b), p.eps, K, C=T_(Cf))
+    ff, gf, stf = lib.ot_sinkhorn_full(fprob, lib.make_opts(tol=0.0, max_iter=5))
+    fref = sinkhorn.full_sinkhorn(_f64(p.a), _f64(p.b), _f64(Cf[:, :n]), p.eps, tol=0.0,
+                                  max_iter=5)
+    assert stf["iters"] == 5
+    assert np.abs(ff.cpu().numpy() - fref["f"]).max() / p.eps < 2e-5
+    assert np.abs(gf.cpu().numpy() - fref["g"]).max() / p.eps < 2e-5
