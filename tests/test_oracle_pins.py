@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 from scipy.special import softmax
 
-from oracle import cost, dual_ascent, grad, lp, objective, projection, sinkhorn
+from oracle import cost, dual_ascent, grad, lp, objective, projection, sinkhorn, srot
 import workloads
 
 
@@ -284,6 +284,67 @@ def test_min_fold_takes_the_smallest_k_among_ties():
     G, kstar = lp.min_fold(Ck.reshape(3, 1, 2))
     assert np.array_equal(G, [[1.0, 1.0]])
     assert np.array_equal(kstar, [[1, 0]])
+
+
+def test_srot_waterfill_root_against_bisection():
+    rng = np.random.default_rng(91)
+    v = rng.uniform(-1, 3, size=37)
+    for t, lam in ((0.3, 0.5), (1e-4, 2.0), (5.0, 0.1)):
+        w = srot.waterfill(v, t, lam)
+        lo, hi = v.min(), v.max() + lam * t
+        for _ in range(200):
+            mid = 0.5 * (lo + hi)
+            if np.maximum(0.0, mid - v).sum() < lam * t:
+                lo = mid
+            else:
+                hi = mid
+        assert abs(w - 0.5 * (lo + hi)) < 1e-12
+        assert abs(np.maximum(0.0, w - v).sum() - lam * t) < 1e-12
+
+
+def test_srot_cyclic_iterates_equal_tiled_full_iterates():
+    """The reduced alternating maximisation equals the full one on the block-circulant cost
+    (K = 1 with the n x n matrix), tiled, at every iteration."""
+    K, m = 3, 5
+    rng = np.random.default_rng(93)
+    Ck = rng.uniform(0, 1, size=(K, m, m))
+    al = rng.dirichlet(np.ones(m)) / K
+    be = rng.dirichlet(np.ones(m)) / K
+    C = cost.block_circulant_from_blocks(Ck)
+    rec_c, rec_f = [], []
+    srot.cyclic_srot(al, be, Ck, 0.2, K, tol=0.0, max_iter=12, record=rec_c)
+    srot.cyclic_srot(np.tile(al, K), np.tile(be, K), C[None], 0.2, 1, tol=0.0, max_iter=12,
+                     record=rec_f)
+    for (wc, zc), (wf, zf) in zip(rec_c, rec_f):
+        assert np.abs(np.tile(wc, K) - wf).max() < 1e-12
+        assert np.abs(np.tile(zc, K) - zf).max() < 1e-12
+
+
+def test_srot_converges_to_the_dual_optimum():
+    """At convergence both marginals hold, primal = dual, and the dual value equals that of an
+    independent L-BFGS maximisation of the concave dual."""
+    from scipy.optimize import minimize
+    K, m, lam = 2, 6, 0.3
+    rng = np.random.default_rng(95)
+    Ck = rng.uniform(0, 1, size=(K, m, m))
+    al = rng.dirichlet(np.ones(m)) / K
+    be = rng.dirichlet(np.ones(m)) / K
+    out = srot.cyclic_srot(al, be, Ck, lam, K, tol=1e-12, max_iter=20000)
+    v = srot.values(out["w"], out["z"], Ck, lam, al, be)
+    assert np.abs(v["row"] - al).max() < 1e-11 and np.abs(v["col"] - be).max() < 1e-13
+    assert abs(v["primal"] - v["dual"]) < 1e-10
+
+    def neg_dual(u):
+        w, z = u[:m], u[m:]
+        y = np.maximum(0.0, w[None, :, None] + z[None, None, :] - Ck)
+        val = w @ al + z @ be - (y * y).sum() / (2 * lam)
+        gw = al - y.sum(axis=(0, 2)) / lam
+        gz = be - y.sum(axis=(0, 1)) / lam
+        return -val, -np.concatenate([gw, gz])
+
+    res = minimize(neg_dual, np.zeros(2 * m), jac=True, method="L-BFGS-B",
+                   options={"ftol": 1e-15, "gtol": 1e-12, "maxiter": 10000})
+    assert abs(-res.fun - v["dual"]) < 1e-9
 
 
 def test_counter_example_single_block_is_not_the_answer():
