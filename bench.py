@@ -63,6 +63,9 @@ def _args():
     ap.add_argument("--lot", action="store_true",
                     help="only the cyclic linear OT steps on the GPU (min-fold, plan scatter) at "
                          "n=8192, K=16")
+    ap.add_argument("--srot", action="store_true",
+                    help="only the quadratically regularised problem (cyclic vs full, n=8192, "
+                         "K=16)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (the reference kernel "
                          "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE) and exit")
@@ -336,6 +339,54 @@ def lot_only(steps, warmup):
                       "plan_scatter_frac_of_hbm": round(gbps / HBM_PEAK_GBS, 3)}), flush=True)
 
 
+def srot_only(steps, warmup):
+    """Quadratically regularised OT (phi(x) = lam/2 x^2, lam = 10 median(C)) at n=8192, K=16:
+    the cyclic alternating maximisation (m = 512) to 1e-6, and per-iteration times of the
+    cyclic and of the full-size problem (the same call with K = 1 on all n points) over 50
+    fixed iterations (one host synchronisation per call).  Host-timed around each call (the call synchronises every iteration for
+    its stopping test)."""
+    import time
+
+    import numpy as np
+    import torch
+
+    import paper_2311_13147_amd as csot
+    import workloads
+
+    p = workloads.symmetric_problem(8192, 16, 2, 0.01, seed=100)
+    T_ = lambda v: torch.from_numpy(np.ascontiguousarray(v)).to("cuda:0")
+    x, y = T_(p.x), T_(p.y)
+    lam = 10.0 * workloads.median_sq_dist_row0(p.x, p.y, p.m)
+    red = csot.Problem(T_(p.a), T_(p.b), p.eps, p.K, x=x, y=y)
+    full = csot.Problem(T_(p.a), T_(p.b), p.eps, 1, x=x, y=y)
+
+    def timed(prob, opts):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        w, z, st = csot.ot_srot_reduced(prob, lam, opts)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3, st
+
+    fixed = csot.make_opts(tol=0.0, max_iter=50)
+    tr, tf, tt = [], [], []
+    for it in range(warmup + steps):
+        a, _ = timed(red, fixed)
+        b, _ = timed(full, fixed)
+        c, st = timed(red, csot.make_opts(tol=1e-6, max_iter=5000))
+        if it >= warmup:
+            tr.append(a)
+            tf.append(b)
+            tt.append(c)
+    print(json.dumps({"workload": "quadratically regularised OT, lam=10*median(C), n=8192, K=16, "
+                                  "m=512, tol=1e-6",
+                      "cyclic_ms_per_iteration": round(sum(tr) / steps / 50, 4),
+                      "full_ms_per_iteration": round(sum(tf) / steps / 50, 4),
+                      "iteration_speedup": round(sum(tf) / sum(tr), 1),
+                      "cyclic_time_to_tol_ms": round(sum(tt) / steps, 3),
+                      "cyclic_iterations_to_tol": st["iters"],
+                      "cyclic_err_row_fp64": st["err_row"]}), flush=True)
+
+
 def copy_calibration():
     import torch
     src = torch.ones(64 * 1024 * 1024, device="cuda:0")
@@ -392,6 +443,9 @@ def main():
         return
     if args.lot:
         lot_only(args.steps, args.warmup)
+        return
+    if args.srot:
+        srot_only(args.steps, args.warmup)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "

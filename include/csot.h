@@ -195,6 +195,24 @@ int ot_lot_fold(const ot_problem* prob, float* G, int32_t* kmin, float* alpha, f
 int ot_lot_expand(const ot_problem* prob, const float* S, const int32_t* kmin, float* T,
                   int64_t ldt, void* stream);
 
+/* Cyclic SROT with the quadratic regulariser phi(x) = (lam/2) x^2, x >= 0 (strongly convex; the
+ * C-SROT section with Thm. 2, eq. dual_problem_cyclic_ROT): alternating maximisation of the
+ * reduced dual over w, z [m] (in/out; zero-started unless opts->warm_start = 1).  An
+ * iteration sets every w_i to the root of eq. derivative_of_objective_function,
+ *   sum_{k,j} max(0, w_i + z_j - C_ijk) = lam alpha_i   (Newton on the piecewise linear sum),
+ * then every z_j likewise; alpha, beta are the folded marginals.  The plan is
+ * T_ijk = max(0, w_i + z_j - C_ijk) / lam (eq. optimality_condition), expanded by Lemma 1.
+ * With tol > 0 the float64 residuals are computed and copied to the host after every iteration
+ * (the call synchronises there; not for graph capture) and it stops when the full-space row
+ * residual sqrt(K) ||T 1 - alpha||_2 <= opts->tol; tol = 0 runs exactly max_iter iterations
+ * and evaluates the residuals once, at the end.  hstats [host] is required.  With K = 1 and
+ * the full cost the same call solves the full-size problem.  The workspace holds the folded
+ * marginals and the residuals (ot_srot_workspace_bytes).  Errors: OT_ERR_ARG, OT_ERR_WORKSPACE,
+ * OT_ERR_NOCONV (outputs valid), OT_ERR_NONFINITE, OT_ERR_HIP. */
+size_t ot_srot_workspace_bytes(const ot_problem* prob);
+int ot_srot_reduced(const ot_problem* prob, double lam, const ot_opts* opts, float* w, float* z,
+                    ot_stats* hstats, void* ws, size_t ws_bytes, void* stream);
+
 /* Objective values and gradients from converged potentials.
  *   reduced = 1: f, g [m] (plan T_ijk = exp((f_i + g_j - C_ijk)/eps) expanded by Lemma 1);
  *   reduced = 0: f, g [n] (plan T_IJ = exp((f_I + g_J - C_IJ)/eps)).

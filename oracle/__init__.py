@@ -16,6 +16,7 @@ grad        envelope-theorem gradients and central finite differences.
 lp          brute-force linear programs (LOT and the small LOT of Thm. 1) via SciPy HiGHS.
 projection  block-circulant projection of a cost matrix (approximate-symmetry workload).
 dual_ascent an independent EROT solver (L-BFGS on the concave dual) used only to pin sinkhorn.
+srot        cyclic SROT with a quadratic regulariser: alternating exact dual maximisation.
 
 Pinning status of every function is listed in each module header.  Functions whose result is
 only a reported number and has no independent pin say "parity unpinned".

@@ -20,6 +20,7 @@ from ._binding import (  # noqa: F401
     ot_lot_fold,
     ot_sinkhorn_full,
     ot_sinkhorn_reduced,
+    ot_srot_reduced,
     ot_symmetrize_cost,
     ot_workspace_bytes,
     raw_lib,

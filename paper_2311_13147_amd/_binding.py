@@ -69,6 +69,8 @@ def _load():
         "ot_expand_plan": (ctypes.c_int, [P, VP, VP, VP, I64, VP]),
         "ot_lot_fold": (ctypes.c_int, [P, VP, VP, VP, VP, VP]),
         "ot_lot_expand": (ctypes.c_int, [P, VP, VP, VP, I64, VP]),
+        "ot_srot_workspace_bytes": (SZ, [P]),
+        "ot_srot_reduced": (ctypes.c_int, [P, D, PO, VP, VP, PS, VP, SZ, VP]),
         "ot_cost_and_grad": (ctypes.c_int, [P, VP, VP, I32, VP, VP, I64, VP, VP, VP, VP, VP, SZ, VP]),
         "ot_last_error": (ctypes.c_char_p, []),
         "ot_version": (ctypes.c_char_p, []),
@@ -84,6 +86,7 @@ _lib = _load()
 LIB_PATH = _LIB_PATH
 EXPORTED = ("ot_workspace_bytes", "ot_fold_kernel", "ot_symmetrize_cost", "ot_sinkhorn_reduced",
             "ot_sinkhorn_full", "ot_expand_plan", "ot_lot_fold", "ot_lot_expand",
+            "ot_srot_workspace_bytes", "ot_srot_reduced",
             "ot_cost_and_grad", "ot_batched_plan_len",
             "ot_batched_plan", "ot_batched_workspace_bytes", "ot_sinkhorn_reduced_batched",
             "ot_last_error", "ot_version")
@@ -316,6 +319,26 @@ def ot_lot_expand(prob: Problem, S, kmin, out=None):
     _check(_lib.ot_lot_expand(prob.c(), _ptr(S), _ptr(kmin), _ptr(out), int(out.stride(0)),
                               _stream()))
     return out
+
+
+def ot_srot_reduced(prob: Problem, lam: float, opts: Optional[OtOpts] = None, out=None):
+    """Cyclic SROT with the quadratic regulariser (lam/2) x^2 -> (w [m], z [m], stats dict).
+    `out` = (w, z) also serves as the warm start when opts.warm_start = 1.  Synchronises."""
+    m = prob.m
+    opts = opts or make_opts()
+    if out is None:
+        out = (torch.zeros(m, dtype=torch.float32, device=prob.device),
+               torch.zeros(m, dtype=torch.float32, device=prob.device))
+    w, z = out
+    _dev_f32(w, "w", (m,))
+    _dev_f32(z, "z", (m,))
+    nbytes = int(_lib.ot_srot_workspace_bytes(prob.c()))
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=prob.device)
+    hs = OtStats()
+    _check(_lib.ot_srot_reduced(prob.c(), float(lam), ctypes.byref(opts), _ptr(w), _ptr(z),
+                                ctypes.byref(hs), _ptr(ws), ws.numel(), _stream()),
+           allow=(OT_ERR_NOCONV,))
+    return w, z, _stats_dict(hs)
 
 
 def ot_cost_and_grad(prob: Problem, f, g, reduced: bool, want_dC=False, want_dxy=False,

@@ -341,6 +341,40 @@ int ot_lot_expand(const ot_problem* prob, const float* S, const int32_t* kmin, f
   return ok();
 }
 
+size_t ot_srot_workspace_bytes(const ot_problem* prob) {
+  if (!prob || prob->n <= 0 || prob->K <= 0 || prob->n % prob->K) return 0;
+  return csot::srot_ws_bytes(geom(prob));
+}
+
+int ot_srot_reduced(const ot_problem* prob, double lam, const ot_opts* opts, float* w, float* z,
+                    ot_stats* hstats, void* ws, size_t ws_bytes, void* stream) {
+  int rc = check_problem(prob);
+  if (rc) return rc;
+  ot_opts o = opts ? *opts : defaults();
+  if ((rc = check_opts(o))) return rc;
+  if (!(lam > 0.0) || !std::isfinite(lam)) return fail(OT_ERR_ARG, "lam must be > 0");
+  if (!w || !z || !hstats) return fail(OT_ERR_ARG, "w, z and hstats must be non-NULL");
+  if (o.warm_start == 2) return fail(OT_ERR_ARG, "warm_start must be 0 or 1");
+  const csot::Geom geo = geom(prob);
+  if ((rc = check_ws(ws, ws_bytes, csot::srot_ws_bytes(geo)))) return rc;
+  double res[4] = {0, 0, 0, 0};
+  hipError_t e = csot::run_srot(geo, lam, o.tol, o.max_iter, 1, o.warm_start, w, z,
+                                ws, static_cast<hipStream_t>(stream), res);
+  if (e != hipSuccess) return hip_fail(e, "srot launch");
+  *hstats = ot_stats{};
+  hstats->iters = (int32_t)res[0];
+  hstats->converged = (int32_t)res[1];
+  hstats->err_row = res[2];
+  hstats->err_col = res[3];
+  hstats->err_row32 = res[2];
+  if (!std::isfinite(res[2]) || !std::isfinite(res[3])) {
+    hstats->flags = 1;
+    return fail(OT_ERR_NONFINITE, "non-finite residual");
+  }
+  if (!hstats->converged && o.tol > 0.0) return fail(OT_ERR_NOCONV, "max_iter reached");
+  return ok();
+}
+
 int ot_cost_and_grad(const ot_problem* prob, const float* f, const float* g, int32_t reduced,
                      double* out, float* dC, int64_t lddc, float* dx, float* dy, float* da,
                      float* db, void* ws, size_t ws_bytes, void* stream) {

@@ -28,6 +28,11 @@ hipError_t launch_lot_fold(const Geom& g, float* G, int32_t* kmin, float* alpha,
 hipError_t launch_lot_expand(int m, int K, const float* S, const int32_t* kmin, float* T,
                              int64_t ldt, hipStream_t s);
 
+// ---- srot.hip ----------------------------------------------------------------------------
+size_t srot_ws_bytes(const Geom& g);
+hipError_t run_srot(const Geom& g, double lam, double tol, int max_iter, int check_every,
+                    int warm, float* w, float* z, void* ws, hipStream_t s, double* res);
+
 // ---- fold.hip ----------------------------------------------------------------------------
 hipError_t launch_fold(const Geom& g, bool fp64, float* logK, float* alpha, float* beta,
                        hipStream_t s);
