@@ -4,7 +4,7 @@
 //
 // With z fixed, w_i is the root of eq. derivative_of_objective_function,
 //   sum_{k,j} max(0, w_i + z_j - C_ijk) = lam alpha_i,
-// a piecewise linear increasing function of w_i.  One wave per point runs Newton's method on
+// a piecewise linear increasing function of w_i.  One workgroup per point runs Newton's method on
 // it from the point's previous value: the slope is the number of active terms; from the left
 // of the root the first step lands right of it (the function is convex), from there the
 // iterates decrease monotonically and stop once the active set is right.  Costs are
@@ -38,19 +38,22 @@ __device__ __forceinline__ float srot_cost(const Geom& g, int a, int b, int k) {
   }
 }
 
+// One workgroup of kSrotWaves waves per point: its threads split the K m terms, and the
+// partial sums of a Newton step are combined through LDS, so that a step costs K m / 256 terms
+// per thread (the cyclic problem has only m points to spread over the chip).
 template <int DIM, bool ROW>
 __global__ void __launch_bounds__(kWave* kSrotWaves)
     srot_update_kernel(Geom g, float lam, const float* __restrict__ other,
                        const float* __restrict__ marg, float* __restrict__ own) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int a = blockIdx.x * kSrotWaves + threadIdx.x / kWave;
-  if (a >= g.m) return;
+  __shared__ float ps[kSrotWaves], pc[kSrotWaves], pm[kSrotWaves];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+  const int a = blockIdx.x;
   const float target = lam * marg[a];
   float w = own[a];
   for (int step = 0; step < 64; ++step) {
     float s = 0.0f, cnt = 0.0f, vmin = INFINITY;
     for (int k = 0; k < g.K; ++k) {
-      for (int b = lane; b < g.m; b += kWave) {
+      for (int b = tid; b < g.m; b += kWave * kSrotWaves) {
         const float v = srot_cost<DIM, ROW>(g, a, b, k) - other[b];
         if (v < w) {
           s += w - v;
@@ -62,6 +65,22 @@ __global__ void __launch_bounds__(kWave* kSrotWaves)
     s = wave_sum_all(s);
     cnt = wave_sum_all(cnt);
     vmin = -wave_max(-vmin);
+    if (lane == 0) {
+      ps[wv] = s;
+      pc[wv] = cnt;
+      pm[wv] = vmin;
+    }
+    __syncthreads();
+    s = 0.0f;
+    cnt = 0.0f;
+    vmin = INFINITY;
+#pragma unroll
+    for (int q = 0; q < kSrotWaves; ++q) {  // the same order in every thread
+      s += ps[q];
+      cnt += pc[q];
+      vmin = fminf(vmin, pm[q]);
+    }
+    __syncthreads();  // the partials are read before the next step overwrites them
     if (cnt == 0.0f) {  // left of every term: move to a point right of the root
       w = vmin + target;
       continue;
@@ -71,7 +90,7 @@ __global__ void __launch_bounds__(kWave* kSrotWaves)
     // the root is reached (the active set is right) up to float32 rounding of the terms
     if (fabsf(dw) <= 2e-7f * (fabsf(w) + fabsf(vmin) + target)) break;
   }
-  if (lane == 0) own[a] = w;
+  if (tid == 0) own[a] = w;
 }
 
 // Residual sums of the current plan T_ijk = max(0, w_i + z_j - C_ijk) / lam: out[a] =
@@ -123,7 +142,7 @@ size_t srot_ws_bytes(const Geom& g) {
 template <int DIM>
 static hipError_t srot_step(const Geom& g, float lam, const float* alpha, const float* beta,
                             float* w, float* z, hipStream_t s) {
-  const dim3 grid((g.m + kSrotWaves - 1) / kSrotWaves), block(kWave * kSrotWaves);
+  const dim3 grid(g.m), block(kWave * kSrotWaves);  // one workgroup per point
   hipLaunchKernelGGL((srot_update_kernel<DIM, true>), grid, block, 0, s, g, lam, z, alpha, w);
   hipLaunchKernelGGL((srot_update_kernel<DIM, false>), grid, block, 0, s, g, lam, w, beta, z);
   return hipGetLastError();
