@@ -2,8 +2,10 @@
  *
  * The library implements, on one AMD MI355X (gfx950), the data-parallel path of the cyclic
  * Sinkhorn method of "Optimal Transport with Cyclic Symmetry" (Takeda, Akagi, Marumo, Niwa;
- * AAAI 2024) and plain full-size Sinkhorn beside it.  Notation: the paper's vector length d,
- * cyclic order n and regulariser lambda are called n, K and eps here; m = n / K.
+ * AAAI 2024) and plain full-size Sinkhorn beside it, plus the data-parallel steps of its
+ * linear (unregularised) variant (Thm. 1) and its quadratically regularised variant (the
+ * C-SROT algorithm).  Notation: the paper's vector length d, cyclic order n and regulariser
+ * lambda are called n, K and eps here (lam for the quadratic regulariser); m = n / K.
  *
  * Conventions shared by every call
  * --------------------------------
