@@ -177,3 +177,34 @@ def test_batched_plan_gang_tasks(B):
     assert list(prob) == [2] * 8 + [1] * 4 + [0]
     assert list(member) == list(range(8)) + list(range(4)) + [0]
     assert list(gang) == [8] * 8 + [4] * 4 + [1]
+
+
+def test_linear_ot_and_srot_arguments_are_checked_before_launch(B):
+    """The linear OT and quadratic SROT entry points reject bad arguments on the host, before
+    any device work: null outputs, a short leading dimension, lam <= 0, a missing host stats
+    struct, warm_start = 2, and a too small workspace."""
+    lib = B.raw_lib()
+    p = _prob(B)
+    assert lib.ot_lot_fold(ctypes.byref(p), None, 8, 8, 8, None) == B.OT_ERR_ARG
+    assert lib.ot_lot_fold(ctypes.byref(p), 8, None, 8, 8, None) == B.OT_ERR_ARG
+    assert lib.ot_lot_expand(ctypes.byref(p), 8, 8, None, 64, None) == B.OT_ERR_ARG
+    assert lib.ot_lot_expand(ctypes.byref(p), 8, 8, 8, 63, None) == B.OT_ERR_ARG
+    assert "ldt" in lib.ot_last_error().decode()
+    st = B.OtStats()
+    need = lib.ot_srot_workspace_bytes(ctypes.byref(p))
+    assert need > 0
+    assert lib.ot_srot_reduced(ctypes.byref(p), 0.0, None, 8, 8, ctypes.byref(st), 8, need,
+                               None) == B.OT_ERR_ARG
+    assert "lam" in lib.ot_last_error().decode()
+    assert lib.ot_srot_reduced(ctypes.byref(p), 1.0, None, 8, 8, None, 8, need,
+                               None) == B.OT_ERR_ARG
+    assert lib.ot_srot_reduced(ctypes.byref(p), 1.0, None, None, 8, ctypes.byref(st), 8, need,
+                               None) == B.OT_ERR_ARG
+    o = B.make_opts(warm_start=2)
+    assert lib.ot_srot_reduced(ctypes.byref(p), 1.0, ctypes.byref(o), 8, 8, ctypes.byref(st), 8,
+                               need, None) == B.OT_ERR_ARG
+    assert lib.ot_srot_reduced(ctypes.byref(p), 1.0, None, 8, 8, ctypes.byref(st), 8,
+                               need - 1, None) == B.OT_ERR_WORKSPACE
+    # the workspace grows with m
+    big = _prob(B, n=4096, K=4)
+    assert lib.ot_srot_workspace_bytes(ctypes.byref(big)) > need
