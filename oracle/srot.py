@@ -17,7 +17,7 @@ conjugate is phi*(y) = max(0, y)^2 / (2 lam), so (phi*)'(y) = max(0, y) / lam.
 Pins (tests/test_oracle_pins.py): the cyclic iterates equal the full problem's tiled at every
 iteration; the water-filling root against bisection; at convergence both marginals hold and
 the primal value equals the dual value; the dual optimum equals that of an independent
-L-BFGS maximisation of the concave dual.
+L-BFGS maximisation of the concave dual; the expanded plan solves the full primal QP (SLSQP).
 """
 from __future__ import annotations
 

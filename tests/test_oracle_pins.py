@@ -347,6 +347,35 @@ def test_srot_converges_to_the_dual_optimum():
     assert abs(-res.fun - v["dual"]) < 1e-9
 
 
+def test_srot_full_plan_solves_the_primal_qp():
+    """The expanded quadratic-regularised plan (Lemma 1 with eq. optimality_condition) solves
+    the full primal QP min <C,T> + lam/2 ||T||^2 over the transport polytope: checked against
+    SciPy's SLSQP on the n x n problem (n = 8), and its value is K times the reduced one."""
+    from scipy.optimize import minimize
+    K, m, lam = 2, 4, 0.5
+    rng = np.random.default_rng(97)
+    Ck = rng.uniform(0, 1, size=(K, m, m))
+    al = rng.dirichlet(np.ones(m)) / K
+    be = rng.dirichlet(np.ones(m)) / K
+    out = srot.cyclic_srot(al, be, Ck, lam, K, tol=1e-13, max_iter=20000)
+    Tk = srot.plan_blocks(out["w"], out["z"], Ck, lam)
+    C = cost.block_circulant_from_blocks(Ck)
+    T = cost.block_circulant_from_blocks(Tk)
+    n = K * m
+    a, b = np.tile(al, K), np.tile(be, K)
+    obj = lambda t: float((C.ravel() * t).sum() + 0.5 * lam * (t * t).sum())
+    cons = [{"type": "eq", "fun": lambda t, i=i: t.reshape(n, n)[i].sum() - a[i]} for i in range(n)]
+    cons += [{"type": "eq", "fun": lambda t, j=j: t.reshape(n, n)[:, j].sum() - b[j]}
+             for j in range(n - 1)]
+    res = minimize(obj, np.full(n * n, 1.0 / (n * n)), method="SLSQP", constraints=cons,
+                   bounds=[(0, None)] * (n * n), options={"ftol": 1e-14, "maxiter": 1000})
+    assert res.success
+    v = srot.values(out["w"], out["z"], Ck, lam, al, be)
+    assert abs(obj(T.ravel()) - K * v["primal"]) < 1e-12
+    assert abs(obj(T.ravel()) - res.fun) < 1e-8
+    assert np.abs(T.ravel() - res.x).max() < 1e-5
+
+
 def test_counter_example_single_block_is_not_the_answer():
     """App. A: solving OT on one symmetric block alone and tiling it is wrong in general;
     the cyclic solution differs from the block-diagonal tiling."""
