@@ -170,6 +170,19 @@ int ot_sinkhorn_full(const ot_problem* prob, const ot_opts* opts, float* f, floa
                      double* dstats, ot_stats* hstats, void* ws, size_t ws_bytes,
                      void* stream);
 
+/* [host] The launch configuration the persistent solvers would use for this problem and these
+ * options on the current device (a query for tests and tuning; it enqueues nothing).
+ *   ot_full_plan_info   info[6] = {workgroups, rows per row block, row blocks per workgroup,
+ *                                  rows per lane RT, column split CQ, dense (dim 0)};
+ *                       the variant (RT, CQ) is the full_solver_kernel instance launched.
+ *   ot_reduced_plan_info info[6] = {workgroups, rows per workgroup, launch stride (8: all
+ *                                  workgroups placed on one XCD), slabs in device memory,
+ *                                  dynamic LDS bytes, threads per workgroup}.
+ * Errors: OT_ERR_ARG (bad problem, options or NULL info), OT_ERR_UNSUPPORTED (no co-resident
+ * configuration, or no device). */
+int ot_full_plan_info(const ot_problem* prob, const ot_opts* opts, int32_t* info);
+int ot_reduced_plan_info(const ot_problem* prob, const ot_opts* opts, int32_t* info);
+
 /* Expansion of the reduced solution to the full block-circulant plan (Lemma 1, eq.
  * blkstr_optimal_solution; eq. optimality_condition; Alg. 2, last steps):
  *   T[r*m + i, c*m + j] = exp((f_i + g_j - C_{ij,(c - r) mod K}) / eps),  T [n, ldt], ldt >= n.

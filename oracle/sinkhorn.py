@@ -14,6 +14,11 @@ full_sinkhorn
     identical in exact arithmetic and only usable when ``max C / eps`` stays far from float64
     underflow (checked).
 
+row_update, col_update
+    The two half-steps of that iteration on a subset of rows (columns), given those rows'
+    (columns') costs to every partner: the loop of ``full_sinkhorn`` is made of them, and large
+    problems are checked one step at a time on sampled rows and columns with them.
+
 fold_marginals, fold_kernel, reduced_sinkhorn, expand_plan
     The cyclic Sinkhorn algorithm (Alg. 2, Sec. "Algorithm for C-EROT"):
     * fold of the marginals (Alg. 3, stage 1): alpha_i = (1/K) sum_r a_{r m + i};
@@ -53,6 +58,25 @@ def _row_residual_full(f, g, C, eps, a):
     return float(np.linalg.norm(T.sum(axis=1) - a))
 
 
+def row_update(g, C_rows, a_rows, eps):
+    """One row half-step on the rows given: ``f_I = eps log a_I - eps LSE_J((g_J - C_IJ)/eps)``
+    (the logarithm of ``p = a / (K q)``), ``C_rows`` holding those rows' costs to all columns."""
+    C_rows = np.asarray(C_rows, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    return eps * np.log(np.asarray(a_rows, dtype=np.float64)) - eps * logsumexp(
+        (g[None, :] - C_rows) / eps, axis=1)
+
+
+def col_update(f, C_cols, b_cols, eps):
+    """One column half-step on the columns given: ``g_J = eps log b_J - eps LSE_I((f_I -
+    C_IJ)/eps)`` (the logarithm of ``q = b / (K^T p)``), ``C_cols`` holding all rows' costs to
+    those columns."""
+    C_cols = np.asarray(C_cols, dtype=np.float64)
+    f = np.asarray(f, dtype=np.float64)
+    return eps * np.log(np.asarray(b_cols, dtype=np.float64)) - eps * logsumexp(
+        (f[:, None] - C_cols) / eps, axis=0)
+
+
 def full_sinkhorn(a, b, C, eps, tol=1e-9, max_iter=100000, g0=None, domain="log",
                   record=None):
     """Plain full-size Sinkhorn.  Returns a dict with f, g, iters, err_row, converged and,
@@ -79,8 +103,8 @@ def full_sinkhorn(a, b, C, eps, tol=1e-9, max_iter=100000, g0=None, domain="log"
             g = eps * np.log(q)
             err = float(np.linalg.norm(p * (Kmat @ q) - a))
         else:
-            f = eps * np.log(a) - eps * logsumexp((g[None, :] - C) / eps, axis=1)
-            g = eps * np.log(b) - eps * logsumexp((f[:, None] - C) / eps, axis=0)
+            f = row_update(g, C, a, eps)
+            g = col_update(f, C, b, eps)
             err = _row_residual_full(f, g, C, eps, a)
         if record is not None and it in record:
             history[it] = (f.copy(), g.copy())

@@ -16,8 +16,10 @@ from ._binding import (  # noqa: F401
     ot_cost_and_grad,
     ot_expand_plan,
     ot_fold_kernel,
+    ot_full_plan_info,
     ot_lot_expand,
     ot_lot_fold,
+    ot_reduced_plan_info,
     ot_sinkhorn_full,
     ot_sinkhorn_reduced,
     ot_srot_reduced,

@@ -67,6 +67,8 @@ def _load():
         "ot_sinkhorn_reduced": (ctypes.c_int, [P, PO, VP, VP, VP, VP, VP, VP, PS, VP, SZ, VP]),
         "ot_sinkhorn_full": (ctypes.c_int, [P, PO, VP, VP, VP, PS, VP, SZ, VP]),
         "ot_expand_plan": (ctypes.c_int, [P, VP, VP, VP, I64, VP]),
+        "ot_full_plan_info": (ctypes.c_int, [P, PO, VP]),
+        "ot_reduced_plan_info": (ctypes.c_int, [P, PO, VP]),
         "ot_lot_fold": (ctypes.c_int, [P, VP, VP, VP, VP, VP]),
         "ot_lot_expand": (ctypes.c_int, [P, VP, VP, VP, I64, VP]),
         "ot_srot_workspace_bytes": (SZ, [P]),
@@ -85,7 +87,8 @@ def _load():
 _lib = _load()
 LIB_PATH = _LIB_PATH
 EXPORTED = ("ot_workspace_bytes", "ot_fold_kernel", "ot_symmetrize_cost", "ot_sinkhorn_reduced",
-            "ot_sinkhorn_full", "ot_expand_plan", "ot_lot_fold", "ot_lot_expand",
+            "ot_sinkhorn_full", "ot_expand_plan", "ot_full_plan_info", "ot_reduced_plan_info",
+            "ot_lot_fold", "ot_lot_expand",
             "ot_srot_workspace_bytes", "ot_srot_reduced",
             "ot_cost_and_grad", "ot_batched_plan_len",
             "ot_batched_plan", "ot_batched_workspace_bytes", "ot_sinkhorn_reduced_batched",
@@ -277,6 +280,22 @@ def ot_sinkhorn_full(prob: Problem, opts: Optional[OtOpts] = None, g0=None, host
                                  ctypes.byref(hs) if hs is not None else None, _ptr(ws),
                                  ws.numel(), ctypes.c_void_p(st)), allow=(OT_ERR_NOCONV,))
     return f, g, (_stats_dict(hs) if hs is not None else dstats)
+
+
+def ot_full_plan_info(prob: Problem, opts: Optional[OtOpts] = None):
+    """Launch configuration of ot_sinkhorn_full on the current device -> dict(workgroups,
+    rows, blocks, RT, CQ, dense)."""
+    info = (ctypes.c_int32 * 6)()
+    _check(_lib.ot_full_plan_info(prob.c(), ctypes.byref(opts) if opts else None, info))
+    return dict(zip(("workgroups", "rows", "blocks", "RT", "CQ", "dense"), list(info)))
+
+
+def ot_reduced_plan_info(prob: Problem, opts: Optional[OtOpts] = None):
+    """Launch configuration of ot_sinkhorn_reduced on the current device -> dict(workgroups,
+    rows, stride, gslab, lds, threads)."""
+    info = (ctypes.c_int32 * 6)()
+    _check(_lib.ot_reduced_plan_info(prob.c(), ctypes.byref(opts) if opts else None, info))
+    return dict(zip(("workgroups", "rows", "stride", "gslab", "lds", "threads"), list(info)))
 
 
 def ot_expand_plan(prob: Problem, f, g, out=None):

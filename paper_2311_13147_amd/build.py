@@ -1,6 +1,6 @@
 """Build libcsot.so (HIP kernels + C ABI) in-tree for gfx950 with hipcc.
 
-Every source under csrc/ goes into one shared library next to this file.  Packed-FP32 VALU
+Every source under csrc/ is compiled to its own object (in parallel) and linked into one\nshared library next to this file.  Packed-FP32 VALU
 instructions are disabled for device code (the host pass warns that it does not know the
 feature; that warning is harmless).
 """
@@ -31,20 +31,39 @@ def sources():
     return srcs
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP/C++ source into libcsot.so; returns the library path."""
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wno-unused-command-line-argument",
-           "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
-           *sources(), "-o", tmp]
+def _flags():
+    return [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-Wno-unused-command-line-argument",
+            "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
+
+
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libcsot.so")
+        raise RuntimeError(f"hipcc failed: {' '.join(cmd[-3:])}")
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every HIP/C++ source into libcsot.so (one object per source, compiled in
+    parallel, then linked); returns the library path."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    srcs = sources()
+    objs = [os.path.join(objdir, os.path.basename(s) + ".o") for s in srcs]
+    jobs = max(1, min(len(srcs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        futs = [ex.submit(_run, [hipcc(), *_flags(), "-c", s, "-o", o], verbose)
+                for s, o in zip(srcs, objs)]
+        for fu in futs:
+            fu.result()
+    tmp = LIB + ".tmp"
+    _run([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
     os.replace(tmp, LIB)
     return LIB
 

@@ -214,8 +214,13 @@ size_t ot_workspace_bytes(const ot_problem* prob, const ot_opts* opts) {
     rp.lds = 0;
     // padded logK copies of the large-m mode: needed above m = 2048 on 256 CUs; sized in from
     // m = 1024 so that devices down to 64 CUs are covered
-    rp.gslab = g.m > 1024 ? 1 : 0;
+    // a workgroup hint above the CU count also moves the slabs to device memory
+    rp.gslab = (g.m > 1024 || o.workgroups > 0) ? 1 : 0;
     need = std::max(need, csot::reduced_ws_bytes(g.m, rp));
+    // and whatever the planner decides on the current device (when there is one)
+    csot::ReducedPlan actual;
+    if (csot::plan_reduced(g.m, o.workgroups, &actual))
+      need = std::max(need, csot::reduced_ws_bytes(g.m, actual));
   }
   {
     csot::FullPlan fp;
@@ -303,6 +308,43 @@ int ot_sinkhorn_full(const ot_problem* prob, const ot_opts* opts, float* f, floa
                                             ws, plan, s, static_cast<hipEvent_t*>(o.timing_events));
   if (e != hipSuccess) return hip_fail(e, "full solver launch");
   if (hstats) return finish_stats(dstats, hstats, o.tol, s);
+  return ok();
+}
+
+int ot_full_plan_info(const ot_problem* prob, const ot_opts* opts, int32_t* info) {
+  int rc = check_problem(prob);
+  if (rc) return rc;
+  ot_opts o = opts ? *opts : defaults();
+  if ((rc = check_opts(o))) return rc;
+  if (!info) return fail(OT_ERR_ARG, "info must be non-NULL");
+  csot::FullPlan plan;
+  if (!csot::plan_full(geom(prob), o.workgroups, &plan))
+    return fail(OT_ERR_UNSUPPORTED, "no co-resident launch configuration for n = %d", prob->n);
+  info[0] = plan.W;
+  info[1] = plan.R;
+  info[2] = plan.P;
+  info[3] = plan.threads / 100;
+  info[4] = plan.threads % 100;
+  info[5] = prob->dim == 0 ? 1 : 0;
+  return ok();
+}
+
+int ot_reduced_plan_info(const ot_problem* prob, const ot_opts* opts, int32_t* info) {
+  int rc = check_problem(prob, false);
+  if (rc) return rc;
+  ot_opts o = opts ? *opts : defaults();
+  if ((rc = check_opts(o))) return rc;
+  if (!info) return fail(OT_ERR_ARG, "info must be non-NULL");
+  csot::ReducedPlan plan;
+  const int m = prob->n / prob->K;
+  if (!csot::plan_reduced(m, o.workgroups, &plan))
+    return fail(OT_ERR_UNSUPPORTED, "no co-resident launch configuration for m = %d", m);
+  info[0] = plan.W;
+  info[1] = plan.R;
+  info[2] = plan.stride;
+  info[3] = plan.gslab;
+  info[4] = (int32_t)plan.lds;
+  info[5] = plan.threads;
   return ok();
 }
 

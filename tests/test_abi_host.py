@@ -120,6 +120,30 @@ def test_workspace_bytes_grows_with_n(B):
     assert lib.ot_workspace_bytes(None, None) == 0
 
 
+def test_workspace_bytes_cover_a_workgroup_hint_above_the_cu_count(B):
+    """A workgroups hint beyond the CU count makes the reduced solver keep its logK slabs in
+    device memory (padded logK and its transpose, 2 m mp floats); the size query covers that
+    with a hint even where m alone would not need it (m = 1024 here)."""
+    lib = B.raw_lib()
+    p = _prob(B, n=2048, K=2)
+    plain = lib.ot_workspace_bytes(ctypes.byref(p), None)
+    hinted = lib.ot_workspace_bytes(ctypes.byref(p), ctypes.byref(B.make_opts(workgroups=600)))
+    assert hinted > plain and hinted >= 2 * 4 * 1024 * 1024
+
+
+def test_plan_queries_reject_bad_arguments(B):
+    lib = B.raw_lib()
+    p = _prob(B)
+    info = (ctypes.c_int32 * 6)()
+    assert lib.ot_full_plan_info(ctypes.byref(p), None, None) == B.OT_ERR_ARG
+    assert lib.ot_reduced_plan_info(ctypes.byref(p), None, None) == B.OT_ERR_ARG
+    bad = _prob(B, n=100, K=7)
+    assert lib.ot_full_plan_info(ctypes.byref(bad), None, info) == B.OT_ERR_ARG
+    assert lib.ot_reduced_plan_info(ctypes.byref(bad), None, info) == B.OT_ERR_ARG
+    assert lib.ot_full_plan_info(ctypes.byref(p), ctypes.byref(B.make_opts(max_iter=0)),
+                                 info) == B.OT_ERR_ARG
+
+
 def test_batched_plan_validation_and_order(B):
     from paper_2311_13147_amd.batched import BatchDesc, _lib
     descs = (BatchDesc * 3)()
