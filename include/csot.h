@@ -160,6 +160,23 @@ int ot_sinkhorn_reduced(const ot_problem* prob, const ot_opts* opts, const float
                         double* dstats, ot_stats* hstats, void* ws, size_t ws_bytes,
                         void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): ot_sinkhorn_reduced with no workspace argument.
+ * Same arguments, kernels and results otherwise.  Its scratch (the potential exchange slots
+ * and residual partials) is a fixed array of OT_REDUCED_SCRATCH_BYTES in device memory, one
+ * copy per device, held until the process ends; the call allocates nothing and calls no
+ * allocating routine.  It covers every m whose slabs fit in LDS (up to m = 2048 on a 256-CU
+ * device) and rejects, before any launch, a problem whose plan needs more scratch than the
+ * array holds (m above that, or a workgroups hint that moves the slabs to device memory):
+ * OT_ERR_UNSUPPORTED.  Runs on the current device; `stream` must belong to it.  The scratch
+ * is cleared by a fill kernel at the start of every call, but every call on one device shares
+ * it: calls that may overlap on one device (several streams, several host threads) race and
+ * must be serialised by the caller.  Errors: as ot_sinkhorn_reduced, minus OT_ERR_WORKSPACE. */
+#define OT_REDUCED_SCRATCH_BYTES (128u * 1024u)
+int ot_sinkhorn_reduced_noalloc(const ot_problem* prob, const ot_opts* opts, const float* logK,
+                                const float* alpha, const float* beta, float* f, float* g,
+                                double* dstats, ot_stats* hstats, void* stream);
+
 /* Plain full-size log-domain Sinkhorn on the n x n problem (Alg. 3, stage 2; the paper's
  * baseline), costs recomputed per tile from the coordinates (dim 2/3) or streamed from the
  * dense C (dim 0).  Same stopping rule, statistics and launch structure as the reduced call.

@@ -22,6 +22,7 @@ from ._binding import (  # noqa: F401
     ot_reduced_plan_info,
     ot_sinkhorn_full,
     ot_sinkhorn_reduced,
+    ot_sinkhorn_reduced_noalloc,
     ot_srot_reduced,
     ot_symmetrize_cost,
     ot_workspace_bytes,

@@ -65,6 +65,7 @@ def _load():
         "ot_fold_kernel": (ctypes.c_int, [P, PO, VP, VP, VP, VP, SZ, VP]),
         "ot_symmetrize_cost": (ctypes.c_int, [P, VP, I64, VP]),
         "ot_sinkhorn_reduced": (ctypes.c_int, [P, PO, VP, VP, VP, VP, VP, VP, PS, VP, SZ, VP]),
+        "ot_sinkhorn_reduced_noalloc": (ctypes.c_int, [P, PO, VP, VP, VP, VP, VP, VP, PS, VP]),
         "ot_sinkhorn_full": (ctypes.c_int, [P, PO, VP, VP, VP, PS, VP, SZ, VP]),
         "ot_expand_plan": (ctypes.c_int, [P, VP, VP, VP, I64, VP]),
         "ot_full_plan_info": (ctypes.c_int, [P, PO, VP]),
@@ -87,6 +88,7 @@ def _load():
 _lib = _load()
 LIB_PATH = _LIB_PATH
 EXPORTED = ("ot_workspace_bytes", "ot_fold_kernel", "ot_symmetrize_cost", "ot_sinkhorn_reduced",
+            "ot_sinkhorn_reduced_noalloc",
             "ot_sinkhorn_full", "ot_expand_plan", "ot_full_plan_info", "ot_reduced_plan_info",
             "ot_lot_fold", "ot_lot_expand",
             "ot_srot_workspace_bytes", "ot_srot_reduced",
@@ -256,6 +258,29 @@ def ot_sinkhorn_reduced(prob: Problem, logK, alpha, beta, opts: Optional[OtOpts]
                                     _ptr(beta), _ptr(f), _ptr(g), _ptr(dstats),
                                     ctypes.byref(hs) if hs is not None else None, _ptr(ws),
                                     ws.numel(), ctypes.c_void_p(st)), allow=(OT_ERR_NOCONV,))
+    return f, g, (_stats_dict(hs) if hs is not None else dstats)
+
+
+def ot_sinkhorn_reduced_noalloc(prob: Problem, logK, alpha, beta, opts: Optional[OtOpts] = None,
+                                host_stats=True, out=None, dstats=None):
+    """ot_sinkhorn_reduced on the library's fixed device scratch (no workspace) -> (f [m],
+    g [m], stats).  Pass `out` and `dstats` to make the call allocate nothing."""
+    m = prob.m
+    _dev_f32(logK, "logK", (m, m))
+    _dev_f32(alpha, "alpha", (m,))
+    _dev_f32(beta, "beta", (m,))
+    opts = opts or make_opts()
+    if out is None:
+        out = (torch.empty(m, dtype=torch.float32, device=prob.device),
+               torch.empty(m, dtype=torch.float32, device=prob.device))
+    f, g = out
+    if dstats is None:
+        dstats = torch.zeros(OT_DSTATS_LEN, dtype=torch.float64, device=prob.device)
+    hs = OtStats() if host_stats else None
+    _check(_lib.ot_sinkhorn_reduced_noalloc(prob.c(), ctypes.byref(opts), _ptr(logK), _ptr(alpha),
+                                            _ptr(beta), _ptr(f), _ptr(g), _ptr(dstats),
+                                            ctypes.byref(hs) if hs is not None else None,
+                                            _stream()), allow=(OT_ERR_NOCONV,))
     return f, g, (_stats_dict(hs) if hs is not None else dstats)
 
 

@@ -288,6 +288,37 @@ int ot_sinkhorn_reduced(const ot_problem* prob, const ot_opts* opts, const float
   return ok();
 }
 
+int ot_sinkhorn_reduced_noalloc(const ot_problem* prob, const ot_opts* opts, const float* logK,
+                                const float* alpha, const float* beta, float* f, float* g,
+                                double* dstats, ot_stats* hstats, void* stream) {
+  int rc = check_problem(prob, false);
+  if (rc) return rc;
+  ot_opts o = opts ? *opts : defaults();
+  if ((rc = check_opts(o))) return rc;
+  if (!logK || !alpha || !beta || !f || !g)
+    return fail(OT_ERR_ARG, "logK, alpha, beta, f and g must be non-NULL");
+  if (!dstats) return fail(OT_ERR_ARG, "dstats must be non-NULL");
+  const int m = prob->n / prob->K;
+  csot::ReducedPlan plan;
+  if (!csot::plan_reduced(m, o.workgroups, &plan))
+    return fail(OT_ERR_UNSUPPORTED, "no co-resident launch configuration for m = %d", m);
+  const size_t need = csot::reduced_ws_bytes(m, plan);
+  if (need > csot::kReducedScratchBytes)
+    return fail(OT_ERR_UNSUPPORTED,
+                "m = %d needs %zu bytes of scratch%s; the allocation-free call holds %zu", m, need,
+                plan.gslab ? " (logK slabs in device memory)" : "", csot::kReducedScratchBytes);
+  void* scratch = nullptr;
+  hipError_t e = csot::reduced_scratch(&scratch);
+  if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  e = csot::launch_sinkhorn_reduced(m, prob->K, prob->eps, logK, alpha, beta, f, g, o.tol,
+                                    o.max_iter, o.warm_start, dstats, scratch, plan, s,
+                                    static_cast<hipEvent_t*>(o.timing_events));
+  if (e != hipSuccess) return hip_fail(e, "reduced solver launch");
+  if (hstats) return finish_stats(dstats, hstats, o.tol, s);
+  return ok();
+}
+
 int ot_sinkhorn_full(const ot_problem* prob, const ot_opts* opts, float* f, float* g,
                      double* dstats, ot_stats* hstats, void* ws, size_t ws_bytes,
                      void* stream) {

@@ -49,6 +49,10 @@ struct ReducedPlan {
   int gslab = 0;  // 1: logK slabs read from padded copies in the workspace (large m)
 };
 bool plan_reduced(int m, int workgroups_hint, ReducedPlan* plan);
+// Bytes of the fixed device scratch behind ot_sinkhorn_reduced_noalloc (OT_REDUCED_SCRATCH_BYTES).
+constexpr size_t kReducedScratchBytes = OT_REDUCED_SCRATCH_BYTES;
+// Device address of that scratch on the current device (looked up once per device).
+hipError_t reduced_scratch(void** ptr);
 size_t reduced_ws_bytes(int m, const ReducedPlan& p);
 hipError_t launch_sinkhorn_reduced(int m, int K, double eps, const float* logK,
                                    const float* alpha, const float* beta, float* f, float* g,

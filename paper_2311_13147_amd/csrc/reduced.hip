@@ -25,6 +25,8 @@
 // iteration t; the full-space norm is sqrt(K) ||r||_2 (every block-row of the expanded plan
 // has these row sums).  At exit the workgroups exchange the returned f, g once more and
 // recompute both marginal errors in float64.
+#include <mutex>
+
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -665,6 +667,35 @@ hipError_t launch_sinkhorn_reduced(int m, int K, double eps, const float* logK,
   if (e != hipSuccess) return e;
   if (events && (e = hipEventRecord(events[1], s)) != hipSuccess) return e;
 
+  return hipSuccess;
+}
+
+// ---- allocation-free entry: fixed scratch in device memory ---------------------------------
+// One copy per device, held until the process ends.  Host code never passes `scratch` itself
+// (in host code the name is a host-side stand-in, not a device address): the device address
+// comes from hipGetSymbolAddress, fetched once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[kReducedScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t reduced_scratch(void** ptr) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
   return hipSuccess;
 }
 
