@@ -253,8 +253,10 @@ int ot_srot_reduced(const ot_problem* prob, double lam, const ot_opts* opts, flo
  *         evaluated as sum T (C + eps (Z - 1)), Z = log T;  for reduced = 1 it is K times the
  *         reduced objective (eq. problem_CROT);
  *     D = <f,a> + <g,b> - eps sum T (eq. dual_problem_cyclic_ROT);
- *   dC   [K, m, m] (reduced, dC[k,i,j] = dP/dC[r*m+i, ((r+k) mod K)*m+j] = T_ijk) or
- *        [n, lddc] (full, = T);  NULL to skip.
+ *   dC   reduced: [m, lddc], lddc >= n, the derivative with respect to block-row 0 of the
+ *        cost (the reduced problem's parameters; eq. problem_CROT): each entry C[i, k*m+j]
+ *        appears in all K block-rows, so dC[i, k*m+j] = K T_ijk;
+ *        full: [n, lddc], lddc >= n, dC = T;  NULL to skip.
  *   dx, dy [n, dim]: dP/dx_I = 2 sum_J T_IJ (x_I - y_J), dP/dy_J = 2 sum_I T_IJ (y_J - x_I);
  *        NULL to skip; must be NULL for dim = 0.
  *   da, db [n]: dP/da = f - mean(f), dP/db = g - mean(g) (tiled for reduced); NULL to skip.

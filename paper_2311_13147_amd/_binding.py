@@ -388,7 +388,8 @@ def ot_srot_reduced(prob: Problem, lam: float, opts: Optional[OtOpts] = None, ou
 def ot_cost_and_grad(prob: Problem, f, g, reduced: bool, want_dC=False, want_dxy=False,
                      want_dab=False, out=None, grads=None):
     """-> dict with 'values' (device double[8]: P, D, <C,T>, err_row, err_col, mass) and the
-    requested gradients dC ([K, m, m] reduced or [n, n] full), dx, dy ([n, dim]), da, db
+    requested gradients dC ([m, n] reduced: K T_ijk at [i, k m + j], the derivative with
+    respect to block-row 0 of the cost; [n, n] full: T), dx, dy ([n, dim]), da, db
     ([n]).  `grads`: optional dict of preallocated float32 outputs (keys dC, dx, dy, da, db)
     used instead of new tensors."""
     dev = prob.device
@@ -402,7 +403,7 @@ def ot_cost_and_grad(prob: Problem, f, g, reduced: bool, want_dC=False, want_dxy
             return torch.empty(shape, dtype=torch.float32, device=dev)
         return _dev_f32(t, key, shape)
 
-    dC = buf("dC", (K, m, m) if reduced else (n, n)) if want_dC else None
+    dC = buf("dC", (m, n) if reduced else (n, n)) if want_dC else None
     dx = dy = None
     if want_dxy:
         dx = buf("dx", (n, prob.dim))
@@ -413,7 +414,7 @@ def ot_cost_and_grad(prob: Problem, f, g, reduced: bool, want_dC=False, want_dxy
         db = buf("db", (n,))
     st = torch.cuda.current_stream().cuda_stream
     ws = workspace(prob, None, st)
-    lddc = n if (dC is not None and not reduced) else 0
+    lddc = n if dC is not None else 0
     _check(_lib.ot_cost_and_grad(prob.c(), _ptr(f), _ptr(g), 1 if reduced else 0, _ptr(vals),
                                  _ptr(dC), lddc, _ptr(dx), _ptr(dy), _ptr(da), _ptr(db),
                                  _ptr(ws), ws.numel(), ctypes.c_void_p(st)))

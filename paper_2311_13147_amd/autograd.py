@@ -10,7 +10,8 @@ optimum; da, db are mean-centred because a, b live on the simplex).
 
 CyclicOTCost.apply(C_row0, a, b, eps, K) is the dense-cost variant: its input is block-row 0
 of a block-circulant cost ([m, n], block k = C_k), each entry of which appears once in every
-block-row of the full cost, so dOT/dC_row0[i, k m + j] = K T_ijk.
+block-row of the full cost, so dOT/dC_row0[i, k m + j] = K T_ijk -- the library's dC output
+for reduced potentials.
 """
 from __future__ import annotations
 
@@ -89,8 +90,5 @@ class CyclicOTCost(torch.autograd.Function):
         C_, a_, b_, f, g = ctx.saved_tensors
         prob = B.Problem(a_, b_, ctx.eps, ctx.K, C=C_)
         res = B.ot_cost_and_grad(prob, f, g, reduced=True, want_dC=True, want_dab=True)
-        K, m = ctx.K, prob.m
-        dC = res["dC"]  # [K, m, m]
-        dC_row0 = (K * dC).permute(1, 0, 2).reshape(m, K * m)
         go = grad_out.to(torch.float32)
-        return (go * dC_row0, go * res["da"], go * res["db"], None, None, None, None, None)
+        return (go * res["dC"], go * res["da"], go * res["db"], None, None, None, None, None)

@@ -456,7 +456,7 @@ int ot_cost_and_grad(const ot_problem* prob, const float* f, const float* g, int
   if (!f || !g || !out) return fail(OT_ERR_ARG, "f, g and out must be non-NULL");
   if (reduced != 0 && reduced != 1) return fail(OT_ERR_ARG, "reduced must be 0 or 1");
   if (prob->dim == 0 && (dx || dy)) return fail(OT_ERR_ARG, "dx/dy need coordinates (dim 2 or 3)");
-  if (dC && !reduced && lddc < prob->n)
+  if (dC && lddc < prob->n)
     return fail(OT_ERR_ARG, "lddc (%lld) < n (%d)", (long long)lddc, prob->n);
   const csot::Geom geo = geom(prob);
   if ((rc = check_ws(ws, ws_bytes, csot::costgrad_ws_bytes(geo)))) return rc;

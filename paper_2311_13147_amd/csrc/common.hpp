@@ -95,6 +95,110 @@ __device__ __forceinline__ float wave_max_v(float v) {
   return fmaxf(__uint_as_float(a[0]), __uint_as_float(a[1]));
 }
 
+// ---- float64 cross-lane moves (each 32-bit half moved on its own) ----------------------
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+// v_permlane32_swap / v_permlane16_swap of the pair (a, b): afterwards a + b is, in lanes whose
+// bit 5 (bit 4) is clear, a + partner's a and, in the others, partner's b + b (partner = lane
+// with that bit flipped).
+__device__ __forceinline__ void swap32_f64(double& a, double& b) {
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(a),
+                                                   (unsigned)__double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(a),
+                                                   (unsigned)__double2hiint(b), false, false);
+  a = __hiloint2double((int)hi[0], (int)lo[0]);
+  b = __hiloint2double((int)hi[1], (int)lo[1]);
+}
+__device__ __forceinline__ void swap16_f64(double& a, double& b) {
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(a),
+                                                   (unsigned)__double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(a),
+                                                   (unsigned)__double2hiint(b), false, false);
+  a = __hiloint2double((int)hi[0], (int)lo[0]);
+  b = __hiloint2double((int)hi[1], (int)lo[1]);
+}
+
+// Wave-wide float64 sum on the vector unit, every lane receiving the result.
+__device__ __forceinline__ double wave_sum_all_d(double v) {
+  v += dpp_f64<kDppXor1>(v);
+  v += dpp_f64<kDppXor2>(v);
+  v += dpp_f64<kDppHalfMirror>(v);
+  v += dpp_f64<kDppMirror>(v);
+  double w = v;
+  swap16_f64(v, w);
+  v += w;
+  w = v;
+  swap32_f64(v, w);
+  return v + w;
+}
+
+constexpr int ilog2_ceil(int v) {
+  int s = 0;
+  while ((1 << s) < v) ++s;
+  return s;
+}
+
+// One DPP halving step of wave_reduce_scatter_d: L values in, L / 2 out (or a plain sum of
+// the last one).  The DPP pattern pairs each lane with a lane that differs from it in BIT.
+template <int CTRL, int BIT, int L, int NV>
+__device__ __forceinline__ void rs_step_dpp(double (&v)[NV], int lane) {
+  if constexpr (L > 1) {
+    const bool hi = (lane & BIT) != 0;
+#pragma unroll
+    for (int q = 0; q < L / 2; ++q) {
+      const double keep = hi ? v[q + L / 2] : v[q];
+      const double send = hi ? v[q] : v[q + L / 2];
+      v[q] = keep + dpp_f64<CTRL>(send);
+    }
+  } else {
+    v[0] += dpp_f64<CTRL>(v[0]);
+  }
+}
+
+// Reduce-scatter of NV = 2^S (S <= 6) float64 values over the 64 lanes of a wave, on the
+// vector unit.  Halving steps over lane bits 5, 4 (permlane swaps), 3, 2 (row and half-row
+// mirrors), 1, 0 (quad permutations): at each, a lane keeps the half of its values selected
+// by that bit and adds its partner's copy of the same half.  Once one value is left the
+// remaining bits are summed outright.  On return v[0] of lane l holds the wave total of value
+// l >> (6 - S).
+template <int S>
+__device__ __forceinline__ void wave_reduce_scatter_d(double (&v)[1 << S], int lane) {
+  static_assert(S >= 0 && S <= 6, "at most 64 values");
+  constexpr int NV = 1 << S;
+  // bit 5
+  if constexpr (S >= 1) {
+#pragma unroll
+    for (int q = 0; q < NV / 2; ++q) {
+      swap32_f64(v[q], v[q + NV / 2]);
+      v[q] += v[q + NV / 2];
+    }
+  } else {
+    double w = v[0];
+    swap32_f64(v[0], w);
+    v[0] += w;
+  }
+  // bit 4
+  if constexpr (S >= 2) {
+#pragma unroll
+    for (int q = 0; q < NV / 4; ++q) {
+      swap16_f64(v[q], v[q + NV / 4]);
+      v[q] += v[q + NV / 4];
+    }
+  } else {
+    double w = v[0];
+    swap16_f64(v[0], w);
+    v[0] += w;
+  }
+  rs_step_dpp<kDppMirror, 8, (S >= 3 ? NV / 4 : 1)>(v, lane);
+  rs_step_dpp<kDppHalfMirror, 4, (S >= 4 ? NV / 8 : 1)>(v, lane);
+  rs_step_dpp<kDppXor2, 2, (S >= 5 ? NV / 16 : 1)>(v, lane);
+  rs_step_dpp<kDppXor1, 1, (S >= 6 ? NV / 32 : 1)>(v, lane);
+}
+
 // (max, sum) merge across the 64 lanes of a wave: DPP inside each row of 16 lanes, then a
 // lane swizzle across rows (xor 16) and a read of lane 32 for the last step.  The result is
 // valid in lane 0.

@@ -7,7 +7,9 @@
 //   D = <f, a> + <g, b> - eps sum T                                    -- eq. dual_problem_cyclic_ROT;
 //   <C, T>, sum T and the L2 marginal errors.
 // Gradients (envelope theorem on the dual; exact at the optimum):
-//   dC = T;  da = f - mean(f);  db = g - mean(g);
+//   dC = T (for reduced potentials: the derivative with respect to block-row 0 of the cost,
+//   each entry of which appears in all K block-rows: dC[i, k m + j] = K T_ijk);
+//   da = f - mean(f);  db = g - mean(g);
 //   dx_I = 2 sum_J T_IJ (x_I - y_J);  dy_J = 2 sum_I T_IJ (y_J - x_I).
 // With reduced potentials T_IJ is the expanded plan, T[r m + i, c m + j] = T_{ij,(c-r) mod K}
 // (Lemma 1), whose cost is block-row 0's; the gradient weights use the actual coordinates.
@@ -45,7 +47,8 @@ struct PassOut {
   double* sums;   // [own points] sum over the other side of T (row or column sums)
   double* part;   // [blocks][3] P, <C,T>, mass partials (row pass) or nullptr
   float* grad;    // [own points, DIM] 2 sum T (own - other), or nullptr
-  float* dC;      // full: [n, lddc] (row pass only); reduced: [K, m, m] or nullptr
+  float* dC;      // row pass only: full [n, lddc] (= T); reduced block-row 0 [m, lddc]
+                  // (dC[i, k m + j] = K T_ijk); or nullptr
   int64_t lddc;
 };
 
@@ -88,7 +91,7 @@ __device__ __forceinline__ void pass_fast(const Geom& g, const float* __restrict
 #pragma unroll
     for (int q = 0; q < kPassRT; ++q)
       dcrow[q] = !(DC && ROW) ? nullptr
-                 : RED ? out.dC + ((int64_t)kk * g.m + ai[q]) * g.m
+                 : RED ? out.dC + (int64_t)ai[q] * out.lddc + (int64_t)kk * g.m
                        : out.dC + (int64_t)(a0 + q) * out.lddc;
 #pragma unroll 2
     for (int b = lane + wv * kWave; b < bl; b += kPassThreads) {
@@ -123,7 +126,7 @@ __device__ __forceinline__ void pass_fast(const Geom& g, const float* __restrict
             vC[q] = fmaf(T, c, vC[q]);
           }
         }
-        if constexpr (DC && ROW) dcrow[q][b] = T;
+        if constexpr (DC && ROW) dcrow[q][b] = RED ? (float)g.K * T : T;
         if constexpr (GRAD) {
 #pragma unroll
           for (int d = 0; d < DIM; ++d) gacc[q][d] = fmaf(T, df[d], gacc[q][d]);
@@ -280,7 +283,8 @@ __global__ void __launch_bounds__(kPassThreads)
         if constexpr (ROW) {
           if (out.dC && a0 + q < own_count) {
             if constexpr (RED) {
-              if (ab[q] == 0) out.dC[((int64_t)kk[q] * g.m + ai[q]) * g.m + b] = T;
+              if (ab[q] == 0)
+                out.dC[(int64_t)ai[q] * out.lddc + (int64_t)kk[q] * g.m + b] = (float)g.K * T;
             } else {
               out.dC[(int64_t)(a0 + q) * out.lddc + B] = T;
             }
@@ -336,6 +340,174 @@ __global__ void __launch_bounds__(kPassThreads)
       out.part[3 * blockIdx.x + 1] = bc;
       out.part[3 * blockIdx.x + 2] = bm;
     }
+  }
+}
+
+// ---- reduced potentials with coordinates: one exponential per (i, j, k) ------------------
+// The expanded plan has K m^2 distinct entries T_ijk (Lemma 1), so each is evaluated once per
+// pass.  Workgroup o < m is the row pass for block-0 row i = o: every lane takes partners j,
+// loads y_{c m + j} for all blocks c, evaluates T_ijk for all k (cost of block-row 0,
+// |x_i - y_{k m + j}|^2) and accumulates the row sum S_i, P and <C, T> from them, stores dC,
+// and forms in float64
+//   Y_i(r) = sum_{k, j} T_ijk y_{((r + k) mod K) m + j},   dx_{r m + i} = 2 (x_{r m + i} S_i - Y_i(r)),
+// the gradient of every block's copy of row i (T[r m + i, c m + j] = T_{ij,(c-r) mod K}).
+// Workgroup m + o is the column pass for column j = o: partners i, T_ijk for all k from
+// x_i and the own y_{k m + j}, the column sum S'_j and
+//   X_j(c) = sum_{k, i} T_ijk x_{((c - k) mod K) m + i},   dy_{c m + j} = 2 (y_{c m + j} S'_j - X_j(c)).
+// The K^2 products per partner are float64 FMAs of the float32 plan entries and coordinates
+// (exact products), and S is summed in float64, so x S - Y keeps full accuracy despite the
+// cancellation: the result is the gradient of the float32-rounded plan.
+constexpr int kAdjThreads = 256;
+constexpr int kAdjWaves = kAdjThreads / kWave;
+
+// K values the adjoint kernel is instantiated for (its K dim float64 sums and K plan entries
+// per partner stay in registers up to K = 16); others use pass_kernel.
+__host__ __device__ constexpr bool adj_supported(int K, int dim) {
+  return (dim == 2 || dim == 3) && (K == 1 || K == 2 || K == 4 || K == 8 || K == 16);
+}
+
+struct AdjOut {
+  double* rowsum;  // [m] block-0 row sums
+  double* colsum;  // [m] block-0 column sums
+  double* part;    // [m][3] P, <C,T>, mass of each block-0 row
+  float* dx;       // [n, DIM] or nullptr
+  float* dy;       // [n, DIM] or nullptr
+  float* dC;       // [m, lddc]: dC[i, k m + j] = K T_ijk, or nullptr
+  int64_t lddc;
+};
+
+template <int DIM, int KT, bool ROW, int NV>
+__device__ __forceinline__ void adj_accumulate(const float (&pt)[KT][DIM], const double (&T64)[KT],
+                                               double (&acc)[NV]) {
+#pragma unroll
+  for (int a = 0; a < KT; ++a) {
+    double pv[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) pv[d] = (double)pt[a][d];
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+      const int t = ROW ? (a - k + KT) % KT : (a + k) % KT;  // output block
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) acc[t * DIM + d] = fma(T64[k], pv[d], acc[t * DIM + d]);
+    }
+  }
+}
+
+template <int DIM, int KT, bool ROW>
+__global__ void __launch_bounds__(kAdjThreads)
+    red_adjoint_kernel(Geom g, const float* __restrict__ f, const float* __restrict__ gp,
+                       float s2, float eps, AdjOut out) {
+  constexpr int NA = KT * DIM;               // gradient sums per own point: (block, component)
+  constexpr int SH = ilog2_ceil(NA);         // reduce-scatter over 2^SH values
+  constexpr int NV = 1 << SH;
+  __shared__ double sh_acc[kAdjWaves][NV];
+  __shared__ double sh_s[kAdjWaves][3];
+  __shared__ float own_pts[ROW ? 1 : KT][DIM];  // column pass: y_{k m + j} of the own column
+  const int m = g.m;
+  const int o = blockIdx.x;  // own point of block 0: row i (ROW) or column j
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  float* __restrict__ grad_out = ROW ? out.dx : out.dy;
+  const bool grad = grad_out != nullptr;
+  const bool dc = ROW && out.dC != nullptr;
+  const float* __restrict__ x = g.x;
+  const float* __restrict__ y = g.y;
+
+  float xo[DIM];  // row pass: x_i (block 0)
+  if constexpr (ROW) {
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) xo[d] = x[(int64_t)o * DIM + d];
+  } else {
+    if (threadIdx.x < NA) {
+      const int k = threadIdx.x / DIM, d = threadIdx.x - k * DIM;
+      own_pts[k][d] = y[((int64_t)k * m + o) * DIM + d];
+    }
+    __syncthreads();
+  }
+  const float po = ROW ? f[o] : gp[o];
+
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  double S = 0.0;
+  float vP = 0.0f, vC = 0.0f;
+
+#pragma unroll 1
+  for (int p = threadIdx.x; p < m; p += kAdjThreads) {
+    // the partner's coordinates in every block: row pass y_{c m + j}, column pass x_{r m + i}
+    float pt[KT][DIM];
+    const float* __restrict__ src = ROW ? y : x;
+#pragma unroll
+    for (int c = 0; c < KT; ++c)
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) pt[c][d] = src[((int64_t)c * m + p) * DIM + d];
+    const float fg = po + (ROW ? gp[p] : f[p]);
+    double T64[KT];
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+      // block-row 0 cost |x_i - y_{k m + j}|^2: row pass x_i own, y_{k m + j} = pt[k];
+      // column pass x_i = pt[0], y_{k m + j} own
+      float c = 0.0f;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const float e = ROW ? xo[d] - pt[k][d] : pt[0][d] - own_pts[ROW ? 0 : k][d];
+        c = fmaf(e, e, c);
+      }
+      const float T = exp2_fast((fg - c) * s2);
+      T64[k] = (double)T;
+      S += T64[k];
+      if constexpr (ROW) {
+        vP = fmaf(T, fg - eps, vP);  // T (C + eps (Z - 1)) = T (f + g - eps)
+        vC = fmaf(T, c, vC);
+        if (dc) out.dC[(int64_t)o * out.lddc + (int64_t)k * m + p] = (float)g.K * T;
+      }
+    }
+    // row: Y(r) += T_k y_{((r + k) mod K)}: pt[a] (block a = r + k) feeds output r = a - k;
+    // column: X(c) += T_k x_{((c - k) mod K)}: pt[a] (block a = c - k) feeds output c = a + k
+    if (grad) adj_accumulate<DIM, KT, ROW>(pt, T64, acc);
+  }
+
+  // sums of the own point: S (and, rows, P and <C,T>) over all lanes, then the waves in a
+  // fixed order
+  {
+    const double s_all = wave_sum_all_d(S);
+    const double p_all = ROW ? wave_sum_all_d((double)vP) : 0.0;
+    const double c_all = ROW ? wave_sum_all_d((double)vC) : 0.0;
+    if (lane == 0) {
+      sh_s[wv][0] = s_all;
+      sh_s[wv][1] = p_all;
+      sh_s[wv][2] = c_all;
+    }
+  }
+  if (grad) {
+    wave_reduce_scatter_d<SH>(acc, lane);
+    if ((lane & ((64 >> SH) - 1)) == 0) sh_acc[wv][lane >> (6 - SH)] = acc[0];
+  }
+  __syncthreads();
+  double tot[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int w = 0; w < kAdjWaves; ++w) {
+    tot[0] += sh_s[w][0];
+    tot[1] += sh_s[w][1];
+    tot[2] += sh_s[w][2];
+  }
+  if (threadIdx.x == 0) {
+    if constexpr (ROW) {
+      out.rowsum[o] = tot[0];
+      out.part[3 * o + 0] = tot[1];
+      out.part[3 * o + 1] = tot[2];
+      out.part[3 * o + 2] = tot[0];
+    } else {
+      out.colsum[o] = tot[0];
+    }
+  }
+  if (grad && threadIdx.x < NA) {
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < kAdjWaves; ++w) v += sh_acc[w][threadIdx.x];
+    const int blk = threadIdx.x / DIM, d = threadIdx.x - blk * DIM;
+    const int64_t P = (int64_t)blk * m + o;  // the own point's copy in block blk
+    const double own = (double)(ROW ? x : y)[P * DIM + d];
+    grad_out[P * DIM + d] = (float)(2.0 * (own * tot[0] - v));
   }
 }
 
@@ -491,7 +663,29 @@ static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 static int pass_blocks(int count) { return (count + kPassPts - 1) / kPassPts; }
 
 size_t costgrad_ws_bytes(const Geom& g) {
-  return 2 * align256(sizeof(double) * g.n) + align256(sizeof(double) * 3 * pass_blocks(g.n));
+  // row / column sums [n] each, then the per-workgroup partials: pass_blocks(n) groups of the
+  // pass kernels or m rows of the adjoint kernel
+  const int nparts = pass_blocks(g.n) > g.n / g.K ? pass_blocks(g.n) : g.n / g.K;
+  return 2 * align256(sizeof(double) * g.n) + align256(sizeof(double) * 3 * (size_t)nparts);
+}
+
+template <int DIM>
+static hipError_t launch_adjoint(const Geom& g, const float* f, const float* gp, float s2,
+                                 float eps, const AdjOut& o, hipStream_t s) {
+  const dim3 grid(g.m), blk(kAdjThreads);
+#define CSOT_ADJ(KT)                                                                          \
+  hipLaunchKernelGGL((red_adjoint_kernel<DIM, KT, true>), grid, blk, 0, s, g, f, gp, s2, eps, o); \
+  hipLaunchKernelGGL((red_adjoint_kernel<DIM, KT, false>), grid, blk, 0, s, g, f, gp, s2, eps, o)
+  switch (g.K) {
+    case 1: CSOT_ADJ(1); break;
+    case 2: CSOT_ADJ(2); break;
+    case 4: CSOT_ADJ(4); break;
+    case 8: CSOT_ADJ(8); break;
+    case 16: CSOT_ADJ(16); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef CSOT_ADJ
+  return hipGetLastError();
 }
 
 template <int DIM>
@@ -521,16 +715,25 @@ hipError_t launch_cost_and_grad(const Geom& g, const float* f, const float* gp, 
   double* part = reinterpret_cast<double*>(base + 2 * align256(sizeof(double) * g.n));
   // Reduced potentials: the values and marginal sums come from block 0's points only (K m^2
   // terms, scaled by K); the coordinate gradients need every point (n^2 terms).
+  const float s2 = (float)(kLog2eD / g.eps);
+  const float eps = (float)g.eps;
+  const double scale = reduced ? (double)g.K : 1.0;
+  hipError_t e;
+  if (reduced && adj_supported(g.K, g.dim)) {
+    AdjOut ao{rowsum, colsum, part, dx, dy, dC, lddc};
+    e = g.dim == 2 ? launch_adjoint<2>(g, f, gp, s2, eps, ao, s)
+                   : launch_adjoint<3>(g, f, gp, s2, eps, ao, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kFinThreads), 0, s, g, reduced, scale, f,
+                       gp, part, g.m, rowsum, colsum, out, da, db);
+    return hipGetLastError();
+  }
   const bool all_rows = !reduced || dx != nullptr;
   const bool all_cols = !reduced || dy != nullptr;
   const int rows = all_rows ? g.n : g.m;
   const int cols = all_cols ? g.n : g.m;
-  const double scale = reduced ? (double)g.K : 1.0;
   PassOut ro{rowsum, part, dx, dC, lddc};
   PassOut co{colsum, nullptr, dy, nullptr, 0};
-  const float s2 = (float)(kLog2eD / g.eps);
-  const float eps = (float)g.eps;
-  hipError_t e;
   switch (g.dim) {
     case 0: e = launch_passes<0>(g, f, gp, reduced, s2, eps, rows, cols, ro, co, s); break;
     case 2: e = launch_passes<2>(g, f, gp, reduced, s2, eps, rows, cols, ro, co, s); break;

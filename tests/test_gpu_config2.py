@@ -241,3 +241,77 @@ def test_expand(lib, cfg):
     l1, ent = _compare_plan(Tr, _plan_rows(cfg, ref["f"], ref["g"], rows))
     print(f"[config2 expand] end-to-end plan L1 {l1:.2e}, entry-wise {ent:.2e}", flush=True)
     assert l1 < REL, l1
+
+
+def _grad_ref(cfg, T, X, Y):
+    """Oracle gradient rows 2 sum_J T_IJ (x_I - y_J) of sampled points and their error scale
+    2 sum_J T_IJ |x_I - y_J| (per component), T given row by row ([rows, N]), X [rows, 2] the
+    sampled points, Y [N, 2] their partners."""
+    D = X[:, None, :] - Y[None, :, :]
+    return 2.0 * np.einsum("ij,ijd->id", T, D), 2.0 * np.einsum("ij,ijd->id", T, np.abs(D))
+
+
+def _full_plan_rows(cfg, f, g, rows):
+    """Oracle rows of the full plan T_IJ = exp((f_I + g_J - C_IJ) / eps) on the given float32
+    coordinates (float64 costs)."""
+    C = cost.sq_euclidean(_f64(cfg.p.x)[rows], _f64(cfg.p.y))
+    return np.exp((f[rows, None] + g[None, :] - C) / cfg.p.eps)
+
+
+def test_gradients(lib, cfg):
+    """Adjoint kernels at the benchmark's shape, both paths, on the oracle's converged
+    potentials rounded to float32: dx at 3 x 64 sampled rows and dy at 3 x 64 sampled columns
+    against the oracle's envelope gradient (2 sum_J T_IJ (x_I - y_J)) over all 8192 partners,
+    dC (reduced: block-row 0, K T_ijk) and the mean-centred da, db.  Error model: every plan
+    entry carries a float32 relative error (exponent and cost rounding), so a gradient
+    component may be off by that relative error times 2 sum_J T_IJ |x_I - y_J|; the bar is
+    2e-5 of that scale (twice the 1e-5 plan bar)."""
+    p = cfg.p
+    m = cfg.m
+    prob = _prob(lib, p)
+    ref = sinkhorn.reduced_sinkhorn(cfg.alpha, cfg.beta, cfg.logK, p.eps, K, tol=1e-6)
+    f32, g32 = ref["f"].astype(np.float32), ref["g"].astype(np.float32)
+    fh, gh = _f64(f32), _f64(g32)
+    rng = np.random.default_rng(41)
+    rows = np.concatenate([r * m + np.sort(rng.choice(m, 64, replace=False)) for r in (0, 5, 15)])
+    cols = np.concatenate([c * m + np.sort(rng.choice(m, 64, replace=False)) for c in (0, 9, 15)])
+    X, Y = _f64(p.x), _f64(p.y)
+    for path in ("reduced", "full"):
+        print(f"[config2 grad] eps={p.eps:.5g} {path}", flush=True)
+        if path == "reduced":
+            res = lib.ot_cost_and_grad(prob, _t(f32), _t(g32), True, want_dC=True, want_dxy=True,
+                                       want_dab=True)
+            Tr = _plan_rows(cfg, fh, gh, rows)
+            # columns of the expanded plan are rows of its transpose: T[r m + i, c m + j] =
+            # T_{ij,(c - r) mod K}, so column c m + j over r, i is Tk[(c - r) mod K][:, j]
+            Tk = sinkhorn.reduced_plan_blocks(fh, gh, cfg.Ck, p.eps)
+            Tc = np.empty((len(cols), N))
+            for t, J in enumerate(cols):
+                c, j = divmod(int(J), m)
+                for r in range(K):
+                    Tc[t, r * m:(r + 1) * m] = Tk[(c - r) % K][:, j]
+            fa, gb = np.tile(fh, K), np.tile(gh, K)
+        else:
+            fa, gb = np.tile(fh, K), np.tile(gh, K)
+            res = lib.ot_cost_and_grad(prob, _t(fa.astype(np.float32)), _t(gb.astype(np.float32)),
+                                       False, want_dxy=True, want_dab=True)
+            Tr = _full_plan_rows(cfg, fa, gb, rows)
+            C = cost.sq_euclidean(X, Y[cols])
+            Tc = np.exp((fa[:, None] + gb[None, cols] - C) / p.eps).T
+        torch.cuda.synchronize()
+        dx_want, dx_scale = _grad_ref(cfg, Tr, X[rows], Y)
+        dy_want, dy_scale = _grad_ref(cfg, Tc, Y[cols], X)
+        worst = 0.0
+        for got, want, scale in ((res["dx"].cpu().numpy()[rows], dx_want, dx_scale),
+                                 (res["dy"].cpu().numpy()[cols], dy_want, dy_scale)):
+            ratio = np.abs(_f64(got) - want) / scale
+            worst = max(worst, float(ratio.max()))
+        print(f"[config2 grad] {path}: max |d grad| / (2 sum T |x - y|) = {worst:.2e}", flush=True)
+        assert worst < 2e-5, worst
+        # da, db: the potentials, tiled and mean-centred
+        for got, want in ((res["da"], fa), (res["db"], gb)):
+            assert np.abs(_f64(got.cpu()) - (want - want.mean())).max() <= 1e-6 * (1 + np.abs(want).max())
+        if path == "reduced":
+            dC = res["dC"][torch.as_tensor(rows[:64], device=DEV)].cpu().numpy()
+            want = K * np.concatenate(list(Tk), axis=1)[rows[:64]]
+            assert np.abs(_f64(dC) - want).sum() / want.sum() < REL
