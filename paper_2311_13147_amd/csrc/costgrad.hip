@@ -366,14 +366,19 @@ __host__ __device__ constexpr bool adj_supported(int K, int dim) {
   return (dim == 2 || dim == 3) && (K == 1 || K == 2 || K == 4 || K == 8 || K == 16);
 }
 
+// Per-point partials of the adjoint kernel (float64), one row of kAdjPart per block-0 index:
+// row workgroup o: P, <C,T>, mass (sum T), (rowsum - alpha)^2, f alpha; column workgroup o:
+// (colsum - beta)^2, g beta.
+constexpr int kAdjPart = 8;
+
 struct AdjOut {
-  double* rowsum;  // [m] block-0 row sums
-  double* colsum;  // [m] block-0 column sums
-  double* part;    // [m][3] P, <C,T>, mass of each block-0 row
+  double* part;    // [m][kAdjPart]
   float* dx;       // [n, DIM] or nullptr
   float* dy;       // [n, DIM] or nullptr
   float* dC;       // [m, lddc]: dC[i, k m + j] = K T_ijk, or nullptr
   int64_t lddc;
+  float* da;       // [n] or nullptr: f tiled, mean-centred
+  float* db;       // [n] or nullptr
 };
 
 template <int DIM, int KT, bool ROW, int NV>
@@ -393,18 +398,31 @@ __device__ __forceinline__ void adj_accumulate(const float (&pt)[KT][DIM], const
   }
 }
 
+// Float64 sum over the workgroup (fixed order: waves, then lanes), every thread receiving it.
+__device__ __forceinline__ double adj_block_sum(double v, double* sh) {
+  v = wave_sum_all_d(v);
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  __syncthreads();
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int w = 0; w < kAdjWaves; ++w) t += sh[w];
+  return t;
+}
+
+// One own point o of block 0: row i = o (ROW) or column j = o.
 template <int DIM, int KT, bool ROW>
-__global__ void __launch_bounds__(kAdjThreads)
-    red_adjoint_kernel(Geom g, const float* __restrict__ f, const float* __restrict__ gp,
-                       float s2, float eps, AdjOut out) {
+__device__ __forceinline__ void adj_body(const Geom& g, const float* __restrict__ f,
+                                         const float* __restrict__ gp, float s2, float eps,
+                                         const AdjOut& out, int o) {
   constexpr int NA = KT * DIM;               // gradient sums per own point: (block, component)
   constexpr int SH = ilog2_ceil(NA);         // reduce-scatter over 2^SH values
   constexpr int NV = 1 << SH;
   __shared__ double sh_acc[kAdjWaves][NV];
-  __shared__ double sh_s[kAdjWaves][3];
+  __shared__ double sh_red[kAdjWaves];
   __shared__ float own_pts[ROW ? 1 : KT][DIM];  // column pass: y_{k m + j} of the own column
   const int m = g.m;
-  const int o = blockIdx.x;  // own point of block 0: row i (ROW) or column j
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   float* __restrict__ grad_out = ROW ? out.dx : out.dy;
   const bool grad = grad_out != nullptr;
@@ -466,40 +484,39 @@ __global__ void __launch_bounds__(kAdjThreads)
     if (grad) adj_accumulate<DIM, KT, ROW>(pt, T64, acc);
   }
 
-  // sums of the own point: S (and, rows, P and <C,T>) over all lanes, then the waves in a
-  // fixed order
-  {
-    const double s_all = wave_sum_all_d(S);
-    const double p_all = ROW ? wave_sum_all_d((double)vP) : 0.0;
-    const double c_all = ROW ? wave_sum_all_d((double)vC) : 0.0;
-    if (lane == 0) {
-      sh_s[wv][0] = s_all;
-      sh_s[wv][1] = p_all;
-      sh_s[wv][2] = c_all;
-    }
-  }
+  // the own point's folded marginal (mean over the K blocks) and the potential's mean (for
+  // da / db), both summed by every workgroup in the same order
+  const float* __restrict__ marg = ROW ? g.a : g.b;
+  const float* __restrict__ pot = ROW ? f : gp;
+  double mv = threadIdx.x < KT ? (double)marg[(int64_t)threadIdx.x * m + o] : 0.0;
+  double ps = 0.0;
+  for (int p = threadIdx.x; p < m; p += kAdjThreads) ps += (double)pot[p];
+  const double tS = adj_block_sum(S, sh_red);
+  const double tP = ROW ? adj_block_sum((double)vP, sh_red) : 0.0;
+  const double tC = ROW ? adj_block_sum((double)vC, sh_red) : 0.0;
+  const double marg_o = adj_block_sum(mv, sh_red) / KT;
+  const double pmean = adj_block_sum(ps, sh_red) / m;
   if (grad) {
     wave_reduce_scatter_d<SH>(acc, lane);
     if ((lane & ((64 >> SH) - 1)) == 0) sh_acc[wv][lane >> (6 - SH)] = acc[0];
   }
   __syncthreads();
-  double tot[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-  for (int w = 0; w < kAdjWaves; ++w) {
-    tot[0] += sh_s[w][0];
-    tot[1] += sh_s[w][1];
-    tot[2] += sh_s[w][2];
-  }
   if (threadIdx.x == 0) {
+    double* pr = out.part + (int64_t)o * kAdjPart;
+    const double dr = tS - marg_o;
     if constexpr (ROW) {
-      out.rowsum[o] = tot[0];
-      out.part[3 * o + 0] = tot[1];
-      out.part[3 * o + 1] = tot[2];
-      out.part[3 * o + 2] = tot[0];
+      pr[0] = tP;
+      pr[1] = tC;
+      pr[2] = tS;
+      pr[3] = dr * dr;
+      pr[4] = (double)po * marg_o;
     } else {
-      out.colsum[o] = tot[0];
+      pr[5] = dr * dr;
+      pr[6] = (double)po * marg_o;
     }
   }
+  float* __restrict__ dpot = ROW ? out.da : out.db;
+  if (dpot && threadIdx.x < KT) dpot[(int64_t)threadIdx.x * m + o] = (float)((double)po - pmean);
   if (grad && threadIdx.x < NA) {
     double v = 0.0;
 #pragma unroll
@@ -507,7 +524,43 @@ __global__ void __launch_bounds__(kAdjThreads)
     const int blk = threadIdx.x / DIM, d = threadIdx.x - blk * DIM;
     const int64_t P = (int64_t)blk * m + o;  // the own point's copy in block blk
     const double own = (double)(ROW ? x : y)[P * DIM + d];
-    grad_out[P * DIM + d] = (float)(2.0 * (own * tot[0] - v));
+    grad_out[P * DIM + d] = (float)(2.0 * (own * tS - v));
+  }
+}
+
+// Workgroups [0, m): rows; [m, 2 m): columns.
+template <int DIM, int KT>
+__global__ void __launch_bounds__(kAdjThreads)
+    red_adjoint_kernel(Geom g, const float* __restrict__ f, const float* __restrict__ gp,
+                       float s2, float eps, AdjOut out) {
+  const int b = blockIdx.x;
+  if (b < g.m) adj_body<DIM, KT, true>(g, f, gp, s2, eps, out, b);
+  else adj_body<DIM, KT, false>(g, f, gp, s2, eps, out, b - g.m);
+}
+
+// The scalars of the full problem from the per-point partials: P, D, <C,T>, both marginal
+// errors and the mass, each a K-multiple of the reduced sum (eq. problem_CROT).
+__global__ void __launch_bounds__(kAdjThreads)
+    red_finalize_kernel(int m, int K, double eps, const double* __restrict__ part,
+                        double* __restrict__ out) {
+  __shared__ double sh[kAdjWaves];
+  double v[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int o = threadIdx.x; o < m; o += kAdjThreads) {
+#pragma unroll
+    for (int q = 0; q < 7; ++q) v[q] += part[(int64_t)o * kAdjPart + q];
+  }
+#pragma unroll
+  for (int q = 0; q < 7; ++q) v[q] = adj_block_sum(v[q], sh);
+  if (threadIdx.x == 0) {
+    const double Kd = (double)K;
+    out[0] = Kd * v[0];
+    out[1] = Kd * (v[4] + v[6]) - eps * Kd * v[2];
+    out[2] = Kd * v[1];
+    out[3] = sqrt(Kd * v[3]);
+    out[4] = sqrt(Kd * v[5]);
+    out[5] = Kd * v[2];
+    out[6] = 0.0;
+    out[7] = 0.0;
   }
 }
 
@@ -665,17 +718,18 @@ static int pass_blocks(int count) { return (count + kPassPts - 1) / kPassPts; }
 size_t costgrad_ws_bytes(const Geom& g) {
   // row / column sums [n] each, then the per-workgroup partials: pass_blocks(n) groups of the
   // pass kernels or m rows of the adjoint kernel
-  const int nparts = pass_blocks(g.n) > g.n / g.K ? pass_blocks(g.n) : g.n / g.K;
-  return 2 * align256(sizeof(double) * g.n) + align256(sizeof(double) * 3 * (size_t)nparts);
+  const size_t parts = 3 * (size_t)pass_blocks(g.n) > (size_t)kAdjPart * (g.n / g.K)
+                           ? 3 * (size_t)pass_blocks(g.n)
+                           : (size_t)kAdjPart * (g.n / g.K);
+  return 2 * align256(sizeof(double) * g.n) + align256(sizeof(double) * parts);
 }
 
 template <int DIM>
 static hipError_t launch_adjoint(const Geom& g, const float* f, const float* gp, float s2,
                                  float eps, const AdjOut& o, hipStream_t s) {
-  const dim3 grid(g.m), blk(kAdjThreads);
-#define CSOT_ADJ(KT)                                                                          \
-  hipLaunchKernelGGL((red_adjoint_kernel<DIM, KT, true>), grid, blk, 0, s, g, f, gp, s2, eps, o); \
-  hipLaunchKernelGGL((red_adjoint_kernel<DIM, KT, false>), grid, blk, 0, s, g, f, gp, s2, eps, o)
+  const dim3 grid(2 * g.m), blk(kAdjThreads);
+#define CSOT_ADJ(KT) \
+  hipLaunchKernelGGL((red_adjoint_kernel<DIM, KT>), grid, blk, 0, s, g, f, gp, s2, eps, o)
   switch (g.K) {
     case 1: CSOT_ADJ(1); break;
     case 2: CSOT_ADJ(2); break;
@@ -720,12 +774,12 @@ hipError_t launch_cost_and_grad(const Geom& g, const float* f, const float* gp, 
   const double scale = reduced ? (double)g.K : 1.0;
   hipError_t e;
   if (reduced && adj_supported(g.K, g.dim)) {
-    AdjOut ao{rowsum, colsum, part, dx, dy, dC, lddc};
+    AdjOut ao{part, dx, dy, dC, lddc, da, db};
     e = g.dim == 2 ? launch_adjoint<2>(g, f, gp, s2, eps, ao, s)
                    : launch_adjoint<3>(g, f, gp, s2, eps, ao, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kFinThreads), 0, s, g, reduced, scale, f,
-                       gp, part, g.m, rowsum, colsum, out, da, db);
+    hipLaunchKernelGGL(red_finalize_kernel, dim3(1), dim3(kAdjThreads), 0, s, g.m, g.K, g.eps,
+                       part, out);
     return hipGetLastError();
   }
   const bool all_rows = !reduced || dx != nullptr;
