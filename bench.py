@@ -31,17 +31,19 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 N, K, DIM, SEED, EPS_FACTOR, TOL = 8192, 16, 2, 100, 0.01, 1e-6
-# Algorithmic flops per (I, J) entry of a half-step, counted on the definition of the update
-# (an fma is 2 flops, exp2 is 1): |x_I - y_J|^2 is dim subtractions, dim multiplies and dim - 1
-# adds; then the scale by log2(e)/eps, the potential, the shift, the exp2 and the accumulation
-# (dim 2: 5 + 5 = 10; dim 3: 8 + 5 = 13)
-FLOPS_PER_ENTRY = {2: 10, 3: 13}
-# fp32 vector peak without packed-FP32 instructions (this build does not emit them):
-# 256 CUs x 4 SIMDs x 16 lanes x 2 flops per FMA x 2.4 GHz.  The published 157.3 TFLOP/s
-# counts packed FMAs and is reported beside it.
-PEAK_FP32_TFLOPS = 78.6
+EPS_FACTOR_2 = 0.1  # the workload's second regulariser (time to tolerance only)
+# Algorithmic work per (I, J) entry of a full-size half-step, counted as the operation count
+# of its definition: one exponential plus the flops around it -- dim subtractions, dim
+# multiply-adds for the squared distance, the scale by 1/eps, the potential add and the
+# accumulation (dim 2: 1 + 7 = 8; dim 3: 1 + 9 = 10).  The published fp32 vector peak of
+# MI355X (157.3 TFLOP/s) counts packed FMAs as 4 flops per lane and cycle; the non-packed peak
+# (this build emits no packed FP32 instructions) and the measured issue ceiling of this exact
+# instruction mix are reported beside it.
+OPS_PER_ENTRY = {2: 8, 3: 10}
 PUBLISHED_FP32_TFLOPS = 157.3
+NON_PACKED_FP32_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
+PROFILE_SUMMARY = "profiles/sinkhorn_n8192_K16_kernel_stats.md"
 
 
 def _args():
@@ -66,6 +68,9 @@ def _args():
     ap.add_argument("--srot", action="store_true",
                     help="only the quadratically regularised problem (cyclic vs full, n=8192, "
                          "K=16)")
+    ap.add_argument("--peaks", action="store_true",
+                    help="only run the device micro-benchmarks (issue rates of fp32/fp64 FMA and "
+                         "exp2, the full-size entry mix, copy bandwidth, slot latencies) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy (the reference kernel "
                          "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE) and exit")
@@ -427,8 +432,25 @@ def _traffic(kernel_file):
         return None
 
 
+def peaks_only():
+    import paper_2311_13147_amd as csot
+    pk = csot.ot_measure_peaks()
+    print(json.dumps({"device_peaks": pk,
+                      "derived": {"fp32_fma_TFLOPs": 2 * pk["fma32_per_s"] / 1e12,
+                                  "fp64_fma_TFLOPs": 2 * pk["fma64_per_s"] / 1e12,
+                                  "exp2_T_per_s": pk["exp2_per_s"] / 1e12,
+                                  "full_entry_mix_T_per_s": pk["full_entry_mix_per_s"] / 1e12,
+                                  "copy_GBps": pk["copy_bytes_per_s"] / 1e9,
+                                  "slot_hop_us_same_xcd": pk["slot_hop_s_same_xcd"] * 1e6,
+                                  "slot_hop_us_cross_xcd": pk["slot_hop_s_cross_xcd"] * 1e6}}),
+          flush=True)
+
+
 def main():
     args = _args()
+    if args.peaks:
+        peaks_only()
+        return
     if args.copy_calibration:
         copy_calibration()
         return
@@ -520,6 +542,16 @@ def main():
         csot.ot_cost_and_grad(prob, ff3, gf3, False, want_dxy=True, want_dab=True, out=vals_fg,
                               grads=grads_fg)
 
+    # the workload's second regulariser, eps = 0.1 median(C): time to the same tolerance
+    p2 = workloads.symmetric_problem(N, K, DIM, EPS_FACTOR_2, seed=SEED)
+    prob2 = csot.Problem(T_(p2.a), T_(p2.b), p2.eps, p2.K, x=T_(p2.x), y=T_(p2.y))
+    logK2 = torch.empty((m, m), device=dev)
+    al2, be2 = torch.empty(m, device=dev), torch.empty(m, device=dev)
+    fr4, gr4 = torch.empty(m, device=dev), torch.empty(m, device=dev)
+    ff4, gf4 = torch.empty(N, device=dev), torch.empty(N, device=dev)
+    ds2 = [torch.zeros(8, dtype=torch.float64, device=dev) for _ in range(2)]
+    csot.workspace(prob2, o_tol)
+
     graphs = {}
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
@@ -538,7 +570,8 @@ def main():
 
     E = lambda: torch.cuda.Event(enable_timing=True)
     legs = ["fold", "red_solve", "expand", "red_grad", "red_fixed", "full_solve", "full_grad",
-            "full_fixed", "red_graph", "full_graph", "red_fb_graph", "full_fb_graph"]
+            "full_fixed", "red_graph", "full_graph", "red_fb_graph", "full_fb_graph",
+            "red_tol_eps2", "full_tol_eps2"]
 
     def step(record):
         ev = {k: (E(), E()) for k in legs}
@@ -569,6 +602,14 @@ def main():
         run("full_graph", graphs["full_graph"].replay)
         run("red_fb_graph", graphs["red_fb_graph"].replay)
         run("full_fb_graph", graphs["full_fb_graph"].replay)
+
+        def red_eps2():
+            csot.ot_fold_kernel(prob2, o_tol, out=(logK2, al2, be2))
+            csot.ot_sinkhorn_reduced(prob2, logK2, al2, be2, o_tol, host_stats=False,
+                                     out=(fr4, gr4), dstats=ds2[0])
+        run("red_tol_eps2", red_eps2)
+        run("full_tol_eps2", lambda: csot.ot_sinkhorn_full(prob2, o_tol, host_stats=False,
+                                                           out=(ff4, gf4), dstats=ds2[1]))
         return ev
 
     def kernel_ms():
@@ -591,6 +632,7 @@ def main():
     st = [d.cpu().tolist() for d in ds]
     it_red, it_full = int(st[0][0]), int(st[2][0])
     stg = [d.cpu().tolist() for d in ds_g]
+    st2 = [d.cpu().tolist() for d in ds2]
     # a replay must reproduce the eager solve: same iteration count, converged, same potentials
     graph_ok = (int(stg[0][0]) == it_red and int(stg[1][0]) == it_full and stg[0][1] == 1.0
                 and stg[1][1] == 1.0 and torch.equal(fr3, fr) and torch.equal(ff3, ff))
@@ -601,15 +643,56 @@ def main():
     ttt_full = ms["full_solve"]
     step_ms = wall * 1e3 / args.steps
 
-    # roofline of the dominant kernel: the full-size solver (fixed-count leg)
-    entries = 2.0 * N * N * args.fixed_full
-    achieved = entries * FLOPS_PER_ENTRY[DIM] / (kern["full_fixed"] * 1e-3) / 1e12
+    pk = csot.ot_measure_peaks()  # after the timed region
+    # roofline of the dominant kernel: the full-size solver (fixed-count leg), in the work
+    # units of its definition (OPS_PER_ENTRY per (I, J) entry of a half-step)
+    units = 2.0 * N * N * args.fixed_full
+    t_full = kern["full_fixed"] * 1e-3
+    achieved = units * OPS_PER_ENTRY[DIM] / t_full / 1e12
     roof = {"bound": "alu", "kernel": "full_solver_kernel", "achieved": round(achieved, 3),
-            "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-            "published_peak": PUBLISHED_FP32_TFLOPS,
+            "peak": PUBLISHED_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PUBLISHED_FP32_TFLOPS, 4),
             "traffic": _traffic("full.hip"),
+            "ops_per_unit": OPS_PER_ENTRY[DIM],
+            "unit_def": "one (I, J) entry of a half-step: 1 exp2 + 7 flops",
+            "units_per_launch": units,
             "kernel_ms_per_launch": round(kern["full_fixed"], 4),
-            "flops_per_launch": entries * FLOPS_PER_ENTRY[DIM]}
+            "source": PROFILE_SUMMARY,
+            "non_packed_peak": NON_PACKED_FP32_TFLOPS,
+            "frac_of_non_packed_peak": round(achieved / NON_PACKED_FP32_TFLOPS, 4),
+            # the measured issue rate of the solver's own instruction mix (ot_measure_peaks)
+            "mix_ceiling_entries_per_s": pk["full_entry_mix_per_s"],
+            "frac_of_mix_ceiling": round(units / t_full / pk["full_entry_mix_per_s"], 4)}
+    # the reduced path's kernels, each against what bounds it
+    red_iter_s = kern["red_fixed"] * 1e-3 / args.fixed_reduced
+    hop = pk["slot_hop_s_same_xcd"]
+    plan_bytes = 4.0 * N * N
+    adj_fma = 2.0 * N * N * DIM      # float64 FMAs: dx and dy of every point
+    fold_units = float(K) * m * m
+    roof_red = {
+        "solver": {"bound": "latency", "us_per_iter": round(red_iter_s * 1e6, 4),
+                   # an iteration holds two dependent exchanges of potentials between
+                   # workgroups (row -> column -> row): two slot hops at least
+                   "floor_us_per_iter": round(2 * hop * 1e6, 4),
+                   "frac": round(2 * hop / red_iter_s, 4),
+                   "slot_hop_us": round(hop * 1e6, 4)},
+        "expand": {"bound": "hbm", "unit": "GB/s",
+                   "achieved": round(plan_bytes / (ms["expand"] * 1e-3) / 1e9, 1),
+                   "peak": HBM_PEAK_GBS,
+                   "frac": round(plan_bytes / (ms["expand"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                   "measured_copy_GBps": round(pk["copy_bytes_per_s"] / 1e9, 1)},
+        "adjoint": {"bound": "alu", "unit": "fp64 FMA/s",
+                    "fp64_fma_per_call": adj_fma, "exp2_per_call": 2.0 * fold_units,
+                    "achieved": adj_fma / (ms["red_grad"] * 1e-3),
+                    "measured_fp64_fma_per_s": pk["fma64_per_s"],
+                    "frac": round(adj_fma / (ms["red_grad"] * 1e-3) / pk["fma64_per_s"], 4),
+                    "leg": "adjoint launch + finalize launch"},
+        "fold": {"bound": "alu", "unit": "TFLOP/s", "ops_per_unit": 8,
+                 "units_per_call": fold_units,
+                 "achieved": round(fold_units * 8 / (ms["fold"] * 1e-3) / 1e12, 3),
+                 "peak": PUBLISHED_FP32_TFLOPS,
+                 "frac": round(fold_units * 8 / (ms["fold"] * 1e-3) / 1e12 / PUBLISHED_FP32_TFLOPS, 4)},
+    }
     red_kernel_us = kern["red_fixed"] * 1e3 / args.fixed_reduced
 
     out = {
@@ -654,36 +737,111 @@ def main():
                       "rel_gap": abs(vr["P"] - vf["P"]) / max(abs(vf["P"]), vf["CT"])},
         "leg_ms": {k: round(v, 4) for k, v in ms.items()},
         "leg_ms_max": {k: round(max(e[k][0].elapsed_time(e[k][1]) for e in evs), 4) for k in legs},
+        "time_to_tol_ms_eps0.1": {
+            "eps": p2.eps,
+            "reduced_fold_plus_solve": round(ms["red_tol_eps2"], 4),
+            "full_solve": round(ms["full_tol_eps2"], 4),
+            "speedup_solve": round(ms["full_tol_eps2"] / ms["red_tol_eps2"], 2),
+            "iterations": {"reduced": int(st2[0][0]), "full": int(st2[1][0])},
+            "marginal_err_fp64": {"reduced_row": st2[0][2], "full_row": st2[1][2]}},
         "expand_GBps": round(4.0 * N * N / (ms["expand"] * 1e-3) / 1e9, 1),
         "roofline": roof,
+        "roofline_reduced_path": roof_red,
+        "device_peaks": pk,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, fr, gr, vr, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
+def _host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return model, os.cpu_count() or 1, usable
+
+
 def cpu_baseline(p, f_gpu, g_gpu, vr, budget_s):
-    """The float64 oracle as it stands, timed on the host: reduced cyclic Sinkhorn on the same
-    workload (a bounded number of iterations), plus the error of the GPU result against the
-    oracle's converged reduced solution."""
+    """The float64 oracle as it stands, timed on the host on bounded samples of the workload:
+    * reduced cyclic Sinkhorn (oracle.sinkhorn.reduced_sinkhorn, one thread): iterations/s --
+      the reported value;
+    * the same iteration on all usable cores (the oracle's own row and column half-steps,
+      row_update / col_update, on row / column chunks in a thread pool; NumPy releases the
+      GIL inside its array operations);
+    * full-size Sinkhorn at n = 8192 (oracle.sinkhorn.full_sinkhorn, one thread, one
+      iteration including its residual pass) and its two half-steps on all cores;
+    plus the error of the GPU result against the oracle's converged reduced solution."""
     import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
 
     from oracle import cost, objective, sinkhorn
 
+    model, nproc, usable = _host_cpu()
+    threads = max(1, min(16, usable))
     Ck = cost.blocks_from_row0(cost.row0_from_points(p.x, p.y, p.K), p.K)
     a, b = p.a.astype(np.float64), p.b.astype(np.float64)
     alpha, beta = sinkhorn.fold_marginals(a, p.K), sinkhorn.fold_marginals(b, p.K)
     t0 = time.perf_counter()
     logK = sinkhorn.fold_kernel(Ck, p.eps)
     t_fold = time.perf_counter() - t0
-    # one timed probe iteration sizes the sample to the time budget
+    # one timed probe iteration sizes the samples to the time budget
     t0 = time.perf_counter()
     sinkhorn.reduced_sinkhorn(alpha, beta, logK, p.eps, p.K, tol=0.0, max_iter=2)
     per_it = (time.perf_counter() - t0) / 2
-    iters = max(5, min(2000, int(budget_s / per_it)))
+    iters = max(5, min(2000, int(0.4 * budget_s / per_it)))
     t0 = time.perf_counter()
     sinkhorn.reduced_sinkhorn(alpha, beta, logK, p.eps, p.K, tol=0.0, max_iter=iters)
     dt = time.perf_counter() - t0
+
+    pool = ThreadPoolExecutor(max_workers=threads)
+
+    def chunks(count):
+        step = (count + threads - 1) // threads
+        return [slice(s0, min(s0 + step, count)) for s0 in range(0, count, step)]
+
+    # reduced iteration on all cores: the row update with C = -eps logK (exponent logK + g/eps)
+    Cred = -p.eps * logK
+    mm = p.m
+    rch, cch = chunks(mm), chunks(mm)
+    g = np.zeros(mm)
+    iters_mt = max(5, iters // 2)
+    t0 = time.perf_counter()
+    for _ in range(iters_mt):
+        f = np.concatenate(list(pool.map(
+            lambda sl: sinkhorn.row_update(g, Cred[sl], alpha[sl], p.eps), rch)))
+        g = np.concatenate(list(pool.map(
+            lambda sl: sinkhorn.col_update(f, Cred[:, sl], beta[sl], p.eps), cch)))
+    dt_mt = time.perf_counter() - t0
+
+    # full size: the float64 cost of the float32 coordinates, then one iteration on one thread
+    # (row and column half-steps and the residual pass) and two half-steps on all cores
+    C = cost.sq_euclidean(p.x, p.y)
+    t0 = time.perf_counter()
+    sinkhorn.full_sinkhorn(a, b, C, p.eps, tol=0.0, max_iter=1)
+    full_1t = time.perf_counter() - t0
+    n = p.n
+    rch, cch = chunks(n), chunks(n)
+    gfull = np.zeros(n)
+    t0 = time.perf_counter()
+    for _ in range(2):
+        ffull = np.concatenate(list(pool.map(
+            lambda sl: sinkhorn.row_update(gfull, C[sl], a[sl], p.eps), rch)))
+        gfull = np.concatenate(list(pool.map(
+            lambda sl: sinkhorn.col_update(ffull, C[:, sl], b[sl], p.eps), cch)))
+    full_mt = (time.perf_counter() - t0) / 2
+    pool.shutdown()
+    del C
+
     ref = sinkhorn.reduced_sinkhorn(alpha, beta, logK, p.eps, p.K, tol=TOL)
     rv = objective.reduced_values(ref["f"], ref["g"], Ck, p.eps, alpha, beta)
     P_ref = p.K * rv["P"]
@@ -694,6 +852,16 @@ def cpu_baseline(p, f_gpu, g_gpu, vr, budget_s):
     return {"value": round(iters / dt, 2), "unit": "iters/s", "cores": 1, "kind": "oracle",
             "sample": f"{iters} float64 reduced Sinkhorn iterations (m={p.m}, NumPy/SciPy "
                       f"logsumexp, one thread) after a {t_fold:.2f} s fold",
+            "host": {"cpu_model": model, "nproc": nproc, "usable_cpus": usable},
+            "reduced_all_cores": {"value": round(iters_mt / dt_mt, 2), "unit": "iters/s",
+                                  "cores": threads,
+                                  "sample": f"{iters_mt} iterations of the oracle's row and "
+                                            f"column half-steps on {threads} threads"},
+            "full_size": {"s_per_iter_one_thread": round(full_1t, 4),
+                          "s_per_iter_all_cores": round(full_mt, 4), "cores": threads,
+                          "sample": f"n={n}: one full_sinkhorn iteration on one thread (with its "
+                                    f"residual pass); two iterations of the half-steps on "
+                                    f"{threads} threads"},
             "oracle_iters_to_tol": ref["iters"],
             "gpu_vs_fp64": {"objective_rel": abs(vr["P"] - P_ref) / max(abs(P_ref), p.K * rv["CT"]),
                             "plan_l1_rel": float(np.abs(Tg - Tr).sum() / Tr.sum())}}

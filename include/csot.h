@@ -325,6 +325,25 @@ int ot_sinkhorn_reduced_batched(const ot_batch_desc* descs, int32_t count, const
                                 int32_t fold_tiles, int32_t value_tiles, const ot_opts* opts,
                                 void* ws, size_t ws_bytes, void* stream);
 
+/* Measurement, not a step of the method: the device's issue rates and latencies that the
+ * roofline figures of the kernels above are quoted against.  Runs short micro-benchmark
+ * kernels on `stream` and synchronises (not for graph capture).  out [host, OT_PEAKS_LEN]:
+ *   [0] fp32 FMA issue rate (non-packed v_fma_f32), lane operations per second;
+ *   [1] fp64 FMA issue rate;  [2] v_exp_f32 issue rate;
+ *   [3] full-size Sinkhorn entries per second of its instruction mix (2 sub, 2 fma, exp2,
+ *       add per entry on pre-scaled coordinates in registers): the ceiling of
+ *       ot_sinkhorn_full;
+ *   [4] device-to-device copy bandwidth, bytes read + written per second (256 MiB buffers);
+ *   [5] one-way latency (s) of an epoch-tagged slot between two workgroups on one XCD with
+ *       XCD-local publication (the reduced solver's exchange; NaN if a wait timed out);
+ *   [6] the same between XCDs with device-scope publication;
+ *   [7] 1 if [5] used XCD-local publication (both workgroups found on one XCD), else 0.
+ * ws: ot_peaks_workspace_bytes() bytes, 256-byte aligned.  Errors: OT_ERR_ARG,
+ * OT_ERR_WORKSPACE, OT_ERR_HIP. */
+#define OT_PEAKS_LEN 8
+size_t ot_peaks_workspace_bytes(void);
+int ot_measure_peaks(double* out, void* ws, size_t ws_bytes, void* stream);
+
 /* Message describing the last non-OK return on the calling thread ("" if none). */
 const char* ot_last_error(void);
 

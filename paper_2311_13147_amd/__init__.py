@@ -19,6 +19,7 @@ from ._binding import (  # noqa: F401
     ot_full_plan_info,
     ot_lot_expand,
     ot_lot_fold,
+    ot_measure_peaks,
     ot_reduced_plan_info,
     ot_sinkhorn_full,
     ot_sinkhorn_reduced,

@@ -75,6 +75,8 @@ def _load():
         "ot_srot_workspace_bytes": (SZ, [P]),
         "ot_srot_reduced": (ctypes.c_int, [P, D, PO, VP, VP, PS, VP, SZ, VP]),
         "ot_cost_and_grad": (ctypes.c_int, [P, VP, VP, I32, VP, VP, I64, VP, VP, VP, VP, VP, SZ, VP]),
+        "ot_peaks_workspace_bytes": (SZ, []),
+        "ot_measure_peaks": (ctypes.c_int, [VP, VP, SZ, VP]),
         "ot_last_error": (ctypes.c_char_p, []),
         "ot_version": (ctypes.c_char_p, []),
     }
@@ -94,6 +96,7 @@ EXPORTED = ("ot_workspace_bytes", "ot_fold_kernel", "ot_symmetrize_cost", "ot_si
             "ot_srot_workspace_bytes", "ot_srot_reduced",
             "ot_cost_and_grad", "ot_batched_plan_len",
             "ot_batched_plan", "ot_batched_workspace_bytes", "ot_sinkhorn_reduced_batched",
+            "ot_peaks_workspace_bytes", "ot_measure_peaks",
             "ot_last_error", "ot_version")
 
 
@@ -419,6 +422,22 @@ def ot_cost_and_grad(prob: Problem, f, g, reduced: bool, want_dC=False, want_dxy
                                  _ptr(dC), lddc, _ptr(dx), _ptr(dy), _ptr(da), _ptr(db),
                                  _ptr(ws), ws.numel(), ctypes.c_void_p(st)))
     return {"values": vals, "dC": dC, "dx": dx, "dy": dy, "da": da, "db": db}
+
+
+OT_PEAKS_LEN = 8
+
+
+def ot_measure_peaks(device="cuda:0"):
+    """Micro-benchmarks of the device (synchronises) -> dict of issue rates (lane operations
+    per second), copy bandwidth (bytes/s) and slot latencies (s)."""
+    nbytes = int(_lib.ot_peaks_workspace_bytes())
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    out = (ctypes.c_double * OT_PEAKS_LEN)()
+    _check(_lib.ot_measure_peaks(out, _ptr(ws), nbytes, _stream()))
+    del ws
+    keys = ("fma32_per_s", "fma64_per_s", "exp2_per_s", "full_entry_mix_per_s", "copy_bytes_per_s",
+            "slot_hop_s_same_xcd", "slot_hop_s_cross_xcd", "same_xcd_local_publication")
+    return dict(zip(keys, list(out)))
 
 
 def values_dict(vals: torch.Tensor):

@@ -511,4 +511,15 @@ int ot_sinkhorn_reduced_batched(const ot_batch_desc* descs, int32_t count, const
   return ok();
 }
 
+size_t ot_peaks_workspace_bytes(void) { return csot::peaks_scratch_bytes(); }
+
+int ot_measure_peaks(double* out, void* ws, size_t ws_bytes, void* stream) {
+  if (!out) return fail(OT_ERR_ARG, "out must be non-NULL");
+  int rc = check_ws(ws, ws_bytes, csot::peaks_scratch_bytes());
+  if (rc) return rc;
+  hipError_t e = csot::measure_peaks(out, ws, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "peaks micro-benchmarks");
+  return ok();
+}
+
 }  // extern "C"

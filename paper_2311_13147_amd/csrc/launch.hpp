@@ -33,6 +33,11 @@ size_t srot_ws_bytes(const Geom& g);
 hipError_t run_srot(const Geom& g, double lam, double tol, int max_iter, int check_every,
                     int warm, float* w, float* z, void* ws, hipStream_t s, double* res);
 
+// ---- peaks.hip ---------------------------------------------------------------------------
+constexpr size_t kPeaksCopyBytes = 256ull << 20;  // copy benchmark: source and destination each
+size_t peaks_scratch_bytes();
+hipError_t measure_peaks(double* out, void* scratch, hipStream_t s);
+
 // ---- fold.hip ----------------------------------------------------------------------------
 hipError_t launch_fold(const Geom& g, bool fp64, float* logK, float* alpha, float* beta,
                        hipStream_t s);
