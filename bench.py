@@ -80,7 +80,8 @@ def _args():
 def batched_only(steps, warmup):
     """The batched workload: 1024 cyclic problems, m log-uniform in [32, 1024], K in
     {4, 8, 16, 32}, 2-D or 3-D, eps = 0.05 median each, tol 1e-6; fold, solve, objective
-    values and first-block gradients of all of them per call, timed with HIP events."""
+    values and the gradients (every point, both marginals) of all of them per call, timed with HIP
+    events."""
     import numpy as np
     import torch
 

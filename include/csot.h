@@ -276,11 +276,12 @@ int ot_cost_and_grad(const ot_problem* prob, const float* f, const float* g, int
  *              rows, folded marginals, then 2 mp + 64 64-bit exchange slots used when
  *              several workgroups solve the problem together);
  *   f, g [m]   out: reduced potentials (g is also the warm-start input);
- *   dx, dy [m, dim] out or NULL: gradients of the full objective w.r.t. the first block's
- *              points, dP/dx_i = 2 sum_{k,j} T_ijk (x_i - y_{km+j}) and
- *              dP/dy_j = 2 sum_{r,i} T_{ij,(K-r) mod K} (y_j - x_{rm+i}), i, j < m;
+ *   dx, dy [n, dim] out or NULL: gradients of the full objective with respect to every
+ *              point, dP/dx_I = 2 sum_J T_IJ (x_I - y_J), dP/dy_J = 2 sum_I T_IJ (y_J - x_I),
+ *              T the expanded plan (as ot_cost_and_grad with reduced potentials);
  *   out [8]    out: {P, D, <C,T>, err_row, err_col, iters, converged, flags} of the full
- *              problem, as ot_cost_and_grad and ot_stats define them. */
+ *              problem, as ot_cost_and_grad and ot_stats define them;
+ *   da, db [n] out or NULL: dP/da = f - mean(f), dP/db = g - mean(g), tiled over the blocks. */
 typedef struct ot_batch_desc {
   int32_t n, K, dim, tile_cfg;
   double eps;
@@ -294,6 +295,8 @@ typedef struct ot_batch_desc {
   float* dx;
   float* dy;
   double* out;
+  float* da;
+  float* db;
 } ot_batch_desc;
 
 /* Number of int32 entries of a batch plan for `count` problems. */
@@ -312,18 +315,20 @@ size_t ot_batched_workspace_bytes(int32_t count);
 
 /* Many independent cyclic problems of uneven size (the reduced path of Alg. 2 for each):
  * fold, cyclic Sinkhorn to tol (each problem stops on its own), objective values, float64
- * marginal errors and first-block gradients.  Launches on `stream`: two small clearing
- * kernels (queue and accumulators), a tiled fold, ONE persistent solve launch (one workgroup per CU, all resident) whose workgroups pop tasks --
- * a whole small problem or one member's share of a large one -- from a device work queue, a
- * tiled value/gradient kernel and a per-problem finalize.  No host synchronisation, memset or
- * allocation, so the call can be captured in a HIP graph.  `plan` is the device copy of
- * ot_batched_plan's output for the same descriptors; fold_tiles and value_tiles are its first
- * two entries (plan[0], plan[1]), passed by value so that no device read is needed.  opts:
- * tol, max_iter, fold_fp64, warm_start and timing_events are honoured.
- * Errors: OT_ERR_ARG, OT_ERR_WORKSPACE, OT_ERR_HIP. */
+ * marginal errors and the gradients of every point (those outputs a descriptor leaves NULL
+ * are skipped).  Launches on `stream`: two small clearing kernels (queue and accumulators), a
+ * tiled fold, ONE persistent solve launch (one workgroup per CU, all resident) whose
+ * workgroups pop tasks -- a whole small problem or one member's share of a large one -- from a
+ * device work queue, one value/gradient launch per (dim, K) class of the batch (tiles of four
+ * block-0 points; every plan entry T_ijk evaluated once per pass, the gradients of all K
+ * copies of a point from float64 sums over the blocks) and a per-problem finalize.  No host
+ * synchronisation, memset or allocation, so the call can be captured in a HIP graph.  `plan`
+ * is the device copy of ot_batched_plan's output for the same descriptors and `plan_host`
+ * [host] that output itself (launch sizes are read from it).  opts: tol, max_iter, fold_fp64,
+ * warm_start and timing_events are honoured.  Errors: OT_ERR_ARG, OT_ERR_WORKSPACE, OT_ERR_HIP. */
 int ot_sinkhorn_reduced_batched(const ot_batch_desc* descs, int32_t count, const int32_t* plan,
-                                int32_t fold_tiles, int32_t value_tiles, const ot_opts* opts,
-                                void* ws, size_t ws_bytes, void* stream);
+                                const int32_t* plan_host, const ot_opts* opts, void* ws,
+                                size_t ws_bytes, void* stream);
 
 /* Measurement, not a step of the method: the device's issue rates and latencies that the
  * roofline figures of the kernels above are quoted against.  Runs short micro-benchmark

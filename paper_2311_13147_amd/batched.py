@@ -27,7 +27,7 @@ class BatchDesc(ctypes.Structure):
                 ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("a", ctypes.c_void_p),
                 ("b", ctypes.c_void_p), ("logK", ctypes.c_void_p), ("f", ctypes.c_void_p),
                 ("g", ctypes.c_void_p), ("dx", ctypes.c_void_p), ("dy", ctypes.c_void_p),
-                ("out", ctypes.c_void_p)]
+                ("out", ctypes.c_void_p), ("da", ctypes.c_void_p), ("db", ctypes.c_void_p)]
 
 
 def _setup_lib():
@@ -41,9 +41,8 @@ def _setup_lib():
     lib.ot_batched_workspace_bytes.argtypes = [ctypes.c_int32]
     lib.ot_sinkhorn_reduced_batched.restype = ctypes.c_int
     lib.ot_sinkhorn_reduced_batched.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
-                                                ctypes.c_int32, ctypes.c_int32,
-                                                ctypes.POINTER(B.OtOpts), ctypes.c_void_p,
-                                                ctypes.c_size_t, ctypes.c_void_p]
+                                                ctypes.c_void_p, ctypes.POINTER(B.OtOpts),
+                                                ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
     return lib
 
 
@@ -78,8 +77,9 @@ class Batch:
     """A batch of cyclic problems resident on `device`.
 
     problems: sequence of dicts with float32 numpy arrays x, y ([n, dim]), a, b ([n]) and
-    scalars eps, K.  Outputs after `run()`: f(p), g(p) ([m]), dx(p), dy(p) ([m, dim]),
-    values(p) -> {P, D, CT, err_row, err_col, iters, converged, flags}."""
+    scalars eps, K.  Outputs after `run()`: f(p), g(p) ([m]), dx(p), dy(p) ([n, dim]: every
+    point), da(p), db(p) ([n]), values(p) -> {P, D, CT, err_row, err_col, iters, converged,
+    flags}."""
 
     def __init__(self, problems: Sequence[dict], device="cuda:0", want_grad=True,
                  tile_cfg: Optional[Sequence[int]] = None, tuning: Optional[dict] = None):
@@ -102,7 +102,7 @@ class Batch:
         # 64-bit words); each problem's scratch starts 16-byte aligned
         osc = off([scratch_floats(m) for m in ms])
         ofg = off(ms)
-        ogr = off([m * d for m, d in zip(ms, dims)])
+        ogr = off([n * d for n, d in zip(ns, dims)])
         f32 = dict(dtype=torch.float32, device=dev)
         X = np.concatenate([np.ascontiguousarray(p["x"], np.float32).ravel() for p in problems])
         Y = np.concatenate([np.ascontiguousarray(p["y"], np.float32).ravel() for p in problems])
@@ -115,6 +115,8 @@ class Batch:
         self.G = torch.zeros(int(ofg[-1]), **f32)
         self.DX = torch.empty(int(ogr[-1]), **f32) if want_grad else None
         self.DY = torch.empty(int(ogr[-1]), **f32) if want_grad else None
+        self.DA = torch.empty(int(oab[-1]), **f32) if want_grad else None
+        self.DB = torch.empty(int(oab[-1]), **f32) if want_grad else None
         self.OUT = torch.zeros((self.count, 8), dtype=torch.float64, device=dev)
         self._off = dict(xy=oxy, ab=oab, fg=ofg, gr=ogr)
         descs = (BatchDesc * self.count)()
@@ -134,6 +136,8 @@ class Batch:
             d.dx = (self.DX.data_ptr() + e4 * int(ogr[p])) if want_grad else None
             d.dy = (self.DY.data_ptr() + e4 * int(ogr[p])) if want_grad else None
             d.out = self.OUT.data_ptr() + e8 * 8 * p
+            d.da = (self.DA.data_ptr() + e4 * int(oab[p])) if want_grad else None
+            d.db = (self.DB.data_ptr() + e4 * int(oab[p])) if want_grad else None
         self.host_descs = descs
         raw = bytes(descs)
         self.D = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(dev)
@@ -151,7 +155,7 @@ class Batch:
         opts = opts or B.make_opts()
         rc = _lib.ot_sinkhorn_reduced_batched(
             ctypes.c_void_p(self.D.data_ptr()), self.count, ctypes.c_void_p(self.PLAN.data_ptr()),
-            int(self.plan_host[0]), int(self.plan_host[1]), ctypes.byref(opts),
+            ctypes.c_void_p(self.plan_host.ctypes.data), ctypes.byref(opts),
             ctypes.c_void_p(self.WS.data_ptr()), self.WS.numel(),
             ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
         B._check(rc)
@@ -181,11 +185,19 @@ class Batch:
 
     def dx(self, p):
         o = self._off["gr"]
-        return self.DX[int(o[p]):int(o[p + 1])].view(self.ms[p], self.dims[p])
+        return self.DX[int(o[p]):int(o[p + 1])].view(self.ns[p], self.dims[p])
 
     def dy(self, p):
         o = self._off["gr"]
-        return self.DY[int(o[p]):int(o[p + 1])].view(self.ms[p], self.dims[p])
+        return self.DY[int(o[p]):int(o[p + 1])].view(self.ns[p], self.dims[p])
+
+    def da(self, p):
+        o = self._off["ab"]
+        return self.DA[int(o[p]):int(o[p + 1])]
+
+    def db(self, p):
+        o = self._off["ab"]
+        return self.DB[int(o[p]):int(o[p + 1])]
 
     def values(self, p):
         v = self.OUT[p].detach().cpu().tolist()

@@ -494,17 +494,17 @@ size_t ot_batched_workspace_bytes(int32_t count) {
 }
 
 int ot_sinkhorn_reduced_batched(const ot_batch_desc* descs, int32_t count, const int32_t* plan,
-                                int32_t fold_tiles, int32_t value_tiles, const ot_opts* opts,
-                                void* ws, size_t ws_bytes, void* stream) {
-  if (!descs || !plan || count <= 0) return fail(OT_ERR_ARG, "descriptors, plan and count > 0 required");
+                                const int32_t* plan_host, const ot_opts* opts, void* ws,
+                                size_t ws_bytes, void* stream) {
+  if (!descs || !plan || !plan_host || count <= 0)
+    return fail(OT_ERR_ARG, "descriptors, plan, plan_host and count > 0 required");
   ot_opts o = opts ? *opts : defaults();
   int rc = check_opts(o);
   if (rc) return rc;
   if ((rc = check_ws(ws, ws_bytes, csot::batched_ws_bytes(count)))) return rc;
-  const int nfold = fold_tiles, nval = value_tiles;
-  if (nfold < count || nval < 2 * count)
-    return fail(OT_ERR_ARG, "fold_tiles / value_tiles must be plan[0] / plan[1]");
-  hipError_t e = csot::launch_batched(descs, count, plan, nfold, nval, o.tol, o.max_iter,
+  if (plan_host[2] != count || plan_host[0] < count || plan_host[1] < 2 * count)
+    return fail(OT_ERR_ARG, "plan_host is not ot_batched_plan's output for %d problems", count);
+  hipError_t e = csot::launch_batched(descs, count, plan, plan_host, o.tol, o.max_iter,
                                       o.fold_fp64, o.warm_start, ws, static_cast<hipStream_t>(stream),
                                       static_cast<hipEvent_t*>(o.timing_events));
   if (e != hipSuccess) return hip_fail(e, "batched launch");

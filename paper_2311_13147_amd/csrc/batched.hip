@@ -6,16 +6,16 @@
 //   2. solve  : ONE persistent launch; each workgroup pops the next problem from a device work
 //               queue (largest first) and runs the cyclic Sinkhorn loop of Alg. 2 on it alone,
 //               synchronising only within the workgroup; logK stays in LDS when it fits;
-//   3. values : tiles of 16 rows (or columns) of one problem -> objective terms, gradients of
-//               the first block's points, float64 marginal sums;
+//   3. values : tiles of 4 rows (or columns) of block 0 of one problem, one wave per point ->
+//               objective terms, marginal sums and the gradients of every point;
 //   4. finalize per problem: P, D, <C,T>, errors.
 //
-// Per problem the cost is block-row 0's: C_ijk = |x_i - y_{k m + j}|^2.  Gradients are with
-// respect to the first block's points (x_i, y_j for i, j < m) of the full problem:
-//   dx_i = 2 sum_{k,j} T_ijk (x_i - y_{k m + j}),
-//   dy_j = 2 sum_{r,i} T_{i j ((K - r) mod K)} (y_j - x_{r m + i}),
-// exactly the first m rows of the single-problem gradients (the other blocks' rows follow
-// from the cyclic symmetry of the data).
+// Per problem the cost is block-row 0's: C_ijk = |x_i - y_{k m + j}|^2.  The gradients are
+// those of the full problem's objective with respect to all n points and both marginals (the
+// envelope gradients of the single-problem ot_cost_and_grad):
+//   dx_I = 2 sum_J T_IJ (x_I - y_J),  dy_J = 2 sum_I T_IJ (y_J - x_I),
+//   da = f - mean(f), db = g - mean(g) (tiled),
+// with T the expanded plan T[r m + i, c m + j] = T_{ij,(c-r) mod K} (Lemma 1).
 #include <algorithm>
 #include <vector>
 
@@ -648,191 +648,288 @@ __global__ void __launch_bounds__(kBSolveThreads) batched_solve_kernel(BSolveArg
   }
 }
 
-// ---- 3. values, gradients and float64 marginal sums ----------------------------------------
-// Tiles [0, nrow) of a problem are row tiles, [nrow, 2 nrow) column tiles (16 points each: a
-// wave owns 4 points and its lanes stride over the partner points, so one partner load feeds
-// four entries).
+// ---- 3. values and gradients of every point ------------------------------------------------
+// One wave per own point of block 0 (row i or column j), four per workgroup; tiles
+// [0, ceil(m / 4)) of a problem are row tiles, the next as many column tiles.  As in the
+// single-problem adjoint, every plan entry T_ijk is evaluated once per pass (lanes stride over
+// the partners, all K shifts per partner) and the gradients of all K copies of the own point
+// come from float64 circular sums over the blocks:
+//   row i   : Y(r) = sum_{k,j} T_ijk y_{((r + k) mod K) m + j},  dx_{r m + i} = 2 (x_{r m + i} S_i - Y(r));
+//   column j: X(c) = sum_{k,i} T_ijk x_{((c - k) mod K) m + i},  dy_{c m + j} = 2 (y_{c m + j} S'_j - X(c)).
+// Above 8 output blocks (16 in 2-D) the sums run in groups of blocks, the partner loop once
+// per group (AdjShape): for each shift k the plan entry is evaluated and multiplied into a
+// window of the partner's copies that slides by one block per shift.  K not in
+// {1, 2, 4, 8, 16, 32} takes a generic loop that re-evaluates the plan entries per output
+// block.
 // acc[p]: {P, <C,T>, mass, sum (rowsum - alpha)^2, sum (colsum - beta)^2, <f,alpha>, <g,beta>}
-constexpr int kVChunk = 1024;  // partner points staged in LDS at a time (4 per thread)
+constexpr int kAdjPts = 4;  // own points (waves) per workgroup
 
-template <int DIM, bool ROW>
-__device__ void values_tile(const ot_batch_desc& d, int a0, double* __restrict__ acc,
-                           float4* __restrict__ sP, float4* __restrict__ sC) {
-  constexpr int Q = 4;
-  const int m = bm(d), K = d.K, mp = bmp(m);
-  const float* L = d.logK;
-  const float* LT = L + (size_t)m * mp;
-  const float* al = LT + (size_t)m * mp;
-  const float* be = al + m;
+constexpr int kAdjChunk = 64;  // partners staged in LDS at a time (one per lane)
+
+struct BAdjShared {
+  float own_y[kAdjPts][32 * 3];       // column pass: y_{k m + j} of each wave's own column
+  double vals[kAdjPts][8];
+  float pts[32 * 3 * kAdjChunk];      // partner chunk: copy in block c, component d, partner
+                                      // q at (c DIM + d) kAdjChunk + q
+  float pot[kAdjChunk];               // the partners' potentials
+};
+
+// Output blocks per group for K shifts: the group's float64 sums and a window of the
+// partner's block copies stay in registers (RB dim doubles + RB dim floats).
+template <int KT, int DIM>
+struct AdjShape {
+  static constexpr int RB = KT < 8 ? KT : 8;
+  static_assert(KT % RB == 0, "groups of RB blocks");
+  static constexpr int NG = KT / RB;
+  static constexpr int NA = RB * DIM;
+  static constexpr int S = ilog2_ceil(NA);  // reduce-scatter over 2^S values
+};
+
+// Called by all four waves of the workgroup (the LDS staging needs every thread); a wave
+// whose own point lies beyond m passes active = false and only helps to stage.
+template <int DIM, int KT, bool ROW>
+__device__ void badj_point(const ot_batch_desc& d, int o, bool active, int lane,
+                           const float* own_y, double* vals, float* sh_pts, float* sh_pot) {
+  const int m = bm(d), K = d.K;
   const float s2 = (float)(kLog2eD / d.eps);
-  const double s2d = kLog2eD / d.eps;
-  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-  const int A0 = a0 + wv * Q;  // first own point of this wave (row i or column j)
-  const bool active = A0 < m;  // inactive waves still stage partners and meet the barriers
-  const float* ownp = ROW ? d.x : d.y;
-  const float* othp = ROW ? d.y : d.x;
-  int Aq[Q];
-  float po[Q][DIM], pa[Q], gacc[Q][DIM], tP[Q], tC[Q], tM[Q];
+  const float eps = (float)d.eps;
+  gcfloat* x = as_global(d.x);
+  gcfloat* y = as_global(d.y);
+  gcfloat* fpot = as_global(d.f);
+  gcfloat* gpot = as_global(d.g);
+  float* __restrict__ gout = ROW ? d.dx : d.dy;
+  const bool grad = gout != nullptr;
+  const int oc = active ? o : 0;  // an inactive wave reads a valid point and writes nothing
+  const float po = ROW ? fpot[oc] : gpot[oc];
+  float xo[DIM];
+  if constexpr (ROW) {
 #pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    Aq[q] = min(A0 + q, m - 1);
-#pragma unroll
-    for (int dd = 0; dd < DIM; ++dd) { po[q][dd] = ownp[(int64_t)Aq[q] * DIM + dd]; gacc[q][dd] = 0.0f; }
-    pa[q] = ROW ? d.f[Aq[q]] : d.g[Aq[q]];
-    tP[q] = tC[q] = tM[q] = 0.0f;
+    for (int dd = 0; dd < DIM; ++dd) xo[dd] = x[oc * DIM + dd];
   }
-  // Partner points b of a chunk are staged in LDS: sC[b] = {cost point, partner potential}
-  // once per chunk (ROW: nothing but g_b; COL: x_b of block-row 0 and f_b), sP[b] = the
-  // gradient partner of block k (ROW: y_{k m + b}; COL: x_{r m + b}, r = (K - k) mod K, whose
-  // entry with column j is T_{b j k}).
-  // potentials enter the exponent scaled to base 2: pas (own) and sC.w (partner)
-  float pas[Q];
+  gcfloat* src = ROW ? y : x;   // the partner's copies in every block
+  // 32-bit element offsets (n dim < 2^31): one register per address, the base in SGPRs
+  auto cost_T = [&](int p, int k, float fg, float& c) -> float {
+    c = 0.0f;
 #pragma unroll
-  for (int q = 0; q < Q; ++q) pas[q] = pa[q] * s2;
-  constexpr int kPre = kVChunk / 256;  // partners per thread per block (256 threads)
-  for (int c0 = 0; c0 < m; c0 += kVChunk) {
-    const int nc = min(kVChunk, m - c0);
-    __syncthreads();  // the previous chunk's readers are done
-    for (int b = threadIdx.x; b < nc; b += blockDim.x) {
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (!ROW) {
-        v.x = d.x[(int64_t)(c0 + b) * DIM];
-        v.y = d.x[(int64_t)(c0 + b) * DIM + 1];
-        if (DIM == 3) v.z = d.x[(int64_t)(c0 + b) * DIM + 2];
-      }
-      v.w = (ROW ? d.g[c0 + b] : d.f[c0 + b]) * s2;
-      sC[b] = v;
+    for (int dd = 0; dd < DIM; ++dd) {
+      // |x_i - y_{k m + j}|^2: row pass partner j = p, column pass partner i = p
+      const float e = ROW ? xo[dd] - y[(k * m + p) * DIM + dd]
+                          : x[p * DIM + dd] -
+                                (KT > 0 ? own_y[k * DIM + dd] : y[(k * m + o) * DIM + dd]);
+      c = fmaf(e, e, c);
     }
-    // the partners of block k + 1 are loaded into registers while block k is processed
-    float4 pre[kPre];
+    return exp2_fast((fg - c) * s2);
+  };
+  double S = 0.0;
+  float vP = 0.0f, vC = 0.0f;
+  if constexpr (KT > 0) {
+    using Sh = AdjShape<KT, DIM>;
+    constexpr int RB = Sh::RB, NG = Sh::NG, NV = 1 << Sh::S;
+    // output groups outermost: the plan entries of a partner are re-evaluated per group (one
+    // exponential per (i, j, k) and group), and only the group's sums live in registers
+#pragma unroll 1
+    for (int gq = 0; gq < NG; ++gq) {
+      if (gq > 0 && !grad) break;  // uniform over the workgroup (one problem)
+      // the group's first output block: it moves only the LDS addresses of the partner
+      // copies and the output rows; the ring slots are compile-time
+      const int rot = gq * RB;
+      double acc[NV];
 #pragma unroll
-    for (int u = 0; u < kPre; ++u) {
-      const int b = threadIdx.x + 256 * u;
-      const int64_t P = (int64_t)c0 + b;  // block 0 (k = 0, r = 0)
-      pre[u] = b < nc ? make_float4(othp[P * DIM], othp[P * DIM + 1], DIM == 3 ? othp[P * DIM + 2] : 0.f, 0.f)
-                      : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
-    for (int k = 0; k < K; ++k) {
-      __syncthreads();  // sP of the previous block is no longer read
+      for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+      // the workgroup's four waves (four own points of this problem and pass) share each
+      // chunk of kAdjChunk partners, staged in LDS with all K block copies
+#pragma unroll 1
+      for (int c0 = 0; c0 < m; c0 += kAdjChunk) {
+        __syncthreads();  // the previous chunk's readers are done
+        const int nc = min(kAdjChunk, m - c0);
+        for (int e = threadIdx.x; e < KT * DIM * kAdjChunk; e += blockDim.x) {
+          const int q = e % kAdjChunk, cd = e / kAdjChunk;
+          const int cb = cd / DIM, dd = cd - cb * DIM;
+          sh_pts[e] = q < nc ? src[(cb * m + c0 + q) * DIM + dd] : 0.0f;
+        }
+        if (threadIdx.x < kAdjChunk)
+          sh_pot[threadIdx.x] = (int)threadIdx.x < nc ? (ROW ? gpot : fpot)[c0 + threadIdx.x] : 0.0f;
+        __syncthreads();
+        if (!active || lane >= nc) continue;
+        const float fg = po + sh_pot[lane];
+        auto P = [&](int cb, int dd) -> float { return sh_pts[(cb * DIM + dd) * kAdjChunk + lane]; };
+        // output block r = rot + rr takes T_k pt(a) with a = r + k (row) or a = r - k
+        // (column).  The RB partner copies in use at shift k live in a ring of float64
+        // values, block a in slot (a - rot) mod RB, so an output's slot (rr + k or rr - k mod
+        // RB) is a compile-time constant and each shift replaces one slot (the copy that
+        // leaves the window) with the one that enters.
+        double ring[RB][DIM];
 #pragma unroll
-      for (int u = 0; u < kPre; ++u) {
-        const int b = threadIdx.x + 256 * u;
-        if (b < nc) sP[b] = pre[u];
-      }
-      __syncthreads();
-      if (k + 1 < K) {
-        const int kn = k + 1, rn = (K - kn) % K;
-        const int64_t pbase = (int64_t)(ROW ? kn : rn) * m + c0;
+        for (int rr = 0; rr < RB; ++rr)
 #pragma unroll
-        for (int u = 0; u < kPre; ++u) {
-          const int b = threadIdx.x + 256 * u;
-          const int64_t P = pbase + b;
-          if (b < nc)
-            pre[u] = make_float4(othp[P * DIM], othp[P * DIM + 1], DIM == 3 ? othp[P * DIM + 2] : 0.f, 0.f);
+          for (int dd = 0; dd < DIM; ++dd) ring[rr][dd] = (double)P((rot + rr) % KT, dd);
+        // shifts in rounds of RB: within a round the ring slot of every (output, shift) pair
+        // is a compile-time constant (k0 is a multiple of RB), and the rounds stay a loop so
+        // that the compiler does not schedule all K shifts' reads at once
+#pragma unroll 1
+        for (int k0 = 0; k0 < KT; k0 += RB) {
+#pragma unroll
+          for (int j = 0; j < RB; ++j) {
+            const int k = k0 + j;
+            // block-row 0 cost |x_i - y_{k m + j}|^2: row pass x_i own, y_{k m + j} the
+            // partner's copy in block k; column pass x_i the partner's copy in block 0
+            float c = 0.0f;
+#pragma unroll
+            for (int dd = 0; dd < DIM; ++dd) {
+              const float e = ROW ? xo[dd] - P(k, dd) : P(0, dd) - own_y[k * DIM + dd];
+              c = fmaf(e, e, c);
+            }
+            const float T = exp2_fast((fg - c) * s2);
+            if (gq == 0) {  // the sums once per partner
+              S += (double)T;
+              if (ROW) {
+                vP = fmaf(T, fg - eps, vP);  // T (C + eps (Z - 1)) = T (f + g - eps)
+                vC = fmaf(T, c, vC);
+              }
+            }
+            if (grad) {
+              const double T64 = (double)T;
+#pragma unroll
+              for (int rr = 0; rr < RB; ++rr) {
+                const int slot = ROW ? (rr + j) % RB : ((rr - j) % RB + RB) % RB;
+#pragma unroll
+                for (int dd = 0; dd < DIM; ++dd)
+                  acc[rr * DIM + dd] = fma(T64, ring[slot][dd], acc[rr * DIM + dd]);
+              }
+              if (k + 1 < KT) {
+                // rows: block rot + k leaves (slot k mod RB), rot + k + RB enters; columns:
+                // block rot - k + RB - 1 leaves (slot (RB - 1 - k) mod RB), rot - k - 1
+                // enters
+                const int slot = ROW ? j : ((RB - 1 - j) % RB + RB) % RB;
+                int a = ROW ? rot + RB + k : rot - k - 1 + 2 * KT;
+                a %= KT;
+#pragma unroll
+                for (int dd = 0; dd < DIM; ++dd) ring[slot][dd] = (double)P(a, dd);
+              }
+            }
+            if (j & 1) __builtin_amdgcn_sched_barrier(0);
+          }
         }
       }
-      if (!active) continue;
-      float yk[Q][DIM];  // COL: y_{k m + j} of the own columns j
-#pragma unroll
-      for (int q = 0; q < Q; ++q)
-#pragma unroll
-        for (int dd = 0; dd < DIM; ++dd) yk[q][dd] = ROW ? 0.0f : d.y[(int64_t)(k * m + Aq[q]) * DIM + dd];
-      for (int b = lane; b < nc; b += kWave) {
-        const float4 P4 = sP[b];
-        const float4 C4 = sC[b];
-        const float pp[3] = {P4.x, P4.y, P4.z};
-        // ROW: the cost uses the partner itself; COL: block-row 0's row point x_b
-        const float cb[3] = {ROW ? P4.x : C4.x, ROW ? P4.y : C4.y, ROW ? P4.z : C4.z};
-        const float obs = C4.w;
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-          float c = 0.0f;
-#pragma unroll
-          for (int dd = 0; dd < DIM; ++dd) {
-            // ROW: C_{i, b, k} = |x_i - y_{k m + b}|^2; COL: C_{b, j, k} = |x_b - y_{k m + j}|^2
-            const float df = ROW ? po[q][dd] - cb[dd] : cb[dd] - yk[q][dd];
-            c = fmaf(df, df, c);
+      if (gq == 0) S = wave_sum_all_d(S);
+      if (grad && active) {
+        wave_reduce_scatter_d<Sh::S>(acc, lane);
+        const int idx = lane >> (6 - Sh::S);
+        if ((lane & ((64 >> Sh::S) - 1)) == 0 && idx < Sh::NA) {
+          const int r = rot + idx / DIM, dd = idx % DIM;
+          const int Pi = r * m + o;
+          const double own = (double)(ROW ? x : y)[Pi * DIM + dd];
+          gout[Pi * DIM + dd] = (float)(2.0 * (own * S - acc[0]));
+        }
+      }
+    }
+  } else {
+    // generic K: output block r at a time, the plan entries re-evaluated per block
+    if (!active) return;
+#pragma unroll 1
+    for (int r = 0; r < (grad ? K : 1); ++r) {
+      double a4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+      for (int p = lane; p < m; p += kWave) {
+        const float fg = po + (ROW ? gpot[p] : fpot[p]);
+#pragma unroll 1
+        for (int k = 0; k < K; ++k) {
+          float c;
+          const float T = cost_T(p, k, fg, c);
+          if (r == 0) {
+            S += (double)T;
+            if (ROW) {
+              vP = fmaf(T, fg - eps, vP);
+              vC = fmaf(T, c, vC);
+            }
           }
-          const float T = exp2_fast(fmaf(-c, s2, pas[q] + obs));
+          if (grad) {
+            const int a = ROW ? (r + k) % K : (r - k + K) % K;
 #pragma unroll
-          for (int dd = 0; dd < DIM; ++dd) gacc[q][dd] = fmaf(T, po[q][dd] - pp[dd], gacc[q][dd]);
-          if (ROW) {
-            // C + eps (Z - 1) = f_i + g_j - eps with Z = (f_i + g_j - C) / eps: the primal
-            // term needs only the plan's g-weighted sum (kept scaled by s2) besides its mass
-            tP[q] = fmaf(T, obs, tP[q]);
-            tC[q] = fmaf(T, c, tC[q]);
-            tM[q] += T;
+            for (int dd = 0; dd < DIM; ++dd)
+              a4[dd] = fma((double)T, (double)src[(a * m + p) * DIM + dd], a4[dd]);
           }
+        }
+      }
+      if (r == 0) S = wave_sum_all_d(S);
+      if (grad) {
+#pragma unroll
+        for (int dd = 0; dd < DIM; ++dd) {
+          const double v = wave_sum_all_d(a4[dd]);
+          const int P = r * m + o;
+          if (lane == 0)
+            gout[P * DIM + dd] = (float)(2.0 * ((double)(ROW ? x : y)[P * DIM + dd] * S - v));
         }
       }
     }
   }
   if (!active) return;
-  double vP = 0.0, vC = 0.0, vM = 0.0, v2 = 0.0, vd = 0.0;
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const bool ok = A0 + q < m;
-    // marginal sum of the own point from logK (base 2 in the scratch): float64 exponents and
-    // sums, float32 exponentials of the exponents less the own potential's part, scaled back
-    // exactly (the terms of a converged row are at most the row's marginal, far from
-    // under- or overflow after the shift)
-    const float* Lrow = (ROW ? L : LT) + (size_t)Aq[q] * mp;
-    const double own2 = (double)pa[q] * s2d;
-    const float* opot = ROW ? d.g : d.f;
-    float emax = -INFINITY;
-    for (int b = lane; b < m; b += kWave)
-      emax = fmaxf(emax, (float)((double)Lrow[b] + (double)opot[b] * s2d + own2));
-    const double sh2 = (double)wave_max_v(emax);
-    double ms = 0.0;
-    for (int b = lane; b < m; b += kWave)
-      ms += (double)exp2_fast((float)((double)Lrow[b] + (double)opot[b] * s2d + own2 - sh2));
-    ms = wave_sum_d(ms) * exp2(sh2);
-    const double target = ROW ? (double)al[Aq[q]] : (double)be[Aq[q]];
-#pragma unroll
-    for (int dd = 0; dd < DIM; ++dd) {
-      const float gsum = wave_sum(gacc[q][dd]);
-      float* dst = ROW ? d.dx : d.dy;
-      if (lane == 0 && dst && ok) dst[(int64_t)Aq[q] * DIM + dd] = 2.0f * gsum;
-    }
-    if (ROW) {
-      const double Tg = wave_sum_d((double)tP[q]) / (double)s2, C = wave_sum_d((double)tC[q]),
-                   Ms = wave_sum_d((double)tM[q]);
-      // sum_{j,k} T_ijk (f_i + g_j - eps)
-      if (ok) { vP += ((double)pa[q] - d.eps) * Ms + Tg; vC += C; vM += Ms; }
-    }
-    if (ok) {
-      v2 += (ms - target) * (ms - target);
-      vd += (double)pa[q] * target;
-    }
-  }
+  // the folded marginal of the own point and the mean of its potential (da, db)
+  double mv = 0.0, ps = 0.0;
+  gcfloat* marg_in = as_global(ROW ? d.a : d.b);
+  for (int r = lane; r < K; r += kWave) mv += (double)marg_in[r * m + o];
+  gcfloat* pot = ROW ? fpot : gpot;
+  for (int q = lane; q < m; q += kWave) ps += (double)pot[q];
+  const double marg = wave_sum_all_d(mv) / K;
+  const double pmean = wave_sum_all_d(ps) / m;
+  float* __restrict__ dpot = ROW ? d.da : d.db;
+  if (dpot)
+    for (int r = lane; r < K; r += kWave) dpot[r * m + o] = (float)((double)po - pmean);
+  const double tP = ROW ? wave_sum_all_d((double)vP) : 0.0;
+  const double tC = ROW ? wave_sum_all_d((double)vC) : 0.0;
   if (lane == 0) {
-    if (ROW) {
-      atomicAdd(&acc[0], vP);
-      atomicAdd(&acc[1], vC);
-      atomicAdd(&acc[2], vM);
-      atomicAdd(&acc[3], v2);
-      atomicAdd(&acc[5], vd);
-    } else {
-      atomicAdd(&acc[4], v2);
-      atomicAdd(&acc[6], vd);
-    }
+    const double dr = S - marg;
+    vals[0] = tP;
+    vals[1] = tC;
+    vals[2] = ROW ? S : 0.0;
+    vals[3] = dr * dr;
+    vals[4] = (double)po * marg;
   }
 }
 
+// Value tiles are grouped by (dim, K) class so that each class runs its own instantiation
+// (its own register allocation): the launch for a class covers the tiles [tile0, tile0 +
+// grid) of the problems vorder[0 .. nq), whose first tiles vstart[] increase.
+template <int DIM, int KT>
 __global__ void __launch_bounds__(256)
-    batched_values_kernel(const ot_batch_desc* __restrict__ descs, int count,
-                          const int32_t* __restrict__ tile_start, double* __restrict__ accs) {
-  const int p = find_problem(tile_start, count, blockIdx.x);
+    batched_values_kernel(const ot_batch_desc* __restrict__ descs,
+                          const int32_t* __restrict__ vorder, const int32_t* __restrict__ vstart,
+                          int nq, int tile0, double* __restrict__ accs) {
+  __shared__ BAdjShared sh;
+  const int tile = tile0 + (int)blockIdx.x;
+  const int q = find_problem(vstart, nq, tile);
+  const int p = vorder[q];
   const ot_batch_desc d = descs[p];
   const int m = bm(d);
-  const int nrow = (m + kBT - 1) / kBT;
-  const int t = blockIdx.x - tile_start[p];
+  const int nrow = (m + kAdjPts - 1) / kAdjPts;
+  const int t = tile - vstart[q];
   double* acc = accs + 8 * (size_t)p;
   const bool row = t < nrow;
-  const int a0 = (row ? t : t - nrow) * kBT;
-  __shared__ float4 sP[kVChunk], sC[kVChunk];
-  if (d.dim == 3) { if (row) values_tile<3, true>(d, a0, acc, sP, sC); else values_tile<3, false>(d, a0, acc, sP, sC); }
-  else { if (row) values_tile<2, true>(d, a0, acc, sP, sC); else values_tile<2, false>(d, a0, acc, sP, sC); }
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const int o = (row ? t : t - nrow) * kAdjPts + wv;
+  const bool active = o < m;
+  // column pass: the own column's y_{k m + j} of every block, staged per wave
+  if (KT > 0 && !row && active) {
+    for (int e = lane; e < KT * DIM; e += kWave) {
+      const int k = e / DIM, dd = e - k * DIM;
+      sh.own_y[wv][e] = d.y[(k * m + o) * DIM + dd];
+    }
+  }
+  if (lane == 0)
+    for (int v = 0; v < 8; ++v) sh.vals[wv][v] = 0.0;
+  __syncthreads();
+  if (row) badj_point<DIM, KT, true>(d, o, active, lane, sh.own_y[wv], sh.vals[wv], sh.pts, sh.pot);
+  else badj_point<DIM, KT, false>(d, o, active, lane, sh.own_y[wv], sh.vals[wv], sh.pts, sh.pot);
+  __syncthreads();
+  // the workgroup's partials: one atomic add per value
+  if (threadIdx.x < 5) {
+    const int v = threadIdx.x;
+    double sum = 0.0;
+    for (int w = 0; w < kAdjPts; ++w) sum += sh.vals[w][v];
+    // rows: P, <C,T>, mass, (rowsum - alpha)^2, <f,alpha>; columns: (colsum - beta)^2, <g,beta>
+    const int slot = row ? (v < 4 ? v : 5) : (v == 3 ? 4 : v == 4 ? 6 : -1);
+    if (slot >= 0) atomicAdd(&acc[slot], sum);
+  }
 }
 
 __global__ void batched_finalize_kernel(const ot_batch_desc* __restrict__ descs, int count,
@@ -858,7 +955,31 @@ __global__ void zero_d_words(double* p, int64_t count) {
 // ---- host ----------------------------------------------------------------------------------
 static size_t a256(size_t v) { return (v + 255) / 256 * 256; }
 
-size_t batched_plan_len(int count) { return 4 + (3 + (size_t)kMaxGangF) * (size_t)count; }
+// Value-tile classes: (dim, K) with K in {1, 2, 4, 8, 16, 32} or any other K.
+constexpr int kKClasses = 7;
+constexpr int kVClasses = 2 * kKClasses;
+static int k_class(int K) {
+  switch (K) {
+    case 1: return 0;
+    case 2: return 1;
+    case 4: return 2;
+    case 8: return 3;
+    case 16: return 4;
+    case 32: return 5;
+    default: return 6;
+  }
+}
+static int v_class(int dim, int K) { return (dim == 3 ? kKClasses : 0) + k_class(K); }
+
+// plan = {nfold, nval, count, ntasks, cls_q[kVClasses + 1], cls_tile[kVClasses + 1],
+//         order[count], fold_start[count], vorder[count], vstart[count], tasks[ntasks]}:
+// problems of value class c are vorder[cls_q[c] .. cls_q[c + 1]), their value tiles
+// [cls_tile[c], cls_tile[c + 1]); vstart[q] is the first value tile of vorder[q].
+constexpr int kPlanHead = 4 + 2 * (kVClasses + 1);
+
+size_t batched_plan_len(int count) {
+  return kPlanHead + (4 + (size_t)kMaxGangF) * (size_t)count;
+}
 
 // Workgroups that solve one problem together: one up to m = 256 (logK then costs a single
 // workgroup at most ~0.1 ms per solve), about 128 rows per member above.
@@ -868,9 +989,8 @@ static int gang_size(int m) {
   return g < kMaxGangF ? g : kMaxGangF;
 }
 
-// plan = {nfold, nval, count, ntasks, order[count], fold_start[count], val_start[count],
-//         tasks[ntasks]}; a task is problem | member << 20 | (G - 1) << 26, largest problems
-// first, the G members of a gang consecutive.
+// tasks: problem | member << 20 | (G - 1) << 26, largest problems first, the G members of a
+// gang consecutive.
 int batched_plan(const ot_batch_desc* h, int count, int32_t* plan) {
   if (count >= (1 << 20)) return -1;
   std::vector<int> idx(count);
@@ -880,23 +1000,44 @@ int batched_plan(const ot_batch_desc* h, int count, int32_t* plan) {
     return m * m * (1.0 + 0.05 * h[p].K);  // iterations ~ m^2 each; fold ~ K m^2 once
   };
   std::stable_sort(idx.begin(), idx.end(), [&](int u, int v) { return cost(u) > cost(v); });
-  int32_t* order = plan + 4;
+  int32_t* cls_q = plan + 4;
+  int32_t* cls_tile = cls_q + kVClasses + 1;
+  int32_t* order = plan + kPlanHead;
   int32_t* fstart = order + count;
-  int32_t* vstart = fstart + count;
+  int32_t* vorder = fstart + count;
+  int32_t* vstart = vorder + count;
   uint32_t* tasks = reinterpret_cast<uint32_t*>(vstart + count);
   int64_t nf = 0, nv = 0;
   int nt = 0;
   for (int p = 0; p < count; ++p) {
     order[p] = idx[p];
     const int m = h[p].n / h[p].K;
-    const int tiles = (m + kBT - 1) / kBT;
     fstart[p] = (int32_t)nf;
-    vstart[p] = (int32_t)nv;
-    nf += tiles;
-    nv += 2 * tiles;
+    nf += (m + kBT - 1) / kBT;
   }
-  for (int q = 0; q < count; ++q) {
-    const int p = idx[q];
+  // value tiles by class, problems in index order within a class
+  std::vector<int> vo(count);
+  for (int p = 0; p < count; ++p) vo[p] = p;
+  std::stable_sort(vo.begin(), vo.end(), [&](int u, int v) {
+    return v_class(h[u].dim, h[u].K) < v_class(h[v].dim, h[v].K);
+  });
+  int q = 0;
+  for (int c = 0; c < kVClasses; ++c) {
+    cls_q[c] = q;
+    cls_tile[c] = (int32_t)nv;
+    while (q < count && v_class(h[vo[q]].dim, h[vo[q]].K) == c) {
+      const int p = vo[q];
+      const int m = h[p].n / h[p].K;
+      vorder[q] = p;
+      vstart[q] = (int32_t)nv;
+      nv += 2 * ((m + kAdjPts - 1) / kAdjPts);
+      ++q;
+    }
+  }
+  cls_q[kVClasses] = q;
+  cls_tile[kVClasses] = (int32_t)nv;
+  for (int r = 0; r < count; ++r) {
+    const int p = idx[r];
     const int G = gang_size(h[p].n / h[p].K);
     for (int k = 0; k < G; ++k) tasks[nt++] = (uint32_t)p | ((uint32_t)k << 20) | ((uint32_t)(G - 1) << 26);
   }
@@ -910,8 +1051,16 @@ int batched_plan(const ot_batch_desc* h, int count, int32_t* plan) {
 
 size_t batched_ws_bytes(int count) { return a256(256) + a256(sizeof(double) * 8 * (size_t)count); }
 
+template <int DIM, int KT>
+static void launch_values_class(const ot_batch_desc* descs, const int32_t* vorder,
+                                const int32_t* vstart, int q0, int q1, int t0, int t1,
+                                double* accs, hipStream_t s) {
+  hipLaunchKernelGGL((batched_values_kernel<DIM, KT>), dim3(t1 - t0), dim3(256), 0, s, descs,
+                     vorder + q0, vstart + q0, q1 - q0, t0, accs);
+}
+
 hipError_t launch_batched(const ot_batch_desc* descs, int count, const int32_t* dplan,
-                          int nfold, int nval, double tol, int max_iter, int fold_fp64,
+                          const int32_t* hplan, double tol, int max_iter, int fold_fp64,
                           int warm, void* ws, hipStream_t s, hipEvent_t* events) {
   char* base = static_cast<char*>(ws);
   uint32_t* queue = reinterpret_cast<uint32_t*>(base);
@@ -920,9 +1069,13 @@ hipError_t launch_batched(const ot_batch_desc* descs, int count, const int32_t* 
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(zero_d_words, dim3(64), dim3(256), 0, s, accs, (int64_t)8 * count);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int32_t* order = dplan + 4;
+  const int nfold = hplan[0];
+  const int32_t* cls_q = hplan + 4;
+  const int32_t* cls_tile = cls_q + kVClasses + 1;
+  const int32_t* order = dplan + kPlanHead;
   const int32_t* fstart = order + count;
-  const int32_t* vstart = fstart + count;
+  const int32_t* vorder = fstart + count;
+  const int32_t* vstart = vorder + count;
   hipLaunchKernelGGL(batched_fold_kernel, dim3(nfold), dim3(256), 0, s, descs, count, fstart,
                      fold_fp64);
   if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -936,7 +1089,7 @@ hipError_t launch_batched(const ot_batch_desc* descs, int count, const int32_t* 
   int dev = 0, cus = 0;
   if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
   if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-  // the device copy of the plan: task count in entry 3, tasks after val_start
+  // the device copy of the plan: task count in entry 3, tasks after vstart
   const uint32_t* tasks = reinterpret_cast<const uint32_t*>(vstart + count);
   BSolveArgs a{descs, count, dplan + 3, tasks, queue, tol, max_iter, warm};
   // one workgroup per CU (the LDS request allows no more), all resident at once, so the
@@ -947,8 +1100,30 @@ hipError_t launch_batched(const ot_batch_desc* descs, int count, const int32_t* 
   hipLaunchKernelGGL(batched_solve_kernel, dim3(grid), dim3(kBSolveThreads), kBMaxLds, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (events && (e = hipEventRecord(events[1], s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(batched_values_kernel, dim3(nval), dim3(256), 0, s, descs, count, vstart, accs);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // values and gradients: one launch per non-empty (dim, K) class
+  for (int c = 0; c < kVClasses; ++c) {
+    const int q0 = cls_q[c], q1 = cls_q[c + 1], t0 = cls_tile[c], t1 = cls_tile[c + 1];
+    if (t1 <= t0) continue;
+#define CSOT_VCLS(D, KT) launch_values_class<D, KT>(descs, vorder, vstart, q0, q1, t0, t1, accs, s)
+    switch (c) {
+      case 0: CSOT_VCLS(2, 1); break;
+      case 1: CSOT_VCLS(2, 2); break;
+      case 2: CSOT_VCLS(2, 4); break;
+      case 3: CSOT_VCLS(2, 8); break;
+      case 4: CSOT_VCLS(2, 16); break;
+      case 5: CSOT_VCLS(2, 32); break;
+      case 6: CSOT_VCLS(2, 0); break;
+      case 7: CSOT_VCLS(3, 1); break;
+      case 8: CSOT_VCLS(3, 2); break;
+      case 9: CSOT_VCLS(3, 4); break;
+      case 10: CSOT_VCLS(3, 8); break;
+      case 11: CSOT_VCLS(3, 16); break;
+      case 12: CSOT_VCLS(3, 32); break;
+      default: CSOT_VCLS(3, 0); break;
+    }
+#undef CSOT_VCLS
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(batched_finalize_kernel, dim3((count + 255) / 256), dim3(256), 0, s, descs,
                      count, accs);
   return hipGetLastError();

@@ -13,6 +13,12 @@ constexpr double kLn2D = 0.69314718055994530942;
 constexpr float kNegBig = -1.0e30f;  // finite "minus infinity" for running maxima
 constexpr int kWave = 64;
 
+// Read-only float data in device (global) memory.  Pointers taken from a descriptor in memory
+// are generic to the compiler, which then emits flat loads with 64-bit address arithmetic;
+// the cast lets it use global loads with 32-bit offsets from a scalar base.
+typedef __attribute__((address_space(1))) const float gcfloat;
+__device__ __forceinline__ gcfloat* as_global(const float* p) { return (gcfloat*)p; }
+
 // 2^x and log2(x) on the transcendental unit (v_exp_f32 / v_log_f32, 1 ulp).
 __device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float log2_fast(float x) { return __builtin_amdgcn_logf(x); }
@@ -140,6 +146,60 @@ constexpr int ilog2_ceil(int v) {
   int s = 0;
   while ((1 << s) < v) ++s;
   return s;
+}
+
+// Reduce-scatter of NV = 2^S float64 values over groups of 2^B consecutive lanes (B <= 6):
+// halving steps over lane bits B-1 .. 0 while more than one value is left, then plain sums
+// over the remaining bits.  On return lane l holds, in v[0 .. L), L = 2^max(S - B, 0), the
+// group totals of values (l mod 2^B) >> max(B - S, 0) ... : value index
+//   (l mod 2^B) * L + j            when S >= B,
+//   (l mod 2^B) >> (B - S)         (j = 0) when S < B.
+template <int BIT, int L, int NV>
+__device__ __forceinline__ void rs_step(double (&v)[NV], int lane) {
+  if constexpr (BIT == 5 || BIT == 4) {
+    if constexpr (L > 1) {
+#pragma unroll
+      for (int q = 0; q < L / 2; ++q) {
+        if constexpr (BIT == 5) swap32_f64(v[q], v[q + L / 2]);
+        else swap16_f64(v[q], v[q + L / 2]);
+        v[q] += v[q + L / 2];
+      }
+    } else {
+      double w = v[0];
+      if constexpr (BIT == 5) swap32_f64(v[0], w);
+      else swap16_f64(v[0], w);
+      v[0] += w;
+    }
+  } else {
+    constexpr int CTRL = BIT == 3 ? kDppMirror : BIT == 2 ? kDppHalfMirror : BIT == 1 ? kDppXor2 : kDppXor1;
+    if constexpr (L > 1) {
+      const bool hi = (lane & (1 << BIT)) != 0;
+#pragma unroll
+      for (int q = 0; q < L / 2; ++q) {
+        const double keep = hi ? v[q + L / 2] : v[q];
+        const double send = hi ? v[q] : v[q + L / 2];
+        v[q] = keep + dpp_f64<CTRL>(send);
+      }
+    } else {
+      v[0] += dpp_f64<CTRL>(v[0]);
+    }
+  }
+}
+
+template <int S, int B, int BIT, int NV>
+__device__ __forceinline__ void group_rs_from(double (&v)[NV], int lane) {
+  if constexpr (BIT >= 0) {
+    constexpr int done = B - 1 - BIT;                       // halving steps so far
+    constexpr int L = done < S ? (NV >> done) : 1;          // values left before this step
+    rs_step<BIT, L, NV>(v, lane);
+    group_rs_from<S, B, BIT - 1, NV>(v, lane);
+  }
+}
+
+template <int S, int B>
+__device__ __forceinline__ void group_reduce_scatter_d(double (&v)[1 << S], int lane) {
+  static_assert(B >= 1 && B <= 6, "groups of 2 to 64 lanes");
+  group_rs_from<S, B, B - 1, (1 << S)>(v, lane);
 }
 
 // One DPP halving step of wave_reduce_scatter_d: L values in, L / 2 out (or a plain sum of

@@ -97,7 +97,7 @@ size_t batched_plan_len(int count);
 int batched_plan(const ot_batch_desc* host_descs, int count, int32_t* plan);
 size_t batched_ws_bytes(int count);
 hipError_t launch_batched(const ot_batch_desc* descs, int count, const int32_t* dplan,
-                          int nfold, int nval, double tol, int max_iter, int fold_fp64,
+                          const int32_t* hplan, double tol, int max_iter, int fold_fp64,
                           int warm, void* ws, hipStream_t s, hipEvent_t* events = nullptr);
 
 }  // namespace csot

@@ -152,10 +152,18 @@ def test_batched_plan_validation_and_order(B):
         d.x = d.y = d.a = d.b = d.logK = d.f = d.g = d.out = 8
     plan = (ctypes.c_int32 * _lib.ot_batched_plan_len(3))()
     assert _lib.ot_batched_plan(descs, 3, plan) == 0
-    order = list(plan[4:7])
+    H = 4 + 2 * 15                         # header: counts, then 14 value classes' bounds
+    order = list(plan[H:H + 3])
     assert order == [1, 2, 0]              # m = 16, 64, 48: largest first
-    assert list(plan[7:10]) == [0, 1, 5]   # fold tiles: ceil(m/16) = 1, 4, 3
-    assert plan[0] == 8 and plan[1] == 16
+    assert list(plan[H + 3:H + 6]) == [0, 1, 5]   # fold tiles: ceil(m/16) = 1, 4, 3
+    # value tiles grouped by (dim, K) class -- K = 2 (problem 2), K = 4 (0), K = 8 (1) -- each
+    # 2 ceil(m/4) tiles of 4 block-0 points (rows, then columns): 24, 8, 32
+    assert list(plan[H + 6:H + 9]) == [2, 0, 1]
+    assert list(plan[H + 9:H + 12]) == [0, 24, 32]
+    cls_q, cls_tile = list(plan[4:19]), list(plan[19:34])
+    assert cls_q[:5] == [0, 0, 1, 2, 3] and cls_q[14] == 3
+    assert cls_tile[:5] == [0, 0, 24, 32, 64] and cls_tile[14] == 64
+    assert plan[0] == 8 and plan[1] == 64
     descs[1].K = 7                          # 512 % 7 != 0
     assert _lib.ot_batched_plan(descs, 3, plan) == B.OT_ERR_ARG
     descs[1].K, descs[1].tile_cfg = 8, 24
@@ -196,7 +204,8 @@ def test_batched_plan_gang_tasks(B):
     assert _lib.ot_batched_plan(descs, 3, plan) == 0
     nt = plan[3]
     assert nt == 8 + 4 + 1
-    tasks = np.frombuffer(plan, dtype=np.uint32)[4 + 3 * 3:4 + 3 * 3 + nt]
+    H = 4 + 2 * 15
+    tasks = np.frombuffer(plan, dtype=np.uint32)[H + 4 * 3:H + 4 * 3 + nt]
     prob, member, gang = tasks & 0xFFFFF, (tasks >> 20) & 63, (tasks >> 26) + 1
     assert list(prob) == [2] * 8 + [1] * 4 + [0]
     assert list(member) == list(range(8)) + list(range(4)) + [0]

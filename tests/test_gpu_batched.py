@@ -36,6 +36,53 @@ def _oracle(p):
     return r, v, Ck
 
 
+def _check_grads(batch, k, p, Ck, rows=None):
+    """The batched gradients of problem k against the oracle's envelope gradients of the
+    expanded plan (Lemma 1) built from the batch's own potentials: dx, dy of every point (or
+    of the sampled `rows` of the expanded plan, and as many sampled columns), da, db.  Error
+    model as for the single-problem adjoint: each plan entry carries a float32 relative error,
+    so a component may be off by that error times 2 sum_J T_IJ |x_I - y_J|; bar 2e-5 of it."""
+    f = batch.f(k).cpu().numpy().astype(np.float64)
+    g = batch.g(k).cpu().numpy().astype(np.float64)
+    X, Y = p.x.astype(np.float64), p.y.astype(np.float64)
+    n, m, K = p.n, p.m, p.K
+    Tk = sinkhorn.reduced_plan_blocks(f, g, Ck, p.eps)                   # [K, m, m]
+    rows = np.arange(n) if rows is None else np.asarray(rows)
+    worst = 0.0
+    for key, pts, other in (("dx", X, Y), ("dy", Y, X)):
+        got = (batch.dx(k) if key == "dx" else batch.dy(k)).cpu().numpy().astype(np.float64)
+        for I in rows:
+            r, i = divmod(int(I), m)
+            # row I of the plan (dx) or column I (dy): blocks (r, c) hold T_{(c - r) mod K}
+            if key == "dx":
+                t = np.concatenate([Tk[(c - r) % K][i] for c in range(K)])
+            else:
+                t = np.concatenate([Tk[(r - c) % K][:, i] for c in range(K)])
+            D = pts[I][None, :] - other
+            want = 2.0 * (t[:, None] * D).sum(0)
+            scale = 2.0 * (t[:, None] * np.abs(D)).sum(0)
+            worst = max(worst, float((np.abs(got[I] - want) / scale).max()))
+    fa, gb = np.tile(f, K), np.tile(g, K)
+    for got, want in ((batch.da(k), fa), (batch.db(k), gb)):
+        got = got.cpu().numpy().astype(np.float64)
+        assert np.abs(got - (want - want.mean())).max() <= 1e-6 * (1 + np.abs(want).max()), k
+    return worst
+
+
+def _check_plan_at_gpu_iterations(batch, k, p, Ck, r, iters):
+    """The reduced plan from the batch's potentials against the oracle's after the same number
+    of iterations (a stop one iteration apart moves the plan by about the 1e-6 residual per
+    row, which is the size of the 1e-5 L1 bar)."""
+    if iters != r["iters"]:
+        r = sinkhorn.reduced_sinkhorn(r["alpha"], r["beta"], r["logK"], p.eps, p.K, tol=0.0,
+                                      max_iter=iters)
+    Tg = sinkhorn.reduced_plan_blocks(batch.f(k).cpu().numpy().astype(np.float64),
+                                      batch.g(k).cpu().numpy().astype(np.float64), Ck, p.eps)
+    Tr = sinkhorn.reduced_plan_blocks(r["f"], r["g"], Ck, p.eps)
+    l1 = np.abs(Tg - Tr).sum() / Tr.sum()
+    assert l1 < 1e-5, (k, l1, iters)
+
+
 def test_batched_equals_unbatched_and_oracle(lib):
     probs = _problems(SMALL)
     print(f"[batched small] {len(probs)} problems", flush=True)
@@ -49,7 +96,7 @@ def test_batched_equals_unbatched_and_oracle(lib):
         prob = lib.Problem(t(p.a), t(p.b), p.eps, p.K, x=t(p.x), y=t(p.y))
         logK, al, be = lib.ot_fold_kernel(prob, opts)
         f, g, st = lib.ot_sinkhorn_reduced(prob, logK, al, be, opts)
-        res = lib.ot_cost_and_grad(prob, f, g, reduced=True, want_dxy=True)
+        res = lib.ot_cost_and_grad(prob, f, g, reduced=True)
         vu = lib.values_dict(res["values"])
         vb = batch.values(k)
         assert vb["converged"] and vb["flags"] == 0, (k, vb)
@@ -58,18 +105,15 @@ def test_batched_equals_unbatched_and_oracle(lib):
         assert abs(vb["P"] - vu["P"]) / scale < 1e-5, (k, vb["P"], vu["P"])
         assert abs(vb["D"] - vu["D"]) / scale < 1e-5
         assert vb["err_row"] <= 1.05e-6
-        m = p.m
-        for got, want in ((batch.dx(k), res["dx"][:m]), (batch.dy(k), res["dy"][:m])):
-            got, want = got.cpu().numpy(), want.cpu().numpy()
-            assert np.abs(got - want).max() / np.abs(want).max() < 1e-4, k
         # the oracle
         r, v, Ck = _oracle(p)
+        worst = _check_grads(batch, k, p, Ck)
+        print(f"[batched small] problem {k} (m={p.m}, K={p.K}, dim={p.dim}): gradients "
+              f"max |d| / scale = {worst:.2e}", flush=True)
+        assert worst < 2e-5, (k, worst)
         assert abs(vb["iters"] - r["iters"]) <= 1
         assert abs(vb["P"] - p.K * v["P"]) / max(abs(p.K * v["P"]), p.K * v["CT"]) < 1e-5
-        Tg = sinkhorn.reduced_plan_blocks(batch.f(k).cpu().numpy().astype(np.float64),
-                                          batch.g(k).cpu().numpy().astype(np.float64), Ck, p.eps)
-        Tr = sinkhorn.reduced_plan_blocks(r["f"], r["g"], Ck, p.eps)
-        assert np.abs(Tg - Tr).sum() / Tr.sum() < 1e-5, k
+        _check_plan_at_gpu_iterations(batch, k, p, Ck, r, vb["iters"])
 
 
 def test_batched_full_workload_sampled(lib):
@@ -98,12 +142,29 @@ def test_batched_full_workload_sampled(lib):
     assert (out[:, 6] == 1).all() and (out[:, 7] == 0).all()
     assert (out[:, 3] <= 1.05e-6).all()
     rng = np.random.default_rng(0)
-    for k in rng.choice(len(probs), size=6, replace=False):
+    # six random problems, plus the largest K = 32 problems in 2-D and 3-D (the adjoint's
+    # two-group case)
+    pick = list(rng.choice(len(probs), size=6, replace=False))
+    for dim in (2, 3):
+        cand = [q for q in range(len(probs)) if probs[q]["_p"].K == 32 and probs[q]["_p"].dim == dim]
+        pick.append(max(cand, key=lambda q: probs[q]["_p"].m))
+    for k in pick:
+        k = int(k)
         p = probs[k]["_p"]
         r, v, Ck = _oracle(p)
-        vb = batch.values(int(k))
+        vb = batch.values(k)
         assert abs(vb["iters"] - r["iters"]) <= 1, (k, vb["iters"], r["iters"])
-        assert abs(vb["P"] - p.K * v["P"]) / max(abs(p.K * v["P"]), p.K * v["CT"]) < 1e-5, k
+        scale = max(abs(p.K * v["P"]), p.K * v["CT"])
+        assert abs(vb["P"] - p.K * v["P"]) / scale < 1e-5, k
+        assert abs(vb["D"] - p.K * v["D"]) / scale < 1e-5, k
+        _check_plan_at_gpu_iterations(batch, k, p, Ck, r, vb["iters"])
+        # gradients at 3 x 16 sampled rows / columns of the expanded plan
+        rows = np.concatenate([c * p.m + rng.choice(p.m, min(16, p.m), replace=False)
+                               for c in (0, p.K // 2, p.K - 1)])
+        worst = _check_grads(batch, k, p, Ck, rows)
+        print(f"[batched full] problem {k} (m={p.m}, K={p.K}, dim={p.dim}): iterations "
+              f"{vb['iters']}, gradients max |d| / scale = {worst:.2e}", flush=True)
+        assert worst < 2e-5, (k, worst)
 
 
 def test_batched_graph_replay(lib):
@@ -116,18 +177,20 @@ def test_batched_graph_replay(lib):
     batch.run(opts)
     torch.cuda.synchronize()
     ref_out = batch.OUT.clone()
-    ref_f, ref_g, ref_dx = batch.F.clone(), batch.G.clone(), batch.DX.clone()
+    ref_f, ref_g, ref_dx, ref_db = batch.F.clone(), batch.G.clone(), batch.DX.clone(), batch.DB.clone()
     graph = batch.capture(opts)
     for rep in range(3):
         batch.OUT.zero_()
         batch.F.fill_(7.0)
         batch.G.zero_()
         batch.DX.fill_(-1.0)
+        batch.DB.fill_(3.0)
         torch.cuda.synchronize()
         graph.replay()
         torch.cuda.synchronize()
         assert torch.equal(batch.F, ref_f), rep
         assert torch.equal(batch.G, ref_g), rep
         assert torch.equal(batch.DX, ref_dx), rep
+        assert torch.equal(batch.DB, ref_db), rep
         # float64 sums use atomics (order may differ): compare to rounding
         assert torch.allclose(batch.OUT, ref_out, rtol=1e-12, atol=1e-15), rep
