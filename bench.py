@@ -11,7 +11,9 @@ One step = one pass of the whole path on that input:
             objective + gradients (dx, dy, da, db);
             plus a fixed-count reduced solve (tol = 0, --fixed-reduced iterations);
   full    : plain full-size Sinkhorn to 1e-6 -> objective + gradients;
-            plus a fixed-count full solve (tol = 0, --fixed-full iterations).
+            plus a fixed-count full solve (tol = 0, --fixed-full iterations);
+  eps 0.1 : reduced and full solves to 1e-6 at eps = 0.1 median(C);
+  batched : one call on 1024 uneven cyclic problems (fold, solve, values, gradients).
 `value` is the reduced Sinkhorn iteration rate (iterations / second) of the fixed-count legs;
 the time-to-tolerance and the full-size rates are reported beside it.  All timing uses HIP
 events on the stream the kernels run on.
@@ -77,111 +79,151 @@ def _args():
     return ap.parse_args()
 
 
-def batched_only(steps, warmup):
+class BatchedLeg:
     """The batched workload: 1024 cyclic problems, m log-uniform in [32, 1024], K in
-    {4, 8, 16, 32}, 2-D or 3-D, eps = 0.05 median each, tol 1e-6; fold, solve, objective
-    values and the gradients (every point, both marginals) of all of them per call, timed with HIP
-    events."""
-    import numpy as np
+    {4, 8, 16, 32}, 2-D or 3-D, eps = 0.05 median each, tol 1e-6.  One call: fold, solve,
+    objective values and the gradients (every point, both marginals) of all of them; the same
+    call without gradients (forward only) and the plain method -- each problem solved at full
+    size, one after another, with values and the same gradients -- are timed beside it."""
+
+    def __init__(self):
+        import torch
+
+        import paper_2311_13147_amd as csot
+        import workloads
+
+        self.items = workloads.batched_problems(1024)
+        self.probs = [dict(x=p.x, y=p.y, a=p.a, b=p.b, eps=p.eps, K=p.K)
+                      for p in (workloads.symmetric_problem(it.m * it.K, it.K, it.dim, 0.05,
+                                                            seed=it.seed)
+                                for it in self.items)]
+        self.batch = csot.Batch(self.probs, device="cuda:0")
+        self.batch_fwd = csot.Batch(self.probs, device="cuda:0", want_grad=False)
+        self.opts = csot.make_opts(tol=1e-6, max_iter=20000)
+        self.csot, self.torch = csot, torch
+
+    def run(self):
+        self.batch.run(self.opts)
+
+    def report(self, ms_call, steps):
+        import numpy as np
+
+        csot, torch = self.csot, self.torch
+        E = lambda: torch.cuda.Event(enable_timing=True)
+        out = self.batch.OUT.cpu().numpy()
+        # the solve kernel alone, timed by events the library records right around its launch
+        sev = (E(), E())
+        opts_ev = csot.make_opts(tol=1e-6, max_iter=20000, timing_events=sev)
+        solve_ms = []
+        for _ in range(steps):
+            self.batch.run(opts_ev)
+            torch.cuda.synchronize()
+            solve_ms.append(sev[0].elapsed_time(sev[1]))
+        solve_ms = sum(solve_ms) / steps
+        # forward only (values, no gradients)
+        self.batch_fwd.run(self.opts)
+        torch.cuda.synchronize()
+        e0, e1 = E(), E()
+        e0.record()
+        for _ in range(steps):
+            self.batch_fwd.run(self.opts)
+        e1.record()
+        torch.cuda.synchronize()
+        fwd_ms = e0.elapsed_time(e1) / steps
+        # Algorithmic bytes of the solve: every pass over a problem's folded kernel that is not
+        # kept in LDS reads m * mp floats (logK rows in the row pass, its transpose in the
+        # column pass).  One workgroup stops at the row pass of iteration iters + 1
+        # (2 iters + 1 passes); a gang tests the state two iterations back (2 iters + 3
+        # passes); LDS-resident problems read logK and its transpose once.
+        lds_floats = 148 * 1024 // 4
+        solve_bytes = 0
+        for m_, it_ in zip(self.batch.ms, out[:, 5]):
+            mp_ = (m_ + 3) // 4 * 4
+            it_ = int(it_)
+            if m_ > 256:
+                passes = 2 * it_ + 3
+            elif 6 * mp_ + 2 * m_ * mp_ <= lds_floats:
+                passes = 2
+            else:
+                passes = 2 * it_ + 1
+            solve_bytes += passes * m_ * mp_ * 4
+        # the float64 FMAs of the gradients: dx and dy of every point, 2 n^2 dim per problem
+        grad_fma = float(sum(2.0 * (it.m * it.K) ** 2 * it.dim for it in self.items))
+
+        # The same problems solved one at a time at full size (n = K m points per side) on the
+        # GPU: full-size Sinkhorn to the same tolerance, then values and the gradients of all
+        # n points and both marginals -- the plain method the batched reduced call replaces.
+        # Outputs preallocated; the loop is timed once with HIP events around it (host
+        # dispatch of the calls included).
+        dev = "cuda:0"
+        T_ = lambda v: torch.from_numpy(np.ascontiguousarray(v)).to(dev)
+        fulls = []
+        for q in self.probs:
+            n, d = q["x"].shape
+            pr = csot.Problem(T_(q["a"]), T_(q["b"]), q["eps"], q["K"], x=T_(q["x"]), y=T_(q["y"]))
+            f32 = dict(dtype=torch.float32, device=dev)
+            fulls.append((pr, (torch.empty(n, **f32), torch.empty(n, **f32)),
+                          torch.zeros(8, dtype=torch.float64, device=dev),
+                          {"dx": torch.empty((n, d), **f32), "dy": torch.empty((n, d), **f32),
+                           "da": torch.empty(n, **f32), "db": torch.empty(n, **f32)},
+                          torch.empty(8, dtype=torch.float64, device=dev)))
+        csot.workspace(max(fulls, key=lambda r: r[0].n)[0])  # the largest, allocated once
+
+        def full_pass():
+            for pr, fg, ds, gr, vals in fulls:
+                f, g, _ = csot.ot_sinkhorn_full(pr, self.opts, host_stats=False, out=fg, dstats=ds)
+                csot.ot_cost_and_grad(pr, f, g, False, want_dxy=True, want_dab=True, grads=gr,
+                                      out=vals)
+
+        full_pass()
+        torch.cuda.synchronize()
+        e0.record()
+        full_pass()
+        e1.record()
+        torch.cuda.synchronize()
+        full_ms = e0.elapsed_time(e1)
+        fout = torch.stack([r[4] for r in fulls]).cpu().numpy()
+        fit = torch.stack([r[2] for r in fulls]).cpu().numpy()
+        del fulls
+        return {"workload": "batched: 1024 cyclic problems, m log-uniform [32, 1024], "
+                            "K in {4,8,16,32}, dim 2/3, eps=0.05*median, tol=1e-6",
+                "ms_per_call": round(ms_call, 3),
+                "problems_per_s": round(1024 / ms_call * 1e3, 1),
+                "forward_only_ms_per_call": round(fwd_ms, 3),
+                "sum_m2": int(sum(it.m * it.m for it in self.items)),
+                "all_converged": bool((out[:, 6] == 1).all()),
+                "max_err_row_fp64": float(out[:, 3].max()),
+                "max_err_col_fp64": float(out[:, 4].max()),
+                "iterations_median_max": [float(np.median(out[:, 5])), float(out[:, 5].max())],
+                "solve_kernel_ms": round(solve_ms, 3),
+                "solve_roofline": {"bound": "hbm", "unit": "GB/s",
+                                   "achieved": round(solve_bytes / (solve_ms * 1e-3) / 1e9, 1),
+                                   "peak": HBM_PEAK_GBS,
+                                   "frac": round(solve_bytes / (solve_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                   "bytes_per_launch": solve_bytes},
+                "gradient_fp64_fma_per_call": grad_fma,
+                "full_size_one_by_one": {
+                    "ms": round(full_ms, 3),
+                    "all_converged": bool((fit[:, 1] == 1).all()),
+                    "max_err_row_fp64": float(fout[:, 3].max()),
+                    "iterations_median_max": [float(np.median(fit[:, 0])), float(fit[:, 0].max())]},
+                "speedup_vs_full_size": round(full_ms / ms_call, 2)}
+
+
+def batched_only(steps, warmup):
     import torch
 
-    import paper_2311_13147_amd as csot
-    import workloads
-
-    items = workloads.batched_problems(1024)
-    probs = [dict(x=p.x, y=p.y, a=p.a, b=p.b, eps=p.eps, K=p.K)
-             for p in (workloads.symmetric_problem(it.m * it.K, it.K, it.dim, 0.05, seed=it.seed)
-                       for it in items)]
-    batch = csot.Batch(probs, device="cuda:0")
-    opts = csot.make_opts(tol=1e-6, max_iter=20000)
-    # the solve kernel alone, timed by events the library records right around its launch
-    sev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-    opts_ev = csot.make_opts(tol=1e-6, max_iter=20000, timing_events=sev)
+    leg = BatchedLeg()
     for _ in range(warmup):
-        batch.run(opts)
+        leg.run()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(steps):
-        batch.run(opts)
+        leg.run()
     e1.record()
     torch.cuda.synchronize()
-    out = batch.OUT.cpu().numpy()
-    ms = e0.elapsed_time(e1) / steps
-    solve_ms = []
-    for _ in range(steps):
-        batch.run(opts_ev)
-        torch.cuda.synchronize()
-        solve_ms.append(sev[0].elapsed_time(sev[1]))
-    solve_ms = sum(solve_ms) / steps
-    # Algorithmic bytes of the solve: every pass over a problem's folded kernel that is not kept
-    # in LDS reads m * mp floats (logK rows in the row pass, its transpose in the column pass).
-    # One workgroup stops at the row pass of iteration iters + 1 (2 iters + 1 passes); a gang
-    # tests the state two iterations back (2 iters + 3 passes); LDS-resident problems read
-    # logK and its transpose once.
-    lds_floats = 148 * 1024 // 4
-    solve_bytes = 0
-    for m_, it_ in zip(batch.ms, out[:, 5]):
-        mp_ = (m_ + 3) // 4 * 4
-        it_ = int(it_)
-        if m_ > 256:
-            passes = 2 * it_ + 3
-        elif 6 * mp_ + 2 * m_ * mp_ <= lds_floats:
-            passes = 2
-        else:
-            passes = 2 * it_ + 1
-        solve_bytes += passes * m_ * mp_ * 4
-
-    # The same problems solved one at a time at full size (n = K m points per side) on the GPU:
-    # full-size Sinkhorn to the same tolerance, then values and coordinate gradients of all n
-    # points -- the plain method the batched reduced call replaces.  Outputs preallocated; the
-    # loop is timed once with HIP events around it (host dispatch of the calls included).
-    dev = "cuda:0"
-    T_ = lambda v: torch.from_numpy(np.ascontiguousarray(v)).to(dev)
-    fulls = []
-    for q in probs:
-        n, d = q["x"].shape
-        pr = csot.Problem(T_(q["a"]), T_(q["b"]), q["eps"], q["K"], x=T_(q["x"]), y=T_(q["y"]))
-        fulls.append((pr, (torch.empty(n, device=dev), torch.empty(n, device=dev)),
-                      torch.zeros(8, dtype=torch.float64, device=dev),
-                      {"dx": torch.empty((n, d), device=dev), "dy": torch.empty((n, d), device=dev)},
-                      torch.empty(8, dtype=torch.float64, device=dev)))
-    csot.workspace(max(fulls, key=lambda r: r[0].n)[0])  # the largest workspace, allocated once
-
-    def full_pass():
-        for pr, fg, ds, gr, vals in fulls:
-            f, g, _ = csot.ot_sinkhorn_full(pr, opts, host_stats=False, out=fg, dstats=ds)
-            csot.ot_cost_and_grad(pr, f, g, False, want_dxy=True, grads=gr, out=vals)
-
-    full_pass()
-    torch.cuda.synchronize()
-    e0.record()
-    full_pass()
-    e1.record()
-    torch.cuda.synchronize()
-    full_ms = e0.elapsed_time(e1)
-    fout = torch.stack([r[4] for r in fulls]).cpu().numpy()
-    fit = torch.stack([r[2] for r in fulls]).cpu().numpy()
-    print(json.dumps({"workload": "batched: 1024 cyclic problems, m log-uniform [32, 1024], "
-                                  "K in {4,8,16,32}, dim 2/3, eps=0.05*median, tol=1e-6",
-                      "ms_per_call": round(ms, 3), "problems_per_s": round(1024 / ms * 1e3, 1),
-                      "sum_m2": int(sum(it.m * it.m for it in items)),
-                      "all_converged": bool((out[:, 6] == 1).all()),
-                      "max_err_row": float(out[:, 3].max()),
-                      "iterations_median_max": [float(np.median(out[:, 5])), float(out[:, 5].max())],
-                      "solve_kernel_ms": round(solve_ms, 3),
-                      "solve_roofline": {"bound": "hbm", "unit": "GB/s",
-                                         "achieved": round(solve_bytes / (solve_ms * 1e-3) / 1e9, 1),
-                                         "peak": HBM_PEAK_GBS,
-                                         "frac": round(solve_bytes / (solve_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                                         "bytes_per_launch": solve_bytes},
-                      "full_size_one_by_one": {
-                          "ms": round(full_ms, 3),
-                          "all_converged": bool((fit[:, 1] == 1).all()),
-                          "max_err_row": float(fout[:, 3].max()),
-                          "iterations_median_max": [float(np.median(fit[:, 0])), float(fit[:, 0].max())]},
-                      "speedup_vs_full_size": round(full_ms / ms, 2)}),
-          flush=True)
+    print(json.dumps(leg.report(e0.elapsed_time(e1) / steps, steps)), flush=True)
 
 
 def two_stage_only(steps, warmup):
@@ -553,6 +595,9 @@ def main():
     ds2 = [torch.zeros(8, dtype=torch.float64, device=dev) for _ in range(2)]
     csot.workspace(prob2, o_tol)
 
+    # the batched workload (config 5): one batched call per step
+    bleg = BatchedLeg()
+
     graphs = {}
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
@@ -572,7 +617,7 @@ def main():
     E = lambda: torch.cuda.Event(enable_timing=True)
     legs = ["fold", "red_solve", "expand", "red_grad", "red_fixed", "full_solve", "full_grad",
             "full_fixed", "red_graph", "full_graph", "red_fb_graph", "full_fb_graph",
-            "red_tol_eps2", "full_tol_eps2"]
+            "red_tol_eps2", "full_tol_eps2", "batched"]
 
     def step(record):
         ev = {k: (E(), E()) for k in legs}
@@ -611,6 +656,7 @@ def main():
         run("red_tol_eps2", red_eps2)
         run("full_tol_eps2", lambda: csot.ot_sinkhorn_full(prob2, o_tol, host_stats=False,
                                                            out=(ff4, gf4), dstats=ds2[1]))
+        run("batched", bleg.run)
         return ev
 
     def kernel_ms():
@@ -749,6 +795,7 @@ def main():
         "roofline": roof,
         "roofline_reduced_path": roof_red,
         "device_peaks": pk,
+        "batched": bleg.report(ms["batched"], args.steps),
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, fr, gr, vr, args.cpu_seconds)
