@@ -667,8 +667,7 @@ constexpr int kAdjPts = 4;  // own points (waves) per workgroup
 constexpr int kAdjChunk = 64;  // partners staged in LDS at a time (one per lane)
 
 struct BAdjShared {
-  float own_y[kAdjPts][32 * 3];       // column pass: y_{k m + j} of each wave's own column
-  double vals[kAdjPts][8];
+  float own_y[kAdjPts][32 * 3 * 4];   // column pass: y_{k m + j} of each wave's own column(s)
   float pts[32 * 3 * kAdjChunk];      // partner chunk: copy in block c, component d, partner
                                       // q at (c DIM + d) kAdjChunk + q
   float pot[kAdjChunk];               // the partners' potentials
@@ -887,6 +886,104 @@ __device__ void badj_point(const ot_batch_desc& d, int o, bool active, int lane,
   }
 }
 
+// Values only (a problem whose descriptor asks for no coordinate gradients): each wave takes
+// four own points, so that a staged partner chunk serves the workgroup's sixteen points; per
+// point the row (column) sum, P and <C, T> of the K m plan entries of block 0, da / db and
+// the marginal terms, as badj_point.
+constexpr int kValPts = 4;  // own points per wave in values-only tiles
+
+template <int DIM, int KT, bool ROW>
+__device__ void bval_points(const ot_batch_desc& d, int o0, int lane, const float* own_y4,
+                            double (*vals)[8], float* sh_pts, float* sh_pot) {
+  const int m = bm(d), K = d.K;
+  const float s2 = (float)(kLog2eD / d.eps);
+  const float eps = (float)d.eps;
+  gcfloat* x = as_global(d.x);
+  gcfloat* y = as_global(d.y);
+  gcfloat* fpot = as_global(d.f);
+  gcfloat* gpot = as_global(d.g);
+  gcfloat* src = ROW ? y : x;
+  float po[kValPts], xo[kValPts][DIM];
+  bool act[kValPts];
+#pragma unroll
+  for (int q = 0; q < kValPts; ++q) {
+    act[q] = o0 + q < m;
+    const int oc = act[q] ? o0 + q : 0;
+    po[q] = ROW ? fpot[oc] : gpot[oc];
+#pragma unroll
+    for (int dd = 0; dd < DIM; ++dd) xo[q][dd] = ROW ? x[oc * DIM + dd] : 0.0f;
+  }
+  double S[kValPts] = {};
+  float vP[kValPts] = {}, vC[kValPts] = {};
+#pragma unroll 1
+  for (int c0 = 0; c0 < m; c0 += kAdjChunk) {
+    __syncthreads();  // the previous chunk's readers are done
+    const int nc = min(kAdjChunk, m - c0);
+    // rows need the partners' copies in every block (the costs' y_{k m + j}); columns only
+    // block 0 (x_i)
+    const int nb = ROW ? KT : 1;
+    for (int e = threadIdx.x; e < nb * DIM * kAdjChunk; e += blockDim.x) {
+      const int qq = e % kAdjChunk, cd = e / kAdjChunk;
+      const int cb = cd / DIM, dd = cd - cb * DIM;
+      sh_pts[e] = qq < nc ? src[(cb * m + c0 + qq) * DIM + dd] : 0.0f;
+    }
+    if (threadIdx.x < kAdjChunk)
+      sh_pot[threadIdx.x] = (int)threadIdx.x < nc ? (ROW ? gpot : fpot)[c0 + threadIdx.x] : 0.0f;
+    __syncthreads();
+    if (lane >= nc) continue;
+    const float pp = sh_pot[lane];
+#pragma unroll 4
+    for (int k = 0; k < KT; ++k) {
+      float pt[DIM];
+#pragma unroll
+      for (int dd = 0; dd < DIM; ++dd) pt[dd] = sh_pts[((ROW ? k : 0) * DIM + dd) * kAdjChunk + lane];
+#pragma unroll
+      for (int q = 0; q < kValPts; ++q) {
+        float c = 0.0f;
+#pragma unroll
+        for (int dd = 0; dd < DIM; ++dd) {
+          const float e = ROW ? xo[q][dd] - pt[dd] : pt[dd] - own_y4[(q * KT + k) * DIM + dd];
+          c = fmaf(e, e, c);
+        }
+        const float fg = po[q] + pp;
+        const float T = act[q] ? exp2_fast((fg - c) * s2) : 0.0f;
+        S[q] += (double)T;
+        if (ROW) {
+          vP[q] = fmaf(T, fg - eps, vP[q]);  // T (C + eps (Z - 1)) = T (f + g - eps)
+          vC[q] = fmaf(T, c, vC[q]);
+        }
+      }
+    }
+  }
+  gcfloat* marg_in = as_global(ROW ? d.a : d.b);
+  gcfloat* pot = ROW ? fpot : gpot;
+  double ps = 0.0;
+  for (int qq = lane; qq < m; qq += kWave) ps += (double)pot[qq];
+  const double pmean = wave_sum_all_d(ps) / m;
+  float* __restrict__ dpot = ROW ? d.da : d.db;
+#pragma unroll
+  for (int q = 0; q < kValPts; ++q) {
+    const double Sq = wave_sum_all_d(S[q]);
+    const double tP = ROW ? wave_sum_all_d((double)vP[q]) : 0.0;
+    const double tC = ROW ? wave_sum_all_d((double)vC[q]) : 0.0;
+    if (!act[q]) continue;
+    const int o = o0 + q;
+    double mv = 0.0;
+    for (int r = lane; r < K; r += kWave) mv += (double)marg_in[r * m + o];
+    const double marg = wave_sum_all_d(mv) / K;
+    if (dpot)
+      for (int r = lane; r < K; r += kWave) dpot[r * m + o] = (float)((double)po[q] - pmean);
+    if (lane == 0) {
+      const double dr = Sq - marg;
+      vals[q][0] = tP;
+      vals[q][1] = tC;
+      vals[q][2] = ROW ? Sq : 0.0;
+      vals[q][3] = dr * dr;
+      vals[q][4] = (double)po[q] * marg;
+    }
+  }
+}
+
 // Value tiles are grouped by (dim, K) class so that each class runs its own instantiation
 // (its own register allocation): the launch for a class covers the tiles [tile0, tile0 +
 // grid) of the problems vorder[0 .. nq), whose first tiles vstart[] increase.
@@ -896,36 +993,62 @@ __global__ void __launch_bounds__(256)
                           const int32_t* __restrict__ vorder, const int32_t* __restrict__ vstart,
                           int nq, int tile0, double* __restrict__ accs) {
   __shared__ BAdjShared sh;
+  __shared__ double vals16[kAdjPts * kValPts][8];
   const int tile = tile0 + (int)blockIdx.x;
   const int q = find_problem(vstart, nq, tile);
   const int p = vorder[q];
   const ot_batch_desc d = descs[p];
   const int m = bm(d);
-  const int nrow = (m + kAdjPts - 1) / kAdjPts;
+  // gradients: 4 own points per tile (one per wave); values only: 16 (four per wave)
+  const bool grad = d.dx != nullptr || d.dy != nullptr;
+  const int ppt = (grad || KT == 0) ? kAdjPts : kAdjPts * kValPts;
+  const int nrow = (m + ppt - 1) / ppt;
   const int t = tile - vstart[q];
   double* acc = accs + 8 * (size_t)p;
   const bool row = t < nrow;
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
-  const int o = (row ? t : t - nrow) * kAdjPts + wv;
-  const bool active = o < m;
-  // column pass: the own column's y_{k m + j} of every block, staged per wave
-  if (KT > 0 && !row && active) {
-    for (int e = lane; e < KT * DIM; e += kWave) {
-      const int k = e / DIM, dd = e - k * DIM;
-      sh.own_y[wv][e] = d.y[(k * m + o) * DIM + dd];
+  const int first = (row ? t : t - nrow) * ppt;
+  if (ppt == kAdjPts) {
+    const int o = first + wv;
+    const bool active = o < m;
+    // column pass: the own column's y_{k m + j} of every block, staged per wave
+    if (KT > 0 && !row && active) {
+      for (int e = lane; e < KT * DIM; e += kWave) {
+        const int k = e / DIM, dd = e - k * DIM;
+        sh.own_y[wv][e] = d.y[(k * m + o) * DIM + dd];
+      }
     }
+    if (lane == 0)
+      for (int v = 0; v < 8; ++v) vals16[wv][v] = 0.0;
+    __syncthreads();
+    if (row) badj_point<DIM, KT, true>(d, o, active, lane, sh.own_y[wv], vals16[wv], sh.pts, sh.pot);
+    else badj_point<DIM, KT, false>(d, o, active, lane, sh.own_y[wv], vals16[wv], sh.pts, sh.pot);
+  } else if constexpr (KT > 0) {
+    const int o0 = first + wv * kValPts;
+    // column pass: y_{k m + j} of the wave's four own columns (the per-wave row of own_y holds
+    // 32 x 3 floats; four points of K <= 32 shifts use K DIM 4 <= 384 floats: the whole array)
+    float* own4 = &sh.own_y[0][0] + wv * (KT * DIM * kValPts);
+    if (!row) {
+      for (int e = lane; e < KT * DIM * kValPts; e += kWave) {
+        const int qq = e / (KT * DIM), r = e - qq * (KT * DIM);
+        const int k = r / DIM, dd = r - k * DIM;
+        const int o = min(o0 + qq, m - 1);
+        own4[e] = d.y[(k * m + o) * DIM + dd];
+      }
+    }
+    if (lane < kValPts)
+      for (int v = 0; v < 8; ++v) vals16[wv * kValPts + lane][v] = 0.0;
+    __syncthreads();
+    if (row) bval_points<DIM, KT, true>(d, o0, lane, own4, &vals16[wv * kValPts], sh.pts, sh.pot);
+    else bval_points<DIM, KT, false>(d, o0, lane, own4, &vals16[wv * kValPts], sh.pts, sh.pot);
   }
-  if (lane == 0)
-    for (int v = 0; v < 8; ++v) sh.vals[wv][v] = 0.0;
-  __syncthreads();
-  if (row) badj_point<DIM, KT, true>(d, o, active, lane, sh.own_y[wv], sh.vals[wv], sh.pts, sh.pot);
-  else badj_point<DIM, KT, false>(d, o, active, lane, sh.own_y[wv], sh.vals[wv], sh.pts, sh.pot);
   __syncthreads();
   // the workgroup's partials: one atomic add per value
   if (threadIdx.x < 5) {
     const int v = threadIdx.x;
+    const int np = ppt;
     double sum = 0.0;
-    for (int w = 0; w < kAdjPts; ++w) sum += sh.vals[w][v];
+    for (int w = 0; w < np; ++w) sum += vals16[w][v];
     // rows: P, <C,T>, mass, (rowsum - alpha)^2, <f,alpha>; columns: (colsum - beta)^2, <g,beta>
     const int slot = row ? (v < 4 ? v : 5) : (v == 3 ? 4 : v == 4 ? 6 : -1);
     if (slot >= 0) atomicAdd(&acc[slot], sum);
@@ -1030,7 +1153,11 @@ int batched_plan(const ot_batch_desc* h, int count, int32_t* plan) {
       const int m = h[p].n / h[p].K;
       vorder[q] = p;
       vstart[q] = (int32_t)nv;
-      nv += 2 * ((m + kAdjPts - 1) / kAdjPts);
+      // value tiles of 4 block-0 points with gradients (one per wave), 16 without (four per
+      // wave) unless K takes the generic path
+      const bool kt = k_class(h[p].K) < 6;
+      const int ppt = (h[p].dx || h[p].dy || !kt) ? kAdjPts : kAdjPts * kValPts;
+      nv += 2 * ((m + ppt - 1) / ppt);
       ++q;
     }
   }

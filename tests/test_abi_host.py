@@ -151,6 +151,11 @@ def test_batched_plan_validation_and_order(B):
         d.n, d.K, d.dim, d.eps = n, K, 2, 0.1
         d.x = d.y = d.a = d.b = d.logK = d.f = d.g = d.out = 8
     plan = (ctypes.c_int32 * _lib.ot_batched_plan_len(3))()
+    # values only (no coordinate gradients): value tiles of 16 block-0 points, 2 ceil(m/16)
+    assert _lib.ot_batched_plan(descs, 3, plan) == 0
+    assert plan[1] == 2 + 8 + 6
+    for d in descs:
+        d.dx = d.dy = 8
     assert _lib.ot_batched_plan(descs, 3, plan) == 0
     H = 4 + 2 * 15                         # header: counts, then 14 value classes' bounds
     order = list(plan[H:H + 3])

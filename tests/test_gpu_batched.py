@@ -116,6 +116,30 @@ def test_batched_equals_unbatched_and_oracle(lib):
         _check_plan_at_gpu_iterations(batch, k, p, Ck, r, vb["iters"])
 
 
+def test_batched_values_only_equals_with_gradients(lib):
+    """A batch that asks for no gradients takes value tiles of 16 points (a different kernel
+    path): same potentials, iterations and values as the batch with gradients (the float64
+    sums differ only in their order)."""
+    probs = _problems(SMALL)
+    print("[batched values only] 12 problems", flush=True)
+    opts = lib.make_opts(tol=1e-6, max_iter=20000, fold_fp64=1)
+    bg = lib.Batch(probs, device=DEV)
+    bv = lib.Batch(probs, device=DEV, want_grad=False)
+    bg.run(opts)
+    bv.run(opts)
+    torch.cuda.synchronize()
+    assert torch.equal(bg.F, bv.F) and torch.equal(bg.G, bv.G)
+    og, ov = bg.OUT.cpu().numpy(), bv.OUT.cpu().numpy()
+    assert (og[:, 5:] == ov[:, 5:]).all()
+    for k in range(len(probs)):
+        scale = max(abs(og[k, 0]), og[k, 2])
+        assert abs(og[k, 0] - ov[k, 0]) <= 1e-9 * scale, k
+        assert abs(og[k, 1] - ov[k, 1]) <= 1e-9 * scale, k
+        assert abs(og[k, 2] - ov[k, 2]) <= 1e-9 * og[k, 2], k
+        assert abs(og[k, 3] - ov[k, 3]) <= 1e-6 * og[k, 3] + 1e-15, k
+        assert abs(og[k, 4] - ov[k, 4]) <= 1e-6 * og[k, 4] + 1e-15, k
+
+
 def test_batched_full_workload_sampled(lib):
     """The uneven workload: 1024 problems, m log-uniform in [32, 1024], K in {4, 8, 16, 32},
     2-D or 3-D, eps = 0.05 median(C) each; every problem converges, sampled problems match
