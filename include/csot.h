@@ -234,13 +234,17 @@ int ot_lot_expand(const ot_problem* prob, const float* S, const int32_t* kmin, f
  *   sum_{k,j} max(0, w_i + z_j - C_ijk) = lam alpha_i   (Newton on the piecewise linear sum),
  * then every z_j likewise; alpha, beta are the folded marginals.  The plan is
  * T_ijk = max(0, w_i + z_j - C_ijk) / lam (eq. optimality_condition), expanded by Lemma 1.
- * With tol > 0 the float64 residuals are computed and copied to the host after every iteration
- * (the call synchronises there; not for graph capture) and it stops when the full-space row
- * residual sqrt(K) ||T 1 - alpha||_2 <= opts->tol; tol = 0 runs exactly max_iter iterations
- * and evaluates the residuals once, at the end.  hstats [host] is required.  With K = 1 and
- * the full cost the same call solves the full-size problem.  The workspace holds the folded
- * marginals and the residuals (ot_srot_workspace_bytes).  Errors: OT_ERR_ARG, OT_ERR_WORKSPACE,
- * OT_ERR_NOCONV (outputs valid), OT_ERR_NONFINITE, OT_ERR_HIP. */
+ * The iterations run in one persistent launch whose workgroups exchange the potentials
+ * through device memory and test convergence on the device: with tol > 0 it stops after the
+ * first iteration whose full-space row residual sqrt(K) ||T 1 - alpha||_2 (float64 sums) is at
+ * most opts->tol; tol = 0 runs exactly max_iter iterations.  The float64 residuals are then
+ * evaluated once and hstats [host, required] is filled by one copy at the end (the call
+ * synchronises there, once).  With K = 1 and the full cost the same call solves the full-size
+ * problem.  m is limited by the staged potential (about 16000 points); beyond it the call
+ * fails with OT_ERR_UNSUPPORTED.  The workspace holds the folded marginals, the residuals,
+ * the exchange slots and the statistics (ot_srot_workspace_bytes).  Errors: OT_ERR_ARG,
+ * OT_ERR_WORKSPACE, OT_ERR_UNSUPPORTED, OT_ERR_NOCONV (outputs valid), OT_ERR_NONFINITE,
+ * OT_ERR_HIP (also a timed-out exchange wait). */
 size_t ot_srot_workspace_bytes(const ot_problem* prob);
 int ot_srot_reduced(const ot_problem* prob, double lam, const ot_opts* opts, float* w, float* z,
                     ot_stats* hstats, void* ws, size_t ws_bytes, void* stream);

@@ -430,9 +430,12 @@ int ot_srot_reduced(const ot_problem* prob, double lam, const ot_opts* opts, flo
   if (o.warm_start == 2) return fail(OT_ERR_ARG, "warm_start must be 0 or 1");
   const csot::Geom geo = geom(prob);
   if ((rc = check_ws(ws, ws_bytes, csot::srot_ws_bytes(geo)))) return rc;
-  double res[4] = {0, 0, 0, 0};
-  hipError_t e = csot::run_srot(geo, lam, o.tol, o.max_iter, 1, o.warm_start, w, z,
-                                ws, static_cast<hipStream_t>(stream), res);
+  if (!csot::srot_supported(geo))
+    return fail(OT_ERR_UNSUPPORTED, "m = %d: the staged potential exceeds the LDS of a workgroup",
+                geo.m);
+  double res[6] = {0, 0, 0, 0, 0, 0};
+  hipError_t e = csot::run_srot(geo, lam, o.tol, o.max_iter, o.warm_start, w, z, ws, res,
+                                static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "srot launch");
   *hstats = ot_stats{};
   hstats->iters = (int32_t)res[0];
@@ -440,8 +443,10 @@ int ot_srot_reduced(const ot_problem* prob, double lam, const ot_opts* opts, flo
   hstats->err_row = res[2];
   hstats->err_col = res[3];
   hstats->err_row32 = res[2];
-  if (!std::isfinite(res[2]) || !std::isfinite(res[3])) {
-    hstats->flags = 1;
+  hstats->flags = (int32_t)res[5];
+  if ((int32_t)res[5] & 2) return fail(OT_ERR_HIP, "srot solver: an exchange wait timed out");
+  if (!std::isfinite(res[2]) || !std::isfinite(res[3]) || ((int32_t)res[5] & 1)) {
+    hstats->flags |= 1;
     return fail(OT_ERR_NONFINITE, "non-finite residual");
   }
   if (!hstats->converged && o.tol > 0.0) return fail(OT_ERR_NOCONV, "max_iter reached");

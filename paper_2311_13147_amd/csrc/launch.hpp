@@ -30,8 +30,9 @@ hipError_t launch_lot_expand(int m, int K, const float* S, const int32_t* kmin, 
 
 // ---- srot.hip ----------------------------------------------------------------------------
 size_t srot_ws_bytes(const Geom& g);
-hipError_t run_srot(const Geom& g, double lam, double tol, int max_iter, int check_every,
-                    int warm, float* w, float* z, void* ws, hipStream_t s, double* res);
+bool srot_supported(const Geom& g);
+hipError_t run_srot(const Geom& g, double lam, double tol, int max_iter, int warm, float* w,
+                    float* z, void* ws, double* res, hipStream_t s);
 
 // ---- peaks.hip ---------------------------------------------------------------------------
 constexpr size_t kPeaksCopyBytes = 256ull << 20;  // copy benchmark: source and destination each
