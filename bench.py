@@ -59,6 +59,9 @@ def _args():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--batched", action="store_true",
                     help="only time the batched workload (1024 uneven cyclic problems) and exit")
+    ap.add_argument("--batched-calls", action="store_true",
+                    help="only the batched calls, with and without gradients (no full-size "
+                         "comparison): a short program for counter runs")
     ap.add_argument("--two-stage", action="store_true",
                     help="only the approximate-symmetry workload: cold full vs two-stage")
     ap.add_argument("--images", action="store_true",
@@ -224,6 +227,27 @@ def batched_only(steps, warmup):
     e1.record()
     torch.cuda.synchronize()
     print(json.dumps(leg.report(e0.elapsed_time(e1) / steps, steps)), flush=True)
+
+
+def batched_calls_only(steps, warmup):
+    """Warm-up + timed batched calls with gradients, then the same without gradients; nothing
+    else (hardware-counter runs profile every dispatch, so the program is kept short)."""
+    import torch
+
+    leg = BatchedLeg()
+    out = {}
+    for name, b in (("with_gradients", leg.batch), ("forward_only", leg.batch_fwd)):
+        for _ in range(warmup):
+            b.run(leg.opts)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            b.run(leg.opts)
+        e1.record()
+        torch.cuda.synchronize()
+        out[name + "_ms"] = round(e0.elapsed_time(e1) / steps, 3)
+    print(json.dumps({"workload": "batched: 1024 cyclic problems (calls only)", **out}), flush=True)
 
 
 def two_stage_only(steps, warmup):
@@ -501,6 +525,9 @@ def main():
         return
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.batched_calls:
+        batched_calls_only(args.steps, args.warmup)
         return
     if args.batched:
         batched_only(args.steps, args.warmup)

@@ -1,7 +1,7 @@
 // Many independent reduced problems of uneven size in one stream of four launches, all
 // capturable in a HIP graph (no host synchronisation, no memset, no allocation):
 //
-//   1. fold   : tiles of 16 rows of one problem -> logK (base 2) and its transpose, alpha, beta
+//   1. fold   : tiles of 32 rows of one problem -> logK (base 2) and its transpose, alpha, beta
 //               (eq. def_Kij; Alg. 3 stage-1 averaging of the marginals);
 //   2. solve  : ONE persistent launch; each workgroup pops the next problem from a device work
 //               queue (largest first) and runs the cyclic Sinkhorn loop of Alg. 2 on it alone,
@@ -25,7 +25,6 @@
 
 namespace csot {
 
-constexpr int kBT = 16;            // rows (or columns) per fold / values tile
 constexpr int kBSolveThreads = 1024;
 constexpr int kBSolveWaves = kBSolveThreads / kWave;
 constexpr int kBMaxLds = 148 * 1024;
@@ -57,103 +56,222 @@ __device__ __forceinline__ Real bcost(const float* __restrict__ x, int I,
 }
 
 // ---- 1. fold -------------------------------------------------------------------------------
-// A tile is 16 rows of one problem; a thread owns one column j and 4 of the rows, so each
-// y_{k m + j} it loads feeds 4 cost evaluations.  Two passes over k: the minimum cost per row,
-// then the shifted exponential sum.  fp64 (default): costs, minimum and shifted exponents in
-// float64, exponentials of the (non-positive) shifted exponents in float32 -- logK accurate
-// to float32 rounding; otherwise all float32.  Output in base 2 (log2 of the folded kernel).
-constexpr int kFoldQ = 4;  // rows per thread
+// A tile is kFoldRows rows of one problem, kFoldQ of them per wave; a lane owns one column j of
+// a 64-column chunk.  The rows of a wave are the same for all its lanes, so their terms a =
+// 2 s2 x_i live in scalar registers and enter the vector FMAs as scalar operands, leaving the
+// vector registers to the per-lane state (shift and sum of each row).  For each chunk the
+// target points y_{k m + j} of up to kFoldKC shifts are staged in LDS (float32 coordinates
+// and -s2 |y|^2 in float64, formed once per point); with K <= kFoldKC one staging serves both
+// passes and the next chunk's points are fetched into registers while this one is computed.
+// Each staged point serves the tile's kFoldRows rows.  Two passes over k: the shift, then
+// the shifted exponential sum.  Output in base 2 (log2 of the folded kernel), in both layouts.
+//
+// fp64 (default): with s2 = log2(e) / eps, a = 2 s2 x_i (per row) and P = s2 |y|^2 (per
+// staged point), u_k = a . y_k - P_k = s2 (|x_i|^2 - C_ijk) costs DIM float64 FMAs; pass 1
+// takes U = max_k u_k, pass 2 sums 2^(u_k - U) (exponents formed in float64, exponentials in
+// float32), and log2 K_ij = U - s2 |x_i|^2 + log2(sum).  Expanding the square cancels terms
+// of size s2 (|x|^2 + |y|^2), which float64 carries with ~1e-16 relative rounding: the
+// exponents stay exact far below float32's output rounding.  fp32 (fold_fp64 = 0): the
+// squared differences directly in float32 (no cancellation beyond the cost's own rounding).
+constexpr int kFoldQ = 8;                        // rows per wave
+constexpr int kFoldThreads = 256;                // 4 waves
+constexpr int kFoldRows = kFoldQ * kFoldThreads / kWave;  // rows per tile (32)
+constexpr int kFoldJC = 64;                      // target columns j per staging (one per lane)
+constexpr int kFoldKC = 32;                      // shifts k per staging
+constexpr int kFoldSR = kFoldKC * kFoldJC / kFoldThreads;  // staged points per thread
+constexpr int kFoldCB = 256;                     // columns per tile
 
-constexpr int kFoldJC = 64;  // target columns j per LDS staging (one per lane of a wave)
-constexpr int kFoldKC = 32;  // shifts k per LDS staging
+__host__ __device__ __forceinline__ int fold_row_blocks(int m) {
+  return (m + kFoldRows - 1) / kFoldRows;
+}
+__host__ __device__ __forceinline__ int fold_col_blocks(int m) {
+  return (m + kFoldCB - 1) / kFoldCB;
+}
 
-// A fold tile: rows [i0, i0 + rows) (four groups of kFoldQ rows, one group per wave) against
-// every column j.  For each chunk of 64 columns the target points y_{k m + j} of up to 32
-// shifts are staged in LDS (K <= 32: one staging serves both passes), so each cost is an LDS
-// read and a few FMAs and every staged point serves the tile's 16 rows.
-template <int DIM, typename Real>
-__device__ __forceinline__ void fold_cols(const ot_batch_desc& d, int i0, int rows, float* L,
-                                          float* LT, float* __restrict__ ys) {
+template <int DIM>
+struct FoldShared {
+  float y[DIM * kFoldKC * kFoldJC];  // [DIM][kFoldKC][kFoldJC], as given
+  double np[kFoldKC * kFoldJC];      // -s2 |y|^2
+};
+
+// max(a, b) of two float64 values by v_max_f64 alone: a running maximum through fmax is
+// re-canonicalised (NaN-quieted) on every use, which costs a second instruction per term.
+__device__ __forceinline__ double vmax_f64(double a, double b) {
+  double r;
+  asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
+// A wave-uniform double moved to scalar registers.
+__device__ __forceinline__ double uniform_d(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+__device__ __forceinline__ void store_fold_row(float* L, float* LT, int mp, int i0, int rows,
+                                               int ib, int j, const float (&v)[kFoldQ]) {
+#pragma unroll
+  for (int q = 0; q < kFoldQ; ++q)
+    if (ib + q < i0 + rows) L[(size_t)(ib + q) * mp + j] = v[q];
+  float* lt = LT + (size_t)j * mp + ib;  // ib is a multiple of 8 and mp of 4: 16-byte aligned
+  if (ib + kFoldQ <= i0 + rows) {
+#pragma unroll
+    for (int q = 0; q < kFoldQ; q += 4)
+      *reinterpret_cast<float4*>(lt + q) = make_float4(v[q], v[q + 1], v[q + 2], v[q + 3]);
+  } else {
+    for (int q = 0; q < kFoldQ && ib + q < i0 + rows; ++q) lt[q] = v[q];
+  }
+}
+
+template <int DIM, bool F64>
+__device__ void fold_tile(const ot_batch_desc& d, int rb, int cb, FoldShared<DIM>& sh) {
   const int m = bm(d), K = d.K, mp = bmp(m);
-  const Real s2 = (Real)(kLog2eD / d.eps);
+  const int i0 = rb * kFoldRows, jb = cb * kFoldCB, je = min(m, jb + kFoldCB);
+  float* L = d.logK;
+  float* LT = L + (size_t)m * mp;
+  const int rows = min(kFoldRows, m - i0);
+  const double s2 = kLog2eD / d.eps;
+  const float s2f = (float)s2;
   const int tj = threadIdx.x % kFoldJC, grp = threadIdx.x / kFoldJC;
   const int ib = i0 + grp * kFoldQ;
-  const bool grp_active = ib < i0 + rows;  // inactive groups still stage and meet barriers
+  const bool grp_active = ib < i0 + rows;  // inactive waves still stage and meet barriers
+  // the wave's rows: a = 2 s2 x (float64, scalar registers) or x (float32)
+  double ax[kFoldQ][DIM];
   float xf[kFoldQ][DIM];
-  Real xq[kFoldQ][DIM];
 #pragma unroll
   for (int q = 0; q < kFoldQ; ++q) {
     const int i = min(ib + q, i0 + rows - 1);
 #pragma unroll
     for (int dd = 0; dd < DIM; ++dd) {
       xf[q][dd] = d.x[(int64_t)i * DIM + dd];
-      xq[q][dd] = (Real)xf[q][dd];
+      ax[q][dd] = uniform_d(2.0 * s2 * (double)xf[q][dd]);
     }
   }
   const int nkc = (K + kFoldKC - 1) / kFoldKC;
-  auto Y = [&](int kk, int dd, int t) -> float& { return ys[(kk * DIM + dd) * kFoldJC + t]; };
-  auto stage = [&](int kc, int j0) {
+  // staging in two steps: the global loads into registers, then the LDS stores
+  float pre[kFoldSR][DIM];
+  auto fetch = [&](int kc, int j0) {
     const int kb = kc * kFoldKC, nk = min(kFoldKC, K - kb);
-    for (int e = threadIdx.x; e < nk * kFoldJC; e += blockDim.x) {
-      const int kk = e / kFoldJC, t = e - kk * kFoldJC, jj = j0 + t;
+#pragma unroll
+    for (int r = 0; r < kFoldSR; ++r) {
+      const int e = threadIdx.x + r * kFoldThreads, kk = e / kFoldJC, jj = j0 + e % kFoldJC;
 #pragma unroll
       for (int dd = 0; dd < DIM; ++dd)
-        Y(kk, dd, t) = jj < m ? d.y[((int64_t)(kb + kk) * m + jj) * DIM + dd] : 0.0f;
+        pre[r][dd] = kk < nk && jj < m ? d.y[((int64_t)(kb + kk) * m + jj) * DIM + dd] : 0.0f;
     }
   };
-  for (int j0 = 0; j0 < m; j0 += kFoldJC) {
-    const int j = j0 + tj;
-    const bool active = grp_active && j < m;
-    // pass 1 (float32): the shift, the minimum cost up to float32 rounding -- any shift that
-    // close to the minimum keeps every shifted exponent <= ~0, and the same value is added
-    // back exactly
-    float cminf[kFoldQ];
+  auto put = [&](int kc) {
+    const int nk = min(kFoldKC, K - kc * kFoldKC);
 #pragma unroll
-    for (int q = 0; q < kFoldQ; ++q) cminf[q] = 3.0e38f;
+    for (int r = 0; r < kFoldSR; ++r) {
+      const int e = threadIdx.x + r * kFoldThreads, kk = e / kFoldJC, t = e % kFoldJC;
+      if (kk < nk) {
+        double n2 = 0.0;
+#pragma unroll
+        for (int dd = 0; dd < DIM; ++dd) {
+          sh.y[(dd * kFoldKC + kk) * kFoldJC + t] = pre[r][dd];
+          n2 = fma((double)pre[r][dd], (double)pre[r][dd], n2);
+        }
+        if constexpr (F64) sh.np[kk * kFoldJC + t] = -s2 * n2;
+      }
+    }
+  };
+  auto ld = [&](int kk, float (&yv)[DIM], double& np) {
+#pragma unroll
+    for (int dd = 0; dd < DIM; ++dd) yv[dd] = sh.y[(dd * kFoldKC + kk) * kFoldJC + tj];
+    if constexpr (F64) np = sh.np[kk * kFoldJC + tj];
+  };
+  if (nkc == 1) fetch(0, jb);
+  for (int j0 = jb; j0 < je; j0 += kFoldJC) {
+    const int j = j0 + tj;
+    const bool active = grp_active && j < je;
+    double U[kFoldQ];
+    float cminf[kFoldQ], sum[kFoldQ];
+#pragma unroll
+    for (int q = 0; q < kFoldQ; ++q) {
+      U[q] = -INFINITY;
+      cminf[q] = 3.0e38f;
+      sum[q] = 0.0f;
+    }
+    // pass 1: the shift (F64: U = max_k u_k; fp32: the minimum cost)
     for (int kc = 0; kc < nkc; ++kc) {
       __syncthreads();  // the previous staging's readers are done
-      stage(kc, j0);
+      if (nkc > 1) fetch(kc, j0);
+      put(kc);
       __syncthreads();
+      if (nkc == 1 && j0 + kFoldJC < je) fetch(0, j0 + kFoldJC);  // in flight during the passes
       const int nk = min(kFoldKC, K - kc * kFoldKC);
       if (active) {
-#pragma unroll 4
+#pragma unroll 2
         for (int kk = 0; kk < nk; ++kk) {
           float yv[DIM];
+          double np = 0.0;
+          ld(kk, yv, np);
+          if constexpr (F64) {
+            double yd[DIM];
 #pragma unroll
-          for (int dd = 0; dd < DIM; ++dd) yv[dd] = Y(kk, dd, tj);
+            for (int dd = 0; dd < DIM; ++dd) yd[dd] = (double)yv[dd];
 #pragma unroll
-          for (int q = 0; q < kFoldQ; ++q) {
-            float c = 0.0f;
+            for (int q = 0; q < kFoldQ; ++q) {
+              double u = np;
 #pragma unroll
-            for (int dd = 0; dd < DIM; ++dd) { const float df = xf[q][dd] - yv[dd]; c = fmaf(df, df, c); }
-            cminf[q] = fminf(c, cminf[q]);
+              for (int dd = 0; dd < DIM; ++dd) u = fma(ax[q][dd], yd[dd], u);
+              U[q] = vmax_f64(U[q], u);
+            }
+          } else {
+#pragma unroll
+            for (int q = 0; q < kFoldQ; ++q) {
+              float c = 0.0f;
+#pragma unroll
+              for (int dd = 0; dd < DIM; ++dd) {
+                const float df = xf[q][dd] - yv[dd];
+                c = fmaf(df, df, c);
+              }
+              cminf[q] = fminf(c, cminf[q]);
+            }
           }
         }
       }
     }
-    Real cmin[kFoldQ];
-#pragma unroll
-    for (int q = 0; q < kFoldQ; ++q) cmin[q] = (Real)cminf[q];
-    float sum[kFoldQ] = {};
+    // pass 2: the shifted exponential sum
     for (int kc = 0; kc < nkc; ++kc) {
       if (nkc > 1) {
         __syncthreads();
-        stage(kc, j0);
+        fetch(kc, j0);
+        put(kc);
         __syncthreads();
       }
       const int nk = min(kFoldKC, K - kc * kFoldKC);
       if (active) {
-#pragma unroll 4
+#pragma unroll 2
         for (int kk = 0; kk < nk; ++kk) {
-          Real yv[DIM];
+          float yv[DIM];
+          double np = 0.0;
+          ld(kk, yv, np);
+          if constexpr (F64) {
+            double yd[DIM];
 #pragma unroll
-          for (int dd = 0; dd < DIM; ++dd) yv[dd] = (Real)Y(kk, dd, tj);
+            for (int dd = 0; dd < DIM; ++dd) yd[dd] = (double)yv[dd];
 #pragma unroll
-          for (int q = 0; q < kFoldQ; ++q) {
-            Real c = 0;
+            for (int q = 0; q < kFoldQ; ++q) {
+              double u = np - U[q];
 #pragma unroll
-            for (int dd = 0; dd < DIM; ++dd) { const Real df = xq[q][dd] - yv[dd]; c = fma(df, df, c); }
-            sum[q] += exp2_fast((float)((cmin[q] - c) * s2));
+              for (int dd = 0; dd < DIM; ++dd) u = fma(ax[q][dd], yd[dd], u);
+              sum[q] += exp2_fast((float)u);
+            }
+          } else {
+#pragma unroll
+            for (int q = 0; q < kFoldQ; ++q) {
+              float c = 0.0f;
+#pragma unroll
+              for (int dd = 0; dd < DIM; ++dd) {
+                const float df = xf[q][dd] - yv[dd];
+                c = fmaf(df, df, c);
+              }
+              sum[q] += exp2_fast((cminf[q] - c) * s2f);
+            }
           }
         }
       }
@@ -161,47 +279,39 @@ __device__ __forceinline__ void fold_cols(const ot_batch_desc& d, int i0, int ro
     if (active) {
       float v[kFoldQ];
 #pragma unroll
-      for (int q = 0; q < kFoldQ; ++q) v[q] = (float)(-cmin[q] * s2 + (Real)log2_fast(sum[q]));
+      for (int q = 0; q < kFoldQ; ++q) {
+        if constexpr (F64) {
+          double xx = 0.0;  // s2 |x|^2 = |a|^2 / (4 s2)
 #pragma unroll
-      for (int q = 0; q < kFoldQ; ++q)
-        if (ib + q < i0 + rows) L[(size_t)(ib + q) * mp + j] = v[q];
-      float* lt = LT + (size_t)j * mp + ib;  // ib is a multiple of 4 and mp too: 16-byte aligned
-      if (ib + kFoldQ <= i0 + rows) {
-        *reinterpret_cast<float4*>(lt) = make_float4(v[0], v[1], v[2], v[3]);
-      } else {
-        for (int q = 0; q < kFoldQ && ib + q < i0 + rows; ++q) lt[q] = v[q];
+          for (int dd = 0; dd < DIM; ++dd) xx = fma(ax[q][dd], ax[q][dd], xx);
+          v[q] = (float)((U[q] - xx / (4.0 * s2)) + (double)log2_fast(sum[q]));
+        } else {
+          v[q] = -cminf[q] * s2f + log2_fast(sum[q]);
+        }
       }
+      store_fold_row(L, LT, mp, i0, rows, ib, j, v);
     }
   }
-}
-
-template <int DIM>
-__device__ void fold_tile(const ot_batch_desc& d, int i0, int fp64_mode) {
-  const int m = bm(d), K = d.K, mp = bmp(m);
-  float* L = d.logK;
-  float* LT = L + (size_t)m * mp;
-  const int rows = min(kBT, m - i0);
-  __shared__ float ys[kFoldKC * DIM * kFoldJC];
-  if (fp64_mode != 0) fold_cols<DIM, double>(d, i0, rows, L, LT, ys);
-  else fold_cols<DIM, float>(d, i0, rows, L, LT, ys);
-  // padding: -inf contributes nothing to a log-sum-exp
-  for (int e = threadIdx.x; e < rows * (mp - m); e += blockDim.x) {
-    const int i = i0 + e / (mp - m), j = m + e % (mp - m);
-    L[(size_t)i * mp + j] = -INFINITY;
+  // padding: -inf contributes nothing to a log-sum-exp.  Columns [m, mp) of the tile's rows
+  // (by the last column block), and of the transpose's rows j of the tile's columns (by the
+  // first row block)
+  if (cb == fold_col_blocks(m) - 1) {
+    for (int e = threadIdx.x; e < rows * (mp - m); e += blockDim.x) {
+      const int i = i0 + e / (mp - m), j = m + e % (mp - m);
+      L[(size_t)i * mp + j] = -INFINITY;
+    }
   }
-  // padding columns of the transpose (rows j < m, columns i in [m, mp)) are written by the
-  // first tile
-  if (i0 == 0) {
-    for (int e = threadIdx.x; e < m * (mp - m); e += blockDim.x) {
-      const int j = e / (mp - m), i = m + e % (mp - m);
+  if (rb == 0) {
+    for (int e = threadIdx.x; e < (je - jb) * (mp - m); e += blockDim.x) {
+      const int j = jb + e / (mp - m), i = m + e % (mp - m);
       LT[(size_t)j * mp + i] = -INFINITY;
     }
   }
-  if (i0 == 0) {  // exchange slots of a gang solve: epochs start at 1, so zero means "none"
+  if (rb == 0 && cb == 0) {  // exchange slots of a gang solve: epochs start at 1 ("none" = 0)
     uint32_t* sw = reinterpret_cast<uint32_t*>(LT + (size_t)m * mp + 2 * (size_t)m);
     for (int e = threadIdx.x; e < 2 * (2 * mp + 2 * kMaxGangF); e += blockDim.x) sw[e] = 0u;
   }
-  if (i0 == 0) {  // folded marginals
+  if (rb == 0 && cb == 0) {  // folded marginals
     float* al = LT + (size_t)m * mp;
     float* be = al + m;
     for (int i = threadIdx.x; i < 2 * m; i += blockDim.x) {
@@ -214,15 +324,20 @@ __device__ void fold_tile(const ot_batch_desc& d, int i0, int fp64_mode) {
   }
 }
 
-__global__ void __launch_bounds__(256)
+// Tiles in the solve order (the largest problems first, so that the small tiles fill the
+// end of the launch); a tile is (row block, column block) of problem order[q].
+template <bool F64>
+__global__ void __launch_bounds__(kFoldThreads)
     batched_fold_kernel(const ot_batch_desc* __restrict__ descs, int count,
-                        const int32_t* __restrict__ tile_start, int fp64_mode) {
-  const int p = find_problem(tile_start, count, blockIdx.x);
-  const ot_batch_desc d = descs[p];
-  const int i0 = (blockIdx.x - tile_start[p]) * kBT;
-  if (i0 >= bm(d)) return;
-  if (d.dim == 3) fold_tile<3>(d, i0, fp64_mode);
-  else fold_tile<2>(d, i0, fp64_mode);
+                        const int32_t* __restrict__ order, const int32_t* __restrict__ tile_start) {
+  const int q = find_problem(tile_start, count, blockIdx.x);
+  const ot_batch_desc d = descs[order[q]];
+  const int m = bm(d), ncb = fold_col_blocks(m);
+  const int t = blockIdx.x - tile_start[q];
+  if (t >= fold_row_blocks(m) * ncb) return;
+  __shared__ FoldShared<3> sh;
+  if (d.dim == 3) fold_tile<3, F64>(d, t / ncb, t % ncb, sh);
+  else fold_tile<2, F64>(d, t / ncb, t % ncb, *reinterpret_cast<FoldShared<2>*>(&sh));
 }
 
 // ---- 2. solve ------------------------------------------------------------------------------
@@ -1096,6 +1211,7 @@ static int v_class(int dim, int K) { return (dim == 3 ? kKClasses : 0) + k_class
 
 // plan = {nfold, nval, count, ntasks, cls_q[kVClasses + 1], cls_tile[kVClasses + 1],
 //         order[count], fold_start[count], vorder[count], vstart[count], tasks[ntasks]}:
+// fold_start[q] is the first fold tile of problem order[q];
 // problems of value class c are vorder[cls_q[c] .. cls_q[c + 1]), their value tiles
 // [cls_tile[c], cls_tile[c + 1]); vstart[q] is the first value tile of vorder[q].
 constexpr int kPlanHead = 4 + 2 * (kVClasses + 1);
@@ -1132,11 +1248,11 @@ int batched_plan(const ot_batch_desc* h, int count, int32_t* plan) {
   uint32_t* tasks = reinterpret_cast<uint32_t*>(vstart + count);
   int64_t nf = 0, nv = 0;
   int nt = 0;
-  for (int p = 0; p < count; ++p) {
-    order[p] = idx[p];
-    const int m = h[p].n / h[p].K;
-    fstart[p] = (int32_t)nf;
-    nf += (m + kBT - 1) / kBT;
+  for (int q = 0; q < count; ++q) {  // fold tiles in the solve order: the largest first
+    order[q] = idx[q];
+    const int m = h[idx[q]].n / h[idx[q]].K;
+    fstart[q] = (int32_t)nf;
+    nf += (int64_t)fold_row_blocks(m) * fold_col_blocks(m);
   }
   // value tiles by class, problems in index order within a class
   std::vector<int> vo(count);
@@ -1203,8 +1319,12 @@ hipError_t launch_batched(const ot_batch_desc* descs, int count, const int32_t* 
   const int32_t* fstart = order + count;
   const int32_t* vorder = fstart + count;
   const int32_t* vstart = vorder + count;
-  hipLaunchKernelGGL(batched_fold_kernel, dim3(nfold), dim3(256), 0, s, descs, count, fstart,
-                     fold_fp64);
+  if (fold_fp64 != 0)
+    hipLaunchKernelGGL(batched_fold_kernel<true>, dim3(nfold), dim3(kFoldThreads), 0, s, descs,
+                       count, order, fstart);
+  else
+    hipLaunchKernelGGL(batched_fold_kernel<false>, dim3(nfold), dim3(kFoldThreads), 0, s, descs,
+                       count, order, fstart);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   static bool attr = false;
   if (!attr) {

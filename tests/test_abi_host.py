@@ -160,7 +160,7 @@ def test_batched_plan_validation_and_order(B):
     H = 4 + 2 * 15                         # header: counts, then 14 value classes' bounds
     order = list(plan[H:H + 3])
     assert order == [1, 2, 0]              # m = 16, 64, 48: largest first
-    assert list(plan[H + 3:H + 6]) == [0, 1, 5]   # fold tiles: ceil(m/16) = 1, 4, 3
+    assert list(plan[H + 3:H + 6]) == [0, 2, 4]   # fold tiles in that order: ceil(m/32) = 2, 2, 1
     # value tiles grouped by (dim, K) class -- K = 2 (problem 2), K = 4 (0), K = 8 (1) -- each
     # 2 ceil(m/4) tiles of 4 block-0 points (rows, then columns): 24, 8, 32
     assert list(plan[H + 6:H + 9]) == [2, 0, 1]
@@ -168,7 +168,7 @@ def test_batched_plan_validation_and_order(B):
     cls_q, cls_tile = list(plan[4:19]), list(plan[19:34])
     assert cls_q[:5] == [0, 0, 1, 2, 3] and cls_q[14] == 3
     assert cls_tile[:5] == [0, 0, 24, 32, 64] and cls_tile[14] == 64
-    assert plan[0] == 8 and plan[1] == 64
+    assert plan[0] == 5 and plan[1] == 64   # fold tiles 1 + 2 + 2
     descs[1].K = 7                          # 512 % 7 != 0
     assert _lib.ot_batched_plan(descs, 3, plan) == B.OT_ERR_ARG
     descs[1].K, descs[1].tile_cfg = 8, 24
