@@ -1007,80 +1007,85 @@ __device__ void badj_point(const ot_batch_desc& d, int o, bool active, int lane,
 // the marginal terms, as badj_point.
 constexpr int kValPts = 4;  // own points per wave in values-only tiles
 
-template <int DIM, int KT, bool ROW>
-__device__ void bval_points(const ot_batch_desc& d, int o0, int lane, const float* own_y4,
-                            double (*vals)[8], float* sh_pts, float* sh_pot) {
+template <int DIM, int KT>
+__device__ void bval_points(const ot_batch_desc& d, int o0, int lane, int wv,
+                            double (*vals)[8], float* sh_pts, float* sh_pot, double* sh_cols,
+                            double* __restrict__ colpart) {
   const int m = bm(d), K = d.K;
   const float s2 = (float)(kLog2eD / d.eps);
-  const float eps = (float)d.eps;
   gcfloat* x = as_global(d.x);
   gcfloat* y = as_global(d.y);
   gcfloat* fpot = as_global(d.f);
   gcfloat* gpot = as_global(d.g);
-  gcfloat* src = ROW ? y : x;
   float po[kValPts], xo[kValPts][DIM];
   bool act[kValPts];
 #pragma unroll
   for (int q = 0; q < kValPts; ++q) {
     act[q] = o0 + q < m;
     const int oc = act[q] ? o0 + q : 0;
-    po[q] = ROW ? fpot[oc] : gpot[oc];
+    po[q] = fpot[oc];
 #pragma unroll
-    for (int dd = 0; dd < DIM; ++dd) xo[q][dd] = ROW ? x[oc * DIM + dd] : 0.0f;
+    for (int dd = 0; dd < DIM; ++dd) xo[q][dd] = x[oc * DIM + dd];
   }
   double S[kValPts] = {};
-  float vP[kValPts] = {}, vC[kValPts] = {};
+  float vC[kValPts] = {};
 #pragma unroll 1
   for (int c0 = 0; c0 < m; c0 += kAdjChunk) {
     __syncthreads();  // the previous chunk's readers are done
     const int nc = min(kAdjChunk, m - c0);
-    // rows need the partners' copies in every block (the costs' y_{k m + j}); columns only
-    // block 0 (x_i)
-    const int nb = ROW ? KT : 1;
-    for (int e = threadIdx.x; e < nb * DIM * kAdjChunk; e += blockDim.x) {
+    // the partners' copies in every block (the costs' y_{k m + j})
+    for (int e = threadIdx.x; e < KT * DIM * kAdjChunk; e += blockDim.x) {
       const int qq = e % kAdjChunk, cd = e / kAdjChunk;
       const int cb = cd / DIM, dd = cd - cb * DIM;
-      sh_pts[e] = qq < nc ? src[(cb * m + c0 + qq) * DIM + dd] : 0.0f;
+      sh_pts[e] = qq < nc ? y[(cb * m + c0 + qq) * DIM + dd] : 0.0f;
     }
     if (threadIdx.x < kAdjChunk)
-      sh_pot[threadIdx.x] = (int)threadIdx.x < nc ? (ROW ? gpot : fpot)[c0 + threadIdx.x] : 0.0f;
+      sh_pot[threadIdx.x] = (int)threadIdx.x < nc ? gpot[c0 + threadIdx.x] : 0.0f;
     __syncthreads();
-    if (lane >= nc) continue;
-    const float pp = sh_pot[lane];
-#pragma unroll 4
-    for (int k = 0; k < KT; ++k) {
-      float pt[DIM];
+    double col = 0.0;  // the lane's column j = c0 + lane: its terms over the wave's rows
+    if (lane < nc) {
+      const float pp = sh_pot[lane];
+#pragma unroll 2
+      for (int k = 0; k < KT; ++k) {
+        float pt[DIM];
 #pragma unroll
-      for (int dd = 0; dd < DIM; ++dd) pt[dd] = sh_pts[((ROW ? k : 0) * DIM + dd) * kAdjChunk + lane];
+        for (int dd = 0; dd < DIM; ++dd) pt[dd] = sh_pts[(k * DIM + dd) * kAdjChunk + lane];
 #pragma unroll
-      for (int q = 0; q < kValPts; ++q) {
-        float c = 0.0f;
+        for (int q = 0; q < kValPts; ++q) {
+          float c = 0.0f;
 #pragma unroll
-        for (int dd = 0; dd < DIM; ++dd) {
-          const float e = ROW ? xo[q][dd] - pt[dd] : pt[dd] - own_y4[(q * KT + k) * DIM + dd];
-          c = fmaf(e, e, c);
-        }
-        const float fg = po[q] + pp;
-        const float T = act[q] ? exp2_fast((fg - c) * s2) : 0.0f;
-        S[q] += (double)T;
-        if (ROW) {
-          vP[q] = fmaf(T, fg - eps, vP[q]);  // T (C + eps (Z - 1)) = T (f + g - eps)
+          for (int dd = 0; dd < DIM; ++dd) {
+            const float e = xo[q][dd] - pt[dd];
+            c = fmaf(e, e, c);
+          }
+          const float fg = po[q] + pp;
+          const float T = act[q] ? exp2_fast((fg - c) * s2) : 0.0f;
+          const double Td = (double)T;
+          S[q] += Td;
+          col += Td;
           vC[q] = fmaf(T, c, vC[q]);
         }
       }
     }
+    // the tile's partial column sums: the four waves' through LDS, one store per column
+    sh_cols[wv * kWave + lane] = col;
+    __syncthreads();
+    if (wv == 0 && lane < nc) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < kAdjPts; ++w) t += sh_cols[w * kWave + lane];
+      colpart[c0 + lane] = t;
+    }
   }
-  gcfloat* marg_in = as_global(ROW ? d.a : d.b);
-  gcfloat* pot = ROW ? fpot : gpot;
+  gcfloat* marg_in = as_global(d.a);
   double ps = 0.0;
-  for (int qq = lane; qq < m; qq += kWave) ps += (double)pot[qq];
+  for (int qq = lane; qq < m; qq += kWave) ps += (double)fpot[qq];
   const double pmean = wave_sum_all_d(ps) / m;
-  float* __restrict__ dpot = ROW ? d.da : d.db;
+  float* __restrict__ dpot = d.da;
 #pragma unroll
   for (int q = 0; q < kValPts; ++q) {
     const double Sq = wave_sum_all_d(S[q]);
-    const double tP = ROW ? wave_sum_all_d((double)vP[q]) : 0.0;
-    const double tC = ROW ? wave_sum_all_d((double)vC[q]) : 0.0;
+    const double tC = wave_sum_all_d((double)vC[q]);
     if (!act[q]) continue;
     const int o = o0 + q;
     double mv = 0.0;
@@ -1090,24 +1095,41 @@ __device__ void bval_points(const ot_batch_desc& d, int o0, int lane, const floa
       for (int r = lane; r < K; r += kWave) dpot[r * m + o] = (float)((double)po[q] - pmean);
     if (lane == 0) {
       const double dr = Sq - marg;
-      vals[q][0] = tP;
+      // sum_{j,k} T_ijk (f_i + g_j - eps) = (f_i - eps) rowsum_i + (the g_j colsum_j terms,
+      // added by batched_finalize_kernel from the column sums)
+      vals[q][0] = ((double)po[q] - d.eps) * Sq;
       vals[q][1] = tC;
-      vals[q][2] = ROW ? Sq : 0.0;
+      vals[q][2] = Sq;
       vals[q][3] = dr * dr;
       vals[q][4] = (double)po[q] * marg;
     }
   }
 }
 
+// Without coordinate gradients (and K with its own instantiation) a problem has only row
+// tiles: the column sums are accumulated in the same pass, each tile's partial per column
+// stored in the problem's folded-kernel scratch (no longer needed after the solve) as
+// colpart[tile][m] doubles, and the column statistics finished by batched_finalize_kernel.
+__host__ __device__ __forceinline__ bool fused_columns(const ot_batch_desc& d, bool kt) {
+  return d.dx == nullptr && d.dy == nullptr && kt;
+}
+__device__ __forceinline__ double* colpart_base(const ot_batch_desc& d) {
+  return reinterpret_cast<double*>(d.logK);
+}
+
 // Value tiles are grouped by (dim, K) class so that each class runs its own instantiation
 // (its own register allocation): the launch for a class covers the tiles [tile0, tile0 +
 // grid) of the problems vorder[0 .. nq), whose first tiles vstart[] increase.
-template <int DIM, int KT>
+//
+// VO selects the values-only problems of the class (with their fused column sums); the other
+// instantiation serves the problems with coordinate gradients.  Both are launched over the
+// class's tiles and a tile of the other kind returns at once, so each has its own register
+// allocation.
+template <int DIM, int KT, bool VO>
 __global__ void __launch_bounds__(256)
     batched_values_kernel(const ot_batch_desc* __restrict__ descs,
                           const int32_t* __restrict__ vorder, const int32_t* __restrict__ vstart,
                           int nq, int tile0, double* __restrict__ accs) {
-  __shared__ BAdjShared sh;
   __shared__ double vals16[kAdjPts * kValPts][8];
   const int tile = tile0 + (int)blockIdx.x;
   const int q = find_problem(vstart, nq, tile);
@@ -1116,14 +1138,16 @@ __global__ void __launch_bounds__(256)
   const int m = bm(d);
   // gradients: 4 own points per tile (one per wave); values only: 16 (four per wave)
   const bool grad = d.dx != nullptr || d.dy != nullptr;
-  const int ppt = (grad || KT == 0) ? kAdjPts : kAdjPts * kValPts;
+  if ((!grad && KT > 0) != VO) return;
+  const int ppt = VO ? kAdjPts * kValPts : kAdjPts;
   const int nrow = (m + ppt - 1) / ppt;
   const int t = tile - vstart[q];
   double* acc = accs + 8 * (size_t)p;
-  const bool row = t < nrow;
+  const bool row = t < nrow;  // values only: every tile is a row tile
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   const int first = (row ? t : t - nrow) * ppt;
-  if (ppt == kAdjPts) {
+  if constexpr (!VO) {
+    __shared__ BAdjShared sh;
     const int o = first + wv;
     const bool active = o < m;
     // column pass: the own column's y_{k m + j} of every block, staged per wave
@@ -1138,24 +1162,17 @@ __global__ void __launch_bounds__(256)
     __syncthreads();
     if (row) badj_point<DIM, KT, true>(d, o, active, lane, sh.own_y[wv], vals16[wv], sh.pts, sh.pot);
     else badj_point<DIM, KT, false>(d, o, active, lane, sh.own_y[wv], vals16[wv], sh.pts, sh.pot);
-  } else if constexpr (KT > 0) {
+  } else {
+    // row tiles only (the column sums in the same pass); LDS sized for the class
+    __shared__ float vo_pts[(KT > 0 ? KT : 1) * DIM * kAdjChunk];
+    __shared__ float vo_pot[kAdjChunk];
+    __shared__ double vo_cols[kAdjPts * kWave];
     const int o0 = first + wv * kValPts;
-    // column pass: y_{k m + j} of the wave's four own columns (the per-wave row of own_y holds
-    // 32 x 3 floats; four points of K <= 32 shifts use K DIM 4 <= 384 floats: the whole array)
-    float* own4 = &sh.own_y[0][0] + wv * (KT * DIM * kValPts);
-    if (!row) {
-      for (int e = lane; e < KT * DIM * kValPts; e += kWave) {
-        const int qq = e / (KT * DIM), r = e - qq * (KT * DIM);
-        const int k = r / DIM, dd = r - k * DIM;
-        const int o = min(o0 + qq, m - 1);
-        own4[e] = d.y[(k * m + o) * DIM + dd];
-      }
-    }
     if (lane < kValPts)
       for (int v = 0; v < 8; ++v) vals16[wv * kValPts + lane][v] = 0.0;
     __syncthreads();
-    if (row) bval_points<DIM, KT, true>(d, o0, lane, own4, &vals16[wv * kValPts], sh.pts, sh.pot);
-    else bval_points<DIM, KT, false>(d, o0, lane, own4, &vals16[wv * kValPts], sh.pts, sh.pot);
+    bval_points<DIM, KT>(d, o0, lane, wv, &vals16[wv * kValPts], vo_pts, vo_pot, vo_cols,
+                         colpart_base(d) + (size_t)t * m);
   }
   __syncthreads();
   // the workgroup's partials: one atomic add per value
@@ -1170,18 +1187,56 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-__global__ void batched_finalize_kernel(const ot_batch_desc* __restrict__ descs, int count,
-                                        const double* __restrict__ accs) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= count) return;
+// One workgroup per problem.  With the column sums fused into the row tiles it first
+// finishes the column statistics from the tiles' partials: sum_j (colsum_j - beta_j)^2 and
+// <g, beta>, beta the folded column marginal (float64 mean over the blocks).
+__global__ void __launch_bounds__(1024)
+    batched_finalize_kernel(const ot_batch_desc* __restrict__ descs,
+                            const double* __restrict__ accs) {
+  __shared__ double red[1024 / kWave];
+  const int p = blockIdx.x;
   const ot_batch_desc d = descs[p];
   const double* acc = accs + 8 * (size_t)p;
-  const double K = d.K;
-  d.out[0] = K * acc[0];
-  d.out[1] = K * (acc[5] + acc[6]) - d.eps * K * acc[2];
-  d.out[2] = K * acc[1];
-  d.out[3] = sqrt(K * acc[3]);
-  d.out[4] = sqrt(K * acc[4]);
+  const int m = bm(d), Ki = d.K;
+  const bool kt = Ki == 1 || Ki == 2 || Ki == 4 || Ki == 8 || Ki == 16 || Ki == 32;
+  double col_err = acc[4], col_dual = acc[6], primal_cols = 0.0;
+  if (fused_columns(d, kt)) {
+    const int ntile = (m + kAdjPts * kValPts - 1) / (kAdjPts * kValPts);
+    const double* colpart = colpart_base(d);
+    double e2 = 0.0, gb = 0.0, gs = 0.0, gc = 0.0;
+    for (int j = threadIdx.x; j < m; j += blockDim.x) {
+      double cp[4] = {0.0, 0.0, 0.0, 0.0};  // four partial sums: the loads overlap
+      int t = 0;
+      for (; t + 4 <= ntile; t += 4)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) cp[u] += colpart[(size_t)(t + u) * m + j];
+      for (; t < ntile; ++t) cp[0] += colpart[(size_t)t * m + j];
+      const double cs = (cp[0] + cp[1]) + (cp[2] + cp[3]);
+      double bm_ = 0.0;
+      for (int r = 0; r < Ki; ++r) bm_ += (double)d.b[(int64_t)r * m + j];
+      bm_ /= Ki;
+      e2 += (cs - bm_) * (cs - bm_);
+      gb += (double)d.g[j] * bm_;
+      gs += (double)d.g[j];
+      gc += (double)d.g[j] * cs;
+    }
+    col_err = block_sum_d(e2, red);
+    col_dual = block_sum_d(gb, red);
+    primal_cols = block_sum_d(gc, red);
+    if (d.db) {  // dP/db = g - mean(g), tiled (written by the column tiles otherwise)
+      const double gmean = block_sum_d(gs, red) / m;
+      for (int e = threadIdx.x; e < Ki * m; e += blockDim.x)
+        d.db[e] = (float)((double)d.g[e % m] - gmean);
+    }
+  }
+  if (threadIdx.x == 0) {
+    const double K = d.K;
+    d.out[0] = K * (acc[0] + primal_cols);
+    d.out[1] = K * (acc[5] + col_dual) - d.eps * K * acc[2];
+    d.out[2] = K * acc[1];
+    d.out[3] = sqrt(K * acc[3]);
+    d.out[4] = sqrt(K * col_err);
+  }
 }
 
 __global__ void zero_d_words(double* p, int64_t count) {
@@ -1210,11 +1265,13 @@ static int k_class(int K) {
 static int v_class(int dim, int K) { return (dim == 3 ? kKClasses : 0) + k_class(K); }
 
 // plan = {nfold, nval, count, ntasks, cls_q[kVClasses + 1], cls_tile[kVClasses + 1],
-//         order[count], fold_start[count], vorder[count], vstart[count], tasks[ntasks]}:
+//         cls_kind[kVClasses], order[count], fold_start[count], vorder[count], vstart[count],
+//         tasks[ntasks]}:
+// cls_kind[c] bit 0: the class has problems with coordinate gradients, bit 1: values-only ones;
 // fold_start[q] is the first fold tile of problem order[q];
 // problems of value class c are vorder[cls_q[c] .. cls_q[c + 1]), their value tiles
 // [cls_tile[c], cls_tile[c + 1]); vstart[q] is the first value tile of vorder[q].
-constexpr int kPlanHead = 4 + 2 * (kVClasses + 1);
+constexpr int kPlanHead = 4 + 2 * (kVClasses + 1) + kVClasses;
 
 size_t batched_plan_len(int count) {
   return kPlanHead + (4 + (size_t)kMaxGangF) * (size_t)count;
@@ -1241,6 +1298,7 @@ int batched_plan(const ot_batch_desc* h, int count, int32_t* plan) {
   std::stable_sort(idx.begin(), idx.end(), [&](int u, int v) { return cost(u) > cost(v); });
   int32_t* cls_q = plan + 4;
   int32_t* cls_tile = cls_q + kVClasses + 1;
+  int32_t* cls_kind = cls_tile + kVClasses + 1;
   int32_t* order = plan + kPlanHead;
   int32_t* fstart = order + count;
   int32_t* vorder = fstart + count;
@@ -1264,6 +1322,7 @@ int batched_plan(const ot_batch_desc* h, int count, int32_t* plan) {
   for (int c = 0; c < kVClasses; ++c) {
     cls_q[c] = q;
     cls_tile[c] = (int32_t)nv;
+    cls_kind[c] = 0;
     while (q < count && v_class(h[vo[q]].dim, h[vo[q]].K) == c) {
       const int p = vo[q];
       const int m = h[p].n / h[p].K;
@@ -1272,8 +1331,9 @@ int batched_plan(const ot_batch_desc* h, int count, int32_t* plan) {
       // value tiles of 4 block-0 points with gradients (one per wave), 16 without (four per
       // wave) unless K takes the generic path
       const bool kt = k_class(h[p].K) < 6;
-      const int ppt = (h[p].dx || h[p].dy || !kt) ? kAdjPts : kAdjPts * kValPts;
-      nv += 2 * ((m + ppt - 1) / ppt);
+      const int ppt = fused_columns(h[p], kt) ? kAdjPts * kValPts : kAdjPts;
+      nv += (fused_columns(h[p], kt) ? 1 : 2) * ((m + ppt - 1) / ppt);
+      cls_kind[c] |= fused_columns(h[p], kt) ? 2 : 1;
       ++q;
     }
   }
@@ -1297,9 +1357,14 @@ size_t batched_ws_bytes(int count) { return a256(256) + a256(sizeof(double) * 8 
 template <int DIM, int KT>
 static void launch_values_class(const ot_batch_desc* descs, const int32_t* vorder,
                                 const int32_t* vstart, int q0, int q1, int t0, int t1,
-                                double* accs, hipStream_t s) {
-  hipLaunchKernelGGL((batched_values_kernel<DIM, KT>), dim3(t1 - t0), dim3(256), 0, s, descs,
-                     vorder + q0, vstart + q0, q1 - q0, t0, accs);
+                                int kind, double* accs, hipStream_t s) {
+  if (kind & 1)
+    hipLaunchKernelGGL((batched_values_kernel<DIM, KT, false>), dim3(t1 - t0), dim3(256), 0, s,
+                       descs, vorder + q0, vstart + q0, q1 - q0, t0, accs);
+  if constexpr (KT > 0)
+    if (kind & 2)
+      hipLaunchKernelGGL((batched_values_kernel<DIM, KT, true>), dim3(t1 - t0), dim3(256), 0, s,
+                         descs, vorder + q0, vstart + q0, q1 - q0, t0, accs);
 }
 
 hipError_t launch_batched(const ot_batch_desc* descs, int count, const int32_t* dplan,
@@ -1315,6 +1380,7 @@ hipError_t launch_batched(const ot_batch_desc* descs, int count, const int32_t* 
   const int nfold = hplan[0];
   const int32_t* cls_q = hplan + 4;
   const int32_t* cls_tile = cls_q + kVClasses + 1;
+  const int32_t* cls_kind = cls_tile + kVClasses + 1;
   const int32_t* order = dplan + kPlanHead;
   const int32_t* fstart = order + count;
   const int32_t* vorder = fstart + count;
@@ -1351,7 +1417,8 @@ hipError_t launch_batched(const ot_batch_desc* descs, int count, const int32_t* 
   for (int c = 0; c < kVClasses; ++c) {
     const int q0 = cls_q[c], q1 = cls_q[c + 1], t0 = cls_tile[c], t1 = cls_tile[c + 1];
     if (t1 <= t0) continue;
-#define CSOT_VCLS(D, KT) launch_values_class<D, KT>(descs, vorder, vstart, q0, q1, t0, t1, accs, s)
+#define CSOT_VCLS(D, KT) \
+  launch_values_class<D, KT>(descs, vorder, vstart, q0, q1, t0, t1, cls_kind[c], accs, s)
     switch (c) {
       case 0: CSOT_VCLS(2, 1); break;
       case 1: CSOT_VCLS(2, 2); break;
@@ -1371,8 +1438,7 @@ hipError_t launch_batched(const ot_batch_desc* descs, int count, const int32_t* 
 #undef CSOT_VCLS
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(batched_finalize_kernel, dim3((count + 255) / 256), dim3(256), 0, s, descs,
-                     count, accs);
+  hipLaunchKernelGGL(batched_finalize_kernel, dim3(count), dim3(1024), 0, s, descs, accs);
   return hipGetLastError();
 }
 

@@ -151,13 +151,15 @@ def test_batched_plan_validation_and_order(B):
         d.n, d.K, d.dim, d.eps = n, K, 2, 0.1
         d.x = d.y = d.a = d.b = d.logK = d.f = d.g = d.out = 8
     plan = (ctypes.c_int32 * _lib.ot_batched_plan_len(3))()
-    # values only (no coordinate gradients): value tiles of 16 block-0 points, 2 ceil(m/16)
+    # values only (no coordinate gradients): row tiles of 16 block-0 points, ceil(m/16) (the
+    # column sums are accumulated in the same pass)
     assert _lib.ot_batched_plan(descs, 3, plan) == 0
-    assert plan[1] == 2 + 8 + 6
+    assert plan[1] == 1 + 4 + 3
+    assert list(plan[34:38]) == [0, 2, 2, 2]  # values-only kind in the K = 2, 4, 8 classes
     for d in descs:
         d.dx = d.dy = 8
     assert _lib.ot_batched_plan(descs, 3, plan) == 0
-    H = 4 + 2 * 15                         # header: counts, then 14 value classes' bounds
+    H = 4 + 2 * 15 + 14                    # header: counts, 14 value classes' bounds, kinds
     order = list(plan[H:H + 3])
     assert order == [1, 2, 0]              # m = 16, 64, 48: largest first
     assert list(plan[H + 3:H + 6]) == [0, 2, 4]   # fold tiles in that order: ceil(m/32) = 2, 2, 1
@@ -168,6 +170,8 @@ def test_batched_plan_validation_and_order(B):
     cls_q, cls_tile = list(plan[4:19]), list(plan[19:34])
     assert cls_q[:5] == [0, 0, 1, 2, 3] and cls_q[14] == 3
     assert cls_tile[:5] == [0, 0, 24, 32, 64] and cls_tile[14] == 64
+    cls_kind = list(plan[34:48])          # bit 0: gradients, bit 1: values only
+    assert cls_kind[:4] == [0, 1, 1, 1] and sum(cls_kind[4:]) == 0
     assert plan[0] == 5 and plan[1] == 64   # fold tiles 1 + 2 + 2
     descs[1].K = 7                          # 512 % 7 != 0
     assert _lib.ot_batched_plan(descs, 3, plan) == B.OT_ERR_ARG
@@ -209,7 +213,7 @@ def test_batched_plan_gang_tasks(B):
     assert _lib.ot_batched_plan(descs, 3, plan) == 0
     nt = plan[3]
     assert nt == 8 + 4 + 1
-    H = 4 + 2 * 15
+    H = 4 + 2 * 15 + 14
     tasks = np.frombuffer(plan, dtype=np.uint32)[H + 4 * 3:H + 4 * 3 + nt]
     prob, member, gang = tasks & 0xFFFFF, (tasks >> 20) & 63, (tasks >> 26) + 1
     assert list(prob) == [2] * 8 + [1] * 4 + [0]
