@@ -273,8 +273,9 @@ int ot_cost_and_grad(const ot_problem* prob, const float* f, const float* g, int
 /* One problem of a batch.  The array of descriptors lives in DEVICE memory (all pointers in
  * it are device pointers); a host copy of the same array is given to ot_batched_plan.
  *   n, K, dim (2 or 3), eps   as in ot_problem; points and marginals x, y [n, dim], a, b [n];
- *   tile_cfg   lanes cooperating on one row in the solve (16, 32, 64; 0 = by size) -- the
- *              value the autotuner picks per size bucket;
+ *   tile_cfg   two launch knobs the autotuner picks per (size bucket, K, dim): bits 0-7 the
+ *              lanes cooperating on one row in the solve (16, 32, 64; 0 = by size), bits 8-15
+ *              the fold's columns per tile in units of 64 (1 .. 16; 0 = 256);
  *   logK       scratch of 2 m mp + 2 m + 2 (2 mp + 64) floats, 16-byte aligned, mp = m
  *              rounded up to a multiple of 4 (folded kernel and its transpose with padded
  *              rows, folded marginals, then 2 mp + 64 64-bit exchange slots used when

@@ -64,6 +64,17 @@ def size_bucket(m: int) -> str:
     return str(b)
 
 
+def tuning_key(m: int, K: int, dim: int) -> str:
+    """Key of the tuning table: size bucket / K / dim."""
+    return f"{size_bucket(m)}/{K}/{dim}"
+
+
+def tuned_cfg(tuning: dict, m: int, K: int, dim: int) -> int:
+    """tile_cfg for one problem: the (bucket, K, dim) entry, else the bucket's, else 0 (the
+    kernels' defaults)."""
+    return int(tuning.get(tuning_key(m, K, dim), tuning.get(size_bucket(m), 0)))
+
+
 def load_tuning(arch: str = "gfx950") -> dict:
     path = os.path.join(_TUNING_DIR, f"{arch}.json")
     try:
@@ -124,7 +135,8 @@ class Batch:
         for p in range(self.count):
             d = descs[p]
             d.n, d.K, d.dim = ns[p], Ks[p], dims[p]
-            d.tile_cfg = int(tile_cfg[p]) if tile_cfg is not None else int(tuning.get(size_bucket(ms[p]), 0))
+            d.tile_cfg = (int(tile_cfg[p]) if tile_cfg is not None
+                          else tuned_cfg(tuning, ms[p], Ks[p], dims[p]))
             d.eps = float(problems[p]["eps"])
             d.x = self.X.data_ptr() + e4 * int(oxy[p])
             d.y = self.Y.data_ptr() + e4 * int(oxy[p])
@@ -139,16 +151,25 @@ class Batch:
             d.da = (self.DA.data_ptr() + e4 * int(oab[p])) if want_grad else None
             d.db = (self.DB.data_ptr() + e4 * int(oab[p])) if want_grad else None
         self.host_descs = descs
-        raw = bytes(descs)
-        self.D = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(dev)
-        plen = int(_lib.ot_batched_plan_len(self.count))
-        plan = (ctypes.c_int32 * plen)()
-        rc = _lib.ot_batched_plan(descs, self.count, plan)
-        B._check(rc)
-        self.plan_host = np.frombuffer(plan, dtype=np.int32).copy()
-        self.PLAN = torch.from_numpy(self.plan_host).to(dev)
+        self._upload()
         self.WS = torch.empty(max(int(_lib.ot_batched_workspace_bytes(self.count)), 256),
                               dtype=torch.uint8, device=dev)
+
+    def _upload(self):
+        """Device copy of the descriptors and the launch plan made from them."""
+        descs = self.host_descs
+        self.D = torch.frombuffer(bytearray(bytes(descs)), dtype=torch.uint8).to(self.device)
+        plen = int(_lib.ot_batched_plan_len(self.count))
+        plan = (ctypes.c_int32 * plen)()
+        B._check(_lib.ot_batched_plan(descs, self.count, plan))
+        self.plan_host = np.frombuffer(plan, dtype=np.int32).copy()
+        self.PLAN = torch.from_numpy(self.plan_host).to(self.device)
+
+    def set_tile_cfg(self, tile_cfg: Sequence[int]):
+        """New launch knobs (see ot_batch_desc.tile_cfg) for every problem; re-plans."""
+        for p in range(self.count):
+            self.host_descs[p].tile_cfg = int(tile_cfg[p])
+        self._upload()
 
     def run(self, opts: Optional[B.OtOpts] = None):
         """Enqueue the batched solve on the current stream (asynchronous)."""

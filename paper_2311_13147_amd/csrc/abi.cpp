@@ -487,8 +487,11 @@ int ot_batched_plan(const ot_batch_desc* h, int32_t count, int32_t* plan) {
       return fail(OT_ERR_ARG, "problem %d: x, y, a, b, logK, f, g and out must be non-NULL", p);
     if (d.n / d.K > 4096)
       return fail(OT_ERR_UNSUPPORTED, "problem %d: block size m = %d above 4096", p, d.n / d.K);
-    if (d.tile_cfg != 0 && d.tile_cfg != 16 && d.tile_cfg != 32 && d.tile_cfg != 64)
-      return fail(OT_ERR_ARG, "problem %d: tile_cfg must be 0, 16, 32 or 64", p);
+    const int lpr = d.tile_cfg & 0xff, fcb = (d.tile_cfg >> 8) & 0xff;
+    if ((lpr != 0 && lpr != 16 && lpr != 32 && lpr != 64) || fcb > 16 || (d.tile_cfg >> 16) != 0)
+      return fail(OT_ERR_ARG,
+                  "problem %d: tile_cfg must be lanes (0, 16, 32, 64) | fold columns / 64 "
+                  "(0 .. 16) << 8", p);
   }
   if (csot::batched_plan(h, count, plan) != 0) return fail(OT_ERR_UNSUPPORTED, "too many tiles");
   return ok();

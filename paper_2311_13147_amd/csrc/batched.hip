@@ -79,13 +79,19 @@ constexpr int kFoldRows = kFoldQ * kFoldThreads / kWave;  // rows per tile (32)
 constexpr int kFoldJC = 64;                      // target columns j per staging (one per lane)
 constexpr int kFoldKC = 32;                      // shifts k per staging
 constexpr int kFoldSR = kFoldKC * kFoldJC / kFoldThreads;  // staged points per thread
-constexpr int kFoldCB = 256;                     // columns per tile
+constexpr int kFoldCB = 256;                     // columns per tile unless tile_cfg says
 
 __host__ __device__ __forceinline__ int fold_row_blocks(int m) {
   return (m + kFoldRows - 1) / kFoldRows;
 }
-__host__ __device__ __forceinline__ int fold_col_blocks(int m) {
-  return (m + kFoldCB - 1) / kFoldCB;
+// columns per fold tile: tile_cfg bits 8-15 in units of 64, 0 = kFoldCB
+__host__ __device__ __forceinline__ int fold_cb_width(int tile_cfg) {
+  const int c = (tile_cfg >> 8) & 0xff;
+  return c > 0 ? 64 * c : kFoldCB;
+}
+__host__ __device__ __forceinline__ int fold_col_blocks(int m, int tile_cfg) {
+  const int w = fold_cb_width(tile_cfg);
+  return (m + w - 1) / w;
 }
 
 template <int DIM>
@@ -128,7 +134,8 @@ __device__ __forceinline__ void store_fold_row(float* L, float* LT, int mp, int 
 template <int DIM, bool F64>
 __device__ void fold_tile(const ot_batch_desc& d, int rb, int cb, FoldShared<DIM>& sh) {
   const int m = bm(d), K = d.K, mp = bmp(m);
-  const int i0 = rb * kFoldRows, jb = cb * kFoldCB, je = min(m, jb + kFoldCB);
+  const int cbw = fold_cb_width(d.tile_cfg);
+  const int i0 = rb * kFoldRows, jb = cb * cbw, je = min(m, jb + cbw);
   float* L = d.logK;
   float* LT = L + (size_t)m * mp;
   const int rows = min(kFoldRows, m - i0);
@@ -295,7 +302,7 @@ __device__ void fold_tile(const ot_batch_desc& d, int rb, int cb, FoldShared<DIM
   // padding: -inf contributes nothing to a log-sum-exp.  Columns [m, mp) of the tile's rows
   // (by the last column block), and of the transpose's rows j of the tile's columns (by the
   // first row block)
-  if (cb == fold_col_blocks(m) - 1) {
+  if (cb == fold_col_blocks(m, d.tile_cfg) - 1) {
     for (int e = threadIdx.x; e < rows * (mp - m); e += blockDim.x) {
       const int i = i0 + e / (mp - m), j = m + e % (mp - m);
       L[(size_t)i * mp + j] = -INFINITY;
@@ -332,7 +339,7 @@ __global__ void __launch_bounds__(kFoldThreads)
                         const int32_t* __restrict__ order, const int32_t* __restrict__ tile_start) {
   const int q = find_problem(tile_start, count, blockIdx.x);
   const ot_batch_desc d = descs[order[q]];
-  const int m = bm(d), ncb = fold_col_blocks(m);
+  const int m = bm(d), ncb = fold_col_blocks(m, d.tile_cfg);
   const int t = blockIdx.x - tile_start[q];
   if (t >= fold_row_blocks(m) * ncb) return;
   __shared__ FoldShared<3> sh;
@@ -755,8 +762,8 @@ __global__ void __launch_bounds__(kBSolveThreads) batched_solve_kernel(BSolveArg
       continue;
     }
     const int m = bm(d);
-    const int lpr = d.tile_cfg == 16 || d.tile_cfg == 32 || d.tile_cfg == 64
-                        ? d.tile_cfg : (m >= 512 ? 64 : m >= 128 ? 32 : 16);
+    const int cfg = d.tile_cfg & 0xff;
+    const int lpr = cfg == 16 || cfg == 32 || cfg == 64 ? cfg : (m >= 512 ? 64 : m >= 128 ? 32 : 16);
     if (lpr == 64) solve_one<64>(d, a, lds, lds_floats, red);
     else if (lpr == 32) solve_one<32>(d, a, lds, lds_floats, red);
     else solve_one<16>(d, a, lds, lds_floats, red);
@@ -1310,7 +1317,7 @@ int batched_plan(const ot_batch_desc* h, int count, int32_t* plan) {
     order[q] = idx[q];
     const int m = h[idx[q]].n / h[idx[q]].K;
     fstart[q] = (int32_t)nf;
-    nf += (int64_t)fold_row_blocks(m) * fold_col_blocks(m);
+    nf += (int64_t)fold_row_blocks(m) * fold_col_blocks(m, h[idx[q]].tile_cfg);
   }
   // value tiles by class, problems in index order within a class
   std::vector<int> vo(count);

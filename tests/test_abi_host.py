@@ -177,6 +177,20 @@ def test_batched_plan_validation_and_order(B):
     assert _lib.ot_batched_plan(descs, 3, plan) == B.OT_ERR_ARG
     descs[1].K, descs[1].tile_cfg = 8, 24
     assert _lib.ot_batched_plan(descs, 3, plan) == B.OT_ERR_ARG
+    descs[1].tile_cfg = 32 | 17 << 8        # fold columns above 16 x 64
+    assert _lib.ot_batched_plan(descs, 3, plan) == B.OT_ERR_ARG
+    descs[1].tile_cfg = 32 | 1 << 8         # 64 fold columns per tile: m = 64 -> 2 x 1 tiles
+    assert _lib.ot_batched_plan(descs, 3, plan) == 0
+    assert plan[0] == 5
+    descs[0].tile_cfg = 16 | 1 << 8         # m = 16: one tile whatever the width
+    descs[2].tile_cfg = 1 << 8              # m = 48 (lanes by size)
+    assert _lib.ot_batched_plan(descs, 3, plan) == 0 and plan[0] == 5
+    descs[0].tile_cfg = descs[2].tile_cfg = 0
+    descs[1].n = 4096                       # m = 512: 16 row blocks x (512 / width) columns
+    for cols, tiles in ((0, 2), (1, 8), (4, 2), (8, 1)):
+        descs[1].tile_cfg = cols << 8
+        assert _lib.ot_batched_plan(descs, 3, plan) == 0 and plan[0] == 16 * tiles + 2 + 1
+    descs[1].n = 512
     descs[1].tile_cfg = 0                   # m = 8192 is above the supported 4096
     descs[1].K = 2
     descs[1].n = 2 * 8192
@@ -250,3 +264,15 @@ def test_linear_ot_and_srot_arguments_are_checked_before_launch(B):
     # the workspace grows with m
     big = _prob(B, n=4096, K=4)
     assert lib.ot_srot_workspace_bytes(ctypes.byref(big)) > need
+
+
+def test_tuning_table_lookup():
+    """The batched tuning table is keyed by size bucket / K / dim; older tables keyed by the
+    bucket alone still apply, and a missing entry leaves the kernels' defaults (0)."""
+    from paper_2311_13147_amd.batched import size_bucket, tuned_cfg, tuning_key
+    assert size_bucket(33) == "64" and size_bucket(64) == "64" and size_bucket(1) == "1"
+    assert tuning_key(300, 16, 3) == "512/16/3"
+    table = {"512/16/3": 64 | 4 << 8, "512": 32}
+    assert tuned_cfg(table, 300, 16, 3) == 64 | 4 << 8
+    assert tuned_cfg(table, 300, 8, 3) == 32
+    assert tuned_cfg(table, 40, 8, 3) == 0
