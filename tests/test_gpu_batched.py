@@ -221,3 +221,34 @@ def test_batched_graph_replay(lib):
         assert torch.equal(batch.DB, ref_db), rep
         # float64 sums use atomics (order may differ): compare to rounding
         assert torch.allclose(batch.OUT, ref_out, rtol=1e-12, atol=1e-15), rep
+
+
+def test_batched_launch_knobs(lib):
+    """The two tuned launch knobs change only how the work is cut: the fold's columns per
+    tile (64, 128, 256, 512) leave every folded entry, hence the potentials and iteration counts,
+    bit for bit unchanged; the lanes per row of the solve (16, 32, 64) reorder the log-sum-exp
+    sums only, so the potentials agree to float32 rounding and the values to 1e-6."""
+    probs = _problems(SMALL + [(600, 4, 2, 13), (1000, 8, 3, 14)])
+    print("[batched knobs] fold widths and lanes per row", flush=True)
+    opts = lib.make_opts(tol=1e-6, max_iter=20000, fold_fp64=1)
+    b = lib.Batch(probs, device=DEV, want_grad=False, tile_cfg=[32] * len(probs))
+    b.run(opts)
+    torch.cuda.synchronize()
+    F0, G0, O0 = b.F.clone(), b.G.clone(), b.OUT.cpu().numpy()
+    for cols in (64, 128, 512):
+        b.set_tile_cfg([32 | (cols // 64) << 8] * len(probs))
+        b.run(opts)
+        torch.cuda.synchronize()
+        assert torch.equal(b.F, F0) and torch.equal(b.G, G0), cols
+        assert (b.OUT.cpu().numpy()[:, 5:] == O0[:, 5:]).all(), cols
+    scale = float(max(F0.abs().max(), G0.abs().max()))
+    for lanes in (16, 64):
+        b.set_tile_cfg([lanes] * len(probs))
+        b.run(opts)
+        torch.cuda.synchronize()
+        O = b.OUT.cpu().numpy()
+        assert np.abs(O[:, 5] - O0[:, 5]).max() <= 1, lanes
+        assert float((b.F - F0).abs().max()) <= 2e-5 * scale, lanes
+        assert float((b.G - G0).abs().max()) <= 2e-5 * scale, lanes
+        rel = np.abs(O[:, 0] - O0[:, 0]) / np.maximum(np.abs(O0[:, 0]), O0[:, 2])
+        assert rel.max() <= 1e-6, (lanes, rel.max())
