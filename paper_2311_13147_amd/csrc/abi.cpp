@@ -510,7 +510,8 @@ int ot_sinkhorn_reduced_batched(const ot_batch_desc* descs, int32_t count, const
   int rc = check_opts(o);
   if (rc) return rc;
   if ((rc = check_ws(ws, ws_bytes, csot::batched_ws_bytes(count)))) return rc;
-  if (plan_host[2] != count || plan_host[0] < count || plan_host[1] < 2 * count)
+  // every problem has at least one fold tile and one value tile
+  if (plan_host[2] != count || plan_host[0] < count || plan_host[1] < count)
     return fail(OT_ERR_ARG, "plan_host is not ot_batched_plan's output for %d problems", count);
   hipError_t e = csot::launch_batched(descs, count, plan, plan_host, o.tol, o.max_iter,
                                       o.fold_fp64, o.warm_start, ws, static_cast<hipStream_t>(stream),

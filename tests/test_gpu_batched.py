@@ -252,3 +252,35 @@ def test_batched_launch_knobs(lib):
         assert float((b.G - G0).abs().max()) <= 2e-5 * scale, lanes
         rel = np.abs(O[:, 0] - O0[:, 0]) / np.maximum(np.abs(O0[:, 0]), O0[:, 2])
         assert rel.max() <= 1e-6, (lanes, rel.max())
+
+
+def test_batched_degenerate_sizes(lib):
+    """Blocks of one and two points (m = 1: every point its own block, the reduced problem
+    1 x 1; m = 2), K = 1 (no symmetry used) and K = 2, with and without gradients, against the
+    float64 oracle: potentials, values and the marginal errors the call reports.  The solver
+    stops on its float32 view of the row residual (<= 1e-6); the reported float64 residual
+    differs from it by the float32 rounding of the folded kernel, which a handful of entries
+    does not average out (up to ~1e-6 here), hence the 2e-6 bound."""
+    shapes = [(1, 8, 2, 21), (2, 4, 3, 22), (40, 1, 2, 23), (3, 2, 2, 24), (1, 32, 3, 25)]
+    probs = _problems(shapes)
+    print("[batched degenerate] m = 1, 2, 3 and K = 1", flush=True)
+    opts = lib.make_opts(tol=1e-6, max_iter=20000, fold_fp64=1)
+    for want_grad in (True, False):
+        batch = lib.Batch(probs, device=DEV, want_grad=want_grad)
+        batch.run(opts)
+        torch.cuda.synchronize()
+        out = batch.OUT.cpu().numpy()
+        for k, q in enumerate(probs):
+            p = q["_p"]
+            r, v, Ck = _oracle(p)
+            assert out[k, 6] == 1, (k, want_grad)
+            assert out[k, 3] <= 2e-6 and out[k, 4] <= 2e-6, (k, out[k, 3:5])
+            P, CT = p.K * v["P"], p.K * v["CT"]
+            assert abs(out[k, 0] - P) <= 1e-5 * max(abs(P), CT), (k, want_grad)
+            f = batch.f(k).cpu().numpy().astype(np.float64)
+            g = batch.g(k).cpu().numpy().astype(np.float64)
+            # potentials are defined up to f + c, g - c: compare f + g pairs and f - f[0]
+            s = max(np.abs(r["f"]).max(), np.abs(r["g"]).max(), p.eps)
+            assert np.abs((f[:, None] + g[None, :]) - (r["f"][:, None] + r["g"][None, :])).max() <= 2e-4 * s, k
+            if want_grad and k == 0:
+                _check_grads(batch, k, p, Ck)

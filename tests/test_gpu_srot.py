@@ -162,3 +162,23 @@ def test_srot_term_storage_variants(lib, name, mk):
         ew = np.abs(w.cpu().numpy() - rw).max() / np.abs(rw).max()
         ez = np.abs(z.cpu().numpy() - rz).max() / np.abs(rz).max()
         assert ew < 2e-5 and ez < 2e-5, (ew, ez)
+
+
+@pytest.mark.parametrize("m,K,dim,seed", [(1, 8, 2, 31), (3, 2, 3, 32), (40, 1, 2, 33)])
+def test_srot_degenerate_sizes(lib, m, K, dim, seed):
+    """One-point blocks (the reduced dual has one w and one z), three-point blocks and K = 1:
+    the tolerance solve against the float64 oracle (iterations +-2, primal value, row
+    residual)."""
+    p = workloads.symmetric_problem(m * K, K, dim, 0.05, seed=seed)
+    Ck = _blocks(p)
+    lam = 10.0 * float(np.median(Ck))
+    al = _f64(p.a).reshape(p.K, p.m).mean(0)
+    be = _f64(p.b).reshape(p.K, p.m).mean(0)
+    print(f"[srot degenerate] m={m} K={K} dim={dim}", flush=True)
+    w, z, st = lib.ot_srot_reduced(_prob(lib, p), lam, lib.make_opts(tol=1e-6, max_iter=5000))
+    ref = srot.cyclic_srot(al, be, Ck, lam, p.K, tol=1e-6, max_iter=5000)
+    assert st["converged"] and abs(st["iters"] - ref["iters"]) <= 2, (st["iters"], ref["iters"])
+    v = srot.values(_f64(w.cpu()), _f64(z.cpu()), Ck, lam, al, be)
+    vr = srot.values(ref["w"], ref["z"], Ck, lam, al, be)
+    assert abs(v["primal"] - vr["primal"]) <= 1e-5 * abs(vr["primal"])
+    assert np.sqrt(p.K) * np.linalg.norm(v["row"] - al) <= 1.1e-6
