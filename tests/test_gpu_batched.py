@@ -284,3 +284,25 @@ def test_batched_degenerate_sizes(lib):
             assert np.abs((f[:, None] + g[None, :]) - (r["f"][:, None] + r["g"][None, :])).max() <= 2e-4 * s, k
             if want_grad and k == 0:
                 _check_grads(batch, k, p, Ck)
+
+
+def test_batched_single_problem_and_large_block(lib):
+    """A batch of one problem, and a batch mixing a block of m = 2000 (a gang of 16
+    workgroups, logK streamed) with small ones: iterations, potentials' plan and value against
+    the float64 oracle."""
+    print("[batched one / large] count 1, m = 2000 in a mixed batch", flush=True)
+    opts = lib.make_opts(tol=1e-6, max_iter=20000, fold_fp64=1)
+    for shapes in ([(300, 4, 2, 41)], [(2000, 2, 2, 42), (20, 4, 3, 43), (70, 8, 2, 44)]):
+        probs = _problems(shapes)
+        batch = lib.Batch(probs, device=DEV)
+        batch.run(opts)
+        torch.cuda.synchronize()
+        out = batch.OUT.cpu().numpy()
+        for k, q in enumerate(probs):
+            p = q["_p"]
+            r, v, Ck = _oracle(p)
+            assert out[k, 6] == 1 and out[k, 3] <= 1.05e-6, (shapes[k], out[k])
+            assert abs(out[k, 5] - r["iters"]) <= 1, (shapes[k], out[k, 5], r["iters"])
+            P, CT = p.K * v["P"], p.K * v["CT"]
+            assert abs(out[k, 0] - P) <= 1e-5 * max(abs(P), CT), shapes[k]
+            _check_plan_at_gpu_iterations(batch, k, p, Ck, r, int(out[k, 5]))
