@@ -13,6 +13,11 @@ One step = one pass of the whole path on that input:
   full    : plain full-size Sinkhorn to 1e-6 -> objective + gradients;
             plus a fixed-count full solve (tol = 0, --fixed-full iterations);
   eps 0.1 : reduced and full solves to 1e-6 at eps = 0.1 median(C);
+  approximate symmetry (n = 16384, K = 32, jittered points, noisy marginals): the plain
+            full-size solve from g = 0 and the two-stage method (projection of the cost,
+            cyclic solve of the averaged problem, full-size solve from its tiled potential);
+  n = 4096, K = 8 : forward + backward (solve to 1e-6, values, all gradients), reduced and
+            full, replayed from graphs;
   batched : one call on 1024 uneven cyclic problems (fold, solve, values, gradients).
 `value` is the reduced Sinkhorn iteration rate (iterations / second) of the fixed-count legs;
 the time-to-tolerance and the full-size rates are reported beside it.  All timing uses HIP
@@ -627,6 +632,51 @@ def main():
     ds2 = [torch.zeros(8, dtype=torch.float64, device=dev) for _ in range(2)]
     csot.workspace(prob2, o_tol)
 
+    # approximate symmetry (config 3, Alg. 3): n=16384, K=32, jitter 1e-3, marginal noise 1%,
+    # eps = 0.05 median of the symmetric cloud -- plain full-size Sinkhorn from g = 0 on the
+    # given data beside the two-stage method (cyclic solve of the block-averaged problem, then
+    # the full-size solve from its tiled potential)
+    p3 = workloads.jittered_problem(16384, 32, sigma=1e-3, noise=0.01, seed=200)
+    prob3 = csot.Problem(T_(p3.a), T_(p3.b), p3.eps, p3.K, x=T_(p3.x), y=T_(p3.y))
+    n3 = p3.n
+    ff5, gf5 = torch.empty(n3, device=dev), torch.empty(n3, device=dev)
+    two_out = (torch.empty(n3, device=dev), torch.empty(n3, device=dev))
+    ds3 = torch.zeros(8, dtype=torch.float64, device=dev)
+    csot.workspace(prob3, o_tol)
+    two_last = {}
+
+    def cfg3_two_stage():
+        two_last["r"] = csot.two_stage_sinkhorn(prob3, tol=TOL, out=two_out)
+
+    # forward + backward at n=4096, K=8 (config 4, eps = 0.05 median): replayed from graphs
+    p4 = workloads.symmetric_problem(4096, 8, 2, 0.05, seed=SEED)
+    prob4 = csot.Problem(T_(p4.a), T_(p4.b), p4.eps, p4.K, x=T_(p4.x), y=T_(p4.y))
+    m4, n4 = p4.m, p4.n
+    b4 = {"logK": torch.empty((m4, m4), device=dev), "al": torch.empty(m4, device=dev),
+          "be": torch.empty(m4, device=dev), "fr": torch.empty(m4, device=dev),
+          "gr": torch.empty(m4, device=dev), "ff": torch.empty(n4, device=dev),
+          "gf": torch.empty(n4, device=dev),
+          "ds": [torch.zeros(8, dtype=torch.float64, device=dev) for _ in range(2)],
+          "vr": torch.empty(8, dtype=torch.float64, device=dev),
+          "vf": torch.empty(8, dtype=torch.float64, device=dev)}
+    g4r = {"dx": torch.empty((n4, 2), **f32), "dy": torch.empty((n4, 2), **f32),
+           "da": torch.empty(n4, **f32), "db": torch.empty(n4, **f32)}
+    g4f = {k: torch.empty_like(v) for k, v in g4r.items()}
+    csot.workspace(prob4, o_tol)
+
+    def cfg4_red_fb():
+        csot.ot_fold_kernel(prob4, o_tol, out=(b4["logK"], b4["al"], b4["be"]))
+        csot.ot_sinkhorn_reduced(prob4, b4["logK"], b4["al"], b4["be"], o_tol, host_stats=False,
+                                 out=(b4["fr"], b4["gr"]), dstats=b4["ds"][0])
+        csot.ot_cost_and_grad(prob4, b4["fr"], b4["gr"], True, want_dxy=True, want_dab=True,
+                              out=b4["vr"], grads=g4r)
+
+    def cfg4_full_fb():
+        csot.ot_sinkhorn_full(prob4, o_tol, host_stats=False, out=(b4["ff"], b4["gf"]),
+                              dstats=b4["ds"][1])
+        csot.ot_cost_and_grad(prob4, b4["ff"], b4["gf"], False, want_dxy=True, want_dab=True,
+                              out=b4["vf"], grads=g4f)
+
     # the batched workload (config 5): one batched call per step
     bleg = BatchedLeg()
 
@@ -636,10 +686,13 @@ def main():
     with torch.cuda.stream(side):
         red_fb()
         full_fb()
+        cfg4_red_fb()
+        cfg4_full_fb()
     torch.cuda.current_stream().wait_stream(side)
     torch.cuda.synchronize()
     for name, fn in (("red_graph", red_tol), ("full_graph", full_tol), ("red_fb_graph", red_fb),
-                     ("full_fb_graph", full_fb)):
+                     ("full_fb_graph", full_fb), ("cfg4_red_fb_graph", cfg4_red_fb),
+                     ("cfg4_full_fb_graph", cfg4_full_fb)):
         gr_ = torch.cuda.CUDAGraph()
         with torch.cuda.graph(gr_):
             fn()
@@ -649,7 +702,8 @@ def main():
     E = lambda: torch.cuda.Event(enable_timing=True)
     legs = ["fold", "red_solve", "expand", "red_grad", "red_fixed", "full_solve", "full_grad",
             "full_fixed", "red_graph", "full_graph", "red_fb_graph", "full_fb_graph",
-            "red_tol_eps2", "full_tol_eps2", "batched"]
+            "red_tol_eps2", "full_tol_eps2", "cfg3_cold_full", "cfg3_two_stage",
+            "cfg4_red_fb_graph", "cfg4_full_fb_graph", "batched"]
 
     def step(record):
         ev = {k: (E(), E()) for k in legs}
@@ -688,6 +742,11 @@ def main():
         run("red_tol_eps2", red_eps2)
         run("full_tol_eps2", lambda: csot.ot_sinkhorn_full(prob2, o_tol, host_stats=False,
                                                            out=(ff4, gf4), dstats=ds2[1]))
+        run("cfg3_cold_full", lambda: csot.ot_sinkhorn_full(prob3, o_tol, host_stats=False,
+                                                            out=(ff5, gf5), dstats=ds3))
+        run("cfg3_two_stage", cfg3_two_stage)
+        run("cfg4_red_fb_graph", graphs["cfg4_red_fb_graph"].replay)
+        run("cfg4_full_fb_graph", graphs["cfg4_full_fb_graph"].replay)
         run("batched", bleg.run)
         return ev
 
@@ -823,6 +882,16 @@ def main():
             "speedup_solve": round(ms["full_tol_eps2"] / ms["red_tol_eps2"], 2),
             "iterations": {"reduced": int(st2[0][0]), "full": int(st2[1][0])},
             "marginal_err_fp64": {"reduced_row": st2[0][2], "full_row": st2[1][2]}},
+        "approximate_symmetry": _cfg3_report(csot, prob3, p3, ms, ds3, ff5, gf5, two_last["r"]),
+        "forward_backward_n4096_K8_graph_ms": {
+            "reduced": round(ms["cfg4_red_fb_graph"], 4),
+            "full": round(ms["cfg4_full_fb_graph"], 4),
+            "speedup": round(ms["cfg4_full_fb_graph"] / ms["cfg4_red_fb_graph"], 2),
+            "iterations": {"reduced": int(b4["ds"][0][0].item()),
+                           "full": int(b4["ds"][1][0].item())},
+            "marginal_err_fp64": {"reduced_row": float(b4["ds"][0][2].item()),
+                                  "full_row": float(b4["ds"][1][2].item())},
+            "objective_rel_gap": _rel_gap(csot.values_dict(b4["vr"]), csot.values_dict(b4["vf"]))},
         "expand_GBps": round(4.0 * N * N / (ms["expand"] * 1e-3) / 1e9, 1),
         "roofline": roof,
         "roofline_reduced_path": roof_red,
@@ -832,6 +901,46 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, fr, gr, vr, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def _rel_gap(va, vb):
+    return abs(va["P"] - vb["P"]) / max(abs(vb["P"]), vb["CT"])
+
+
+def _cfg3_report(csot, prob3, p3, ms, ds3, ff5, gf5, two):
+    """The approximate-symmetry leg: times of the cold full-size solve and of the two-stage
+    method, and (evaluated once, after the timed region) Table 2's quantities for the cyclic
+    solve of the block-averaged problem alone: its objective against the full-size optimum on
+    the given data, and the marginal error of its tiled potentials against the given
+    marginals."""
+    import torch
+
+    sf = ds3.cpu().tolist()
+    o = csot.make_opts(tol=TOL, max_iter=20000, fold_fp64=1)
+    csym = csot.ot_symmetrize_cost(prob3)
+    sprob = csot.Problem(prob3.a, prob3.b, prob3.eps, prob3.K, C=csym)
+    logK, al, be = csot.ot_fold_kernel(sprob, o)
+    fr, gr, st1 = csot.ot_sinkhorn_reduced(sprob, logK, al, be, o)
+    K = prob3.K
+    vf = csot.values_dict(csot.ot_cost_and_grad(prob3, ff5, gf5, reduced=False)["values"])
+    vc = csot.values_dict(csot.ot_cost_and_grad(prob3, fr.repeat(K), gr.repeat(K),
+                                                reduced=False)["values"])
+    v2 = csot.values_dict(csot.ot_cost_and_grad(prob3, two["f"], two["g"],
+                                                reduced=False)["values"])
+    torch.cuda.synchronize()
+    return {"workload": f"n={p3.n}, K={K}, m={p3.m}, jitter 1e-3, marginal noise 1%, "
+                        "eps=0.05*median, tol=1e-6",
+            "cold_full_ms": round(ms["cfg3_cold_full"], 4),
+            "two_stage_ms": round(ms["cfg3_two_stage"], 4),
+            "speedup_two_stage": round(ms["cfg3_cold_full"] / ms["cfg3_two_stage"], 3),
+            "iterations": {"cold_full": int(sf[0]), "stage1": two["stage1"]["iters"],
+                           "stage2": two["stage2"]["iters"]},
+            "err_row_fp64": {"cold_full": sf[2], "two_stage": two["stage2"]["err_row"]},
+            "two_stage_objective_rel_diff": _rel_gap(v2, vf),
+            "cyclic_of_averaged": {"iterations": st1["iters"],
+                                   "objective_rel_gap": _rel_gap(vc, vf),
+                                   "marginal_err_vs_given": {"row": vc["err_row"],
+                                                             "col": vc["err_col"]}}}
 
 
 def _host_cpu():
