@@ -1031,6 +1031,26 @@ def cpu_baseline(p, f_gpu, g_gpu, vr, budget_s):
     pool.shutdown()
     del C
 
+    # forward + backward at n = 4096, K = 8 (eps = 0.05 median), one thread: the oracle's
+    # reduced solve to 1e-6 and its envelope gradients of the tiled potentials, beside the
+    # full-size solve to 1e-6 and the same gradients
+    from oracle import grad as ograd
+    import workloads
+    p4 = workloads.symmetric_problem(4096, 8, 2, 0.05, seed=SEED)
+    a4, b4 = p4.a.astype(np.float64), p4.b.astype(np.float64)
+    x4, y4 = p4.x.astype(np.float64), p4.y.astype(np.float64)
+    t0 = time.perf_counter()
+    Ck4 = cost.blocks_from_row0(cost.row0_from_points(p4.x, p4.y, p4.K), p4.K)
+    al4, be4 = sinkhorn.fold_marginals(a4, p4.K), sinkhorn.fold_marginals(b4, p4.K)
+    r4 = sinkhorn.reduced_sinkhorn(al4, be4, sinkhorn.fold_kernel(Ck4, p4.eps), p4.eps, p4.K,
+                                   tol=TOL)
+    ograd.envelope_grads(np.tile(r4["f"], p4.K), np.tile(r4["g"], p4.K), x4, y4, p4.eps)
+    fb_red = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    rf4 = sinkhorn.full_sinkhorn(a4, b4, cost.sq_euclidean(p4.x, p4.y), p4.eps, tol=TOL)
+    ograd.envelope_grads(rf4["f"], rf4["g"], x4, y4, p4.eps)
+    fb_full = time.perf_counter() - t0
+
     ref = sinkhorn.reduced_sinkhorn(alpha, beta, logK, p.eps, p.K, tol=TOL)
     rv = objective.reduced_values(ref["f"], ref["g"], Ck, p.eps, alpha, beta)
     P_ref = p.K * rv["P"]
@@ -1051,6 +1071,11 @@ def cpu_baseline(p, f_gpu, g_gpu, vr, budget_s):
                           "sample": f"n={n}: one full_sinkhorn iteration on one thread (with its "
                                     f"residual pass); two iterations of the half-steps on "
                                     f"{threads} threads"},
+            "forward_backward_n4096_K8": {
+                "reduced_s": round(fb_red, 4), "full_s": round(fb_full, 4), "cores": 1,
+                "sample": "oracle solve to 1e-6 (reduced: fold + cyclic Sinkhorn; full: "
+                          "full_sinkhorn on the n x n cost) and the envelope gradients of every "
+                          "point and marginal, one thread"},
             "oracle_iters_to_tol": ref["iters"],
             "gpu_vs_fp64": {"objective_rel": abs(vr["P"] - P_ref) / max(abs(P_ref), p.K * rv["CT"]),
                             "plan_l1_rel": float(np.abs(Tg - Tr).sum() / Tr.sum())}}
