@@ -874,61 +874,137 @@ __device__ void badj_point(const ot_batch_desc& d, int o, bool active, int lane,
         if (!active || lane >= nc) continue;
         const float fg = po + sh_pot[lane];
         auto P = [&](int cb, int dd) -> float { return sh_pts[(cb * DIM + dd) * kAdjChunk + lane]; };
-        // output block r = rot + rr takes T_k pt(a) with a = r + k (row) or a = r - k
-        // (column).  The RB partner copies in use at shift k live in a ring of float64
-        // values, block a in slot (a - rot) mod RB, so an output's slot (rr + k or rr - k mod
-        // RB) is a compile-time constant and each shift replaces one slot (the copy that
-        // leaves the window) with the one that enters.
-        double ring[RB][DIM];
-#pragma unroll
-        for (int rr = 0; rr < RB; ++rr)
-#pragma unroll
-          for (int dd = 0; dd < DIM; ++dd) ring[rr][dd] = (double)P((rot + rr) % KT, dd);
-        // shifts in rounds of RB: within a round the ring slot of every (output, shift) pair
-        // is a compile-time constant (k0 is a multiple of RB), and the rounds stay a loop so
-        // that the compiler does not schedule all K shifts' reads at once
-#pragma unroll 1
-        for (int k0 = 0; k0 < KT; k0 += RB) {
-#pragma unroll
-          for (int j = 0; j < RB; ++j) {
-            const int k = k0 + j;
-            // block-row 0 cost |x_i - y_{k m + j}|^2: row pass x_i own, y_{k m + j} the
-            // partner's copy in block k; column pass x_i the partner's copy in block 0
+        // dim 3 with K >= 8: a ring of plan entries (RB values) and one partner copy per step;
+        // otherwise a ring of partner copies (RB DIM values) and one plan entry per step.  The
+        // first keeps the large dim-3 classes within 128 registers (4 waves per SIMD instead
+        // of 3) at the price of RB - 1 recomputed entries per window; elsewhere the second is
+        // faster.
+        if constexpr (DIM == 3 && KT >= 8) {
+          // output block r = rot + rr takes T_k pt(a) with a = r + k (row) or a = r - k
+          // (column).  The loop runs over the partner copy a: each copy is read once (as
+          // float64) and multiplied by the RB plan entries it meets, T_{a - r} (row) or T_{r - a}
+          // (column), which live in a ring of RB float64 slots, slot k mod RB -- a compile-time
+          // constant for every (output, step) pair, since the steps go in rounds of RB and rot is
+          // a multiple of RB.  Each step computes the one entry that enters the window; the
+          // RB - 1 entries of the first window are computed before the loop.  (A ring of the
+          // RB partner copies instead would hold RB DIM values.)
+          double tr[RB];
+          auto entry = [&](int k) -> float {
             float c = 0.0f;
-#pragma unroll
+  #pragma unroll
             for (int dd = 0; dd < DIM; ++dd) {
               const float e = ROW ? xo[dd] - P(k, dd) : P(0, dd) - own_y[k * DIM + dd];
               c = fmaf(e, e, c);
             }
             const float T = exp2_fast((fg - c) * s2);
-            if (gq == 0) {  // the sums once per partner
+            if (gq == 0) {  // the sums once per (partner, shift)
               S += (double)T;
               if (ROW) {
                 vP = fmaf(T, fg - eps, vP);  // T (C + eps (Z - 1)) = T (f + g - eps)
                 vC = fmaf(T, c, vC);
               }
             }
-            if (grad) {
-              const double T64 = (double)T;
-#pragma unroll
-              for (int rr = 0; rr < RB; ++rr) {
-                const int slot = ROW ? (rr + j) % RB : ((rr - j) % RB + RB) % RB;
-#pragma unroll
-                for (int dd = 0; dd < DIM; ++dd)
-                  acc[rr * DIM + dd] = fma(T64, ring[slot][dd], acc[rr * DIM + dd]);
+            return T;
+          };
+          if (grad) {
+            // the first window: rows need k = -rot - rr (slot RB - rr), columns k = rot + rr
+            // (slot rr), rr = 1 .. RB - 1; recomputed here, not counted in the sums
+  #pragma unroll
+            for (int rr = 1; rr < RB; ++rr) {
+              const int k = ROW ? ((KT - rot - rr) % KT + KT) % KT : (rot + rr) % KT;
+              float c = 0.0f;
+  #pragma unroll
+              for (int dd = 0; dd < DIM; ++dd) {
+                const float e = ROW ? xo[dd] - P(k, dd) : P(0, dd) - own_y[k * DIM + dd];
+                c = fmaf(e, e, c);
               }
-              if (k + 1 < KT) {
-                // rows: block rot + k leaves (slot k mod RB), rot + k + RB enters; columns:
-                // block rot - k + RB - 1 leaves (slot (RB - 1 - k) mod RB), rot - k - 1
-                // enters
-                const int slot = ROW ? j : ((RB - 1 - j) % RB + RB) % RB;
-                int a = ROW ? rot + RB + k : rot - k - 1 + 2 * KT;
-                a %= KT;
-#pragma unroll
-                for (int dd = 0; dd < DIM; ++dd) ring[slot][dd] = (double)P(a, dd);
-              }
+              tr[ROW ? RB - rr : rr] = (double)exp2_fast((fg - c) * s2);
             }
-            if (j & 1) __builtin_amdgcn_sched_barrier(0);
+          }
+  #pragma unroll 1
+          for (int a0 = 0; a0 < KT; a0 += RB) {
+  #pragma unroll
+            for (int j = 0; j < RB; ++j) {
+              const int a = a0 + j;
+              // the entry entering the window: rows k = a - rot, columns k = rot - a (mod K)
+              const int kn = ROW ? ((a - rot) % KT + KT) % KT : ((rot - a) % KT + KT) % KT;
+              const float T = entry(kn);
+              if (grad) {
+                const int sn = ROW ? j : (RB - j) % RB;
+                tr[sn] = (double)T;
+                double pa[DIM];
+  #pragma unroll
+                for (int dd = 0; dd < DIM; ++dd) pa[dd] = (double)P(a, dd);
+  #pragma unroll
+                for (int rr = 0; rr < RB; ++rr) {
+                  // rows: k = a - rot - rr, slot (j - rr) mod RB; columns: k = rot + rr - a,
+                  // slot (rr - j) mod RB
+                  const int slot = ROW ? ((j - rr) % RB + RB) % RB : ((rr - j) % RB + RB) % RB;
+  #pragma unroll
+                  for (int dd = 0; dd < DIM; ++dd)
+                    acc[rr * DIM + dd] = fma(tr[slot], pa[dd], acc[rr * DIM + dd]);
+                }
+              }
+              if (j & 1) __builtin_amdgcn_sched_barrier(0);
+            }
+          }
+        } else {
+          // output block r = rot + rr takes T_k pt(a) with a = r + k (row) or a = r - k
+          // (column).  The RB partner copies in use at shift k live in a ring of float64
+          // values, block a in slot (a - rot) mod RB, so an output's slot (rr + k or rr - k mod
+          // RB) is a compile-time constant and each shift replaces one slot (the copy that
+          // leaves the window) with the one that enters.
+          double ring[RB][DIM];
+  #pragma unroll
+          for (int rr = 0; rr < RB; ++rr)
+  #pragma unroll
+            for (int dd = 0; dd < DIM; ++dd) ring[rr][dd] = (double)P((rot + rr) % KT, dd);
+          // shifts in rounds of RB: within a round the ring slot of every (output, shift) pair
+          // is a compile-time constant (k0 is a multiple of RB), and the rounds stay a loop so
+          // that the compiler does not schedule all K shifts' reads at once
+  #pragma unroll 1
+          for (int k0 = 0; k0 < KT; k0 += RB) {
+  #pragma unroll
+            for (int j = 0; j < RB; ++j) {
+              const int k = k0 + j;
+              // block-row 0 cost |x_i - y_{k m + j}|^2: row pass x_i own, y_{k m + j} the
+              // partner's copy in block k; column pass x_i the partner's copy in block 0
+              float c = 0.0f;
+  #pragma unroll
+              for (int dd = 0; dd < DIM; ++dd) {
+                const float e = ROW ? xo[dd] - P(k, dd) : P(0, dd) - own_y[k * DIM + dd];
+                c = fmaf(e, e, c);
+              }
+              const float T = exp2_fast((fg - c) * s2);
+              if (gq == 0) {  // the sums once per partner
+                S += (double)T;
+                if (ROW) {
+                  vP = fmaf(T, fg - eps, vP);  // T (C + eps (Z - 1)) = T (f + g - eps)
+                  vC = fmaf(T, c, vC);
+                }
+              }
+              if (grad) {
+                const double T64 = (double)T;
+  #pragma unroll
+                for (int rr = 0; rr < RB; ++rr) {
+                  const int slot = ROW ? (rr + j) % RB : ((rr - j) % RB + RB) % RB;
+  #pragma unroll
+                  for (int dd = 0; dd < DIM; ++dd)
+                    acc[rr * DIM + dd] = fma(T64, ring[slot][dd], acc[rr * DIM + dd]);
+                }
+                if (k + 1 < KT) {
+                  // rows: block rot + k leaves (slot k mod RB), rot + k + RB enters; columns:
+                  // block rot - k + RB - 1 leaves (slot (RB - 1 - k) mod RB), rot - k - 1
+                  // enters
+                  const int slot = ROW ? j : ((RB - 1 - j) % RB + RB) % RB;
+                  int a = ROW ? rot + RB + k : rot - k - 1 + 2 * KT;
+                  a %= KT;
+  #pragma unroll
+                  for (int dd = 0; dd < DIM; ++dd) ring[slot][dd] = (double)P(a, dd);
+                }
+              }
+              if (j & 1) __builtin_amdgcn_sched_barrier(0);
+            }
           }
         }
       }
