@@ -873,6 +873,7 @@ __device__ void badj_point(const ot_batch_desc& d, int o, bool active, int lane,
         __syncthreads();
         if (!active || lane >= nc) continue;
         const float fg = po + sh_pot[lane];
+        const float fgs = fg * s2;  // exponent (fg - c) s2 as one FMA per entry
         auto P = [&](int cb, int dd) -> float { return sh_pts[(cb * DIM + dd) * kAdjChunk + lane]; };
         // dim 3 with K >= 8: a ring of plan entries (RB values) and one partner copy per step;
         // otherwise a ring of partner copies (RB DIM values) and one plan entry per step.  The
@@ -896,7 +897,7 @@ __device__ void badj_point(const ot_batch_desc& d, int o, bool active, int lane,
               const float e = ROW ? xo[dd] - P(k, dd) : P(0, dd) - own_y[k * DIM + dd];
               c = fmaf(e, e, c);
             }
-            const float T = exp2_fast((fg - c) * s2);
+            const float T = exp2_fast(fmaf(c, -s2, fgs));
             if (gq == 0) {  // the sums once per (partner, shift)
               S += (double)T;
               if (ROW) {
@@ -918,7 +919,7 @@ __device__ void badj_point(const ot_batch_desc& d, int o, bool active, int lane,
                 const float e = ROW ? xo[dd] - P(k, dd) : P(0, dd) - own_y[k * DIM + dd];
                 c = fmaf(e, e, c);
               }
-              tr[ROW ? RB - rr : rr] = (double)exp2_fast((fg - c) * s2);
+              tr[ROW ? RB - rr : rr] = (double)exp2_fast(fmaf(c, -s2, fgs));
             }
           }
   #pragma unroll 1
@@ -975,7 +976,7 @@ __device__ void badj_point(const ot_batch_desc& d, int o, bool active, int lane,
                 const float e = ROW ? xo[dd] - P(k, dd) : P(0, dd) - own_y[k * DIM + dd];
                 c = fmaf(e, e, c);
               }
-              const float T = exp2_fast((fg - c) * s2);
+              const float T = exp2_fast(fmaf(c, -s2, fgs));
               if (gq == 0) {  // the sums once per partner
                 S += (double)T;
                 if (ROW) {
@@ -1128,6 +1129,9 @@ __device__ void bval_points(const ot_batch_desc& d, int o0, int lane, int wv,
     double col = 0.0;  // the lane's column j = c0 + lane: its terms over the wave's rows
     if (lane < nc) {
       const float pp = sh_pot[lane];
+      float fgs[kValPts];  // exponent (f_i + g_j - c) s2 as one FMA per entry
+#pragma unroll
+      for (int q = 0; q < kValPts; ++q) fgs[q] = (po[q] + pp) * s2;
 #pragma unroll 2
       for (int k = 0; k < KT; ++k) {
         float pt[DIM];
@@ -1141,8 +1145,7 @@ __device__ void bval_points(const ot_batch_desc& d, int o0, int lane, int wv,
             const float e = xo[q][dd] - pt[dd];
             c = fmaf(e, e, c);
           }
-          const float fg = po[q] + pp;
-          const float T = act[q] ? exp2_fast((fg - c) * s2) : 0.0f;
+          const float T = act[q] ? exp2_fast(fmaf(c, -s2, fgs[q])) : 0.0f;
           const double Td = (double)T;
           S[q] += Td;
           col += Td;
