@@ -339,19 +339,26 @@ __device__ __forceinline__ uint64_t slot_load(uint64_t* slot) {
 }
 
 // Wait until `w` (already loaded from `slot`) carries `epoch`; returns false on abort.
-// Polls are pipelined: the next load is issued before the previous one is examined, so a
-// new poll leaves every half round trip instead of every full one.
+// Polls are pipelined: DEPTH loads are in flight, a new one issued before the oldest is
+// examined, so a poll leaves every 1/DEPTH of a round trip; SLEEP (units of 64 cycles) spaces
+// them further.
+template <int SLEEP = 2, int DEPTH = 2>
 __device__ __forceinline__ bool slot_wait(uint64_t* slot, uint64_t& w, uint32_t epoch,
                                           uint32_t* abort_flag) {
+  static_assert(DEPTH >= 2, "at least two polls in flight");
   if ((uint32_t)(w >> 32) == epoch) return true;
   uint32_t spins = 0;
-  uint64_t next = slot_load(slot);
+  uint64_t q[DEPTH - 1];
+#pragma unroll
+  for (int k = 0; k < DEPTH - 1; ++k) q[k] = slot_load(slot);
   for (;;) {
-    __builtin_amdgcn_s_sleep(2);
+    if constexpr (SLEEP > 0) __builtin_amdgcn_s_sleep(SLEEP);
     const uint64_t after = slot_load(slot);
-    w = next;
+    w = q[0];
     if ((uint32_t)(w >> 32) == epoch) return true;
-    next = after;
+#pragma unroll
+    for (int k = 0; k + 1 < DEPTH - 1; ++k) q[k] = q[k + 1];
+    q[DEPTH - 2] = after;
     if (++spins >= kSpinLimit) {
       __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return false;
@@ -378,6 +385,7 @@ __device__ __forceinline__ float slot_value(uint64_t w) {
 // `extra` is non-null, the `nextra` slots of `extra` into xv.  Every thread issues all its
 // loads first and then waits on the ones not yet current, so both sets cost one round trip.
 // Returns false on abort.
+template <int SLEEP = 2, int DEPTH = 2>
 __device__ __forceinline__ bool stage_slots(uint64_t* src, int m, int mp, uint32_t epoch,
                                             float* Vs, uint64_t* extra, int nextra,
                                             uint32_t xepoch, float* xv, uint32_t* abort_flag,
@@ -397,12 +405,12 @@ __device__ __forceinline__ bool stage_slots(uint64_t* src, int m, int mp, uint32
     for (int u = 0; u < kB; ++u) {
       const int j = base + u * (int)blockDim.x;
       if (j < m) {
-        if (ok) ok = slot_wait(src + j, w[u], epoch, abort_flag);
+        if (ok) ok = slot_wait<SLEEP, DEPTH>(src + j, w[u], epoch, abort_flag);
         Vs[j] = slot_value(w[u]);
       } else if (j < mp) {
         Vs[j] = 0.0f;
       } else if (j < total) {
-        if (ok) ok = slot_wait(extra + (j - mp), w[u], xepoch, abort_flag);
+        if (ok) ok = slot_wait<SLEEP, DEPTH>(extra + (j - mp), w[u], xepoch, abort_flag);
         xv[j - mp] = slot_value(w[u]);
       }
     }

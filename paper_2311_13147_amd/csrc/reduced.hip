@@ -36,6 +36,12 @@ constexpr int kRedThreads = 1024;        // 16 waves; one row (column) per wave 
 constexpr int kRedWaves = kRedThreads / kWave;
 constexpr int kMaxLds = 150 * 1024;
 constexpr int kSweep = 4 * kWave * 2;    // elements per register sweep (two float4 per lane)
+// Exchange polling of the iteration loop: loads in flight per polled slot, and the sleep
+// between polls (units of 64 cycles).  The 32 workgroups of m = 512 poll the same 4 KB of
+// slots, so more loads in flight lengthen the exchange (measured at n = 8192, K = 16: 2.56 us
+// per iteration with two in flight and no sleep, 2.88 with three, 3.24 with four, 2.63 with
+// two and a sleep of 128 cycles).
+constexpr int kPollDepth = 2, kPollSleep = 0;
 
 struct RedParams {
   int m, mp, K, W, R, max_iter, warm;
@@ -161,6 +167,40 @@ __device__ __forceinline__ float wave_update(const float* __restrict__ row,
   const float Fn = lm - wave_lse2(row, vec, mp, lane);
   *sum_out = -1.0f;  // not available: the caller uses the potential difference
   return Fn;
+}
+
+// The same update when the padded row is one sweep (mp == kSweep) held in registers: l0, l1
+// are this lane's 8 entries of the row (natural logK), as the LDS forms read them.
+__device__ __forceinline__ float wave_update_reg(const float4& l0, const float4& l1,
+                                                 const float* __restrict__ vec, int lane,
+                                                 float lm, float prev, bool shifted,
+                                                 float* sum_out) {
+  const int q0 = 4 * lane, q1 = q0 + 4 * kWave;
+  const float4 v0 = *reinterpret_cast<const float4*>(vec + q0);
+  const float4 v1 = *reinterpret_cast<const float4*>(vec + q1);
+  const float t[8] = {fmaf(l0.x, kLog2e, v0.x), fmaf(l0.y, kLog2e, v0.y),
+                      fmaf(l0.z, kLog2e, v0.z), fmaf(l0.w, kLog2e, v0.w),
+                      fmaf(l1.x, kLog2e, v1.x), fmaf(l1.y, kLog2e, v1.y),
+                      fmaf(l1.z, kLog2e, v1.z), fmaf(l1.w, kLog2e, v1.w)};
+  if (shifted) {
+    float s = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s += exp2_fast(t[k] + prev);
+    const float S = wave_sum_v(s);
+    if (S >= kMinShiftedSum && S < INFINITY) {
+      *sum_out = S;
+      return lm - log2_fast(S) + prev;
+    }
+  }
+  float mx = fmaxf(fmaxf(fmaxf(t[0], t[1]), fmaxf(t[2], t[3])),
+                   fmaxf(fmaxf(t[4], t[5]), fmaxf(t[6], t[7])));
+  mx = fmaxf(kNegBig, wave_max_v(mx));
+  float s = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) s += exp2_fast(t[k] - mx);
+  s = wave_sum_v(s);
+  *sum_out = -1.0f;
+  return lm - (mx + log2_fast(s));
 }
 
 // GSLAB: the slabs are read from the padded copies in device memory (large m); otherwise they
@@ -297,6 +337,19 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
   int iters_done = 0, converged = 0, flags = 0;
   float err2 = 0.0f;
 
+  // A row of one sweep and at most one row (column) per wave: each wave keeps its row and its
+  // column of logK in registers for the whole solve, so that a half-step reads only the
+  // staged potentials from LDS.
+  const bool reg = !GSLAB && mp == kSweep && nr <= kRedWaves;
+  float4 lr0 = {}, lr1 = {}, lc0 = {}, lc1 = {};
+  if (reg && wv < nr) {
+    const int q0 = 4 * lane, q1 = q0 + 4 * kWave;
+    lr0 = *reinterpret_cast<const float4*>(Ls + (size_t)wv * mp + q0);
+    lr1 = *reinterpret_cast<const float4*>(Ls + (size_t)wv * mp + q1);
+    lc0 = *reinterpret_cast<const float4*>(LTs + (size_t)wv * mp + q0);
+    lc1 = *reinterpret_cast<const float4*>(LTs + (size_t)wv * mp + q1);
+  }
+
   // When the launch placed every workgroup on one XCD (stride 8), confirm it: then the
   // potentials can be published through that XCD's L2 alone (slot_publish_local), which
   // halves the exchange latency.  Otherwise every publication is agent-scope.
@@ -333,7 +386,8 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
       float S;
       const float Fo = Fcur[rl];
       const float Fn =
-          wave_update<GSLAB>(Ls + (size_t)rl * mp, VsG, mp, lane, la2[rl], Fo, t >= 2, &S);
+          reg ? wave_update_reg(lr0, lr1, VsG, lane, la2[rl], Fo, t >= 2, &S)
+              : wave_update<GSLAB>(Ls + (size_t)rl * mp, VsG, mp, lane, la2[rl], Fo, t >= 2, &S);
       if (lane == 0) {
         publish(p.fx + r0 + rl, Fn, t);  // first: the other workgroups wait for it
         if (t >= 2) {
@@ -365,7 +419,7 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
     }
 
     // ---- exchange F^t (barrier), residual partial of iteration t, column update -----------
-    if (!stage_slots(p.fx, m, mp, t, VsF, nullptr, 0, 0, nullptr, abort_flag, &s_bad)) {
+    if (!stage_slots<kPollSleep, kPollDepth>(p.fx, m, mp, t, VsF, nullptr, 0, 0, nullptr, abort_flag, &s_bad)) {
       flags |= 2;
       break;
     }
@@ -378,7 +432,8 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
       float S;
       const float Go = Gcur[cl];
       const float Gn =
-          wave_update<GSLAB>(LTs + (size_t)cl * mp, VsF, mp, lane, lb2[cl], Go, true, &S);
+          reg ? wave_update_reg(lc0, lc1, VsF, lane, lb2[cl], Go, true, &S)
+              : wave_update<GSLAB>(LTs + (size_t)cl * mp, VsF, mp, lane, lb2[cl], Go, true, &S);
       if (lane == 0) {
         publish(p.gx + r0 + cl, Gn, t);
         Gprev[cl] = Go;
@@ -390,7 +445,7 @@ __global__ void __launch_bounds__(kRedThreads) reduced_solver_kernel(RedParams p
     // A workgroup that is one iteration ahead may already publish its next residual partial
     // while this one still polls; the parity buffers keep the two apart.
     const int nres = t >= 2 ? p.W : 0;
-    if (!stage_slots(p.gx, m, mp, t, VsG, p.rsx + (t & 1u) * p.W, nres, t, rsv, abort_flag,
+    if (!stage_slots<kPollSleep, kPollDepth>(p.gx, m, mp, t, VsG, p.rsx + (t & 1u) * p.W, nres, t, rsv, abort_flag,
                      &s_bad)) {
       flags |= 2;
       break;
