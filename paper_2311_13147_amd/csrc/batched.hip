@@ -1085,6 +1085,205 @@ __device__ void badj_point(const ot_batch_desc& d, int o, bool active, int lane,
   }
 }
 
+// ---- gradients on the float64 matrix cores (K in {1, 2, 4, 8, 16, 32}) --------------------
+// For the K copies of an own point the circular sums above are one matrix product per pass:
+//   row    : Y[i, (r, d)] = sum_{(k, j)} T_ijk B[(k, j), (r, d)],  B = y_{((r + k) mod K) m + j, d}
+//   column : X[j, (c, d)] = sum_{(k, i)} T_ijk B[(k, i), (c, d)],  B = x_{((c - k) mod K) m + i, d}
+// (inner index (shift, partner), K DIM output columns).  A wave takes 16 own points; for each
+// quad of partners and each shift its 64 lanes evaluate the 16 x 4 plan entries T (lane l: own
+// point l mod 16, partner l / 16) -- the A operand of v_mfma_f64_16x16x4f64 -- and gather the
+// matching 4 x 16 B operands from the staged partner copies, one per tile of 16 output columns.
+// Every plan entry is evaluated once per pass, and the float64 products and sums run on the
+// matrix cores.  The lane layout: A[l mod 16][l / 16], B[l / 16][l mod 16], and the four
+// results of lane l are D[l / 16 + 4 v][l mod 16], v = 0..3.
+typedef double v4d __attribute__((ext_vector_type(4)));
+constexpr int kMfPts = 16;                      // own points per wave
+constexpr int kGradPts = kAdjPts * kMfPts;      // own points per gradient tile
+constexpr int kGradChunk = 32;                  // partners staged in LDS at a time
+
+// LDS geometry of a class: a staged partner holds its NC = K DIM copy components twice in a
+// row (so that the component of block (r + k) mod K or (c - k) mod K is read at r DIM + d +
+// k DIM or c DIM + d + NC - k DIM without a wrap), rows kGradRow floats apart -- an odd
+// multiple of 16, so that the four partners of a quad fall in disjoint quarters of the 64 LDS
+// banks while the 16 lanes of each read 16 consecutive words; the own copies of the column
+// tiles are rows of NC + 1 floats (an odd stride, one bank per own point).
+template <int KT, int DIM>
+struct GradLds {
+  static constexpr int NC = KT * DIM;
+  static constexpr int kRow = ((2 * NC + 15) / 16) | 1;
+  static constexpr int ROWF = 16 * kRow;          // floats per staged partner
+  static constexpr int OWNF = NC + 1;             // floats per own point
+};
+
+template <int DIM, int KT, bool ROW>
+__device__ void bgrad_tile(const ot_batch_desc& d, int first, int wv, int lane, double* wvals,
+                           float* sh_pts, float* sh_pot, float* sh_own, double* sh_S) {
+  using L = GradLds<KT, DIM>;
+  constexpr int NC = L::NC;                   // output columns (block, component)
+  constexpr int NCT = (NC + 15) / 16;         // column tiles of the matrix product
+  constexpr int NS = NCT <= 2 ? 2 : 1;        // accumulator sets (alternating shifts)
+  constexpr int RF = L::ROWF, OF = L::OWNF;
+  static_assert((KT & (KT - 1)) == 0 && KT >= 1 && KT <= 32, "K a power of two up to 32");
+  const int m = bm(d), K = d.K;
+  const float s2 = (float)(kLog2eD / d.eps);
+  const float eps = (float)d.eps;
+  gcfloat* x = as_global(d.x);
+  gcfloat* y = as_global(d.y);
+  gcfloat* fpot = as_global(d.f);
+  gcfloat* gpot = as_global(d.g);
+  float* __restrict__ gout = ROW ? d.dx : d.dy;
+  const bool grad = gout != nullptr;
+  const int r16 = lane & 15, iq = lane >> 4;
+  const int o0 = first + wv * kMfPts;          // the wave's first own point
+  const bool actA = o0 + r16 < m;              // own point of this lane's A entries
+  const int oc = actA ? o0 + r16 : 0;
+  const float po = ROW ? fpot[oc] : gpot[oc];
+  float xo[DIM];
+  if constexpr (ROW) {
+#pragma unroll
+    for (int dd = 0; dd < DIM; ++dd) xo[dd] = x[oc * DIM + dd];
+  } else {
+    // the own columns' copies y_{k m + j} of every block
+    float* own = sh_own + (size_t)wv * kMfPts * OF;
+    for (int e = lane; e < kMfPts * NC; e += kWave) {
+      const int q = e / NC, kd = e - q * NC;
+      const int o = min(o0 + q, m - 1);
+      own[q * OF + kd] = y[((kd / DIM) * m + o) * DIM + kd % DIM];
+    }
+  }
+  // this lane's B column in each tile (block r, component d as r DIM + d); the padding columns
+  // of a last partial tile read a valid column and their results are not stored
+  int bcol[NCT];
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct) bcol[ct] = min(ct * 16 + r16, NC - 1) + (ROW ? 0 : NC);
+  v4d acc[NS][NCT];
+#pragma unroll
+  for (int u = 0; u < NS; ++u)
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) acc[u][ct] = v4d{0.0, 0.0, 0.0, 0.0};
+  // value sums: float64 per plan entry for the marginal, float32 over the K shifts of a
+  // partner for P and <C, T> (then float64), as the point-per-wave path accumulates them
+  double S = 0.0, tP = 0.0, tC = 0.0;
+  gcfloat* src = ROW ? y : x;
+  const float* own = sh_own + ((size_t)wv * kMfPts + r16) * OF;
+#pragma unroll 1
+  for (int c0 = 0; c0 < m; c0 += kGradChunk) {
+    __syncthreads();  // the previous chunk's readers are done
+    const int nc = min(kGradChunk, m - c0);
+    for (int e = threadIdx.x; e < NC * kGradChunk; e += blockDim.x) {
+      const int q = e % kGradChunk, cd = e / kGradChunk;
+      const int cb = cd / DIM, dd = cd - cb * DIM;
+      const float v = q < nc ? src[(cb * m + c0 + q) * DIM + dd] : 0.0f;
+      sh_pts[q * RF + cd] = v;
+      sh_pts[q * RF + cd + NC] = v;
+    }
+    if (threadIdx.x < kGradChunk)
+      sh_pot[threadIdx.x] = (int)threadIdx.x < nc ? (ROW ? gpot : fpot)[c0 + threadIdx.x] : 0.0f;
+    __syncthreads();
+#pragma unroll 1
+    for (int jq = 0; jq < nc; jq += 4) {
+      const int jl = jq + iq;  // this lane's partner (A inner index and B row), < kGradChunk
+      const float fg = po + sh_pot[jl];
+      // exponent (fg - c) s2 as one FMA; -inf (T = 0) for an own point or partner beyond m
+      const float fgs = actA && jl < nc ? fg * s2 : -INFINITY;
+      const float* pp = sh_pts + jl * RF;
+      float vP = 0.0f, vC = 0.0f;
+      // (unrolled by two: a full unroll holds 254 registers at K = 32, dim 3 for the same time)
+#pragma unroll 2
+      for (int k = 0; k < KT; ++k) {
+        float c = 0.0f;
+#pragma unroll
+        for (int dd = 0; dd < DIM; ++dd) {
+          const float e = ROW ? xo[dd] - pp[k * DIM + dd] : pp[dd] - own[k * DIM + dd];
+          c = fmaf(e, e, c);
+        }
+        const float T = exp2_fast(fmaf(c, -s2, fgs));
+        const double a = (double)T;
+        S += a;
+        if (ROW) {
+          vP = fmaf(T, fg - eps, vP);  // T (C + eps (Z - 1)) = T (f + g - eps)
+          vC = fmaf(T, c, vC);
+        }
+        // (run also when this pass has no gradient output: the products are then unused)
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+          // row: block (r + k) mod K at r DIM + d + k DIM; column: block (c - k) mod K at
+          // c DIM + d + NC - k DIM (bcol holds the NC)
+          const double b = (double)pp[bcol[ct] + (ROW ? k * DIM : -k * DIM)];
+          acc[k % NS][ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[k % NS][ct], 0, 0, 0);
+        }
+      }
+      if (ROW) {
+        tP += (double)vP;
+        tC += (double)vC;
+      }
+    }
+  }
+  // own point r16's sums: its four lanes (one per partner of a quad)
+  S += __shfl_xor(S, 16, kWave);
+  S += __shfl_xor(S, 32, kWave);
+  tP += __shfl_xor(tP, 16, kWave);
+  tP += __shfl_xor(tP, 32, kWave);
+  tC += __shfl_xor(tC, 16, kWave);
+  tC += __shfl_xor(tC, 32, kWave);
+  if (iq == 0) sh_S[wv * kMfPts + r16] = S;
+  __syncthreads();
+  if (grad) {
+    // lane l holds the sums of own points o0 + l / 16 + 4 v for its column of each tile
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) {
+      v4d D = acc[0][ct];
+      if constexpr (NS == 2) D += acc[1][ct];
+      const int col = ct * 16 + r16;
+      if (col >= NC) continue;
+      const int r = col / DIM, dd = col - r * DIM;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int q = iq + 4 * v;
+        const int o = o0 + q;
+        if (o >= m) continue;
+        const int Pi = r * m + o;
+        const double ownc = (double)(ROW ? x : y)[Pi * DIM + dd];
+        gout[Pi * DIM + dd] = (float)(2.0 * (ownc * sh_S[wv * kMfPts + q] - D[v]));
+      }
+    }
+  }
+  // per own point: folded marginal, da / db, and the value terms (lanes 0..15)
+  gcfloat* marg_in = as_global(ROW ? d.a : d.b);
+  gcfloat* pot = ROW ? fpot : gpot;
+  double ps = 0.0;
+  for (int q = lane; q < m; q += kWave) ps += (double)pot[q];
+  const double pmean = wave_sum_all_d(ps) / m;
+  float* __restrict__ dpot = ROW ? d.da : d.db;
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0, v4 = 0.0;
+  if (iq == 0 && actA) {
+    const int o = o0 + r16;
+    double mv = 0.0;
+    for (int r = 0; r < K; ++r) mv += (double)marg_in[r * m + o];
+    const double marg = mv / K;
+    if (dpot)
+      for (int r = 0; r < K; ++r) dpot[r * m + o] = (float)((double)po - pmean);
+    const double dr = S - marg;
+    v0 = ROW ? tP : 0.0;
+    v1 = ROW ? tC : 0.0;
+    v2 = ROW ? S : 0.0;
+    v3 = dr * dr;
+    v4 = (double)po * marg;
+  }
+  v0 = wave_sum_all_d(v0);
+  v1 = wave_sum_all_d(v1);
+  v2 = wave_sum_all_d(v2);
+  v3 = wave_sum_all_d(v3);
+  v4 = wave_sum_all_d(v4);
+  if (lane == 0) {
+    wvals[0] = v0;
+    wvals[1] = v1;
+    wvals[2] = v2;
+    wvals[3] = v3;
+    wvals[4] = v4;
+  }
+}
+
 // Values only (a problem whose descriptor asks for no coordinate gradients): each wave takes
 // four own points, so that a staged partner chunk serves the workgroup's sixteen points; per
 // point the row (column) sum, P and <C, T> of the K m plan entries of block 0, da / db and
@@ -1225,14 +1424,27 @@ __global__ void __launch_bounds__(256)
   // gradients: 4 own points per tile (one per wave); values only: 16 (four per wave)
   const bool grad = d.dx != nullptr || d.dy != nullptr;
   if ((!grad && KT > 0) != VO) return;
-  const int ppt = VO ? kAdjPts * kValPts : kAdjPts;
+  const int ppt = VO ? kAdjPts * kValPts : (KT > 0 ? kGradPts : kAdjPts);
   const int nrow = (m + ppt - 1) / ppt;
   const int t = tile - vstart[q];
   double* acc = accs + 8 * (size_t)p;
   const bool row = t < nrow;  // values only: every tile is a row tile
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   const int first = (row ? t : t - nrow) * ppt;
-  if constexpr (!VO) {
+  if constexpr (!VO && KT > 0) {
+    // 16 own points per wave on the matrix cores; LDS sized for the class
+    using L = GradLds<KT, DIM>;
+    __shared__ float g_pts[kGradChunk * L::ROWF];
+    __shared__ float g_pot[kGradChunk];
+    __shared__ float g_own[kAdjPts * kMfPts * L::OWNF];  // column tiles' own copies
+    __shared__ double g_S[kGradPts];
+    if (lane == 0)
+      for (int v = 0; v < 8; ++v) vals16[wv][v] = 0.0;
+    if (row)
+      bgrad_tile<DIM, KT, true>(d, first, wv, lane, vals16[wv], g_pts, g_pot, g_own, g_S);
+    else
+      bgrad_tile<DIM, KT, false>(d, first, wv, lane, vals16[wv], g_pts, g_pot, g_own, g_S);
+  } else if constexpr (!VO) {
     __shared__ BAdjShared sh;
     const int o = first + wv;
     const bool active = o < m;
@@ -1264,7 +1476,7 @@ __global__ void __launch_bounds__(256)
   // the workgroup's partials: one atomic add per value
   if (threadIdx.x < 5) {
     const int v = threadIdx.x;
-    const int np = ppt;
+    const int np = VO ? ppt : kAdjPts;  // one partial per wave with gradients
     double sum = 0.0;
     for (int w = 0; w < np; ++w) sum += vals16[w][v];
     // rows: P, <C,T>, mass, (rowsum - alpha)^2, <f,alpha>; columns: (colsum - beta)^2, <g,beta>
@@ -1414,10 +1626,10 @@ int batched_plan(const ot_batch_desc* h, int count, int32_t* plan) {
       const int m = h[p].n / h[p].K;
       vorder[q] = p;
       vstart[q] = (int32_t)nv;
-      // value tiles of 4 block-0 points with gradients (one per wave), 16 without (four per
-      // wave) unless K takes the generic path
+      // value tiles of block-0 points: with gradients 64 (16 per wave, matrix cores), or 4
+      // (one per wave) when K takes the generic path; 16 without (four per wave)
       const bool kt = k_class(h[p].K) < 6;
-      const int ppt = fused_columns(h[p], kt) ? kAdjPts * kValPts : kAdjPts;
+      const int ppt = fused_columns(h[p], kt) ? kAdjPts * kValPts : (kt ? kGradPts : kAdjPts);
       nv += (fused_columns(h[p], kt) ? 1 : 2) * ((m + ppt - 1) / ppt);
       cls_kind[c] |= fused_columns(h[p], kt) ? 2 : 1;
       ++q;

@@ -164,15 +164,19 @@ def test_batched_plan_validation_and_order(B):
     assert order == [1, 2, 0]              # m = 16, 64, 48: largest first
     assert list(plan[H + 3:H + 6]) == [0, 2, 4]   # fold tiles in that order: ceil(m/32) = 2, 2, 1
     # value tiles grouped by (dim, K) class -- K = 2 (problem 2), K = 4 (0), K = 8 (1) -- each
-    # 2 ceil(m/4) tiles of 4 block-0 points (rows, then columns): 24, 8, 32
+    # 2 ceil(m/64) tiles of 64 block-0 points (rows, then columns; matrix-core gradients): 2, 2, 2
     assert list(plan[H + 6:H + 9]) == [2, 0, 1]
-    assert list(plan[H + 9:H + 12]) == [0, 24, 32]
+    assert list(plan[H + 9:H + 12]) == [0, 2, 4]
     cls_q, cls_tile = list(plan[4:19]), list(plan[19:34])
     assert cls_q[:5] == [0, 0, 1, 2, 3] and cls_q[14] == 3
-    assert cls_tile[:5] == [0, 0, 24, 32, 64] and cls_tile[14] == 64
+    assert cls_tile[:5] == [0, 0, 2, 4, 6] and cls_tile[14] == 6
     cls_kind = list(plan[34:48])          # bit 0: gradients, bit 1: values only
     assert cls_kind[:4] == [0, 1, 1, 1] and sum(cls_kind[4:]) == 0
-    assert plan[0] == 5 and plan[1] == 64   # fold tiles 1 + 2 + 2
+    assert plan[0] == 5 and plan[1] == 6    # fold tiles 1 + 2 + 2
+    # a K outside {1, 2, 4, 8, 16, 32} takes the generic gradient path: tiles of 4 points
+    descs[2].K = 3                          # n = 96: m = 32, 2 ceil(32 / 4) = 16 tiles
+    assert _lib.ot_batched_plan(descs, 3, plan) == 0 and plan[1] == 4 + 16
+    descs[2].K = 2
     descs[1].K = 7                          # 512 % 7 != 0
     assert _lib.ot_batched_plan(descs, 3, plan) == B.OT_ERR_ARG
     descs[1].K, descs[1].tile_cfg = 8, 24

@@ -119,10 +119,12 @@ def test_batched_equals_unbatched_and_oracle(lib):
 def test_batched_values_only_equals_with_gradients(lib):
     """A batch that asks for no gradients takes value tiles of 16 points with the column sums
     fused into the row pass (a different kernel path): same potentials, iterations and values
-    as the batch with gradients.  The float64 sums differ only in their order, except the
-    primal value: the gradient path accumulates T (f + g - eps) per lane in float32, the
+    as the batch with gradients.  The float64 sums differ only in their order, except two:
+    the primal value (the gradient path accumulates T (f + g - eps) in float32 partials, the
     values-only path forms the same sum as sum_i (f_i - eps) rowsum_i + sum_j g_j colsum_j
-    from the float64 marginal sums, so the two agree to float32 accumulation (1e-7)."""
+    from the float64 marginal sums) and <C, T> (float32 partials in both, over the K shifts of
+    one partner on the matrix-core gradient path, over every chunk and shift of a lane on the
+    values-only path): these agree to float32 accumulation (1e-7)."""
     probs = _problems(SMALL)
     print("[batched values only] 12 problems", flush=True)
     opts = lib.make_opts(tol=1e-6, max_iter=20000, fold_fp64=1)
@@ -138,7 +140,7 @@ def test_batched_values_only_equals_with_gradients(lib):
         scale = max(abs(og[k, 0]), og[k, 2])
         assert abs(og[k, 0] - ov[k, 0]) <= 1e-7 * scale, k
         assert abs(og[k, 1] - ov[k, 1]) <= 1e-9 * scale, k
-        assert abs(og[k, 2] - ov[k, 2]) <= 1e-9 * og[k, 2], k
+        assert abs(og[k, 2] - ov[k, 2]) <= 1e-7 * og[k, 2], k
         assert abs(og[k, 3] - ov[k, 3]) <= 1e-6 * og[k, 3] + 1e-15, k
         assert abs(og[k, 4] - ov[k, 4]) <= 1e-6 * og[k, 4] + 1e-15, k
 
