@@ -8,7 +8,8 @@
 // Work split: workgroup w owns rows [w R, w R + R) and columns [w R, w R + R).  It keeps its
 // row slab of logK and its column slab (a transposed copy) in LDS for the whole solve (natural
 // log as stored; one fma per entry turns it into L), so an iteration reads no matrix data from
-// memory.  The new potentials are published as epoch-tagged 64-bit slots (value | iteration);
+// memory; for m <= 512 (one row and one column per wave) each wave holds its row and column in
+// registers instead, and a half-step reads only the staged potentials from LDS.  The new potentials are published as epoch-tagged 64-bit slots (value | iteration);
 // each workgroup polls the m slots of the other potential until they carry the current
 // iteration and stages them in LDS.  The data is its own ready flag, so there is no counter
 // barrier and no cache flush; the dependency chain (F^t needs every G^{t-1}, G^t needs every
