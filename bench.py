@@ -155,7 +155,8 @@ class BatchedLeg:
             else:
                 passes = 2 * it_ + 1
             solve_bytes += passes * m_ * mp_ * 4
-        # the float64 FMAs of the gradients: dx and dy of every point, 2 n^2 dim per problem
+        # the float64 multiply-adds of the gradients (on the matrix cores): dx and dy of every
+        # point, 2 n^2 dim per problem
         grad_fma = float(sum(2.0 * (it.m * it.K) ** 2 * it.dim for it in self.items))
 
         # The same problems solved one at a time at full size (n = K m points per side) on the
@@ -519,7 +520,8 @@ def peaks_only():
                                   "full_entry_mix_T_per_s": pk["full_entry_mix_per_s"] / 1e12,
                                   "copy_GBps": pk["copy_bytes_per_s"] / 1e9,
                                   "slot_hop_us_same_xcd": pk["slot_hop_s_same_xcd"] * 1e6,
-                                  "slot_hop_us_cross_xcd": pk["slot_hop_s_cross_xcd"] * 1e6}}),
+                                  "slot_hop_us_cross_xcd": pk["slot_hop_s_cross_xcd"] * 1e6,
+                                  "fp64_matrix_TFLOPs": 2 * pk["mfma64_madd_per_s"] / 1e12}}),
           flush=True)
 
 

@@ -347,10 +347,11 @@ int ot_sinkhorn_reduced_batched(const ot_batch_desc* descs, int32_t count, const
  *   [5] one-way latency (s) of an epoch-tagged slot between two workgroups on one XCD with
  *       XCD-local publication (the reduced solver's exchange; NaN if a wait timed out);
  *   [6] the same between XCDs with device-scope publication;
- *   [7] 1 if [5] used XCD-local publication (both workgroups found on one XCD), else 0.
+ *   [7] 1 if [5] used XCD-local publication (both workgroups found on one XCD), else 0;
+ *   [8] float64 matrix-core rate (v_mfma_f64_16x16x4f64), multiply-adds per second.
  * ws: ot_peaks_workspace_bytes() bytes, 256-byte aligned.  Errors: OT_ERR_ARG,
  * OT_ERR_WORKSPACE, OT_ERR_HIP. */
-#define OT_PEAKS_LEN 8
+#define OT_PEAKS_LEN 9
 size_t ot_peaks_workspace_bytes(void);
 int ot_measure_peaks(double* out, void* ws, size_t ws_bytes, void* stream);
 

@@ -424,19 +424,21 @@ def ot_cost_and_grad(prob: Problem, f, g, reduced: bool, want_dC=False, want_dxy
     return {"values": vals, "dC": dC, "dx": dx, "dy": dy, "da": da, "db": db}
 
 
-OT_PEAKS_LEN = 8
+OT_PEAKS_LEN = 9
 
 
 def ot_measure_peaks(device="cuda:0"):
     """Micro-benchmarks of the device (synchronises) -> dict of issue rates (lane operations
-    per second), copy bandwidth (bytes/s) and slot latencies (s)."""
+    per second; the matrix cores in multiply-adds per second), copy bandwidth (bytes/s) and
+    slot latencies (s)."""
     nbytes = int(_lib.ot_peaks_workspace_bytes())
     ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
     out = (ctypes.c_double * OT_PEAKS_LEN)()
     _check(_lib.ot_measure_peaks(out, _ptr(ws), nbytes, _stream()))
     del ws
     keys = ("fma32_per_s", "fma64_per_s", "exp2_per_s", "full_entry_mix_per_s", "copy_bytes_per_s",
-            "slot_hop_s_same_xcd", "slot_hop_s_cross_xcd", "same_xcd_local_publication")
+            "slot_hop_s_same_xcd", "slot_hop_s_cross_xcd", "same_xcd_local_publication",
+            "mfma64_madd_per_s")
     return dict(zip(keys, list(out)))
 
 

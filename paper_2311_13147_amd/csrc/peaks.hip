@@ -8,6 +8,8 @@
 //   entry mix   the full-size Sinkhorn inner step per (I, J) entry on pre-scaled coordinates
 //               in registers: 2 subtractions, 2 FMAs, one exp2 and the accumulation -- the
 //               instruction mix whose issue rate bounds the full-size solver
+//   fp64 MFMA   v_mfma_f64_16x16x4f64 (16 x 4 by 4 x 16, 1024 multiply-adds) on 8 independent
+//               accumulators per wave -- the matrix cores the batched gradients run on
 //   copy        float4 device-to-device copy of a buffer much larger than the caches
 //   slot hop    one-way latency of an epoch-tagged slot (common.hpp) between two workgroups:
 //               on one XCD with XCD-local publication (the reduced solver's exchange) and
@@ -54,6 +56,24 @@ __global__ void __launch_bounds__(kPeakThreads) peak_fma64_kernel(double* out, i
   double s = 0.0;
 #pragma unroll
   for (int c = 0; c < kPeakChains; ++c) s += v[c];
+  if (s == -1.0) out[blockIdx.x] = s;
+}
+
+typedef double v4d_peak __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(kPeakThreads) peak_mfma64_kernel(double* out, int iters) {
+  v4d_peak acc[kPeakChains];
+#pragma unroll
+  for (int c = 0; c < kPeakChains; ++c) acc[c] = v4d_peak{0.0, 0.0, 0.0, 0.0};
+  const double a = 1.0 + 1e-3 * (threadIdx.x & 15), b = 1e-7 * (1 + (threadIdx.x >> 4));
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int c = 0; c < kPeakChains; ++c)
+      acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int c = 0; c < kPeakChains; ++c) s += (acc[c][0] + acc[c][1]) + (acc[c][2] + acc[c][3]);
   if (s == -1.0) out[blockIdx.x] = s;
 }
 
@@ -258,6 +278,13 @@ hipError_t measure_peaks(double* out, void* scratch, hipStream_t s) {
     out[5 + v] = ab ? NAN : tt / (2.0 * hops);
     if (v == 0) out[7] = used_local;
   }
+  // fp64 matrix cores: 1024 multiply-adds per wave instruction
+  const int itf = 1024;
+  if ((e = timed([&] { hipLaunchKernelGGL(peak_mfma64_kernel, dim3(blocks), dim3(kPeakThreads), 0,
+                                          s, reinterpret_cast<double*>(sink), itf); },
+                 s, &t)) != hipSuccess)
+    return e;
+  out[8] = (double)blocks * (kPeakThreads / kWave) * itf * kPeakChains * 1024.0 / t;
   return hipSuccess;
 }
 

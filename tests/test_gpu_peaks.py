@@ -1,7 +1,7 @@
 """The device micro-benchmarks behind the roofline figures (ot_measure_peaks): every rate is
 positive and finite and below what the chip's unit counts allow (256 CUs, 64 lanes of fp32 or
-fp64 FMA and at most 64 lanes of exp2 per CU and clock, 2.4 GHz), the exp2 rate is below the
-FMA rate, the slot hops are sub-microsecond to tens of microseconds, and the same-XCD hop used
+fp64 FMA and at most 64 lanes of exp2 per CU and clock, 2.4 GHz; 1024 float64 matrix-core
+multiply-adds per 64 cycles per SIMD), the exp2 rate is below the FMA rate, the slot hops are sub-microsecond to tens of microseconds, and the same-XCD hop used
 XCD-local publication on a device whose blocks are dealt round-robin to 8 XCDs."""
 import math
 
@@ -24,3 +24,8 @@ def test_peaks_are_plausible(lib):
     for key in ("slot_hop_s_same_xcd", "slot_hop_s_cross_xcd"):
         assert math.isfinite(pk[key]) and 1e-8 < pk[key] < 5e-5, (key, pk[key])
     assert pk["same_xcd_local_publication"] in (0.0, 1.0)
+    # float64 matrix cores: at most 1024 multiply-adds per 64 cycles per SIMD (the published
+    # 78.6 TFLOP/s at 2.4 GHz), and well above the vector unit's fp64 rate
+    mfma_peak = 256 * 4 * 16 * 2.4e9 * 1.05
+    assert math.isfinite(pk["mfma64_madd_per_s"]) and 0 < pk["mfma64_madd_per_s"] <= mfma_peak
+    assert pk["mfma64_madd_per_s"] > 0.5 * pk["fma64_per_s"]
