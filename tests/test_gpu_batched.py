@@ -263,9 +263,10 @@ def test_batched_degenerate_sizes(lib):
     stops on its float32 view of the row residual (<= 1e-6); the reported float64 residual
     differs from it by the float32 rounding of the folded kernel, which a handful of entries
     does not average out (up to ~1e-6 here), hence the 2e-6 bound."""
-    shapes = [(1, 8, 2, 21), (2, 4, 3, 22), (40, 1, 2, 23), (3, 2, 2, 24), (1, 32, 3, 25)]
+    shapes = [(1, 8, 2, 21), (2, 4, 3, 22), (40, 1, 2, 23), (3, 2, 2, 24), (1, 32, 3, 25),
+              (130, 1, 3, 26)]
     probs = _problems(shapes)
-    print("[batched degenerate] m = 1, 2, 3 and K = 1", flush=True)
+    print("[batched degenerate] m = 1, 2, 3, 130 and K = 1", flush=True)
     opts = lib.make_opts(tol=1e-6, max_iter=20000, fold_fp64=1)
     for want_grad in (True, False):
         batch = lib.Batch(probs, device=DEV, want_grad=want_grad)
@@ -284,8 +285,11 @@ def test_batched_degenerate_sizes(lib):
             # potentials are defined up to f + c, g - c: compare f + g pairs and f - f[0]
             s = max(np.abs(r["f"]).max(), np.abs(r["g"]).max(), p.eps)
             assert np.abs((f[:, None] + g[None, :]) - (r["f"][:, None] + r["g"][None, :])).max() <= 2e-4 * s, k
-            if want_grad and k == 0:
-                _check_grads(batch, k, p, Ck)
+            if want_grad:
+                # every gradient tile shape: one point, a partial tile, K = 1 and 2, three tiles
+                # of 64 own points with a ragged tail (m = 130)
+                worst = _check_grads(batch, k, p, Ck)
+                assert worst < 2e-5, (k, worst)
 
 
 def test_batched_single_problem_and_large_block(lib):
