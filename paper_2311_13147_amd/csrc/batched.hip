@@ -1610,11 +1610,14 @@ int batched_plan(const ot_batch_desc* h, int count, int32_t* plan) {
     fstart[q] = (int32_t)nf;
     nf += (int64_t)fold_row_blocks(m) * fold_col_blocks(m, h[idx[q]].tile_cfg);
   }
-  // value tiles by class, problems in index order within a class
+  // value tiles by class, the largest problems first within a class (their tiles run longest,
+  // so that the small ones fill the end of the launch), then in index order
   std::vector<int> vo(count);
   for (int p = 0; p < count; ++p) vo[p] = p;
   std::stable_sort(vo.begin(), vo.end(), [&](int u, int v) {
-    return v_class(h[u].dim, h[u].K) < v_class(h[v].dim, h[v].K);
+    const int cu = v_class(h[u].dim, h[u].K), cv = v_class(h[v].dim, h[v].K);
+    if (cu != cv) return cu < cv;
+    return h[u].n / h[u].K > h[v].n / h[v].K;
   });
   int q = 0;
   for (int c = 0; c < kVClasses; ++c) {
