@@ -177,6 +177,14 @@ def test_batched_plan_validation_and_order(B):
     descs[2].K = 3                          # n = 96: m = 32, 2 ceil(32 / 4) = 16 tiles
     assert _lib.ot_batched_plan(descs, 3, plan) == 0 and plan[1] == 4 + 16
     descs[2].K = 2
+    # within a class the largest problem's tiles come first (they run longest)
+    same = (BatchDesc * 3)()
+    for d, n in zip(same, (64, 512, 256)):  # K = 4: m = 16, 128, 64
+        d.n, d.K, d.dim, d.eps = n, 4, 2, 0.1
+        d.x = d.y = d.a = d.b = d.logK = d.f = d.g = d.out = d.dx = d.dy = 8
+    assert _lib.ot_batched_plan(same, 3, plan) == 0
+    assert list(plan[H + 6:H + 9]) == [1, 2, 0]   # m = 128, 64, 16
+    assert list(plan[H + 9:H + 12]) == [0, 4, 6]  # 2 ceil(m / 64) tiles: 4, 2, 2
     descs[1].K = 7                          # 512 % 7 != 0
     assert _lib.ot_batched_plan(descs, 3, plan) == B.OT_ERR_ARG
     descs[1].K, descs[1].tile_cfg = 8, 24
