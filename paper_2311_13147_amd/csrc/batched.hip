@@ -771,46 +771,24 @@ __global__ void __launch_bounds__(kBSolveThreads) batched_solve_kernel(BSolveArg
 }
 
 // ---- 3. values and gradients of every point ------------------------------------------------
-// One wave per own point of block 0 (row i or column j), four per workgroup; tiles
-// [0, ceil(m / 4)) of a problem are row tiles, the next as many column tiles.  As in the
-// single-problem adjoint, every plan entry T_ijk is evaluated once per pass (lanes stride over
-// the partners, all K shifts per partner) and the gradients of all K copies of the own point
-// come from float64 circular sums over the blocks:
+// Every plan entry T_ijk is evaluated once per pass, and the gradients of all K copies of an own
+// point of block 0 come from float64 circular sums over the blocks:
 //   row i   : Y(r) = sum_{k,j} T_ijk y_{((r + k) mod K) m + j},  dx_{r m + i} = 2 (x_{r m + i} S_i - Y(r));
 //   column j: X(c) = sum_{k,i} T_ijk x_{((c - k) mod K) m + i},  dy_{c m + j} = 2 (y_{c m + j} S'_j - X(c)).
-// Above 8 output blocks (16 in 2-D) the sums run in groups of blocks, the partner loop once
-// per group (AdjShape): for each shift k the plan entry is evaluated and multiplied into a
-// window of the partner's copies that slides by one block per shift.  K not in
-// {1, 2, 4, 8, 16, 32} takes a generic loop that re-evaluates the plan entries per output
-// block.
+// For K in {1, 2, 4, 8, 16, 32} they run as a matrix product on the float64 matrix cores
+// (bgrad_tile, 16 own points per wave); any other K takes badj_point: one wave per own point,
+// four per workgroup (tiles [0, ceil(m / 4)) of a problem are row tiles, the next as many
+// column tiles), lanes over the partners, one output block at a time with the plan entries
+// re-evaluated per block.
 // acc[p]: {P, <C,T>, mass, sum (rowsum - alpha)^2, sum (colsum - beta)^2, <f,alpha>, <g,beta>}
 constexpr int kAdjPts = 4;  // own points (waves) per workgroup
 
 constexpr int kAdjChunk = 64;  // partners staged in LDS at a time (one per lane)
 
-struct BAdjShared {
-  float own_y[kAdjPts][32 * 3 * 4];   // column pass: y_{k m + j} of each wave's own column(s)
-  float pts[32 * 3 * kAdjChunk];      // partner chunk: copy in block c, component d, partner
-                                      // q at (c DIM + d) kAdjChunk + q
-  float pot[kAdjChunk];               // the partners' potentials
-};
-
-// Output blocks per group for K shifts: the group's float64 sums and a window of the
-// partner's block copies stay in registers (RB dim doubles + RB dim floats).
-template <int KT, int DIM>
-struct AdjShape {
-  static constexpr int RB = KT < 8 ? KT : 8;
-  static_assert(KT % RB == 0, "groups of RB blocks");
-  static constexpr int NG = KT / RB;
-  static constexpr int NA = RB * DIM;
-  static constexpr int S = ilog2_ceil(NA);  // reduce-scatter over 2^S values
-};
-
-// Called by all four waves of the workgroup (the LDS staging needs every thread); a wave
-// whose own point lies beyond m passes active = false and only helps to stage.
-template <int DIM, int KT, bool ROW>
-__device__ void badj_point(const ot_batch_desc& d, int o, bool active, int lane,
-                           const float* own_y, double* vals, float* sh_pts, float* sh_pot) {
+// Generic K.  Called by all four waves of the workgroup; a wave whose own point lies beyond m
+// passes active = false.
+template <int DIM, bool ROW>
+__device__ void badj_point(const ot_batch_desc& d, int o, bool active, int lane, double* vals) {
   const int m = bm(d), K = d.K;
   const float s2 = (float)(kLog2eD / d.eps);
   const float eps = (float)d.eps;
@@ -828,240 +806,57 @@ __device__ void badj_point(const ot_batch_desc& d, int o, bool active, int lane,
     for (int dd = 0; dd < DIM; ++dd) xo[dd] = x[oc * DIM + dd];
   }
   gcfloat* src = ROW ? y : x;   // the partner's copies in every block
-  // 32-bit element offsets (n dim < 2^31): one register per address, the base in SGPRs
   auto cost_T = [&](int p, int k, float fg, float& c) -> float {
     c = 0.0f;
 #pragma unroll
     for (int dd = 0; dd < DIM; ++dd) {
       // |x_i - y_{k m + j}|^2: row pass partner j = p, column pass partner i = p
       const float e = ROW ? xo[dd] - y[(k * m + p) * DIM + dd]
-                          : x[p * DIM + dd] -
-                                (KT > 0 ? own_y[k * DIM + dd] : y[(k * m + o) * DIM + dd]);
+                          : x[p * DIM + dd] - y[(k * m + o) * DIM + dd];
       c = fmaf(e, e, c);
     }
     return exp2_fast((fg - c) * s2);
   };
   double S = 0.0;
   float vP = 0.0f, vC = 0.0f;
-  if constexpr (KT > 0) {
-    using Sh = AdjShape<KT, DIM>;
-    constexpr int RB = Sh::RB, NG = Sh::NG, NV = 1 << Sh::S;
-    // output groups outermost: the plan entries of a partner are re-evaluated per group (one
-    // exponential per (i, j, k) and group), and only the group's sums live in registers
+  if (!active) return;
+  // output block r at a time, the plan entries re-evaluated per block
 #pragma unroll 1
-    for (int gq = 0; gq < NG; ++gq) {
-      if (gq > 0 && !grad) break;  // uniform over the workgroup (one problem)
-      // the group's first output block: it moves only the LDS addresses of the partner
-      // copies and the output rows; the ring slots are compile-time
-      const int rot = gq * RB;
-      double acc[NV];
+  for (int r = 0; r < (grad ? K : 1); ++r) {
+    double a4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+    for (int p = lane; p < m; p += kWave) {
+      const float fg = po + (ROW ? gpot[p] : fpot[p]);
+#pragma unroll 1
+      for (int k = 0; k < K; ++k) {
+        float c;
+        const float T = cost_T(p, k, fg, c);
+        if (r == 0) {
+          S += (double)T;
+          if (ROW) {
+            vP = fmaf(T, fg - eps, vP);
+            vC = fmaf(T, c, vC);
+          }
+        }
+        if (grad) {
+          const int a = ROW ? (r + k) % K : (r - k + K) % K;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-      // the workgroup's four waves (four own points of this problem and pass) share each
-      // chunk of kAdjChunk partners, staged in LDS with all K block copies
-#pragma unroll 1
-      for (int c0 = 0; c0 < m; c0 += kAdjChunk) {
-        __syncthreads();  // the previous chunk's readers are done
-        const int nc = min(kAdjChunk, m - c0);
-        for (int e = threadIdx.x; e < KT * DIM * kAdjChunk; e += blockDim.x) {
-          const int q = e % kAdjChunk, cd = e / kAdjChunk;
-          const int cb = cd / DIM, dd = cd - cb * DIM;
-          sh_pts[e] = q < nc ? src[(cb * m + c0 + q) * DIM + dd] : 0.0f;
-        }
-        if (threadIdx.x < kAdjChunk)
-          sh_pot[threadIdx.x] = (int)threadIdx.x < nc ? (ROW ? gpot : fpot)[c0 + threadIdx.x] : 0.0f;
-        __syncthreads();
-        if (!active || lane >= nc) continue;
-        const float fg = po + sh_pot[lane];
-        const float fgs = fg * s2;  // exponent (fg - c) s2 as one FMA per entry
-        auto P = [&](int cb, int dd) -> float { return sh_pts[(cb * DIM + dd) * kAdjChunk + lane]; };
-        // dim 3 with K >= 8: a ring of plan entries (RB values) and one partner copy per step;
-        // otherwise a ring of partner copies (RB DIM values) and one plan entry per step.  The
-        // first keeps the large dim-3 classes within 128 registers (4 waves per SIMD instead
-        // of 3) at the price of RB - 1 recomputed entries per window; elsewhere the second is
-        // faster.
-        if constexpr (DIM == 3 && KT >= 8) {
-          // output block r = rot + rr takes T_k pt(a) with a = r + k (row) or a = r - k
-          // (column).  The loop runs over the partner copy a: each copy is read once (as
-          // float64) and multiplied by the RB plan entries it meets, T_{a - r} (row) or T_{r - a}
-          // (column), which live in a ring of RB float64 slots, slot k mod RB -- a compile-time
-          // constant for every (output, step) pair, since the steps go in rounds of RB and rot is
-          // a multiple of RB.  Each step computes the one entry that enters the window; the
-          // RB - 1 entries of the first window are computed before the loop.  (A ring of the
-          // RB partner copies instead would hold RB DIM values.)
-          double tr[RB];
-          auto entry = [&](int k) -> float {
-            float c = 0.0f;
-  #pragma unroll
-            for (int dd = 0; dd < DIM; ++dd) {
-              const float e = ROW ? xo[dd] - P(k, dd) : P(0, dd) - own_y[k * DIM + dd];
-              c = fmaf(e, e, c);
-            }
-            const float T = exp2_fast(fmaf(c, -s2, fgs));
-            if (gq == 0) {  // the sums once per (partner, shift)
-              S += (double)T;
-              if (ROW) {
-                vP = fmaf(T, fg - eps, vP);  // T (C + eps (Z - 1)) = T (f + g - eps)
-                vC = fmaf(T, c, vC);
-              }
-            }
-            return T;
-          };
-          if (grad) {
-            // the first window: rows need k = -rot - rr (slot RB - rr), columns k = rot + rr
-            // (slot rr), rr = 1 .. RB - 1; recomputed here, not counted in the sums
-  #pragma unroll
-            for (int rr = 1; rr < RB; ++rr) {
-              const int k = ROW ? ((KT - rot - rr) % KT + KT) % KT : (rot + rr) % KT;
-              float c = 0.0f;
-  #pragma unroll
-              for (int dd = 0; dd < DIM; ++dd) {
-                const float e = ROW ? xo[dd] - P(k, dd) : P(0, dd) - own_y[k * DIM + dd];
-                c = fmaf(e, e, c);
-              }
-              tr[ROW ? RB - rr : rr] = (double)exp2_fast(fmaf(c, -s2, fgs));
-            }
-          }
-  #pragma unroll 1
-          for (int a0 = 0; a0 < KT; a0 += RB) {
-  #pragma unroll
-            for (int j = 0; j < RB; ++j) {
-              const int a = a0 + j;
-              // the entry entering the window: rows k = a - rot, columns k = rot - a (mod K)
-              const int kn = ROW ? ((a - rot) % KT + KT) % KT : ((rot - a) % KT + KT) % KT;
-              const float T = entry(kn);
-              if (grad) {
-                const int sn = ROW ? j : (RB - j) % RB;
-                tr[sn] = (double)T;
-                double pa[DIM];
-  #pragma unroll
-                for (int dd = 0; dd < DIM; ++dd) pa[dd] = (double)P(a, dd);
-  #pragma unroll
-                for (int rr = 0; rr < RB; ++rr) {
-                  // rows: k = a - rot - rr, slot (j - rr) mod RB; columns: k = rot + rr - a,
-                  // slot (rr - j) mod RB
-                  const int slot = ROW ? ((j - rr) % RB + RB) % RB : ((rr - j) % RB + RB) % RB;
-  #pragma unroll
-                  for (int dd = 0; dd < DIM; ++dd)
-                    acc[rr * DIM + dd] = fma(tr[slot], pa[dd], acc[rr * DIM + dd]);
-                }
-              }
-              if (j & 1) __builtin_amdgcn_sched_barrier(0);
-            }
-          }
-        } else {
-          // output block r = rot + rr takes T_k pt(a) with a = r + k (row) or a = r - k
-          // (column).  The RB partner copies in use at shift k live in a ring of float64
-          // values, block a in slot (a - rot) mod RB, so an output's slot (rr + k or rr - k mod
-          // RB) is a compile-time constant and each shift replaces one slot (the copy that
-          // leaves the window) with the one that enters.
-          double ring[RB][DIM];
-  #pragma unroll
-          for (int rr = 0; rr < RB; ++rr)
-  #pragma unroll
-            for (int dd = 0; dd < DIM; ++dd) ring[rr][dd] = (double)P((rot + rr) % KT, dd);
-          // shifts in rounds of RB: within a round the ring slot of every (output, shift) pair
-          // is a compile-time constant (k0 is a multiple of RB), and the rounds stay a loop so
-          // that the compiler does not schedule all K shifts' reads at once
-  #pragma unroll 1
-          for (int k0 = 0; k0 < KT; k0 += RB) {
-  #pragma unroll
-            for (int j = 0; j < RB; ++j) {
-              const int k = k0 + j;
-              // block-row 0 cost |x_i - y_{k m + j}|^2: row pass x_i own, y_{k m + j} the
-              // partner's copy in block k; column pass x_i the partner's copy in block 0
-              float c = 0.0f;
-  #pragma unroll
-              for (int dd = 0; dd < DIM; ++dd) {
-                const float e = ROW ? xo[dd] - P(k, dd) : P(0, dd) - own_y[k * DIM + dd];
-                c = fmaf(e, e, c);
-              }
-              const float T = exp2_fast(fmaf(c, -s2, fgs));
-              if (gq == 0) {  // the sums once per partner
-                S += (double)T;
-                if (ROW) {
-                  vP = fmaf(T, fg - eps, vP);  // T (C + eps (Z - 1)) = T (f + g - eps)
-                  vC = fmaf(T, c, vC);
-                }
-              }
-              if (grad) {
-                const double T64 = (double)T;
-  #pragma unroll
-                for (int rr = 0; rr < RB; ++rr) {
-                  const int slot = ROW ? (rr + j) % RB : ((rr - j) % RB + RB) % RB;
-  #pragma unroll
-                  for (int dd = 0; dd < DIM; ++dd)
-                    acc[rr * DIM + dd] = fma(T64, ring[slot][dd], acc[rr * DIM + dd]);
-                }
-                if (k + 1 < KT) {
-                  // rows: block rot + k leaves (slot k mod RB), rot + k + RB enters; columns:
-                  // block rot - k + RB - 1 leaves (slot (RB - 1 - k) mod RB), rot - k - 1
-                  // enters
-                  const int slot = ROW ? j : ((RB - 1 - j) % RB + RB) % RB;
-                  int a = ROW ? rot + RB + k : rot - k - 1 + 2 * KT;
-                  a %= KT;
-  #pragma unroll
-                  for (int dd = 0; dd < DIM; ++dd) ring[slot][dd] = (double)P(a, dd);
-                }
-              }
-              if (j & 1) __builtin_amdgcn_sched_barrier(0);
-            }
-          }
-        }
-      }
-      if (gq == 0) S = wave_sum_all_d(S);
-      if (grad && active) {
-        wave_reduce_scatter_d<Sh::S>(acc, lane);
-        const int idx = lane >> (6 - Sh::S);
-        if ((lane & ((64 >> Sh::S) - 1)) == 0 && idx < Sh::NA) {
-          const int r = rot + idx / DIM, dd = idx % DIM;
-          const int Pi = r * m + o;
-          const double own = (double)(ROW ? x : y)[Pi * DIM + dd];
-          gout[Pi * DIM + dd] = (float)(2.0 * (own * S - acc[0]));
+          for (int dd = 0; dd < DIM; ++dd)
+            a4[dd] = fma((double)T, (double)src[(a * m + p) * DIM + dd], a4[dd]);
         }
       }
     }
-  } else {
-    // generic K: output block r at a time, the plan entries re-evaluated per block
-    if (!active) return;
-#pragma unroll 1
-    for (int r = 0; r < (grad ? K : 1); ++r) {
-      double a4[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 1
-      for (int p = lane; p < m; p += kWave) {
-        const float fg = po + (ROW ? gpot[p] : fpot[p]);
-#pragma unroll 1
-        for (int k = 0; k < K; ++k) {
-          float c;
-          const float T = cost_T(p, k, fg, c);
-          if (r == 0) {
-            S += (double)T;
-            if (ROW) {
-              vP = fmaf(T, fg - eps, vP);
-              vC = fmaf(T, c, vC);
-            }
-          }
-          if (grad) {
-            const int a = ROW ? (r + k) % K : (r - k + K) % K;
+    if (r == 0) S = wave_sum_all_d(S);
+    if (grad) {
 #pragma unroll
-            for (int dd = 0; dd < DIM; ++dd)
-              a4[dd] = fma((double)T, (double)src[(a * m + p) * DIM + dd], a4[dd]);
-          }
-        }
-      }
-      if (r == 0) S = wave_sum_all_d(S);
-      if (grad) {
-#pragma unroll
-        for (int dd = 0; dd < DIM; ++dd) {
-          const double v = wave_sum_all_d(a4[dd]);
-          const int P = r * m + o;
-          if (lane == 0)
-            gout[P * DIM + dd] = (float)(2.0 * ((double)(ROW ? x : y)[P * DIM + dd] * S - v));
-        }
+      for (int dd = 0; dd < DIM; ++dd) {
+        const double v = wave_sum_all_d(a4[dd]);
+        const int P = r * m + o;
+        if (lane == 0)
+          gout[P * DIM + dd] = (float)(2.0 * ((double)(ROW ? x : y)[P * DIM + dd] * S - v));
       }
     }
   }
-  if (!active) return;
   // the folded marginal of the own point and the mean of its potential (da, db)
   double mv = 0.0, ps = 0.0;
   gcfloat* marg_in = as_global(ROW ? d.a : d.b);
@@ -1445,21 +1240,13 @@ __global__ void __launch_bounds__(256)
     else
       bgrad_tile<DIM, KT, false>(d, first, wv, lane, vals16[wv], g_pts, g_pot, g_own, g_S);
   } else if constexpr (!VO) {
-    __shared__ BAdjShared sh;
+    // generic K: one own point per wave
     const int o = first + wv;
     const bool active = o < m;
-    // column pass: the own column's y_{k m + j} of every block, staged per wave
-    if (KT > 0 && !row && active) {
-      for (int e = lane; e < KT * DIM; e += kWave) {
-        const int k = e / DIM, dd = e - k * DIM;
-        sh.own_y[wv][e] = d.y[(k * m + o) * DIM + dd];
-      }
-    }
     if (lane == 0)
       for (int v = 0; v < 8; ++v) vals16[wv][v] = 0.0;
-    __syncthreads();
-    if (row) badj_point<DIM, KT, true>(d, o, active, lane, sh.own_y[wv], vals16[wv], sh.pts, sh.pot);
-    else badj_point<DIM, KT, false>(d, o, active, lane, sh.own_y[wv], vals16[wv], sh.pts, sh.pot);
+    if (row) badj_point<DIM, true>(d, o, active, lane, vals16[wv]);
+    else badj_point<DIM, false>(d, o, active, lane, vals16[wv]);
   } else {
     // row tiles only (the column sums in the same pass); LDS sized for the class
     __shared__ float vo_pts[(KT > 0 ? KT : 1) * DIM * kAdjChunk];
