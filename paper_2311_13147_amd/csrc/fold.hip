@@ -188,15 +188,140 @@ __global__ void __launch_bounds__(kFoldTJ* kFoldTI)
   }
 }
 
+// Point clouds with float64 costs: the square expanded, -C_ijk s2 = -s2 |x_i|^2 + u_k with
+// u_k = a_i . y_{k m + j} - P_kj, a_i = 2 s2 x_i, P_kj = s2 |y_{k m + j}|^2, all in float64
+// (the expansion loses nothing visible at float32 output: its rounding is ~1e-16 of
+// s2 |x| |y|).  The block's 64 columns j of up to 32 shifts are staged in LDS as float64 with
+// their P, and each thread folds kFoldRPT rows of its column, so a staged value serves them
+// all: a term costs DIM FMAs and a max in the first pass and DIM FMAs, an add, the conversion
+// and the exponential in the second.  logK_ij = ln 2 (-s2 |x_i|^2 + U + log2 sum_k 2^(u_k - U)),
+// U = max_k u_k.
+constexpr int kFoldRPT = 2;  // rows per thread
+
+template <int DIM>
+__global__ void __launch_bounds__(kFoldTJ* kFoldTI)
+    fold_points_kernel(Geom g, float* __restrict__ logK, float* __restrict__ alpha,
+                       float* __restrict__ beta, int iblocks) {
+  const int tj = threadIdx.x % kFoldTJ;
+  const int ti = threadIdx.x / kFoldTJ;
+  if ((int)blockIdx.y == iblocks) {
+    // marginal fold: 2*m outputs over the x-dimension of this block row
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < 2 * g.m) {
+      const float* v = t < g.m ? g.a : g.b;
+      const int i = t < g.m ? t : t - g.m;
+      double acc = 0.0;
+      for (int r = 0; r < g.K; ++r) acc += (double)v[(int64_t)r * g.m + i];
+      (t < g.m ? alpha : beta)[i] = (float)(acc / (double)g.K);
+    }
+    return;
+  }
+  __shared__ double ys[kFoldKC][DIM][kFoldTJ];
+  __shared__ double ps[kFoldKC][kFoldTJ];
+  const int m = g.m;
+  const int j0 = blockIdx.x * kFoldTJ;
+  const int j = j0 + tj;
+  const int ib = blockIdx.y * (kFoldTI * kFoldRPT) + ti * kFoldRPT;
+  const double s2 = kLog2eD / g.eps;
+  double a[kFoldRPT][DIM], xx[kFoldRPT], U[kFoldRPT];
+  float sum[kFoldRPT];
+#pragma unroll
+  for (int q = 0; q < kFoldRPT; ++q) {
+    const int ic = min(ib + q, m - 1);
+    double n2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const double xv = (double)g.x[(int64_t)ic * DIM + d];
+      a[q][d] = 2.0 * s2 * xv;
+      n2 = fma(xv, xv, n2);
+    }
+    xx[q] = s2 * n2;
+    U[q] = -1.0e300;
+    sum[q] = 0.0f;
+  }
+  const int nkc = (g.K + kFoldKC - 1) / kFoldKC;
+  auto stage = [&](int kc) {
+    const int kb = kc * kFoldKC;
+    const int nk = min(kFoldKC, g.K - kb);
+    for (int e = threadIdx.x; e < nk * kFoldTJ; e += blockDim.x) {
+      const int kk = e / kFoldTJ, t = e - kk * kFoldTJ;
+      const int jj = j0 + t;
+      double n2 = 0.0;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        const double v = jj < m ? (double)g.y[((int64_t)(kb + kk) * m + jj) * DIM + d] : 0.0;
+        ys[kk][d][t] = v;
+        n2 = fma(v, v, n2);
+      }
+      ps[kk][t] = s2 * n2;
+    }
+  };
+  // pass 1: U = max_k u_k
+  for (int kc = 0; kc < nkc; ++kc) {
+    if (kc > 0) __syncthreads();  // the previous chunk's readers are done
+    stage(kc);
+    __syncthreads();
+    const int nk = min(kFoldKC, g.K - kc * kFoldKC);
+    for (int kk = 0; kk < nk; ++kk) {
+      double yv[DIM];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) yv[d] = ys[kk][d][tj];
+      const double P = ps[kk][tj];
+#pragma unroll
+      for (int q = 0; q < kFoldRPT; ++q) {
+        double u = -P;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) u = fma(a[q][d], yv[d], u);
+        U[q] = u > U[q] ? u : U[q];
+      }
+    }
+  }
+  // pass 2: sum_k 2^(u_k - U) (one staging when K <= 32)
+  for (int kc = 0; kc < nkc; ++kc) {
+    if (nkc > 1) {
+      __syncthreads();
+      stage(kc);
+      __syncthreads();
+    }
+    const int nk = min(kFoldKC, g.K - kc * kFoldKC);
+    for (int kk = 0; kk < nk; ++kk) {
+      double yv[DIM];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) yv[d] = ys[kk][d][tj];
+      const double P = ps[kk][tj];
+#pragma unroll
+      for (int q = 0; q < kFoldRPT; ++q) {
+        double t = -(P + U[q]);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) t = fma(a[q][d], yv[d], t);
+        sum[q] += exp2_fast((float)t);
+      }
+    }
+  }
+  if (j < m) {
+#pragma unroll
+    for (int q = 0; q < kFoldRPT; ++q)
+      if (ib + q < m)
+        logK[(int64_t)(ib + q) * m + j] =
+            (float)((U[q] - xx[q] + (double)log2_fast(sum[q])) * kLn2D);
+  }
+}
+
 template <int DIM, bool FP64>
 static hipError_t launch_fold_t(const Geom& g, float* logK, float* alpha, float* beta,
                                 hipStream_t s) {
   const int jblocks = (g.m + kFoldTJ - 1) / kFoldTJ;
-  const int iblocks = (g.m + kFoldTI - 1) / kFoldTI;
   const int mblocks = (2 * g.m + kFoldTJ * kFoldTI - 1) / (kFoldTJ * kFoldTI);
   const int gx = jblocks > mblocks ? jblocks : mblocks;
-  hipLaunchKernelGGL((fold_kernel<DIM, FP64>), dim3(gx, iblocks + 1), dim3(kFoldTJ * kFoldTI),
-                     0, s, g, logK, alpha, beta, iblocks);
+  if constexpr (DIM > 0 && FP64) {
+    const int iblocks = (g.m + kFoldTI * kFoldRPT - 1) / (kFoldTI * kFoldRPT);
+    hipLaunchKernelGGL((fold_points_kernel<DIM>), dim3(gx, iblocks + 1),
+                       dim3(kFoldTJ * kFoldTI), 0, s, g, logK, alpha, beta, iblocks);
+  } else {
+    const int iblocks = (g.m + kFoldTI - 1) / kFoldTI;
+    hipLaunchKernelGGL((fold_kernel<DIM, FP64>), dim3(gx, iblocks + 1), dim3(kFoldTJ * kFoldTI),
+                       0, s, g, logK, alpha, beta, iblocks);
+  }
   return hipGetLastError();
 }
 
