@@ -97,6 +97,38 @@ def test_reduced_fixed_iterations(lib, name, mk):
         assert df < 2e-5 and dg < 2e-5, (df, dg)
 
 
+@pytest.mark.parametrize("name,mk", CASES[:2] + CASES[4:5], ids=[c[0] for c in CASES[:2] + CASES[4:5]])
+def test_reduced_warm_start(lib, name, mk):
+    """warm_start = 1: the solve starts from the g it is given (Alg. 2 with q = exp(g/eps) in
+    place of 1).  From the oracle's g after 7 cold iterations, 1 and 4 further iterations
+    match the oracle started from the same g, and a tolerance solve from it stops earlier than
+    the cold one with the same marginal error."""
+    p = mk()
+    prob = _problem(lib, p)
+    ref0 = _reduced_ref(p, 0.0, 7)
+    g0 = ref0["g"].astype(np.float32)
+    opts = lib.make_opts(tol=0.0, max_iter=1, fold_fp64=1)
+    logK, alpha, beta = lib.ot_fold_kernel(prob, opts)
+    for its in (1, 4):
+        print(f"[reduced warm] {name} iters={its}", flush=True)
+        o = lib.make_opts(tol=0.0, max_iter=its, fold_fp64=1)
+        f, g, st = lib.ot_sinkhorn_reduced(prob, logK, alpha, beta, o, g0=T_(g0))
+        ref = sinkhorn.reduced_sinkhorn(ref0["alpha"], ref0["beta"], ref0["logK"], p.eps, p.K,
+                                        tol=0.0, max_iter=its, g0=_f64(g0))
+        assert st["iters"] == its
+        df = np.abs(f.cpu().numpy() - ref["f"]).max() / p.eps
+        dg = np.abs(g.cpu().numpy() - ref["g"]).max() / p.eps
+        assert df < 2e-5 and dg < 2e-5, (its, df, dg)
+    o = lib.make_opts(tol=1e-6, max_iter=5000, fold_fp64=1)
+    _, _, cold = lib.ot_sinkhorn_reduced(prob, logK, alpha, beta, o)
+    _, _, warm = lib.ot_sinkhorn_reduced(prob, logK, alpha, beta,
+                                         lib.make_opts(tol=1e-6, max_iter=5000, fold_fp64=1),
+                                         g0=T_(g0))
+    assert warm["converged"] and cold["converged"]
+    assert warm["iters"] <= cold["iters"], (warm["iters"], cold["iters"])
+    assert warm["err_row"] <= 1.05e-6
+
+
 def test_reduced_more_workgroups_than_one_xcd(lib):
     """m = 1000 needs 63 workgroups, more than one XCD holds: the solver is launched without
     the one-XCD placement and publishes with agent-scope stores (dstats[7] = 0); fixed
